@@ -1,0 +1,421 @@
+"""CPU oracle for the Q-adic transform path (TEST INFRASTRUCTURE ONLY).
+
+This module is the checker, not the product.  Only the test suite, the
+smoke check in ``__graft_entry__`` and the CPU-baseline leg of ``bench.py``
+may import it.  It shares no code with the HIP library: no tables, no
+helpers, no constants.  Everything is plain Python integers (arbitrary
+precision) plus, for the larger GEMM cases, numpy int64 matrix products
+used as a library step.
+
+Source: J.-G. Dumas, "Q-adic Transform Revisited" (arXiv 0710.0510).
+
+Conventions
+-----------
+* A polynomial over GF(p) is a list of ints ``c`` with ``c[i]`` the
+  coefficient of X^i, every value in [0, p).
+* ``k`` is the number of coefficients of an operand (degree < k), so a
+  product has 2k-1 coefficients (reading of Thm. 1, where Alg. 1 states
+  "degree less than k").
+* A field GF(p^k) is given by p and the k low coefficients ``P_low`` of a
+  monic defining polynomial P = X^k + sum_i P_low[i] X^i (Section 7).
+
+Every function names the passage it follows.  Where the method reaches a
+result that has a plain definition (a polynomial or matrix product over
+GF(p) or GF(p^k)), the oracle is that definition; the paper's own steps
+(Alg. 1, Alg. 2, Alg. 3, Alg. 4) are written out separately so that tests
+can check the paper's printed intermediates and Thm. 2 / Thm. 3's
+invariants.
+"""
+
+from __future__ import annotations
+
+import itertools
+from typing import Iterable, List, Sequence, Tuple
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Integers and primes
+# ---------------------------------------------------------------------------
+
+
+def is_prime(n: int) -> bool:
+    """Trial division; the characteristic p of Section 2 must be prime."""
+    if n < 2:
+        return False
+    d = 2
+    while d * d <= n:
+        if n % d == 0:
+            return False
+        d += 1
+    return True
+
+
+# ---------------------------------------------------------------------------
+# O1: polynomial product over GF(p) (Section 2, eq. (1); Alg. 1 ENSURE)
+# ---------------------------------------------------------------------------
+
+
+def poly_mul_z(a: Sequence[int], b: Sequence[int]) -> List[int]:
+    """Product in Z[X]: coefficient j is sum_i a_i b_{j-i} (eq. (1))."""
+    if not a or not b:
+        return []
+    out = [0] * (len(a) + len(b) - 1)
+    for i, ai in enumerate(a):
+        for j, bj in enumerate(b):
+            out[i + j] += ai * bj
+    return out
+
+
+def poly_mul_mod_p(a: Sequence[int], b: Sequence[int], p: int) -> List[int]:
+    """R = a*b in GF(p)[X], all len(a)+len(b)-1 coefficients kept (Alg. 1)."""
+    return [c % p for c in poly_mul_z(a, b)]
+
+
+# ---------------------------------------------------------------------------
+# O3: arithmetic in GF(p^k) = GF(p)[X]/(P) (Section 7)
+# ---------------------------------------------------------------------------
+
+
+def monic(P_low: Sequence[int]) -> List[int]:
+    """Full coefficient list of the monic P = X^k + sum P_low[i] X^i."""
+    return list(P_low) + [1]
+
+
+def poly_rem(c: Sequence[int], P_low: Sequence[int], p: int) -> List[int]:
+    """Remainder of c modulo the monic P over GF(p), as k coefficients.
+
+    Plain long division from the top coefficient down: X^k is replaced by
+    -sum P_low[i] X^i.
+    """
+    k = len(P_low)
+    r = [x % p for x in c]
+    for top in range(len(r) - 1, k - 1, -1):
+        lead = r[top]
+        if lead:
+            r[top] = 0
+            for i in range(k):
+                r[top - k + i] = (r[top - k + i] - lead * P_low[i]) % p
+    r = r[:k] + [0] * max(0, k - len(r))
+    return r
+
+
+def field_add(a: Sequence[int], b: Sequence[int], p: int) -> List[int]:
+    return [(x + y) % p for x, y in zip(a, b)]
+
+
+def field_mul(a: Sequence[int], b: Sequence[int], p: int,
+              P_low: Sequence[int]) -> List[int]:
+    """Schoolbook product of two elements, then reduction modulo P."""
+    return poly_rem(poly_mul_z(a, b), P_low, p)
+
+
+def field_pow(a: Sequence[int], e: int, p: int, P_low: Sequence[int]) -> List[int]:
+    k = len(P_low)
+    result = [1] + [0] * (k - 1)
+    base = list(a)
+    while e:
+        if e & 1:
+            result = field_mul(result, base, p, P_low)
+        base = field_mul(base, base, p, P_low)
+        e >>= 1
+    return result
+
+
+def all_elements(p: int, k: int) -> Iterable[List[int]]:
+    """Every element of GF(p^k) in coefficient form, base-p order."""
+    for t in itertools.product(range(p), repeat=k):
+        yield list(reversed(t))
+
+
+def is_irreducible(P_low: Sequence[int], p: int) -> bool:
+    """P monic of degree k is irreducible iff no monic divisor of degree
+    1..k//2 exists (plain trial division over GF(p))."""
+    k = len(P_low)
+    P = monic(P_low)
+    for d in range(1, k // 2 + 1):
+        for low in itertools.product(range(p), repeat=d):
+            D = list(low) + [1]
+            if _poly_rem_general(P, D, p) == [0] * d:
+                return False
+    return True
+
+
+def _poly_rem_general(c: Sequence[int], D: Sequence[int], p: int) -> List[int]:
+    """Remainder of c by a monic D (used only for irreducibility)."""
+    d = len(D) - 1
+    r = [x % p for x in c]
+    for top in range(len(r) - 1, d - 1, -1):
+        lead = r[top]
+        if lead:
+            for i in range(d + 1):
+                r[top - d + i] = (r[top - d + i] - lead * D[i]) % p
+    return r[:d]
+
+
+# ---------------------------------------------------------------------------
+# O4: matrix product over GF(p^k) (Alg. 4 ENSURE, applied entrywise)
+# ---------------------------------------------------------------------------
+
+
+def gemm_gfpk_small(A, B, p: int, P_low: Sequence[int]):
+    """C[i][j] = sum_l A[i][l] * B[l][j] in GF(p^k); one field product and
+    one field addition at a time.  A is M x K x k, B is K x N x k (nested
+    lists or arrays of ints in [0, p)); returns an M x N x k list."""
+    k = len(P_low)
+    M, K = len(A), len(A[0]) if len(A) else 0
+    N = len(B[0]) if K else 0
+    C = []
+    for i in range(M):
+        row = []
+        for j in range(N):
+            acc = [0] * k
+            for l in range(K):
+                acc = field_add(acc, field_mul(list(A[i][l]), list(B[l][j]), p, P_low), p)
+            row.append(acc)
+        C.append(row)
+    return C
+
+
+def gemm_gfpk_planes(A: np.ndarray, B: np.ndarray, p: int,
+                     P_low: Sequence[int]) -> np.ndarray:
+    """Same product, accumulated in Z[X] and reduced once.
+
+    GF(p^k) is the image of Z[X] under reduction mod (p, P), a ring
+    homomorphism, so summing the Z[X] products first and reducing at the
+    end gives the same field element.  Plane t of the Z[X] sum is
+    sum_{i+j=t} A_i @ B_j where A_i is the M x K integer matrix of the i-th
+    coefficients; numpy's int64 matmul is the library step (exact: every
+    entry is below K*k*(p-1)^2 < 2^63).  Then each of the 2k-1 planes is
+    reduced mod p and X^t (t >= k) is replaced by its remainder mod P.
+    """
+    A = np.asarray(A, dtype=np.int64)
+    B = np.asarray(B, dtype=np.int64)
+    k = len(P_low)
+    M, K = A.shape[0], A.shape[1]
+    N = B.shape[1]
+    planes = [np.zeros((M, N), dtype=np.int64) for _ in range(2 * k - 1)]
+    for i in range(k):
+        Ai = np.ascontiguousarray(A[:, :, i])
+        for j in range(k):
+            planes[i + j] += Ai @ np.ascontiguousarray(B[:, :, j])
+    planes = [pl % p for pl in planes]
+    out = np.zeros((M, N, k), dtype=np.int64)
+    for t in range(2 * k - 1):
+        xt = poly_rem([0] * t + [1], P_low, p)  # X^t mod P
+        for s in range(k):
+            if xt[s]:
+                out[:, :, s] += xt[s] * planes[t]
+    return (out % p).astype(np.uint8)
+
+
+def gemm_entry(A_row: np.ndarray, B_col: np.ndarray, p: int,
+               P_low: Sequence[int]) -> List[int]:
+    """One entry C[i][j] = sum_l A[i][l] B[l][j] over GF(p^k), big ints.
+
+    ``A_row`` is K x k, ``B_col`` is K x k.  Accumulate in Z[X] (exact) and
+    reduce once (same homomorphism argument as ``gemm_gfpk_planes``)."""
+    k = len(P_low)
+    acc = [0] * (2 * k - 1)
+    for a, b in zip(A_row.tolist(), B_col.tolist()):
+        for i in range(k):
+            ai = a[i]
+            if ai:
+                for j in range(k):
+                    acc[i + j] += ai * b[j]
+    return poly_rem(acc, P_low, p)
+
+
+def polymul_batch(a: np.ndarray, b: np.ndarray, p: int) -> np.ndarray:
+    """Row-wise O1 on n x k arrays: out[r] = a[r] * b[r] in GF(p)[X]."""
+    a = np.asarray(a, dtype=np.int64)
+    b = np.asarray(b, dtype=np.int64)
+    n, k = a.shape
+    out = np.zeros((n, 2 * k - 1), dtype=np.int64)
+    for i in range(k):
+        for j in range(k):
+            out[:, i + j] += a[:, i] * b[:, j]
+    return (out % p).astype(np.uint8)
+
+
+# ---------------------------------------------------------------------------
+# DQT: evaluation at q (Section 2, eq. (1); Alg. 1 first step)
+# ---------------------------------------------------------------------------
+
+
+def dqt(coeffs: Sequence[int], q: int) -> int:
+    """Evaluate sum c_i X^i at X = q with Horner's rule (Alg. 1, step 1)."""
+    v = 0
+    for c in reversed(list(coeffs)):
+        v = v * q + c
+    return v
+
+
+def qadic_digits(r: int, q: int, n: int) -> List[int]:
+    """The n base-q digits of r >= 0, least significant first (radix
+    conversion of Alg. 1, step 3)."""
+    out = []
+    for _ in range(n):
+        r, d = divmod(r, q)
+        out.append(d)
+    return out
+
+
+def dqt_inverse(r: int, q: int, n: int, p: int) -> List[int]:
+    """O2 as a definition: base-q digits of r, each taken mod p (Alg. 1,
+    steps 3-4; also Alg. 2's ENSURE, mu_i = digit_i mod p)."""
+    return [d % p for d in qadic_digits(r, q, n)]
+
+
+def polymul_dqt(a: Sequence[int], b: Sequence[int], p: int, q: int) -> List[int]:
+    """Alg. 1 step by step, in big integers: pack both operands at q,
+    multiply once, convert back in radix q, reduce each digit mod p."""
+    k = max(len(a), len(b))
+    r = dqt(a, q) * dqt(b, q)
+    return dqt_inverse(r, q, 2 * k - 1, p)
+
+
+# ---------------------------------------------------------------------------
+# eq. (2): the exactness conditions of Thm. 1
+# ---------------------------------------------------------------------------
+
+
+def eq2_holds(p: int, k: int, q: int, n_q: int, m: int = 53) -> bool:
+    """q > n_q k (p-1)^2 and (2k-1) log2(q) < m, checked in integers:
+    the second inequality is q^(2k-1) < 2^m."""
+    return q > n_q * k * (p - 1) ** 2 and q ** (2 * k - 1) < 2 ** m
+
+
+def max_pow2_q(p: int, k: int, m: int = 53) -> Tuple[int, int]:
+    """Largest q = 2^b with q^(2k-1) < 2^m, and the largest n_q it allows
+    under eq. (2)."""
+    b = 1
+    while (2 ** (b + 1)) ** (2 * k - 1) < 2 ** m:
+        b += 1
+    q = 2 ** b
+    nq = (q - 1) // (k * (p - 1) ** 2) if p > 1 else 0
+    return q, nq
+
+
+# ---------------------------------------------------------------------------
+# Alg. 2 (REDQ), as printed, in big integers
+# ---------------------------------------------------------------------------
+
+
+def redq_steps(r: int, p: int, q: int, d: int):
+    """Alg. 2 step by step for r = sum_{i<=d} mu~_i q^i >= 0.
+
+    Returns (rop, u, mu, rho):
+      rop = floor(r / p);
+      u_i = floor(r / q^i) - p * floor(rop / q^i), i = 0..d;
+      mu_d = u_d; mu_i = (u_i - q u_{i+1}) mod p for i < d;
+      rho = sum mu_i q^i.
+    """
+    rop = r // p
+    u = [r // q ** i - p * (rop // q ** i) for i in range(d + 1)]
+    mu = [0] * (d + 1)
+    mu[d] = u[d] % p
+    for i in range(d):
+        mu[i] = (u[i] - q * u[i + 1]) % p
+    rho = sum(m * q ** i for i, m in enumerate(mu))
+    return rop, u, mu, rho
+
+
+def q_matrix(d: int, q: int, p: int) -> List[List[int]]:
+    """Q_d of Section 5.1 reduced mod p: 1 on the diagonal and -q on the
+    superdiagonal, so that mu = Q_d u (mod p)."""
+    Q = [[0] * (d + 1) for _ in range(d + 1)]
+    for i in range(d + 1):
+        Q[i][i] = 1
+        if i < d:
+            Q[i][i + 1] = (-q) % p
+    return Q
+
+
+def mat_vec_mod(Q: Sequence[Sequence[int]], v: Sequence[int], p: int) -> List[int]:
+    return [sum(a * b for a, b in zip(row, v)) % p for row in Q]
+
+
+def toeplitz_powers(d: int, q: int) -> List[List[int]]:
+    """Upper-triangular Toeplitz matrix of powers of q (Section 5.1), whose
+    inverse is Q_d."""
+    return [[q ** (j - i) if j >= i else 0 for j in range(d + 1)]
+            for i in range(d + 1)]
+
+
+def q6_by_three_q2(u: Sequence[int], q: int, p: int) -> List[int]:
+    """Alg. 3: Q_6 applied to u_0..u_6 with three overlapping Q_2 products,
+    keeping the first two entries of the first two."""
+    Q2 = q_matrix(2, q, p)
+    a = mat_vec_mod(Q2, u[0:3], p)
+    b = mat_vec_mod(Q2, u[2:5], p)
+    c = mat_vec_mod(Q2, u[4:7], p)
+    return [a[0], a[1], b[0], b[1], c[0], c[1], c[2]]
+
+
+def q_by_windows(u: Sequence[int], q: int, p: int, w: int) -> List[int]:
+    """Section 5.2 generalised: Q_d through overlapping Q_{w-1} windows of
+    w residues each, advancing by w-1; ceil(d/(w-1)) windows."""
+    d = len(u) - 1
+    Qw = q_matrix(w - 1, q, p)
+    mu = [0] * (d + 1)
+    start = 0
+    while True:
+        win = list(u[start:start + w])
+        win += [0] * (w - len(win))
+        part = mat_vec_mod(Qw, win, p)
+        last = start + w - 1 >= d
+        keep = w if last else w - 1
+        for j in range(keep):
+            if start + j <= d:
+                mu[start + j] = part[j]
+        if last:
+            return mu
+        start += w - 1
+
+
+# ---------------------------------------------------------------------------
+# Thm. 3: the L and H tables of Alg. 4, and Alg. 4 itself
+# ---------------------------------------------------------------------------
+
+
+def table_L(uw: Sequence[int], q: int, p: int) -> List[int]:
+    """L indexed by (u_0..u_{k-1}): sum_{i<=k-2} ((u_i - q u_{i+1}) mod p) X^i,
+    as k coefficients (its degree is below k-1, so it is already reduced)."""
+    k = len(uw)
+    out = [0] * k
+    for i in range(k - 1):
+        out[i] = (uw[i] - q * uw[i + 1]) % p
+    return out
+
+
+def table_H(uw: Sequence[int], q: int, p: int, P_low: Sequence[int]) -> List[int]:
+    """H indexed by (u_{k-1}..u_{2k-2}):
+    u_{2k-2} X^{2k-2} + sum_{i=k-1}^{2k-3} ((u_i - q u_{i+1}) mod p) X^i,
+    reduced modulo P."""
+    k = len(uw)
+    poly = [0] * (2 * k - 1)
+    poly[2 * k - 2] = uw[k - 1] % p
+    for t in range(k - 1):       # i = k-1+t runs over k-1 .. 2k-3
+        poly[k - 1 + t] = (uw[t] - q * uw[t + 1]) % p
+    return poly_rem(poly, P_low, p)
+
+
+def fgdp(v1, v2, p: int, P_low: Sequence[int], q: int) -> List[int]:
+    """Alg. 4 step by step in big integers for one dot product v1^T v2 over
+    GF(p^k): pack at q, one integer dot product, rop, the 2k-1 residues
+    u_i, then L + H from the two tables."""
+    k = len(P_low)
+    r = sum(dqt(a, q) * dqt(b, q) for a, b in zip(v1, v2))
+    rop = r // p
+    u = [r // q ** i - p * (rop // q ** i) for i in range(2 * k - 1)]
+    L = table_L(u[0:k], q, p)
+    H = table_H(u[k - 1:2 * k - 1], q, p, P_low)
+    return field_add(L, H, p)
+
+
+def binary_index(uw: Sequence[int], p: int) -> int:
+    """Section 5.3 binary indexing: sum u_i 2^(c*i) with c = ceil(log2 p),
+    u_0 least significant."""
+    c = max(1, (p - 1).bit_length())
+    return sum(int(x) << (c * i) for i, x in enumerate(uw))

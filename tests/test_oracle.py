@@ -1,0 +1,335 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these tests re-types an oracle formula: each compares the oracle
+with a value printed in the paper (tests/golden/), a closed form, a library
+routine, an invariant, or brute force on tiny inputs.
+"""
+import itertools
+import random
+
+import numpy as np
+import pytest
+
+from oracle import gf
+from golden_io import load
+
+CONFIG_FIELDS = [(3, (1, 0)), (7, (1, 0)), (3, (2, 0, 0, 2)), (5, (3, 3, 0))]
+
+
+# --- worked examples printed in the paper ---------------------------------
+
+def test_example1_dqt():
+    g = load("ex1_dqt.txt")
+    p, q = g["p"], g["q"]
+    assert gf.dqt(g["a"], q) == g["packed_a"]
+    assert gf.dqt(g["b"], q) == g["packed_b"]
+    assert gf.dqt(g["a"], q) * gf.dqt(g["b"], q) == g["product"]
+    assert gf.qadic_digits(g["product"], q, 3) == g["digits"]
+    assert gf.dqt_inverse(g["product"], q, 3, p) == g["result"]
+    assert gf.polymul_dqt(g["a"], g["b"], p, q) == g["result"]
+    assert gf.poly_mul_mod_p(g["a"], g["b"], p) == g["result"]
+
+
+def test_example2_p_divides_q():
+    g = load("ex2_redq_p_divides_q.txt")
+    p, q = g["p"], g["q"]
+    r = gf.dqt(g["a"], q) * gf.dqt(g["b"], q)
+    assert r == g["product"]
+    assert r - p * g["quotients"] == g["reduced"]
+    rop, u, mu, rho = gf.redq_steps(r, p, q, 4)
+    assert mu == g["result"]
+    assert rho == g["reduced"]
+    assert u == g["result"]                 # p | q: no correction needed
+    assert gf.dqt_inverse(r, q, 5, p) == g["result"]
+    assert gf.poly_mul_mod_p(g["a"], g["b"], p) == g["result"]
+    # the quotient vector holds floor(digit / p) for every digit
+    digits = gf.qadic_digits(r, q, 5)
+    assert gf.dqt([d // p for d in digits], q) == g["quotients"]
+
+
+def test_example3_full_redq():
+    g = load("ex3_redq_full.txt")
+    p, q = g["p"], g["q"]
+    r = gf.dqt(g["R"], q)
+    assert r == g["packed"]
+    rop, u, mu, rho = gf.redq_steps(r, p, q, 3)
+    assert rop == g["rop"]
+    assert rop * p == g["rop_times_p"]
+    assert u == g["u"]
+    assert r // q == g["shifted"]
+    assert (rop // q) * p == g["shifted_rop_times_p"]
+    Q3 = gf.q_matrix(3, q, p)
+    assert Q3[0][1] == Q3[1][2] == Q3[2][3] == g["correction"]
+    assert gf.mat_vec_mod(Q3, u, p) == g["result"]
+    assert mu == g["result"]
+    assert [c % p for c in g["R"]] == g["result"]
+
+
+# --- Thm. 2 and the REDQ algorithm against the definition -----------------
+
+@pytest.mark.parametrize("p,q,d", [(3, 8, 4), (5, 8, 3), (7, 16, 2), (3, 4, 5),
+                                   (5, 6, 3), (2, 4, 4), (3, 10, 3)])
+def test_redq_bruteforce(p, q, d):
+    for r in range(q ** (d + 1)):
+        rop, u, mu, rho = gf.redq_steps(r, p, q, d)
+        assert all(0 <= x < p for x in u), (r, u)            # Thm. 2, first part
+        assert u == [(r // q ** i) % p for i in range(d + 1)]  # Thm. 2, second part
+        assert mu == [x % p for x in gf.qadic_digits(r, q, d + 1)]
+        assert mu == gf.dqt_inverse(r, q, d + 1, p)
+
+
+def test_lemma2_nested_floors():
+    rnd = random.Random(7)
+    for _ in range(5000):
+        r = rnd.randrange(0, 10 ** 12)
+        a, b = rnd.randrange(1, 1000), rnd.randrange(1, 1000)
+        assert (r // b) // a == r // (a * b) == (r // a) // b
+
+
+@pytest.mark.parametrize("d,q,p", [(3, 10 ** 6, 23), (6, 128, 3), (4, 1024, 5), (2, 2 ** 17, 7)])
+def test_qd_inverts_toeplitz(d, q, p):
+    Q = gf.q_matrix(d, q, p)
+    T = gf.toeplitz_powers(d, q)
+    prod = [[sum(Q[i][l] * T[l][j] for l in range(d + 1)) % p for j in range(d + 1)]
+            for i in range(d + 1)]
+    assert prod == [[int(i == j) for j in range(d + 1)] for i in range(d + 1)]
+
+
+@pytest.mark.parametrize("q", [128, 1024, 10 ** 6, 5])
+def test_alg3_q6_from_three_q2_exhaustive(q):
+    p = 3
+    Q6 = gf.q_matrix(6, q, p)
+    for u in itertools.product(range(p), repeat=7):
+        assert gf.q6_by_three_q2(u, q, p) == gf.mat_vec_mod(Q6, u, p)
+
+
+@pytest.mark.parametrize("p,d,w", [(3, 6, 3), (3, 6, 4), (5, 4, 3), (2, 8, 5)])
+def test_time_memory_windows(p, d, w):
+    q = 2 ** 7 + 3
+    Qd = gf.q_matrix(d, q, p)
+    for u in itertools.product(range(p), repeat=d + 1):
+        assert gf.q_by_windows(u, q, p, w) == gf.mat_vec_mod(Qd, u, p)
+
+
+# --- polynomial products ----------------------------------------------------
+
+def test_poly_mul_matches_numpy_convolve():
+    rnd = np.random.default_rng(11)
+    for _ in range(200):
+        la, lb = rnd.integers(1, 9, size=2)
+        a = rnd.integers(0, 50, size=la).tolist()
+        b = rnd.integers(0, 50, size=lb).tolist()
+        assert gf.poly_mul_z(a, b) == np.convolve(a, b).tolist()
+
+
+def test_poly_mul_k1_is_integer_product():
+    for p in (2, 3, 5, 7, 11):
+        for x in range(p):
+            for y in range(p):
+                assert gf.poly_mul_mod_p([x], [y], p) == [(x * y) % p]
+
+
+def test_polymul_batch_rowwise_and_exhaustive_cfg1():
+    p, k = 5, 3
+    elems = [list(e) for e in gf.all_elements(p, k)]
+    a = np.array([x for x in elems for _ in elems], dtype=np.uint8)
+    b = np.array([y for _ in elems for y in elems], dtype=np.uint8)
+    out = gf.polymul_batch(a, b, p)
+    rnd = random.Random(3)
+    for idx in rnd.sample(range(len(a)), 400):
+        want = [int(c) for c in np.convolve(a[idx].astype(int), b[idx].astype(int)) % p]
+        assert out[idx].tolist() == want
+
+
+def test_dqt_alg1_agrees_when_eq2_holds_and_fails_past_bound():
+    p, k = 5, 3
+    # q = 64 is the smallest power of two above k (p-1)^2 = 48
+    assert gf.eq2_holds(p, k, 64, 1)
+    for a in itertools.product(range(p), repeat=k):
+        b = [p - 1] * k
+        assert gf.polymul_dqt(list(a), b, p, 64) == gf.poly_mul_mod_p(list(a), b, p)
+    # at q = k (p-1)^2 exactly the middle digit of (p-1,...)^2 reaches q and carries
+    q = k * (p - 1) ** 2
+    assert not gf.eq2_holds(p, k, q, 1)
+    a = [p - 1] * k
+    assert gf.polymul_dqt(a, a, p, q) != gf.poly_mul_mod_p(a, a, p)
+
+
+# --- the fields -------------------------------------------------------------
+
+def test_irreducible_counts_match_gauss_formula():
+    # number of monic irreducible polynomials of degree n over GF(p):
+    # (1/n) sum_{d | n} mobius(d) p^(n/d)
+    def mobius(n):
+        res, m, f = 1, n, 2
+        while f * f <= m:
+            if m % f == 0:
+                m //= f
+                if m % f == 0:
+                    return 0
+                res = -res
+            f += 1
+        return -res if m > 1 else res
+
+    for p, n in [(2, 2), (2, 3), (2, 4), (3, 2), (3, 3), (3, 4), (5, 2), (5, 3), (7, 2)]:
+        want = sum(mobius(d) * p ** (n // d) for d in range(1, n + 1) if n % d == 0) // n
+        got = sum(gf.is_irreducible(list(low), p)
+                  for low in itertools.product(range(p), repeat=n))
+        assert got == want, (p, n)
+
+
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_config_polynomials_irreducible(p, P_low):
+    assert gf.is_irreducible(P_low, p)
+
+
+def test_reducible_rejected():
+    assert not gf.is_irreducible([2, 0], 3)      # X^2 + 2 = (X+1)(X+2) over GF(3)
+    assert not gf.is_irreducible([0, 0, 1], 5)   # X^3 + X^2 = X^2 (X+1)
+
+
+def test_gf9_textbook():
+    # GF(9) = GF(3)[X]/(X^2+1): X is a square root of -1
+    assert gf.field_mul([0, 1], [0, 1], 3, (1, 0)) == [2, 0]
+    assert gf.field_mul([1, 1], [1, 2], 3, (1, 0)) == [2, 0]   # (1+X)(1+2X) = 1+3X+2X^2 = -1
+
+
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_field_axioms(p, P_low):
+    k = len(P_low)
+    elems = [tuple(e) for e in gf.all_elements(p, k)]
+    one = tuple([1] + [0] * (k - 1))
+    zero = tuple([0] * k)
+    mul = {}
+    for a in elems:
+        for b in elems:
+            mul[a, b] = tuple(gf.field_mul(a, b, p, P_low))
+    order = p ** k
+    for a in elems:
+        assert mul[a, one] == a
+        assert mul[a, zero] == zero
+        # a^(p^k) = a for every element
+        assert tuple(gf.field_pow(a, order, p, P_low)) == a
+        if a != zero:
+            # inverse exists, hence no zero divisors
+            inv = tuple(gf.field_pow(a, order - 2, p, P_low))
+            assert mul[a, inv] == one
+        for b in elems:
+            assert mul[a, b] == mul[b, a]
+            if a != zero and b != zero:
+                assert mul[a, b] != zero
+    rnd = random.Random(5)
+    for _ in range(3000):
+        a, b, c = (rnd.choice(elems) for _ in range(3))
+        assert mul[mul[a, b], c] == mul[a, mul[b, c]]
+        bc = tuple(gf.field_add(b, c, p))
+        assert mul[a, bc] == tuple(gf.field_add(mul[a, b], mul[a, c], p))
+        # Frobenius: (a + b)^p = a^p + b^p
+        lhs = gf.field_pow(gf.field_add(a, b, p), p, p, P_low)
+        rhs = gf.field_add(gf.field_pow(a, p, p, P_low), gf.field_pow(b, p, p, P_low), p)
+        assert lhs == rhs
+    # the multiplicative group is cyclic of order p^k - 1
+    def elem_order(a):
+        e, x = 1, a
+        while x != one:
+            x, e = mul[x, a], e + 1
+        return e
+    assert max(elem_order(a) for a in elems if a != zero) == order - 1
+
+
+# --- GEMM over GF(p^k) -----------------------------------------------------
+
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_gemm_two_reduction_orders_agree(p, P_low):
+    k = len(P_low)
+    rng = np.random.default_rng(21)
+    A = rng.integers(0, p, size=(5, 7, k))
+    B = rng.integers(0, p, size=(7, 6, k))
+    small = np.array(gf.gemm_gfpk_small(A.tolist(), B.tolist(), p, P_low), dtype=np.uint8)
+    planes = gf.gemm_gfpk_planes(A, B, p, P_low)
+    assert np.array_equal(small, planes)
+    for i in range(5):
+        for j in range(6):
+            assert gf.gemm_entry(A[i], B[:, j], p, P_low) == planes[i, j].tolist()
+
+
+def test_gemm_k1_is_numpy_matmul_mod_p():
+    p = 11
+    rng = np.random.default_rng(3)
+    A = rng.integers(0, p, size=(17, 29, 1))
+    B = rng.integers(0, p, size=(29, 13, 1))
+    want = (A[:, :, 0] @ B[:, :, 0]) % p
+    # k = 1: the "field" is GF(p) itself; P = X + 0 has degree 1
+    got = gf.gemm_gfpk_planes(A, B, p, [0])
+    assert np.array_equal(got[:, :, 0], want)
+
+
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_gemm_identity_and_associativity(p, P_low):
+    k = len(P_low)
+    rng = np.random.default_rng(8)
+    A = rng.integers(0, p, size=(6, 6, k))
+    I = np.zeros((6, 6, k), dtype=np.int64)
+    for i in range(6):
+        I[i, i, 0] = 1
+    assert np.array_equal(gf.gemm_gfpk_planes(A, I, p, P_low), A)
+    assert np.array_equal(gf.gemm_gfpk_planes(I, A, p, P_low), A)
+    B = rng.integers(0, p, size=(6, 4, k))
+    C = rng.integers(0, p, size=(4, 5, k))
+    left = gf.gemm_gfpk_planes(gf.gemm_gfpk_planes(A, B, p, P_low), C, p, P_low)
+    right = gf.gemm_gfpk_planes(A, gf.gemm_gfpk_planes(B, C, p, P_low), p, P_low)
+    assert np.array_equal(left, right)
+
+
+# --- Thm. 3: the L/H tables and Alg. 4 -------------------------------------
+
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_lh_tables_reduce_the_corrected_digits(p, P_low):
+    k = len(P_low)
+    q, _ = gf.max_pow2_q(p, k)
+    d = 2 * k - 2
+    Qd = gf.q_matrix(d, q, p)
+    for u in itertools.product(range(p), repeat=2 * k - 1):
+        mu = gf.mat_vec_mod(Qd, u, p)
+        want = gf.poly_rem(mu, P_low, p)
+        got = gf.field_add(gf.table_L(u[:k], q, p), gf.table_H(u[k - 1:], q, p, P_low), p)
+        assert got == want
+
+
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_fgdp_equals_dot_product(p, P_low):
+    k = len(P_low)
+    q, nq = gf.max_pow2_q(p, k)
+    rng = np.random.default_rng(4)
+    for n in (1, 2, min(nq, 40), nq if nq <= 64 else 64):
+        v1 = rng.integers(0, p, size=(n, k))
+        v2 = rng.integers(0, p, size=(n, k))
+        assert gf.fgdp(v1.tolist(), v2.tolist(), p, P_low, q) == gf.gemm_entry(v1, v2, p, P_low)
+    # adversarial: all coefficients p-1 at the largest admissible block
+    n = min(nq, 64)
+    v = [[p - 1] * k] * n
+    assert gf.fgdp(v, v, p, P_low, q) == gf.gemm_entry(np.array(v), np.array(v), p, P_low)
+
+
+@pytest.mark.parametrize("p,k", [(7, 2), (3, 4), (5, 3), (3, 2), (5, 3)])
+def test_max_pow2_q_is_tight(p, k):
+    q, nq = gf.max_pow2_q(p, k)
+    assert gf.eq2_holds(p, k, q, nq)
+    assert not gf.eq2_holds(p, k, q, nq + 1)
+    assert not gf.eq2_holds(p, k, 2 * q, 1)
+
+
+def test_block_bound_is_tight_for_dot_products():
+    # GF(3^4) at q = 2^7: n_q = 7 passes, n_q = 8 overflows the middle digit
+    p, P_low, q = 3, (2, 0, 0, 2), 128
+    k = 4
+    v = [[p - 1] * k] * 7
+    assert gf.eq2_holds(p, k, q, 7) and not gf.eq2_holds(p, k, q, 8)
+    assert gf.fgdp(v, v, p, P_low, q) == gf.gemm_entry(np.array(v), np.array(v), p, P_low)
+    v8 = [[p - 1] * k] * 8
+    assert gf.fgdp(v8, v8, p, P_low, q) != gf.gemm_entry(np.array(v8), np.array(v8), p, P_low)
+
+
+def test_binary_index_layout():
+    assert gf.binary_index([1, 2, 0, 1], 3) == 1 + (2 << 2) + (1 << 6)
+    assert gf.binary_index([4, 4, 4], 5) == 4 + (4 << 3) + (4 << 6)
