@@ -1,0 +1,247 @@
+/*
+ * fqt.h -- C ABI of the Q-adic transform (FQT) library for MI355X (gfx950).
+ *
+ * Method: J.-G. Dumas, "Q-adic Transform Revisited" (arXiv 0710.0510).
+ *   - DQT packing (Section 2, eq. (1)): a polynomial sum_i a_i X^i over GF(p)
+ *     with k coefficients is evaluated at an integer q and held as an exact
+ *     integer inside an IEEE binary64 number.
+ *   - Exact floating-point products / dot products / GEMM on the packed values
+ *     (Alg. 1 step 2, Alg. 4 step 2), exact while eq. (2) holds:
+ *         q > n_q * k * (p-1)^2   and   (2k-1) * log2(q) < 53,
+ *     n_q being the number of products accumulated before a reduction.
+ *   - The inverse transform REDQ (Section 4, Alg. 2): one floor division by p
+ *     gives every residue u_i = floor(r/q^i) - p*floor(floor(r/p)/q^i) in
+ *     [0, p) (Thm. 2); the corrections mu_i = u_i - q*u_{i+1} mod p are either
+ *     applied directly (the matrix Q_d of Section 5.1) or folded, together with
+ *     the reduction modulo the defining polynomial, into the two tables L and
+ *     H of Alg. 4 (Thm. 3), indexed in binary (Section 5.3).
+ *
+ * Data format (all entry points):
+ *   - A field element or a polynomial operand is k consecutive uint8 bytes,
+ *     byte i holding the coefficient of X^i, every byte in [0, p).  Outputs
+ *     are canonical: every coefficient in [0, p), degree below k (fields) or
+ *     below 2k-1 (polynomial products).
+ *   - Matrices are row-major; leading dimensions count ELEMENTS (not bytes).
+ *   - Buffers named "device" are device pointers (hipMalloc / torch CUDA
+ *     tensors) on the current HIP device.  The caller allocates and frees
+ *     every data buffer; the library never frees them and never keeps them.
+ *   - Input bytes must lie in [0, p).  This is a documented precondition of
+ *     the device paths (checked by the tests, not by the kernels).
+ *
+ * Errors and asynchrony:
+ *   - Every call returns an fqt_status.  All argument and exactness checks run
+ *     on the host before anything is launched, so every error code except
+ *     FQT_ERR_DEVICE is reported without touching a GPU.
+ *   - Launches are asynchronous on the caller's stream (NULL = default
+ *     stream).  A device failure shows up as FQT_ERR_DEVICE from the call that
+ *     observed it.
+ *   - fqt_last_error() returns a thread-local, human-readable message for the
+ *     last failing call of the calling thread.
+ *   - Nothing throws across this ABI.
+ */
+#ifndef FQT_H
+#define FQT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* fqt_stream_t; /* same type as hipStream_t */
+
+typedef enum {
+  FQT_OK = 0,
+  FQT_ERR_INVALID_ARG = 1, /* null pointer, negative size, bad leading
+                              dimension, overlapping input/output buffers */
+  FQT_ERR_BOUNDS = 2,      /* eq. (2) violated for the requested q / n_q */
+  FQT_ERR_NOT_PRIME = 3,   /* p is not prime */
+  FQT_ERR_REDUCIBLE = 4,   /* the defining polynomial is reducible */
+  FQT_ERR_UNSUPPORTED = 5, /* parameters outside what the kernels handle */
+  FQT_ERR_DEVICE = 6,      /* a HIP runtime call failed */
+  FQT_ERR_OOM = 7          /* host or device allocation failed */
+} fqt_status;
+
+typedef enum {
+  FQT_PATH_AUTO = 0,       /* the autotuner's (or the default) choice */
+  FQT_PATH_PACKED_F64 = 1, /* q-adic packed FP64 MFMA + REDQ (the FQT) */
+  FQT_PATH_INT8 = 2,       /* coefficient-wise INT8 MFMA, INT32 accumulation,
+                              delayed reduction (Section 6, eq. (3)) */
+  FQT_PATH_PLAIN = 3       /* comparator: schoolbook product with % p and
+                              division by P for every product, no packing */
+} fqt_path;
+
+typedef enum {
+  FQT_UNPACK_POLY = 0,  /* ndigits coefficients mod p (Alg. 2 + Q_d) */
+  FQT_UNPACK_FIELD = 1  /* k coefficients mod p and mod P (Alg. 4 L + H) */
+} fqt_unpack_mode;
+
+typedef struct fqt_field_s* fqt_field; /* opaque, immutable after creation */
+
+/* One product of a batch: C (M x N) = A (M x K) * B (K x N) over the field.
+ * Pointers are device pointers; ld* count elements. */
+typedef struct {
+  int64_t M, N, K;
+  int64_t lda, ldb, ldc;
+  const uint8_t* A;
+  const uint8_t* B;
+  uint8_t* C;
+} fqt_gemm_desc;
+
+/* Tuning knobs of the GEMM paths; zero fields mean "library default". */
+typedef struct {
+  uint32_t log2q;  /* packed path: q = 2^log2q; 0 = largest allowed by eq.(2) */
+  uint32_t n_q;    /* packed path: products per K-block before a REDQ; 0 = the
+                      largest eq. (2) allows for q */
+  uint32_t tile;   /* kernel tile configuration id (see fqt_tile_count); 0 =
+                      default for the shape */
+  uint32_t reserved;
+} fqt_gemm_opts;
+
+/* ---- field handle (Section 7: GF(p^k) = GF(p)[X]/(P)) ------------------- */
+
+/* Create GF(p^k) with defining polynomial P = X^k + sum_{i<k} P_low[i] X^i.
+ *   p      prime, 2 <= p <= 127 (FQT_ERR_NOT_PRIME / FQT_ERR_UNSUPPORTED)
+ *   k      1 <= k <= 4 (FQT_ERR_UNSUPPORTED); k == 1 is the prime field
+ *   P_low  host array of k values in [0, p); for k == 1 may be NULL (P = X)
+ *   out    receives the handle; destroy with fqt_field_destroy.
+ * P must be irreducible (FQT_ERR_REDUCIBLE).  The L/H tables of Thm. 3 must
+ * fit the binary indexing of Section 5.3 with at most 4096 entries each
+ * (k * ceil(log2 p) <= 12), else FQT_ERR_UNSUPPORTED.  Needs no GPU: device
+ * copies of the tables are made on first use on each device. */
+fqt_status fqt_field_create(uint32_t p, uint32_t k, const uint32_t* P_low,
+                            fqt_field* out);
+void fqt_field_destroy(fqt_field f);
+
+/* Host copy of the L and H tables of Alg. 4 / Thm. 3 for radix q.
+ *   L, H   host arrays of at least *n_entries uint32 each (may be NULL to
+ *          query the size); entry index = sum_i u_i << (i*ceil(log2 p)),
+ *          u_0 least significant (Section 5.3).  An entry holds k
+ *          coefficients, coefficient s in byte s.  Index tuples with some
+ *          u_i >= p are unused and hold 0.
+ *   For L the tuple is (u_0..u_{k-1}); for H it is (u_{k-1}..u_{2k-2}). */
+fqt_status fqt_field_tables(fqt_field f, uint64_t q, uint32_t* L, uint32_t* H,
+                            size_t* n_entries);
+
+/* ---- parameters (Thm. 1, eq. (2), m = 53) -------------------------------- */
+
+/* Choose q for a block of n_q products (n_q >= 1).
+ *   pow2_q    nonzero: q is the LARGEST power of two with q^(2k-1) < 2^53
+ *             (so digit extraction is a shift, Section 2); zero: the largest
+ *             integer q with q^(2k-1) < 2^53.
+ *   carry_in  nonzero: the bound is q > n_q*k*(p-1)^2 + (p-1), which also
+ *             admits a reduced value re-entering the accumulator.
+ *   q_out     receives q (may be NULL)
+ *   nq_max_out receives the largest n_q that q admits (may be NULL)
+ * Returns FQT_ERR_BOUNDS if no q satisfies eq. (2) for n_q. */
+fqt_status fqt_params(uint32_t p, uint32_t k, uint64_t n_q, int pow2_q,
+                      int carry_in, uint64_t* q_out, uint64_t* nq_max_out);
+
+/* ---- DQT: pack (Alg. 1 step 1, Section 2) -------------------------------- */
+
+/* packed[i] = sum_j coeffs[i*k + j] * q^j as an exact binary64.
+ *   coeffs  device, n*k bytes;  packed  device, n doubles.
+ *   q       2 <= q, p*q^(k-1) <= 2^53 (FQT_ERR_BOUNDS otherwise).  Powers of
+ *           two use shifts; other q use an exact FP64 Horner evaluation. */
+fqt_status fqt_pack(fqt_field f, uint64_t q, const uint8_t* coeffs, size_t n,
+                    double* packed, fqt_stream_t s);
+
+/* ---- inverse transform: REDQ (Alg. 2; Alg. 4 steps 3-10) ----------------- */
+
+/* packed[i] = sum_{j<ndigits} d_j q^j with 0 <= d_j < q (an exact integer
+ * below 2^53; the caller guarantees the digit bound, eq. (2)).
+ *   POLY:  out holds n*ndigits bytes, out[i*ndigits + j] = d_j mod p
+ *          (REDQ residues u_j, then the Q_d correction).
+ *   FIELD: ndigits <= 2k-1; out holds n*k bytes, the element
+ *          sum_j (d_j mod p) X^j reduced modulo P (REDQ residues, then the
+ *          L and H tables of Thm. 3 and one addition in the field).
+ *   q      2 <= q, q^ndigits <= 2^53 (FQT_ERR_BOUNDS), ndigits in [1, 16]. */
+fqt_status fqt_unpack_redq(fqt_field f, uint64_t q, const double* packed,
+                           size_t n, uint32_t ndigits, fqt_unpack_mode mode,
+                           uint8_t* out, fqt_stream_t s);
+
+/* Same with packed values held as uint64, for values beyond binary64's exact
+ * range (the paper's Example 2 is one).  Any value below 2^64 is accepted;
+ * q^(ndigits-1) must be below 2^64 (FQT_ERR_BOUNDS).  The top digit is then
+ * floor(r / q^(ndigits-1)), whatever its size. */
+fqt_status fqt_unpack_redq_u64(fqt_field f, uint64_t q, const uint64_t* packed,
+                               size_t n, uint32_t ndigits,
+                               fqt_unpack_mode mode, uint8_t* out,
+                               fqt_stream_t s);
+
+/* ---- Alg. 1: batch of independent polynomial products over GF(p) -------- */
+
+/* c[i] = a[i] * b[i] in GF(p)[X] for i < n: pack at q, one FP64 product,
+ * REDQ and the Q_d correction.
+ *   a, b  device, n*k bytes;  c  device, n*(2k-1) bytes.
+ *   q     must satisfy eq. (2) with n_q = 1 (FQT_ERR_BOUNDS), any q >= 2;
+ *         powers of two use the shift path.  1 <= k <= 8. */
+fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q,
+                             const uint8_t* a, const uint8_t* b, size_t n,
+                             uint8_t* c, fqt_stream_t s);
+
+/* ---- GEMM over GF(p^k) (Alg. 4 for every entry, Section 7) -------------- */
+
+/* C = A * B over the field; A is M x K, B is K x N, C is M x N elements.
+ *   lda >= K, ldb >= N, ldc >= N (elements).  M, N, K >= 0; K == 0 writes
+ *   zeros.  C must not overlap A or B.
+ *   path  FQT_PATH_PACKED_F64: packed FP64 MFMA with q = 2^b and K-blocks of
+ *         n_q products, REDQ residues at every block boundary, L/H at the end.
+ *         FQT_PATH_INT8: INT8 MFMA on coefficient planes, INT32 accumulation.
+ *         FQT_PATH_PLAIN: per-product schoolbook comparator.
+ *         FQT_PATH_AUTO: the autotuned choice for this field and shape.
+ * The library may keep a device workspace per field and device. */
+fqt_status fqt_gemm_gfpk(fqt_field f, fqt_path path, int64_t M, int64_t N,
+                         int64_t K, const uint8_t* A, int64_t lda,
+                         const uint8_t* B, int64_t ldb, uint8_t* C,
+                         int64_t ldc, fqt_stream_t s);
+
+/* fqt_gemm_gfpk with explicit tuning knobs (NULL opts = defaults).  Returns
+ * FQT_ERR_BOUNDS when opts ask for a q / n_q that breaks eq. (2). */
+fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path,
+                            const fqt_gemm_opts* opts, int64_t M, int64_t N,
+                            int64_t K, const uint8_t* A, int64_t lda,
+                            const uint8_t* B, int64_t ldb, uint8_t* C,
+                            int64_t ldc, fqt_stream_t s);
+
+/* Batch of independent GEMMs of uneven sizes in ONE persistent launch.
+ *   descs  host array of count descriptors (device data pointers).
+ * The first call with a given descriptor list builds a plan (tiles sorted by
+ * cost, uploaded to the device) and captures it in a hipGraph; later calls
+ * with an identical list and stream replay the graph.  FQT_PATH_PLAIN runs
+ * one launch per product (the comparator). */
+fqt_status fqt_gemm_gfpk_batched(fqt_field f, fqt_path path, int64_t count,
+                                 const fqt_gemm_desc* descs, fqt_stream_t s);
+
+/* Same with tuning knobs (NULL = defaults / autotuned). */
+fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path,
+                                    const fqt_gemm_opts* opts, int64_t count,
+                                    const fqt_gemm_desc* descs,
+                                    fqt_stream_t s);
+
+/* ---- autotuner ----------------------------------------------------------- */
+
+/* Time every admissible (path, q, n_q, tile) candidate on the given problem
+ * (a single GEMM when count == 1, else a batch), require byte-identical
+ * outputs across candidates (FQT_ERR_DEVICE with a message otherwise), and
+ * remember the fastest for FQT_PATH_AUTO on this field and shape class.  The
+ * winner is written to best (may be NULL) and appended to the JSON cache
+ * file cache_path (may be NULL).  C buffers are overwritten. */
+fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
+                        const char* cache_path, fqt_path* best_path,
+                        fqt_gemm_opts* best, fqt_stream_t s);
+
+/* Number of tile configurations of a path (ids 1..count). */
+uint32_t fqt_tile_count(fqt_path path);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+
+const char* fqt_last_error(void);
+const char* fqt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FQT_H */

@@ -1,0 +1,744 @@
+// Host side of the FQT library: the C ABI declared in include/fqt.h.
+//
+// Everything that can be checked is checked here, synchronously, before any
+// launch: field validity (Section 7: p prime, P monic irreducible), the
+// exactness conditions of Thm. 1 / eq. (2), pointer and size sanity.  Tables
+// of Thm. 3 are built here from their definitions and copied to each device
+// on first use.
+
+#include "fqt.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cinttypes>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "fqt_internal.h"
+
+using namespace fqt;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fqt_status fail(fqt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+fqt_status ok() { return FQT_OK; }
+
+fqt_status hip_fail(hipError_t e, const char* what) {
+  return fail(FQT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define FQT_HIP(call)                                 \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+bool is_prime_u32(uint32_t n) {
+  if (n < 2) return false;
+  for (uint32_t d = 2; d * d <= n; ++d)
+    if (n % d == 0) return false;
+  return true;
+}
+
+uint32_t ceil_log2(uint32_t x) {  // smallest c with 2^c >= x
+  uint32_t c = 0;
+  while ((1u << c) < x) ++c;
+  return c;
+}
+
+// a^e computed in 128-bit with saturation at 2^64 (returns false on overflow)
+bool pow_u64(uint64_t a, uint32_t e, uint64_t* out) {
+  unsigned __int128 v = 1;
+  for (uint32_t i = 0; i < e; ++i) {
+    v *= a;
+    if (v > (unsigned __int128)UINT64_MAX) return false;
+  }
+  *out = (uint64_t)v;
+  return true;
+}
+
+// q^e <= 2^m, exactly.
+bool pow_at_most(uint64_t q, uint32_t e, uint32_t m) {
+  unsigned __int128 v = 1, lim = (unsigned __int128)1 << m;
+  for (uint32_t i = 0; i < e; ++i) {
+    v *= q;
+    if (v > lim) return false;
+  }
+  return true;
+}
+
+// q^e < 2^m, exactly.
+bool pow_below(uint64_t q, uint32_t e, uint32_t m) {
+  unsigned __int128 v = 1, lim = (unsigned __int128)1 << m;
+  for (uint32_t i = 0; i < e; ++i) {
+    v *= q;
+    if (v >= lim) return false;
+  }
+  return true;
+}
+
+// ---- polynomial helpers over GF(p) (host) --------------------------------
+
+// Remainder of c (length n) modulo the monic D = X^d + sum D_low[i] X^i.
+std::vector<uint32_t> poly_mod(std::vector<uint32_t> c, const uint32_t* D_low, uint32_t d,
+                               uint32_t p) {
+  for (int64_t t = (int64_t)c.size() - 1; t >= (int64_t)d; --t) {
+    const uint32_t lead = c[t] % p;
+    c[t] = 0;
+    if (!lead) continue;
+    for (uint32_t i = 0; i < d; ++i)
+      c[t - d + i] = (c[t - d + i] + lead * (p - D_low[i] % p)) % p;
+  }
+  c.resize(d, 0);
+  return c;
+}
+
+bool irreducible(const uint32_t* P_low, uint32_t k, uint32_t p) {
+  std::vector<uint32_t> P(P_low, P_low + k);
+  P.push_back(1);
+  for (uint32_t d = 1; d <= k / 2; ++d) {
+    std::vector<uint32_t> D(d, 0);
+    uint64_t count = 1;
+    for (uint32_t i = 0; i < d; ++i) count *= p;
+    for (uint64_t idx = 0; idx < count; ++idx) {
+      uint64_t t = idx;
+      for (uint32_t i = 0; i < d; ++i) {
+        D[i] = (uint32_t)(t % p);
+        t /= p;
+      }
+      auto r = poly_mod(P, D.data(), d, p);
+      bool zero = true;
+      for (uint32_t x : r) zero = zero && x == 0;
+      if (zero) return false;
+    }
+  }
+  return true;
+}
+
+struct DevTables {
+  uint32_t* L = nullptr;
+  uint32_t* H = nullptr;
+};
+
+struct BatchPlan {
+  std::vector<uint8_t> key;
+  GemmArgs* d_descs = nullptr;
+  TileItem* d_items = nullptr;
+  uint32_t* d_counter = nullptr;
+  int32_t n_items = 0;
+  int grid = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int device = -1;
+};
+
+struct TuneEntry {
+  fqt_path path;
+  fqt_gemm_opts opts;
+};
+
+}  // namespace
+
+struct fqt_field_s {
+  uint32_t p = 0, k = 0, cb = 0, tbl_log2 = 0;
+  uint32_t P_low[4] = {0, 0, 0, 0};
+  std::mutex mu;
+  std::map<uint32_t, std::pair<std::vector<uint32_t>, std::vector<uint32_t>>> host_tables;
+  std::map<std::pair<int, uint32_t>, DevTables> dev_tables;
+  std::vector<std::unique_ptr<BatchPlan>> plans;
+  std::map<std::string, TuneEntry> tuned;
+};
+
+namespace {
+
+FieldArgs field_args(const fqt_field_s* f, uint64_t q) {
+  FieldArgs fa{};
+  fa.p = f->p;
+  fa.cb = f->cb;
+  fa.negp24 = (1u << 24) - f->p;
+  fa.mod_magic = (uint32_t)(((1ull << 32) + f->p - 1) / f->p);
+  fa.sub_magic = 0x01010101u * (0x80u - f->p);
+  fa.c = (uint32_t)((f->p - (uint32_t)(q % f->p)) % f->p);
+  fa.inv_p = 1.0 / (double)f->p;
+  return fa;
+}
+
+// Thm. 3: L over (u_0..u_{k-1}) and H over (u_{k-1}..u_{2k-2}).
+void build_tables(const fqt_field_s* f, uint64_t q, std::vector<uint32_t>& L,
+                  std::vector<uint32_t>& H) {
+  const uint32_t p = f->p, k = f->k, cb = f->cb;
+  const uint32_t qm = (uint32_t)(q % p);
+  const size_t n = (size_t)1 << (k * cb);
+  L.assign(n, 0);
+  H.assign(n, 0);
+  std::vector<uint32_t> w(k);
+  uint64_t count = 1;
+  for (uint32_t i = 0; i < k; ++i) count *= p;
+  for (uint64_t idx = 0; idx < count; ++idx) {
+    uint64_t t = idx;
+    size_t bin = 0;
+    for (uint32_t i = 0; i < k; ++i) {
+      w[i] = (uint32_t)(t % p);
+      t /= p;
+      bin |= (size_t)w[i] << (cb * i);
+    }
+    // corrected digit: (w_i - q w_{i+1}) mod p
+    auto corr = [&](uint32_t i) { return (w[i] + (p - qm) * w[i + 1]) % p; };
+    // L: sum_{i <= k-2} corr(i) X^i
+    uint32_t le = 0;
+    for (uint32_t i = 0; i + 1 < k; ++i) le |= corr(i) << (8 * i);
+    L[bin] = le;
+    // H: w_{k-1} X^{2k-2} + sum_{t<k-1} corr(t) X^{k-1+t}, reduced mod P
+    std::vector<uint32_t> poly(2 * k - 1, 0);
+    poly[2 * k - 2] = w[k - 1];
+    for (uint32_t i = 0; i + 1 < k; ++i) poly[k - 1 + i] = corr(i);
+    auto red = poly_mod(poly, f->P_low, k, p);
+    uint32_t he = 0;
+    for (uint32_t i = 0; i < k; ++i) he |= red[i] << (8 * i);
+    H[bin] = he;
+  }
+}
+
+const std::pair<std::vector<uint32_t>, std::vector<uint32_t>>& host_tables(fqt_field_s* f,
+                                                                          uint64_t q) {
+  const uint32_t key = (uint32_t)(q % f->p);
+  auto it = f->host_tables.find(key);
+  if (it == f->host_tables.end()) {
+    std::vector<uint32_t> L, H;
+    build_tables(f, q, L, H);
+    it = f->host_tables.emplace(key, std::make_pair(std::move(L), std::move(H))).first;
+  }
+  return it->second;
+}
+
+fqt_status device_tables(fqt_field_s* f, uint64_t q, DevTables* out) {
+  std::lock_guard<std::mutex> lk(f->mu);
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  const auto key = std::make_pair(dev, (uint32_t)(q % f->p));
+  auto it = f->dev_tables.find(key);
+  if (it != f->dev_tables.end()) {
+    *out = it->second;
+    return ok();
+  }
+  const auto& ht = host_tables(f, q);
+  const size_t bytes = ht.first.size() * sizeof(uint32_t);
+  DevTables dt;
+  FQT_HIP(hipMalloc(&dt.L, bytes));
+  FQT_HIP(hipMalloc(&dt.H, bytes));
+  FQT_HIP(hipMemcpy(dt.L, ht.first.data(), bytes, hipMemcpyHostToDevice));
+  FQT_HIP(hipMemcpy(dt.H, ht.second.data(), bytes, hipMemcpyHostToDevice));
+  f->dev_tables[key] = dt;
+  *out = dt;
+  return ok();
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return na && nb && x < y + nb && y < x + na;
+}
+
+uint32_t max_pow2_b(uint32_t k) {  // largest b with (2k-1) b < 53, i.e. q^(2k-1) < 2^53
+  return 52 / (2 * k - 1);
+}
+
+// Matrix extent in bytes for rows x cols elements with leading dimension ld.
+size_t mat_bytes(int64_t rows, int64_t cols, int64_t ld, uint32_t k) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)(((rows - 1) * ld + cols) * (int64_t)k);
+}
+
+fqt_status check_gemm_args(const fqt_field_s* f, int64_t M, int64_t N, int64_t K,
+                           const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb,
+                           uint8_t* C, int64_t ldc) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (M < 0 || N < 0 || K < 0) return fail(FQT_ERR_INVALID_ARG, "negative dimension");
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
+    return fail(FQT_ERR_UNSUPPORTED, "dimension above 2^31-1");
+  if (lda < std::max<int64_t>(K, 1) || ldb < std::max<int64_t>(N, 1) ||
+      ldc < std::max<int64_t>(N, 1))
+    return fail(FQT_ERR_INVALID_ARG, "leading dimension smaller than the row length");
+  if (M && N && !C) return fail(FQT_ERR_INVALID_ARG, "null C");
+  if (M && K && !A) return fail(FQT_ERR_INVALID_ARG, "null A");
+  if (K && N && !B) return fail(FQT_ERR_INVALID_ARG, "null B");
+  const size_t nc = mat_bytes(M, N, ldc, f->k);
+  if (overlap(C, nc, A, mat_bytes(M, K, lda, f->k)) || overlap(C, nc, B, mat_bytes(K, N, ldb, f->k)))
+    return fail(FQT_ERR_INVALID_ARG, "C overlaps A or B");
+  return ok();
+}
+
+// Resolved parameters of the packed path.
+struct PackedChoice {
+  uint32_t b;
+  uint32_t nq;        // products per K-block actually used (multiple of 4)
+  uint32_t tile;
+  bool multi;
+};
+
+fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t K, int64_t M,
+                          int64_t N, PackedChoice* pc) {
+  const uint32_t p = f->p, k = f->k;
+  const uint32_t bmax = max_pow2_b(k);
+  uint32_t b = (o && o->log2q) ? o->log2q : bmax;
+  if (b > bmax || b < 1)
+    return fail(FQT_ERR_BOUNDS, "q = 2^%u breaks (2k-1) log2 q < 53 (k = %u)", b, k);
+  // residue windows [b*i, b*i+8) must stay below bit 52 of the binary64 pattern
+  if (b * (2 * k - 2) + 8 > 52)
+    return fail(FQT_ERR_UNSUPPORTED, "q = 2^%u leaves no room for the residue bytes (k = %u)", b,
+                k);
+  const uint64_t q = 1ull << b;
+  const uint64_t unit = (uint64_t)k * (p - 1) * (p - 1);
+  const uint64_t nq_max = unit ? (q - 1) / unit : UINT32_MAX;  // eq. (2): q > n_q k (p-1)^2
+  uint64_t nq = (o && o->n_q) ? o->n_q : nq_max;
+  if (nq > nq_max)
+    return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks q > n_q k (p-1)^2 for q = 2^%u", nq, b);
+  nq = std::min<uint64_t>(nq, 1u << 30) & ~3ull;  // whole MFMA k-groups
+  if (nq < 4)
+    return fail(FQT_ERR_UNSUPPORTED, "n_q below 4 (q = 2^%u, p = %u, k = %u)", b, p, k);
+  const bool multi = (uint64_t)K > nq;
+  if (multi) {
+    const uint64_t nblocks = ((uint64_t)K + 15) / 16 * 16 / nq + 1;
+    if (nblocks * (2 * p - 1) >= 65536)
+      return fail(FQT_ERR_UNSUPPORTED, "too many K-blocks (%" PRIu64 ") for the residue lanes",
+                  nblocks);
+  }
+  uint32_t tile = (o && o->tile) ? o->tile : 0;
+  if (tile > (uint32_t)kPackedTiles) return fail(FQT_ERR_INVALID_ARG, "unknown tile id %u", tile);
+  if (!tile) {
+    // default: the largest tile that still gives at least one wave per SIMD
+    const int64_t mn = M * N;
+    tile = mn >= (int64_t)4096 * 4096 ? 4 : (mn >= (int64_t)1024 * 2048 ? 3 : (mn >= 256 * 256 ? 2 : 1));
+  }
+  pc->b = b;
+  pc->nq = (uint32_t)nq;
+  pc->tile = tile;
+  pc->multi = multi;
+  return ok();
+}
+
+std::string shape_key(const fqt_field_s* f, int64_t count, int64_t M, int64_t N, int64_t K) {
+  auto bucket = [](int64_t x) {
+    int64_t b = 1;
+    while (b < x) b <<= 1;
+    return b;
+  };
+  char buf[128];
+  std::snprintf(buf, sizeof buf, "p%u_k%u_c%lld_%lld_%lld_%lld", f->p, f->k, (long long)count,
+                (long long)bucket(M), (long long)bucket(N), (long long)bucket(K));
+  return buf;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* fqt_last_error(void) { return g_last_error.c_str(); }
+
+const char* fqt_version(void) { return "fqt-mi355x 0.1 (gfx950)"; }
+
+uint32_t fqt_tile_count(fqt_path path) {
+  return path == FQT_PATH_PACKED_F64 ? (uint32_t)kPackedTiles : 1u;
+}
+
+fqt_status fqt_field_create(uint32_t p, uint32_t k, const uint32_t* P_low, fqt_field* out) {
+  if (!out) return fail(FQT_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
+  if (p > 127) return fail(FQT_ERR_UNSUPPORTED, "p = %u above 127", p);
+  if (k < 1 || k > 4) return fail(FQT_ERR_UNSUPPORTED, "k = %u outside [1, 4]", k);
+  if (k > 1 && !P_low) return fail(FQT_ERR_INVALID_ARG, "null defining polynomial");
+  auto f = std::make_unique<fqt_field_s>();
+  f->p = p;
+  f->k = k;
+  f->cb = std::max(1u, ceil_log2(p));
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint32_t c = P_low ? P_low[i] : 0;
+    if (c >= p) return fail(FQT_ERR_INVALID_ARG, "P coefficient %u not in [0, p)", c);
+    f->P_low[i] = c;
+  }
+  if (!irreducible(f->P_low, k, p))
+    return fail(FQT_ERR_REDUCIBLE, "defining polynomial is reducible over GF(%u)", p);
+  f->tbl_log2 = k * f->cb;
+  if (f->tbl_log2 > 12)
+    return fail(FQT_ERR_UNSUPPORTED, "tables of 2^%u entries exceed 4096", f->tbl_log2);
+  *out = f.release();
+  return ok();
+}
+
+void fqt_field_destroy(fqt_field f) {
+  if (!f) return;
+  for (auto& kv : f->dev_tables) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+      hipSetDevice(kv.first.first);
+      hipFree(kv.second.L);
+      hipFree(kv.second.H);
+      hipSetDevice(cur);
+    }
+  }
+  for (auto& pl : f->plans) {
+    if (pl->exec) hipGraphExecDestroy(pl->exec);
+    if (pl->graph) hipGraphDestroy(pl->graph);
+    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
+    hipFree(pl->d_descs);
+    hipFree(pl->d_items);
+    hipFree(pl->d_counter);
+  }
+  delete f;
+}
+
+fqt_status fqt_field_tables(fqt_field f, uint64_t q, uint32_t* L, uint32_t* H,
+                            size_t* n_entries) {
+  if (!f || !n_entries) return fail(FQT_ERR_INVALID_ARG, "null argument");
+  if (q < 2) return fail(FQT_ERR_INVALID_ARG, "q < 2");
+  std::lock_guard<std::mutex> lk(f->mu);
+  const auto& t = host_tables(f, q);
+  const size_t n = t.first.size();
+  if ((L || H) && *n_entries < n)
+    return fail(FQT_ERR_INVALID_ARG, "table buffers hold %zu entries, need %zu", *n_entries, n);
+  *n_entries = n;
+  if (L) std::memcpy(L, t.first.data(), n * sizeof(uint32_t));
+  if (H) std::memcpy(H, t.second.data(), n * sizeof(uint32_t));
+  return ok();
+}
+
+fqt_status fqt_params(uint32_t p, uint32_t k, uint64_t n_q, int pow2_q, int carry_in,
+                      uint64_t* q_out, uint64_t* nq_max_out) {
+  if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
+  if (k < 1 || k > 16) return fail(FQT_ERR_UNSUPPORTED, "k = %u outside [1, 16]", k);
+  if (n_q < 1) return fail(FQT_ERR_INVALID_ARG, "n_q must be at least 1");
+  const uint32_t e = 2 * k - 1;
+  uint64_t q;
+  if (pow2_q) {
+    q = 1ull << (52 / e);  // largest 2^b with b * e < 53
+  } else {
+    // largest integer q with q^e < 2^53
+    q = (uint64_t)std::floor(std::pow(2.0, 53.0 / e));
+    while (q > 1 && !pow_below(q, e, 53)) --q;
+    while (pow_below(q + 1, e, 53)) ++q;
+  }
+  const unsigned __int128 unit = (unsigned __int128)k * (p - 1) * (p - 1);
+  const unsigned __int128 extra = carry_in ? (p - 1) : 0;
+  // eq. (2): q > n_q k (p-1)^2 (+ (p-1) when a reduced value re-enters)
+  uint64_t nq_max = 0;
+  if (unit == 0) nq_max = UINT64_MAX;
+  else if ((unsigned __int128)q > extra) nq_max = (uint64_t)(((unsigned __int128)q - 1 - extra) / unit);
+  if (q_out) *q_out = q;
+  if (nq_max_out) *nq_max_out = nq_max;
+  if (n_q > nq_max)
+    return fail(FQT_ERR_BOUNDS, "no q with q^%u < 2^53 exceeds %" PRIu64 " * %u * (%u-1)^2", e,
+                n_q, k, p);
+  return ok();
+}
+
+fqt_status fqt_pack(fqt_field f, uint64_t q, const uint8_t* coeffs, size_t n, double* packed,
+                    fqt_stream_t s) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (n && (!coeffs || !packed)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (q < 2) return fail(FQT_ERR_INVALID_ARG, "q < 2");
+  // largest packed value (p-1) * sum_{j<k} q^j must be exact in binary64
+  unsigned __int128 mx = 0, qp = 1;
+  for (uint32_t j = 0; j < f->k; ++j) {
+    mx += (unsigned __int128)(f->p - 1) * qp;
+    qp *= q;
+    if (qp > ((unsigned __int128)1 << 70)) break;
+  }
+  if (mx > ((unsigned __int128)1 << 53) || qp > ((unsigned __int128)1 << 70))
+    return fail(FQT_ERR_BOUNDS, "packed values exceed 2^53 at q = %" PRIu64, q);
+  if (overlap(coeffs, n * f->k, packed, n * sizeof(double)))
+    return fail(FQT_ERR_INVALID_ARG, "input and output overlap");
+  const int pow2 = (q & (q - 1)) == 0;
+  const uint32_t b = pow2 ? (uint32_t)__builtin_ctzll(q) : 0;
+  FQT_HIP(launch_pack((int)f->k, q, pow2, b, coeffs, n, packed, (hipStream_t)s));
+  return ok();
+}
+
+static fqt_status unpack_common(fqt_field f, uint64_t q, const void* packed, size_t n,
+                                uint32_t ndigits, fqt_unpack_mode mode, uint8_t* out,
+                                fqt_stream_t s, bool wide) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (n && (!packed || !out)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (q < 2) return fail(FQT_ERR_INVALID_ARG, "q < 2");
+  if (mode != FQT_UNPACK_POLY && mode != FQT_UNPACK_FIELD)
+    return fail(FQT_ERR_INVALID_ARG, "unknown unpack mode");
+  if (ndigits < 1 || ndigits > 15) return fail(FQT_ERR_UNSUPPORTED, "ndigits outside [1, 15]");
+  if (mode == FQT_UNPACK_FIELD && ndigits > 2 * f->k - 1)
+    return fail(FQT_ERR_INVALID_ARG, "FIELD mode takes at most 2k-1 = %u digits", 2 * f->k - 1);
+  // binary64: every value is an exact integer below q^ndigits <= 2^53 (eq. (2), m = 53);
+  // uint64: any value, as long as the top digit's place q^(ndigits-1) is below 2^64
+  if (wide ? !pow_below(q, ndigits - 1, 64) : !pow_at_most(q, ndigits, 53))
+    return fail(FQT_ERR_BOUNDS, "q^%u exceeds the %s range", ndigits, wide ? "uint64" : "binary64");
+  const size_t ob = mode == FQT_UNPACK_POLY ? ndigits : f->k;
+  if (overlap(packed, n * 8, out, n * ob)) return fail(FQT_ERR_INVALID_ARG, "buffers overlap");
+  const int pow2 = (q & (q - 1)) == 0;
+  const uint32_t b = pow2 ? (uint32_t)__builtin_ctzll(q) : 0;
+  const FieldArgs fa = field_args(f, q);
+  DevTables dt;
+  if (mode == FQT_UNPACK_FIELD) {
+    fqt_status st = device_tables(f, q, &dt);
+    if (st) return st;
+  }
+  if (wide)
+    FQT_HIP(launch_unpack_u64((int)f->k, ndigits, (int)mode, q, pow2, b, fa, dt.L, dt.H,
+                              (const uint64_t*)packed, n, out, (hipStream_t)s));
+  else
+    FQT_HIP(launch_unpack_f64((int)f->k, ndigits, (int)mode, q, pow2, b, fa, dt.L, dt.H,
+                              (const double*)packed, n, out, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_unpack_redq(fqt_field f, uint64_t q, const double* packed, size_t n,
+                           uint32_t ndigits, fqt_unpack_mode mode, uint8_t* out, fqt_stream_t s) {
+  return unpack_common(f, q, packed, n, ndigits, mode, out, s, false);
+}
+
+fqt_status fqt_unpack_redq_u64(fqt_field f, uint64_t q, const uint64_t* packed, size_t n,
+                               uint32_t ndigits, fqt_unpack_mode mode, uint8_t* out,
+                               fqt_stream_t s) {
+  return unpack_common(f, q, packed, n, ndigits, mode, out, s, true);
+}
+
+fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q, const uint8_t* a,
+                             const uint8_t* b, size_t n, uint8_t* c, fqt_stream_t s) {
+  if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
+  if (p > 127) return fail(FQT_ERR_UNSUPPORTED, "p = %u above 127", p);
+  if (k < 1 || k > 8) return fail(FQT_ERR_UNSUPPORTED, "k = %u outside [1, 8]", k);
+  if (n && (!a || !b || !c)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (q < 2) return fail(FQT_ERR_INVALID_ARG, "q < 2");
+  // eq. (2) with n_q = 1
+  if (!((unsigned __int128)q > (unsigned __int128)k * (p - 1) * (p - 1)) ||
+      !pow_below(q, 2 * k - 1, 53))
+    return fail(FQT_ERR_BOUNDS, "q = %" PRIu64 " breaks eq. (2) for p = %u, k = %u", q, p, k);
+  const size_t nc = n * (2 * k - 1);
+  if (overlap(c, nc, a, n * k) || overlap(c, nc, b, n * k))
+    return fail(FQT_ERR_INVALID_ARG, "output overlaps an input");
+  fqt_field_s tmp;
+  tmp.p = p;
+  tmp.k = k;
+  tmp.cb = std::max(1u, ceil_log2(p));
+  const FieldArgs fa = field_args(&tmp, q);
+  const int pow2 = (q & (q - 1)) == 0;
+  const uint32_t bb = pow2 ? (uint32_t)__builtin_ctzll(q) : 0;
+  FQT_HIP(launch_polymul((int)k, q, pow2, bb, fa, a, b, n, c, (hipStream_t)s));
+  return ok();
+}
+
+static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
+                              hipStream_t s) {
+  PackedChoice pc;
+  fqt_status st = resolve_packed(f, opts, g.K, g.M, g.N, &pc);
+  if (st) return st;
+  const uint64_t q = 1ull << pc.b;
+  DevTables dt;
+  st = device_tables(f, q, &dt);
+  if (st) return st;
+  PackedParams pp{};
+  pp.b = pc.b;
+  pp.nq_groups = pc.nq / 4;
+  pp.tbl_log2 = f->tbl_log2;
+  pp.aligned = ((((uintptr_t)g.A) | ((uintptr_t)g.B)) & 3) == 0 && (g.lda * f->k) % 4 == 0 &&
+               (g.ldb * f->k) % 4 == 0;
+  pp.fa = field_args(f, q);
+  pp.L = dt.L;
+  pp.H = dt.H;
+  FQT_HIP(launch_gemm_packed((int)f->k, (int)pc.tile, pc.multi, g, pp, s));
+  return ok();
+}
+
+fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opts, int64_t M,
+                            int64_t N, int64_t K, const uint8_t* A, int64_t lda,
+                            const uint8_t* B, int64_t ldb, uint8_t* C, int64_t ldc,
+                            fqt_stream_t s) {
+  fqt_status st = check_gemm_args(f, M, N, K, A, lda, B, ldb, C, ldc);
+  if (st) return st;
+  GemmArgs g{A, B, C, M, N, K, lda, ldb, ldc};
+  if (M == 0 || N == 0) return ok();
+  if (path == FQT_PATH_AUTO) {
+    std::lock_guard<std::mutex> lk(f->mu);
+    auto it = f->tuned.find(shape_key(f, 1, M, N, K));
+    if (it != f->tuned.end()) {
+      path = it->second.path;
+      if (!opts) opts = &it->second.opts;
+    } else {
+      path = FQT_PATH_PACKED_F64;
+    }
+  }
+  switch (path) {
+    case FQT_PATH_PACKED_F64:
+      return gemm_packed(f, opts, g, (hipStream_t)s);
+    case FQT_PATH_PLAIN: {
+      const FieldArgs fa = field_args(f, 2);
+      FQT_HIP(launch_gemm_plain((int)f->k, g, fa, f->P_low, (hipStream_t)s));
+      return ok();
+    }
+    case FQT_PATH_INT8:
+      return fail(FQT_ERR_UNSUPPORTED, "INT8 path not built");
+    default:
+      return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
+  }
+}
+
+fqt_status fqt_gemm_gfpk(fqt_field f, fqt_path path, int64_t M, int64_t N, int64_t K,
+                         const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb,
+                         uint8_t* C, int64_t ldc, fqt_stream_t s) {
+  return fqt_gemm_gfpk_ex(f, path, nullptr, M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
+static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t count,
+                                 const fqt_gemm_desc* descs, hipStream_t s) {
+  int64_t Kmax = 0, Mmax = 0, Nmax = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    Kmax = std::max(Kmax, descs[i].K);
+    Mmax = std::max(Mmax, descs[i].M);
+    Nmax = std::max(Nmax, descs[i].N);
+  }
+  PackedChoice pc;
+  fqt_gemm_opts o = opts ? *opts : fqt_gemm_opts{0, 0, 0, 0};
+  if (!o.tile) o.tile = 2;
+  fqt_status st = resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc);
+  if (st) return st;
+  const uint64_t q = 1ull << pc.b;
+  DevTables dt;
+  st = device_tables(f, q, &dt);
+  if (st) return st;
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+
+  // Plan key: the descriptor bytes, the resolved parameters and the device.
+  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + sizeof(PackedChoice) + sizeof(int));
+  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
+  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, &pc, sizeof pc);
+  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count + sizeof pc, &dev, sizeof dev);
+
+  std::lock_guard<std::mutex> lk(f->mu);
+  BatchPlan* plan = nullptr;
+  for (auto& p : f->plans)
+    if (p->key == key) plan = p.get();
+  if (!plan) {
+    int bm, bn;
+    packed_tile_shape((int)pc.tile, &bm, &bn);
+    std::vector<GemmArgs> args(count);
+    std::vector<TileItem> items;
+    bool aligned = true;
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      args[i] = GemmArgs{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
+      aligned = aligned && ((((uintptr_t)d.A) | ((uintptr_t)d.B)) & 3) == 0 &&
+                (d.lda * f->k) % 4 == 0 && (d.ldb * f->k) % 4 == 0;
+      const int tm = (int)((d.M + bm - 1) / bm), tn = (int)((d.N + bn - 1) / bn);
+      for (int a = 0; a < tm; ++a)
+        for (int c = 0; c < tn; ++c) items.push_back(TileItem{(int32_t)i, a, c, 0});
+    }
+    // Longest-processing-time first: a tile costs about K (same tile area).
+    std::stable_sort(items.begin(), items.end(), [&](const TileItem& x, const TileItem& y) {
+      return descs[x.gemm].K > descs[y.gemm].K;
+    });
+    auto pl = std::make_unique<BatchPlan>();
+    pl->key = key;
+    pl->n_items = (int32_t)items.size();
+    pl->device = dev;
+    FQT_HIP(hipMalloc(&pl->d_descs, sizeof(GemmArgs) * std::max<int64_t>(count, 1)));
+    FQT_HIP(hipMalloc(&pl->d_items, sizeof(TileItem) * std::max<size_t>(items.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_counter, 2 * sizeof(uint32_t)));
+    FQT_HIP(hipMemcpy(pl->d_descs, args.data(), sizeof(GemmArgs) * count, hipMemcpyHostToDevice));
+    if (!items.empty())
+      FQT_HIP(hipMemcpy(pl->d_items, items.data(), sizeof(TileItem) * items.size(),
+                        hipMemcpyHostToDevice));
+    FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
+    hipDeviceProp_t prop;
+    FQT_HIP(hipGetDeviceProperties(&prop, dev));
+    const int occ = packed_batched_occupancy((int)f->k, (int)pc.tile, pc.multi, f->tbl_log2);
+    pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * occ, pl->n_items));
+    PackedParams pp{};
+    pp.b = pc.b;
+    pp.nq_groups = pc.nq / 4;
+    pp.tbl_log2 = f->tbl_log2;
+    pp.aligned = aligned;
+    pp.fa = field_args(f, q);
+    pp.L = dt.L;
+    pp.H = dt.H;
+    // Capture the persistent launch once; later calls replay the graph.
+    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.multi, pl->d_descs,
+                                               pl->d_items, pl->n_items, pl->d_counter, pl->grid,
+                                               pp, pl->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    pl->graph = graph;
+    FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
+    plan = pl.get();
+    f->plans.push_back(std::move(pl));
+  }
+  if (plan->n_items == 0) return ok();
+  FQT_HIP(hipGraphLaunch(plan->exec, s));
+  return ok();
+}
+
+fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opts,
+                                    int64_t count, const fqt_gemm_desc* descs, fqt_stream_t s) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (count < 0 || (count && !descs)) return fail(FQT_ERR_INVALID_ARG, "bad descriptor array");
+  for (int64_t i = 0; i < count; ++i) {
+    const fqt_gemm_desc& d = descs[i];
+    fqt_status st = check_gemm_args(f, d.M, d.N, d.K, d.A, d.lda, d.B, d.ldb, d.C, d.ldc);
+    if (st) return fail(st, "descriptor %lld: %s", (long long)i, g_last_error.c_str());
+  }
+  if (count == 0) return ok();
+  if (path == FQT_PATH_AUTO) path = FQT_PATH_PACKED_F64;
+  switch (path) {
+    case FQT_PATH_PACKED_F64:
+      return batched_packed(f, opts, count, descs, (hipStream_t)s);
+    case FQT_PATH_PLAIN: {
+      const FieldArgs fa = field_args(f, 2);
+      for (int64_t i = 0; i < count; ++i) {
+        const fqt_gemm_desc& d = descs[i];
+        GemmArgs g{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
+        FQT_HIP(launch_gemm_plain((int)f->k, g, fa, f->P_low, (hipStream_t)s));
+      }
+      return ok();
+    }
+    case FQT_PATH_INT8:
+      return fail(FQT_ERR_UNSUPPORTED, "INT8 path not built");
+    default:
+      return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
+  }
+}
+
+fqt_status fqt_gemm_gfpk_batched(fqt_field f, fqt_path path, int64_t count,
+                                 const fqt_gemm_desc* descs, fqt_stream_t s) {
+  return fqt_gemm_gfpk_batched_ex(f, path, nullptr, count, descs, s);
+}
+
+fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
+                        const char* cache_path, fqt_path* best_path, fqt_gemm_opts* best,
+                        fqt_stream_t s) {
+  (void)f; (void)count; (void)descs; (void)cache_path; (void)best_path; (void)best; (void)s;
+  return fail(FQT_ERR_UNSUPPORTED, "autotuner not built");
+}
+
+}  // extern "C"

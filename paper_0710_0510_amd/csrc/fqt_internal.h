@@ -1,0 +1,79 @@
+// Internal declarations shared by the host API (fqt_api.cpp) and the kernel
+// translation units.  Not installed; the public interface is include/fqt.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fqt_device.h"
+
+namespace fqt {
+
+// One GEMM problem; ld* in elements.
+struct GemmArgs {
+  const uint8_t* A;
+  const uint8_t* B;
+  uint8_t* C;
+  int64_t M, N, K, lda, ldb, ldc;
+};
+
+// Parameters of the packed-FP64 path (Alg. 4 with K-blocks, eq. (2)).
+struct PackedParams {
+  uint32_t b;          // q = 2^b
+  uint32_t nq_groups;  // K-block = 4*nq_groups products (MFMA k-groups of 4)
+  uint32_t tbl_log2;   // each table has 2^tbl_log2 entries (k*cb)
+  uint32_t aligned;    // rows of A and B start on 4-byte boundaries
+  FieldArgs fa;
+  const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)
+  const uint32_t* H;
+};
+
+// Tile work item of the persistent batched kernel.
+struct TileItem {
+  int32_t gemm;    // index into the descriptor array
+  int32_t tm, tn;  // tile coordinates
+  int32_t pad;
+};
+
+// Tile configurations of the packed path (WG of 256 threads = 2x2 waves).
+// id -> (TM, TN): wave tile 16TM x 16TN, workgroup tile 32TM x 32TN.
+constexpr int kPackedTiles = 4;
+inline void packed_tile_shape(int id, int* bm, int* bn) {
+  static const int tm[kPackedTiles] = {1, 2, 2, 4};
+  static const int tn[kPackedTiles] = {1, 2, 4, 4};
+  *bm = 32 * tm[id - 1];
+  *bn = 32 * tn[id - 1];
+}
+
+// ---- launchers (each returns the launch's hipError_t) ----------------------
+
+hipError_t launch_pack(int k, uint64_t q, int pow2, uint32_t b, const uint8_t* coeffs,
+                       size_t n, double* out, hipStream_t s);
+
+// mode 0 = POLY, 1 = FIELD.  For FIELD, L/H are device tables.
+hipError_t launch_unpack_f64(int k, uint32_t nd, int mode, uint64_t q, int pow2, uint32_t b,
+                             const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
+                             const double* in, size_t n, uint8_t* out, hipStream_t s);
+hipError_t launch_unpack_u64(int k, uint32_t nd, int mode, uint64_t q, int pow2, uint32_t b,
+                             const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
+                             const uint64_t* in, size_t n, uint8_t* out, hipStream_t s);
+
+hipError_t launch_polymul(int k, uint64_t q, int pow2, uint32_t b, const FieldArgs& fa,
+                          const uint8_t* a, const uint8_t* bb, size_t n, uint8_t* c,
+                          hipStream_t s);
+
+hipError_t launch_gemm_packed(int k, int tile, bool multi, const GemmArgs& g,
+                              const PackedParams& pp, hipStream_t s);
+
+hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArgs* descs,
+                                      const TileItem* items, int32_t n_items,
+                                      uint32_t* counter, int grid, const PackedParams& pp,
+                                      hipStream_t s);
+
+int packed_batched_occupancy(int k, int tile, bool multi, uint32_t tbl_log2);
+
+// Plain comparator: schoolbook with % p and division by P per product.
+hipError_t launch_gemm_plain(int k, const GemmArgs& g, const FieldArgs& fa,
+                             const uint32_t* P_low, hipStream_t s);
+
+}  // namespace fqt

@@ -1,0 +1,411 @@
+// Packed-FP64 GEMM over GF(p^k) on gfx950 MFMA (the FQT path).
+//
+// Alg. 4 (fast dot product over GF(p^k) via FQT) for every entry of C:
+//   1. DQT of each operand element at q = 2^b (Section 2: shifts), fused into
+//      the global->LDS loader: k coefficient bytes -> one exact binary64.
+//   2. The dot products as one dense FP64 contraction on the matrix cores
+//      (v_mfma_f64_16x16x4f64); exact while eq. (2) holds, i.e. at most n_q
+//      products per K-block with q > n_q k (p-1)^2 and q^(2k-1) < 2^53.
+//   3. REDQ residues u_0..u_{2k-2} of each block (Alg. 4 steps 3-7, Thm. 2).
+//   4. Two table lookups L[u_0..u_{k-1}] + H[u_{k-1}..u_{2k-2}] (Thm. 3) and
+//      one coefficient-wise addition mod p.
+//
+// Delayed reduction across K-blocks (Section 6: the reduction "can be
+// delayed" while eq. (2) holds; how blocks combine is left open).  The
+// residue vector is linear in the digits modulo p (Thm. 2: u_i = sum_{j>=i}
+// mu_j q^(j-i) mod p), and L + H is linear in u, so block residues are summed
+// in 16-bit lanes and the tables are applied once at the end.  A block
+// boundary therefore costs one FMA for rop plus a shift and a 24-bit
+// multiply-add per digit; the accumulator restarts at the 2^52 bias.
+//
+// Layout: workgroup = 256 threads = 2 x 2 waves; wave tile 16TM x 16TN made of
+// TM x TN MFMA blocks of 16 x 16; workgroup tile BM x BN = 32TM x 32TN;
+// K-tiles of BK = 16 elements, double-buffered in LDS as packed doubles.
+// MFMA 16x16x4 f64 operand layout (per lane l of the wave):
+//   A: row l%16, k l/16;  B: k l/16, column l%16;
+//   D: element v in 0..3 at row l/16 + 4v, column l%16 (checked on gfx950).
+
+#include "fqt_internal.h"
+
+namespace fqt {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <int KE, int TM, int TN>
+struct PT {
+  static constexpr int BM = 32 * TM;
+  static constexpr int BN = 32 * TN;
+  static constexpr int BK = 16;
+  static constexpr int SA = BK + 1;    // A row stride (doubles): conflict-free reads
+  static constexpr int SB = BN + 16;   // B row stride (doubles)
+  static constexpr int ND = 2 * KE - 1;
+  static constexpr int NW = (ND + 1) / 2;  // 16-bit-lane words per output element
+  static constexpr int NCA = BM * BK / 4;  // A chunks: 4 consecutive k of one row
+  static constexpr int NCB = BK * BN / 4;  // B chunks: 4 consecutive n of one k-row
+  static constexpr int RA = (NCA + 255) / 256;
+  static constexpr int RB = (NCB + 255) / 256;
+  static constexpr int LDS_A = BM * SA;
+  static constexpr int LDS_B = BK * SB;
+};
+
+// Raw bytes of a 4-element chunk (4*KE bytes) from a row segment starting at
+// element (row, col) with ld elements per row; missing elements read as 0.
+template <int KE>
+__device__ __forceinline__ void load_chunk(const uint8_t* base, int64_t row, int64_t col,
+                                           int64_t nrows, int64_t ncols, int64_t ld,
+                                           bool aligned, uint32_t (&raw)[KE]) {
+  if (aligned && row < nrows && col + 3 < ncols) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(base + (row * ld + col) * KE);
+#pragma unroll
+    for (int j = 0; j < KE; ++j) raw[j] = src[j];
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < KE; ++j) raw[j] = 0;
+  if (row >= nrows) return;
+  const uint8_t* src = base + row * ld * KE;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (col + e < ncols) {
+#pragma unroll
+      for (int c = 0; c < KE; ++c) {
+        const int j = e * KE + c;
+        raw[j >> 2] |= (uint32_t)src[(col + e) * KE + c] << (8 * (j & 3));
+      }
+    }
+  }
+}
+
+// Element e (0..3) of a raw chunk: its KE bytes in the low bytes of a word.
+template <int KE>
+__device__ __forceinline__ uint32_t chunk_elem(const uint32_t (&raw)[KE], int e) {
+  const int o = e * KE;
+  if ((o & 3) == 0) return raw[o >> 2];
+  const uint32_t lo = raw[o >> 2];
+  const uint32_t hi = ((o >> 2) + 1 < KE) ? raw[(o >> 2) + 1] : 0u;
+  return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+}
+
+template <int KE, int TM, int TN, bool MULTI>
+__device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int tile_n,
+                                            const PackedParams& pp, double* __restrict__ As,
+                                            double* __restrict__ Bs,
+                                            const uint32_t* __restrict__ Ls,
+                                            const uint32_t* __restrict__ Hs) {
+  using T = PT<KE, TM, TN>;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm0 = (wave >> 1) * 16 * TM;
+  const int wn0 = (wave & 1) * 16 * TN;
+  const int64_t m0 = (int64_t)tile_m * T::BM;
+  const int64_t n0 = (int64_t)tile_n * T::BN;
+  const bool aligned = pp.aligned != 0;
+  const uint32_t b = pp.b;
+
+  const v4d bias = {kTwo52, kTwo52, kTwo52, kTwo52};
+  v4d acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = bias;
+
+  uint32_t W[MULTI ? TM : 1][MULTI ? TN : 1][4][MULTI ? T::NW : 1];
+  if constexpr (MULTI) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int w = 0; w < T::NW; ++w) W[i][j][v][w] = 0;
+  }
+
+  uint32_t ra[T::RA][KE];
+  uint32_t rb[T::RB][KE];
+
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int r = 0; r < T::RA; ++r) {
+      const int c = tid + 256 * r;
+      if (c < T::NCA) {
+        const int row = c / (T::BK / 4);
+        const int kc = c % (T::BK / 4);
+        load_chunk<KE>(g.A, m0 + row, k0 + 4 * kc, g.M, g.K, g.lda, aligned, ra[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < T::RB; ++r) {
+      const int c = tid + 256 * r;
+      if (c < T::NCB) {
+        const int kr = c / (T::BN / 4);
+        const int nc = c % (T::BN / 4);
+        load_chunk<KE>(g.B, k0 + kr, n0 + 4 * nc, g.K, g.N, g.ldb, aligned, rb[r]);
+      }
+    }
+  };
+
+  auto lstore = [&](int buf) {
+    double* as = As + buf * T::LDS_A;
+    double* bs = Bs + buf * T::LDS_B;
+#pragma unroll
+    for (int r = 0; r < T::RA; ++r) {
+      const int c = tid + 256 * r;
+      if (c < T::NCA) {
+        const int row = c / (T::BK / 4);
+        const int kc = c % (T::BK / 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          as[row * T::SA + 4 * kc + e] = (double)dqt_shift<KE>(chunk_elem<KE>(ra[r], e), b);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < T::RB; ++r) {
+      const int c = tid + 256 * r;
+      if (c < T::NCB) {
+        const int kr = c / (T::BN / 4);
+        const int nc = c % (T::BN / 4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          bs[kr * T::SB + 4 * nc + e] = (double)dqt_shift<KE>(chunk_elem<KE>(rb[r], e), b);
+      }
+    }
+  };
+
+  auto boundary = [&]() {
+    if constexpr (MULTI) {
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            uint32_t t[T::ND];
+            redq_residues_biased<T::ND>(acc[i][j][v], b, pp.fa, t);
+#pragma unroll
+            for (int w = 0; w < T::NW; ++w) {
+              const uint32_t lo = t[2 * w];
+              const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
+              W[i][j][v][w] += perm_b32(hi, lo, 0x0c040c00u);
+            }
+          }
+          acc[i][j] = bias;
+        }
+    }
+  };
+
+  const int64_t nkt = (g.K + T::BK - 1) / T::BK;
+  uint32_t gcnt = 0;
+  if (nkt > 0) {
+    gload(0);
+    lstore(0);
+    __syncthreads();
+  }
+  for (int64_t kt = 0; kt < nkt; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < nkt) gload((kt + 1) * T::BK);
+    const double* as = As + buf * T::LDS_A;
+    const double* bs = Bs + buf * T::LDS_B;
+#pragma unroll
+    for (int gk = 0; gk < T::BK / 4; ++gk) {
+      double a[TM], bb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = as[(wm0 + 16 * i + (lane & 15)) * T::SA + 4 * gk + (lane >> 4)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bb[j] = bs[(4 * gk + (lane >> 4)) * T::SB + wn0 + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+      if constexpr (MULTI) {
+        if (++gcnt == pp.nq_groups) {
+          boundary();
+          gcnt = 0;
+        }
+      }
+    }
+    if (kt + 1 < nkt) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  // Epilogue: final residues, L + H (Thm. 3), store k bytes per element.
+  const FieldArgs& fa = pp.fa;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        uint32_t t[T::ND];
+        redq_residues_biased<T::ND>(acc[i][j][v], b, fa, t);
+        uint32_t u[T::ND];
+        if constexpr (MULTI) {
+#pragma unroll
+          for (int w = 0; w < T::NW; ++w) {
+            const uint32_t lo = t[2 * w];
+            const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
+            const uint32_t tot = W[i][j][v][w] + perm_b32(hi, lo, 0x0c040c00u);
+            u[2 * w] = mod_p_small(tot & 0xffffu, fa);
+            if (2 * w + 1 < T::ND) u[2 * w + 1] = mod_p_small(tot >> 16, fa);
+          }
+        } else {
+#pragma unroll
+          for (int d = 0; d < T::ND; ++d) {
+            const uint32_t x = t[d] & 0xffu;
+            u[d] = x >= fa.p ? x - fa.p : x;
+          }
+        }
+        uint32_t il = 0, ih = 0;
+#pragma unroll
+        for (int d = 0; d < KE; ++d) {
+          il |= u[d] << (fa.cb * d);
+          ih |= u[KE - 1 + d] << (fa.cb * d);
+        }
+        const uint32_t tmask = (1u << pp.tbl_log2) - 1u;  // keeps lookups inside the tables
+        const uint32_t e = add_bytes_mod_p(Ls[il & tmask], Hs[ih & tmask], fa);
+        const int64_t row = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
+        const int64_t col = n0 + wn0 + 16 * j + (lane & 15);
+        if (row < g.M && col < g.N) store_elem<KE>(g.C + (row * g.ldc + col) * KE, e);
+      }
+}
+
+template <int KE, int TM, int TN>
+__device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls, uint32_t* Hs) {
+  const int n = 1 << pp.tbl_log2;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    Ls[i] = pp.L[i];
+    Hs[i] = pp.H[i];
+  }
+}
+
+template <int KE, int TM, int TN, bool MULTI>
+__global__ __launch_bounds__(256) void gemm_packed_kernel(GemmArgs g, PackedParams pp,
+                                                          int tiles_n, int ntiles) {
+  using T = PT<KE, TM, TN>;
+  __shared__ double As[2 * T::LDS_A];
+  __shared__ double Bs[2 * T::LDS_B];
+  extern __shared__ uint32_t tabs[];
+  uint32_t* Ls = tabs;
+  uint32_t* Hs = tabs + (1 << pp.tbl_log2);
+  load_tables<KE, TM, TN>(pp, Ls, Hs);
+  __syncthreads();
+  // XCD-aware order: the 8 XCDs receive workgroups round-robin; give each XCD
+  // a contiguous run of tiles so that its L2 serves shared A rows / B columns.
+  int tile = blockIdx.x;
+  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  packed_tile<KE, TM, TN, MULTI>(g, tile / tiles_n, tile % tiles_n, pp, As, Bs, Ls, Hs);
+}
+
+template <int KE, int TM, int TN, bool MULTI>
+__global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
+    const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items, int32_t n_items,
+    uint32_t* counter, PackedParams pp) {
+  using T = PT<KE, TM, TN>;
+  __shared__ double As[2 * T::LDS_A];
+  __shared__ double Bs[2 * T::LDS_B];
+  __shared__ int32_t cur;
+  extern __shared__ uint32_t tabs[];
+  uint32_t* Ls = tabs;
+  uint32_t* Hs = tabs + (1 << pp.tbl_log2);
+  load_tables<KE, TM, TN>(pp, Ls, Hs);
+  for (;;) {
+    if (threadIdx.x == 0) cur = (int32_t)atomicAdd(&counter[0], 1u);
+    __syncthreads();
+    const int32_t it = cur;
+    __syncthreads();
+    if (it >= n_items) break;
+    const TileItem ti = items[it];
+    const GemmArgs g = descs[ti.gemm];
+    packed_tile<KE, TM, TN, MULTI>(g, ti.tm, ti.tn, pp, As, Bs, Ls, Hs);
+  }
+  // The last workgroup to leave resets the queue for the next launch (every
+  // workgroup has made its final counter[0] increment before counter[1]).
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t done = atomicAdd(&counter[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&counter[0], 0u);
+      atomicExch(&counter[1], 0u);
+    }
+  }
+}
+
+template <int KE, int TM, int TN, bool MULTI>
+static hipError_t launch_one(const GemmArgs& g, const PackedParams& pp, hipStream_t s) {
+  using T = PT<KE, TM, TN>;
+  const int tiles_m = (int)((g.M + T::BM - 1) / T::BM);
+  const int tiles_n = (int)((g.N + T::BN - 1) / T::BN);
+  const int ntiles = tiles_m * tiles_n;
+  if (ntiles == 0) return hipSuccess;
+  const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
+  hipLaunchKernelGGL((gemm_packed_kernel<KE, TM, TN, MULTI>), dim3(ntiles), dim3(256), dyn, s,
+                     g, pp, tiles_n, ntiles);
+  return hipGetLastError();
+}
+
+template <int KE, int TM, int TN, bool MULTI>
+static hipError_t launch_batched(const GemmArgs* descs, const TileItem* items, int32_t n_items,
+                                 uint32_t* counter, int grid, const PackedParams& pp,
+                                 hipStream_t s) {
+  const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
+  hipLaunchKernelGGL((gemm_packed_batched_kernel<KE, TM, TN, MULTI>), dim3(grid), dim3(256), dyn,
+                     s, descs, items, n_items, counter, pp);
+  return hipGetLastError();
+}
+
+// Dispatch over (k, tile id, multi-block).
+#define FQT_TILE_SWITCH(FN, KE, MULTI, ...)                   \
+  switch (tile) {                                             \
+    case 1: return FN<KE, 1, 1, MULTI>(__VA_ARGS__);          \
+    case 2: return FN<KE, 2, 2, MULTI>(__VA_ARGS__);          \
+    case 3: return FN<KE, 2, 4, MULTI>(__VA_ARGS__);          \
+    case 4: return FN<KE, 4, 4, MULTI>(__VA_ARGS__);          \
+    default: return hipErrorInvalidValue;                     \
+  }
+
+#define FQT_K_SWITCH(FN, ...)                                                         \
+  switch (k) {                                                                        \
+    case 1: if (multi) { FQT_TILE_SWITCH(FN, 1, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 1, false, __VA_ARGS__) } \
+    case 2: if (multi) { FQT_TILE_SWITCH(FN, 2, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 2, false, __VA_ARGS__) } \
+    case 3: if (multi) { FQT_TILE_SWITCH(FN, 3, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 3, false, __VA_ARGS__) } \
+    case 4: if (multi) { FQT_TILE_SWITCH(FN, 4, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 4, false, __VA_ARGS__) } \
+    default: return hipErrorInvalidValue;                                             \
+  }
+
+hipError_t launch_gemm_packed(int k, int tile, bool multi, const GemmArgs& g,
+                              const PackedParams& pp, hipStream_t s) {
+  FQT_K_SWITCH(launch_one, g, pp, s)
+}
+
+hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArgs* descs,
+                                      const TileItem* items, int32_t n_items, uint32_t* counter,
+                                      int grid, const PackedParams& pp, hipStream_t s) {
+  FQT_K_SWITCH(launch_batched, descs, items, n_items, counter, grid, pp, s)
+}
+
+// Occupancy of the batched kernel (workgroups per CU) for the persistent grid.
+int packed_batched_occupancy(int k, int tile, bool multi, uint32_t tbl_log2) {
+  int blocks = 0;
+  const size_t dyn = 2u * (1u << tbl_log2) * sizeof(uint32_t);
+#define FQT_OCC(KE, TM, TN, MU)                                                              \
+  if (k == KE && tile_tm == TM && tile_tn == TN && multi == MU) {                           \
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
+            &blocks, (const void*)gemm_packed_batched_kernel<KE, TM, TN, MU>, 256, dyn) !=  \
+        hipSuccess)                                                                          \
+      blocks = 1;                                                                            \
+  }
+  static const int tms[kPackedTiles] = {1, 2, 2, 4};
+  static const int tns[kPackedTiles] = {1, 2, 4, 4};
+  const int tile_tm = tms[tile - 1], tile_tn = tns[tile - 1];
+#define FQT_OCC_K(KE) FQT_OCC(KE, 1, 1, true) FQT_OCC(KE, 2, 2, true) FQT_OCC(KE, 2, 4, true) \
+  FQT_OCC(KE, 4, 4, true) FQT_OCC(KE, 1, 1, false) FQT_OCC(KE, 2, 2, false)                  \
+  FQT_OCC(KE, 2, 4, false) FQT_OCC(KE, 4, 4, false)
+  FQT_OCC_K(1) FQT_OCC_K(2) FQT_OCC_K(3) FQT_OCC_K(4)
+#undef FQT_OCC_K
+#undef FQT_OCC
+  return blocks > 0 ? blocks : 1;
+}
+
+}  // namespace fqt

@@ -1,0 +1,256 @@
+// Streaming transforms of the Q-adic path on gfx950:
+//   * DQT pack (Section 2, eq. (1); Alg. 1 step 1): k coefficient bytes ->
+//     one exact binary64 evaluation at q (shifts for q = 2^b, an exact FP64
+//     Horner evaluation otherwise).
+//   * REDQ unpack (Alg. 2; Alg. 4 steps 3-10): one floor division by p gives
+//     rop; u_i = floor(r/q^i) - p floor(rop/q^i) for every digit (Thm. 2);
+//     then either the Q_d correction mu_i = u_i + c u_{i+1} mod p (c = -q mod
+//     p, Section 5.1) for polynomial output, or L[u_0..u_{k-1}] +
+//     H[u_{k-1}..u_{2k-2}] (Thm. 3) for field output.
+//   * Alg. 1 for a batch of independent polynomial products: pack, one FP64
+//     product, REDQ + Q_d.
+// These kernels are bound by HBM bandwidth; every workgroup stages its input
+// and output bytes through LDS so that global accesses are whole dwords.
+
+#include "fqt_internal.h"
+
+namespace fqt {
+
+constexpr int kTB = 256;  // threads per workgroup, items per workgroup
+
+// Copy len bytes g[off, off+len) into LDS (bytes at or beyond total read 0).
+__device__ __forceinline__ void stage_in(uint8_t* lds, const uint8_t* g, size_t off, size_t len,
+                                         size_t total) {
+  const bool al = (((uintptr_t)(g + off)) & 3) == 0;
+  if (al) {
+    const size_t nd = len >> 2;
+    const uint32_t* gs = reinterpret_cast<const uint32_t*>(g + off);
+    uint32_t* ls = reinterpret_cast<uint32_t*>(lds);
+    for (size_t i = threadIdx.x; i < nd; i += blockDim.x) {
+      if (off + 4 * i + 3 < total) {
+        ls[i] = gs[i];
+      } else {
+        uint32_t w = 0;
+        for (int j = 0; j < 4; ++j)
+          if (off + 4 * i + j < total) w |= (uint32_t)g[off + 4 * i + j] << (8 * j);
+        ls[i] = w;
+      }
+    }
+    for (size_t i = 4 * nd + threadIdx.x; i < len; i += blockDim.x)
+      lds[i] = off + i < total ? g[off + i] : 0;
+  } else {
+    for (size_t i = threadIdx.x; i < len; i += blockDim.x) lds[i] = off + i < total ? g[off + i] : 0;
+  }
+}
+
+// Copy len bytes from LDS to g[off, off+len), never writing at or past total.
+__device__ __forceinline__ void stage_out(uint8_t* g, const uint8_t* lds, size_t off, size_t len,
+                                          size_t total) {
+  const size_t lim = off + len < total ? len : (off < total ? total - off : 0);
+  const bool al = (((uintptr_t)(g + off)) & 3) == 0;
+  if (al) {
+    const size_t nd = lim >> 2;
+    uint32_t* gs = reinterpret_cast<uint32_t*>(g + off);
+    const uint32_t* ls = reinterpret_cast<const uint32_t*>(lds);
+    for (size_t i = threadIdx.x; i < nd; i += blockDim.x) gs[i] = ls[i];
+    for (size_t i = 4 * nd + threadIdx.x; i < lim; i += blockDim.x) g[off + i] = lds[i];
+  } else {
+    for (size_t i = threadIdx.x; i < lim; i += blockDim.x) g[off + i] = lds[i];
+  }
+}
+
+// Exact floor(x / d) for x < 2^53, d >= 2: binary64 estimate, then one
+// correction from the exact remainder (the estimate is off by at most 1).
+__device__ __forceinline__ uint64_t floor_div53(uint64_t x, uint64_t d, double inv_d) {
+  uint64_t t = (uint64_t)__builtin_floor((double)x * inv_d);
+  const int64_t e = (int64_t)(x - t * d);
+  if (e < 0) t -= 1;
+  else if (e >= (int64_t)d) t += 1;
+  return t;
+}
+
+// Evaluation at q of the k coefficients at src (Alg. 1 step 1).
+__device__ __forceinline__ double dqt_eval(const uint8_t* src, int k, int pow2, uint32_t b,
+                                           double qd) {
+  if (pow2) {
+    uint64_t v = 0;
+    for (int j = k - 1; j >= 0; --j) v = (v << b) | src[j];
+    return (double)v;
+  }
+  double v = 0.0;
+  for (int j = k - 1; j >= 0; --j) v = __builtin_fma(v, qd, (double)src[j]);
+  return v;
+}
+
+// ---- pack ------------------------------------------------------------------
+
+__global__ __launch_bounds__(kTB) void pack_kernel(const uint8_t* __restrict__ coeffs, size_t n,
+                                                   int k, int pow2, uint32_t b, double qd,
+                                                   double* __restrict__ out) {
+  __shared__ uint8_t buf[kTB * 16];
+  const size_t base = (size_t)blockIdx.x * kTB;
+  stage_in(buf, coeffs, base * k, (size_t)kTB * k, n * k);
+  __syncthreads();
+  const size_t i = base + threadIdx.x;
+  if (i < n) out[i] = dqt_eval(buf + threadIdx.x * k, k, pow2, b, qd);
+}
+
+hipError_t launch_pack(int k, uint64_t q, int pow2, uint32_t b, const uint8_t* coeffs, size_t n,
+                       double* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t grid = (n + kTB - 1) / kTB;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)grid), dim3(kTB), 0, s, coeffs, n, k, pow2, b,
+                     (double)q, out);
+  return hipGetLastError();
+}
+
+// ---- REDQ ------------------------------------------------------------------
+
+struct RedqArgs {
+  uint64_t q;
+  double inv_q;
+  double inv_p;
+  uint32_t p, b, pow2, c;  // c = (-q) mod p
+  uint32_t mod_magic;
+};
+
+// Residues u_0..u_{nd-1} of Alg. 2 for r < 2^53 (binary64 input, WIDE = 0)
+// or r < 2^64 (uint64 input, WIDE = 1).  Every u_i is exact in [0, p).
+template <bool WIDE>
+__device__ __forceinline__ void redq_residues(uint64_t r, int nd, const RedqArgs& ra,
+                                              uint32_t* u) {
+  const uint64_t p = ra.p;
+  uint64_t rop = WIDE ? r / p : floor_div53(r, p, ra.inv_p);  // Alg. 2, first step
+  uint64_t x = r, y = rop;
+  for (int i = 0; i < nd; ++i) {
+    u[i] = (uint32_t)(x - p * y);  // floor(r/q^i) - p floor(rop/q^i)
+    if (ra.pow2) {
+      x >>= ra.b;
+      y >>= ra.b;
+    } else if (WIDE) {
+      x /= ra.q;  // Lemma 2: floor(floor(r/q^i)/q) = floor(r/q^(i+1))
+      y /= ra.q;
+    } else {
+      x = floor_div53(x, ra.q, ra.inv_q);
+      y = floor_div53(y, ra.q, ra.inv_q);
+    }
+  }
+}
+
+__device__ __forceinline__ uint32_t modp(uint32_t x, const RedqArgs& ra) {
+  return x - __umulhi(x, ra.mod_magic) * ra.p;
+}
+
+template <bool WIDE>
+__global__ __launch_bounds__(kTB) void unpack_kernel(const void* __restrict__ in, size_t n,
+                                                     int k, int nd, int mode, RedqArgs ra,
+                                                     FieldArgs fa, const uint32_t* __restrict__ L,
+                                                     const uint32_t* __restrict__ H,
+                                                     uint8_t* __restrict__ out) {
+  __shared__ uint8_t buf[kTB * 16];
+  const size_t base = (size_t)blockIdx.x * kTB;
+  const size_t i = base + threadIdx.x;
+  const int ob = mode == 0 ? nd : k;  // output bytes per value
+  if (i < n) {
+    uint64_t r;
+    if (WIDE) r = reinterpret_cast<const uint64_t*>(in)[i];
+    else r = (uint64_t)reinterpret_cast<const double*>(in)[i];
+    uint32_t u[16];
+    const int nr = mode == 0 ? nd : 2 * k - 1;
+    redq_residues<WIDE>(r, nr, ra, u);
+    uint8_t* dst = buf + threadIdx.x * ob;
+    if (mode == 0) {
+      // Q_d: mu_{nd-1} = u_{nd-1}; mu_i = u_i - q u_{i+1} = u_i + c u_{i+1} mod p.
+      for (int d = 0; d < nd - 1; ++d) dst[d] = (uint8_t)modp(u[d] + ra.c * u[d + 1], ra);
+      dst[nd - 1] = (uint8_t)u[nd - 1];
+    } else {
+      uint32_t il = 0, ih = 0;
+      for (int d = 0; d < k; ++d) {
+        il |= u[d] << (fa.cb * d);
+        ih |= u[k - 1 + d] << (fa.cb * d);
+      }
+      const uint32_t tmask = (1u << (fa.cb * k)) - 1u;  // keeps lookups inside the tables
+      const uint32_t e = add_bytes_mod_p(L[il & tmask], H[ih & tmask], fa);
+      for (int d = 0; d < k; ++d) dst[d] = (uint8_t)(e >> (8 * d));
+    }
+  }
+  __syncthreads();
+  stage_out(out, buf, base * ob, (size_t)kTB * ob, n * ob);
+}
+
+static RedqArgs make_redq(uint64_t q, int pow2, uint32_t b, const FieldArgs& fa) {
+  RedqArgs ra;
+  ra.q = q;
+  ra.inv_q = 1.0 / (double)q;
+  ra.inv_p = fa.inv_p;
+  ra.p = fa.p;
+  ra.b = b;
+  ra.pow2 = (uint32_t)pow2;
+  ra.c = (uint32_t)((fa.p - (q % fa.p)) % fa.p);
+  ra.mod_magic = fa.mod_magic;
+  return ra;
+}
+
+hipError_t launch_unpack_f64(int k, uint32_t nd, int mode, uint64_t q, int pow2, uint32_t b,
+                             const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
+                             const double* in, size_t n, uint8_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t grid = (n + kTB - 1) / kTB;
+  hipLaunchKernelGGL(unpack_kernel<false>, dim3((unsigned)grid), dim3(kTB), 0, s,
+                     (const void*)in, n, k, (int)nd, mode, make_redq(q, pow2, b, fa), fa, L, H,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack_u64(int k, uint32_t nd, int mode, uint64_t q, int pow2, uint32_t b,
+                             const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
+                             const uint64_t* in, size_t n, uint8_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t grid = (n + kTB - 1) / kTB;
+  hipLaunchKernelGGL(unpack_kernel<true>, dim3((unsigned)grid), dim3(kTB), 0, s,
+                     (const void*)in, n, k, (int)nd, mode, make_redq(q, pow2, b, fa), fa, L, H,
+                     out);
+  return hipGetLastError();
+}
+
+// ---- Alg. 1 on a batch of polynomial pairs -----------------------------------
+
+__global__ __launch_bounds__(kTB) void polymul_kernel(const uint8_t* __restrict__ a,
+                                                      const uint8_t* __restrict__ bb, size_t n,
+                                                      int k, RedqArgs ra,
+                                                      uint8_t* __restrict__ c) {
+  __shared__ uint8_t sa[kTB * 8];
+  __shared__ uint8_t sb[kTB * 8];
+  __shared__ uint8_t sc[kTB * 15];
+  const size_t base = (size_t)blockIdx.x * kTB;
+  stage_in(sa, a, base * k, (size_t)kTB * k, n * k);
+  stage_in(sb, bb, base * k, (size_t)kTB * k, n * k);
+  __syncthreads();
+  const int nd = 2 * k - 1;
+  const size_t i = base + threadIdx.x;
+  if (i < n) {
+    const double qd = (double)ra.q;
+    const double va = dqt_eval(sa + threadIdx.x * k, k, ra.pow2, ra.b, qd);
+    const double vb = dqt_eval(sb + threadIdx.x * k, k, ra.pow2, ra.b, qd);
+    const double r = va * vb;  // Alg. 1 step 2: exact, r < q^(2k-1) < 2^53
+    uint32_t u[16];
+    redq_residues<false>((uint64_t)r, nd, ra, u);
+    uint8_t* dst = sc + threadIdx.x * nd;
+    for (int d = 0; d < nd - 1; ++d) dst[d] = (uint8_t)modp(u[d] + ra.c * u[d + 1], ra);
+    dst[nd - 1] = (uint8_t)u[nd - 1];
+  }
+  __syncthreads();
+  stage_out(c, sc, base * nd, (size_t)kTB * nd, n * nd);
+}
+
+hipError_t launch_polymul(int k, uint64_t q, int pow2, uint32_t b, const FieldArgs& fa,
+                          const uint8_t* a, const uint8_t* bb, size_t n, uint8_t* c,
+                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const size_t grid = (n + kTB - 1) / kTB;
+  hipLaunchKernelGGL(polymul_kernel, dim3((unsigned)grid), dim3(kTB), 0, s, a, bb, n, k,
+                     make_redq(q, pow2, b, fa), c);
+  return hipGetLastError();
+}
+
+}  // namespace fqt

@@ -1,0 +1,263 @@
+"""Python binding of libfqt.so (the C ABI in include/fqt.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  torch supplies device memory (tensor data pointers) and the
+current HIP stream.  The binding never falls back to any other
+implementation: if the library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfqt.so")
+
+FQT_OK = 0
+STATUS_NAMES = {
+    0: "FQT_OK", 1: "FQT_ERR_INVALID_ARG", 2: "FQT_ERR_BOUNDS", 3: "FQT_ERR_NOT_PRIME",
+    4: "FQT_ERR_REDUCIBLE", 5: "FQT_ERR_UNSUPPORTED", 6: "FQT_ERR_DEVICE", 7: "FQT_ERR_OOM",
+}
+PATHS = {"auto": 0, "packed": 1, "int8": 2, "plain": 3}
+PATH_NAMES = {v: k for k, v in PATHS.items()}
+UNPACK_POLY, UNPACK_FIELD = 0, 1
+
+EXPORTED = [
+    "fqt_field_create", "fqt_field_destroy", "fqt_field_tables", "fqt_params", "fqt_pack",
+    "fqt_unpack_redq", "fqt_unpack_redq_u64", "fqt_polymul_batch", "fqt_gemm_gfpk",
+    "fqt_gemm_gfpk_ex", "fqt_gemm_gfpk_batched", "fqt_gemm_gfpk_batched_ex", "fqt_autotune",
+    "fqt_tile_count", "fqt_last_error", "fqt_version",
+]
+
+
+class FqtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS_NAMES.get(status, str(status))
+
+
+class GemmOpts(ctypes.Structure):
+    _fields_ = [("log2q", ctypes.c_uint32), ("n_q", ctypes.c_uint32),
+                ("tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class GemmDesc(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           f"`python paper_0710_0510_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    c_int, c_u32, c_u64, c_i64, c_sz = (ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64,
+                                       ctypes.c_int64, ctypes.c_size_t)
+    vp = ctypes.c_void_p
+    sig = {
+        "fqt_field_create": (c_int, [c_u32, c_u32, ctypes.POINTER(c_u32), ctypes.POINTER(vp)]),
+        "fqt_field_destroy": (None, [vp]),
+        "fqt_field_tables": (c_int, [vp, c_u64, vp, vp, ctypes.POINTER(c_sz)]),
+        "fqt_params": (c_int, [c_u32, c_u32, c_u64, c_int, c_int, ctypes.POINTER(c_u64),
+                               ctypes.POINTER(c_u64)]),
+        "fqt_pack": (c_int, [vp, c_u64, vp, c_sz, vp, vp]),
+        "fqt_unpack_redq": (c_int, [vp, c_u64, vp, c_sz, c_u32, c_int, vp, vp]),
+        "fqt_unpack_redq_u64": (c_int, [vp, c_u64, vp, c_sz, c_u32, c_int, vp, vp]),
+        "fqt_polymul_batch": (c_int, [c_u32, c_u32, c_u64, vp, vp, c_sz, vp, vp]),
+        "fqt_gemm_gfpk": (c_int, [vp, c_int, c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp,
+                                  c_i64, vp]),
+        "fqt_gemm_gfpk_ex": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_i64, c_i64, c_i64,
+                                     vp, c_i64, vp, c_i64, vp, c_i64, vp]),
+        "fqt_gemm_gfpk_batched": (c_int, [vp, c_int, c_i64, ctypes.POINTER(GemmDesc), vp]),
+        "fqt_gemm_gfpk_batched_ex": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_i64,
+                                             ctypes.POINTER(GemmDesc), vp]),
+        "fqt_autotune": (c_int, [vp, c_i64, ctypes.POINTER(GemmDesc), ctypes.c_char_p,
+                                 ctypes.POINTER(c_int), ctypes.POINTER(GemmOpts), vp]),
+        "fqt_tile_count": (c_u32, [c_int]),
+        "fqt_last_error": (ctypes.c_char_p, []),
+        "fqt_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != FQT_OK:
+        raise FqtError(status, lib().fqt_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().fqt_last_error().decode()
+
+
+def version() -> str:
+    return lib().fqt_version().decode()
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def params(p: int, k: int, n_q: int, pow2: bool = True, carry_in: bool = False) -> Tuple[int, int]:
+    """(q, largest n_q for q) from eq. (2); raises FqtError(FQT_ERR_BOUNDS)."""
+    q, nq = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib().fqt_params(p, k, n_q, int(pow2), int(carry_in), ctypes.byref(q), ctypes.byref(nq)))
+    return q.value, nq.value
+
+
+def params_raw(p: int, k: int, n_q: int, pow2: bool = True, carry_in: bool = False):
+    """(status, q, nq_max) without raising."""
+    q, nq = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    st = lib().fqt_params(p, k, n_q, int(pow2), int(carry_in), ctypes.byref(q), ctypes.byref(nq))
+    return st, q.value, nq.value
+
+
+class Field:
+    """GF(p^k) with defining polynomial X^k + sum P_low[i] X^i."""
+
+    def __init__(self, p: int, k: int, P_low: Sequence[int] = ()):
+        arr = (ctypes.c_uint32 * max(k, 1))(*([int(x) for x in P_low] or [0] * k))
+        h = ctypes.c_void_p(0)
+        _check(lib().fqt_field_create(p, k, arr if P_low else None, ctypes.byref(h)))
+        self.handle = h
+        self.p, self.k, self.P_low = p, k, tuple(P_low)
+
+    def close(self):
+        if getattr(self, "handle", None) and self.handle.value:
+            lib().fqt_field_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tables(self, q: int):
+        """Host copies (L, H) of the Thm. 3 tables as lists of uint32."""
+        n = ctypes.c_size_t(0)
+        _check(lib().fqt_field_tables(self.handle, q, None, None, ctypes.byref(n)))
+        L = (ctypes.c_uint32 * n.value)()
+        H = (ctypes.c_uint32 * n.value)()
+        _check(lib().fqt_field_tables(self.handle, q, L, H, ctypes.byref(n)))
+        return list(L), list(H)
+
+
+def create_field_status(p: int, k: int, P_low: Sequence[int]):
+    """Status code of fqt_field_create (the handle is destroyed)."""
+    arr = (ctypes.c_uint32 * max(k, 1))(*([int(x) for x in P_low] or [0] * max(k, 1)))
+    h = ctypes.c_void_p(0)
+    st = lib().fqt_field_create(p, k, arr if P_low else None, ctypes.byref(h))
+    if st == FQT_OK:
+        lib().fqt_field_destroy(h)
+    return st
+
+
+# ---- device entry points (torch tensors on the current device) -----------------
+
+def pack(field: Field, q: int, coeffs, out=None, stream=None):
+    import torch
+    n = coeffs.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=coeffs.device)
+    _check(lib().fqt_pack(field.handle, q, _ptr(coeffs), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def unpack_redq(field: Field, q: int, packed, ndigits: int, mode: int, out=None, stream=None):
+    import torch
+    n = packed.shape[0]
+    ob = ndigits if mode == UNPACK_POLY else field.k
+    if out is None:
+        out = torch.empty((n, ob), dtype=torch.uint8, device=packed.device)
+    fn = lib().fqt_unpack_redq_u64 if packed.dtype == torch.int64 else lib().fqt_unpack_redq
+    _check(fn(field.handle, q, _ptr(packed), n, ndigits, mode, _ptr(out), _stream(stream)))
+    return out
+
+
+def polymul_batch(p: int, k: int, q: int, a, b, out=None, stream=None):
+    import torch
+    n = a.shape[0]
+    if out is None:
+        out = torch.empty((n, 2 * k - 1), dtype=torch.uint8, device=a.device)
+    _check(lib().fqt_polymul_batch(p, k, q, _ptr(a), _ptr(b), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def _opts(opts) -> Optional[ctypes.POINTER(GemmOpts)]:
+    if opts is None:
+        return None
+    if isinstance(opts, GemmOpts):
+        return ctypes.pointer(opts)
+    return ctypes.pointer(GemmOpts(int(opts.get("log2q", 0)), int(opts.get("n_q", 0)),
+                                   int(opts.get("tile", 0)), 0))
+
+
+def _ld(t, k: int) -> int:
+    """Leading dimension in elements of a rows x cols x k tensor (the row
+    length when the stride carries no information: empty or one row)."""
+    rows, cols = t.shape[0], t.shape[1]
+    if t.numel() == 0 or rows <= 1:
+        return max(cols, 1)
+    return t.stride(0) // k
+
+
+def gemm(field: Field, A, B, C=None, path: str = "auto", opts=None, stream=None):
+    """C = A B over the field; A is M x K x k, B is K x N x k (uint8)."""
+    import torch
+    M, K = A.shape[0], A.shape[1]
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N, field.k), dtype=torch.uint8, device=A.device)
+    lda, ldb, ldc = _ld(A, field.k), _ld(B, field.k), _ld(C, field.k)
+    _check(lib().fqt_gemm_gfpk_ex(field.handle, PATHS[path], _opts(opts), M, N, K, _ptr(A),
+                                  lda, _ptr(B), ldb, _ptr(C), ldc, _stream(stream)))
+    return C
+
+
+def make_descs(field: Field, As, Bs, Cs):
+    arr = (GemmDesc * len(As))()
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        arr[i] = GemmDesc(A.shape[0], B.shape[1], A.shape[1], _ld(A, field.k),
+                          _ld(B, field.k), _ld(C, field.k),
+                          A.data_ptr(), B.data_ptr(), C.data_ptr())
+    return arr
+
+
+def gemm_batched(field: Field, descs, path: str = "auto", opts=None, stream=None):
+    """Run a batch described by ``make_descs`` (the descriptor array)."""
+    _check(lib().fqt_gemm_gfpk_batched_ex(field.handle, PATHS[path], _opts(opts), len(descs),
+                                          descs, _stream(stream)))
+
+
+def autotune(field: Field, descs, cache_path: Optional[str] = None, stream=None):
+    path = ctypes.c_int(0)
+    best = GemmOpts()
+    _check(lib().fqt_autotune(field.handle, len(descs), descs,
+                              cache_path.encode() if cache_path else None, ctypes.byref(path),
+                              ctypes.byref(best), _stream(stream)))
+    return PATH_NAMES[path.value], {"log2q": best.log2q, "n_q": best.n_q, "tile": best.tile}
+
+
+def tile_count(path: str) -> int:
+    return lib().fqt_tile_count(PATHS[path])

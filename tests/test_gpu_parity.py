@@ -1,0 +1,284 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every comparison is bit-exact: the method is exact integer arithmetic and
+the canonical representative of a result is unique.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import gf
+from paper_0710_0510_amd import fqt
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CONFIG_FIELDS = [(7, 2, (1, 0)), (3, 4, (2, 0, 0, 2)), (5, 3, (3, 3, 0)), (3, 2, (1, 0))]
+
+
+def note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    fqt.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ---- Alg. 1: batched polynomial products -------------------------------------
+
+def test_polymul_cfg1_exhaustive():
+    p, k, q = 5, 3, 64
+    note("polymul exhaustive GF(5) k=3 q=64")
+    elems = np.array([e for e in gf.all_elements(p, k)], dtype=np.uint8)
+    a = np.repeat(elems, len(elems), axis=0)
+    b = np.tile(elems, (len(elems), 1))
+    out = host(fqt.polymul_batch(p, k, q, dev(a), dev(b)))
+    assert np.array_equal(out, gf.polymul_batch(a, b, p))
+
+
+def test_polymul_cfg1_workload():
+    from paper_0710_0510_amd import workloads as W
+    w = W.WORKLOADS["polymul-gf5-k3"]
+    a, b = W.polymul_inputs(w)
+    note("polymul workload 65536")
+    out = host(fqt.polymul_batch(w.p, w.k, w.q, dev(a), dev(b)))
+    assert np.array_equal(out, gf.polymul_batch(a, b, w.p))
+
+
+def test_polymul_example1_general_q():
+    note("polymul example 1 q=100")
+    a = np.array([[1, 1]], dtype=np.uint8)
+    b = np.array([[2, 1]], dtype=np.uint8)
+    out = host(fqt.polymul_batch(3, 2, 100, dev(a), dev(b)))
+    assert out.tolist() == [[2, 0, 1]]
+
+
+@pytest.mark.parametrize("p,k,q,n", [(3, 2, 100, 1000), (7, 2, 2 ** 17, 257), (5, 3, 1552, 255),
+                                     (3, 4, 190, 999), (2, 7, 8, 4097), (11, 1, 2 ** 40, 33),
+                                     (13, 3, 1000, 700), (127, 2, 2 ** 15, 300),
+                                     (127, 2, 32259, 300)])
+def test_polymul_params(p, k, q, n):
+    note(f"polymul p={p} k={k} q={q} n={n}")
+    assert gf.eq2_holds(p, k, q, 1)
+    rng = np.random.default_rng(p * 1000 + k)
+    a = rng.integers(0, p, size=(n, k), dtype=np.uint8)
+    b = rng.integers(0, p, size=(n, k), dtype=np.uint8)
+    a[0] = p - 1
+    b[0] = p - 1
+    out = host(fqt.polymul_batch(p, k, q, dev(a), dev(b)))
+    assert np.array_equal(out, gf.polymul_batch(a, b, p))
+
+
+def test_polymul_empty():
+    out = fqt.polymul_batch(5, 3, 64, torch.empty((0, 3), dtype=torch.uint8, device="cuda"),
+                            torch.empty((0, 3), dtype=torch.uint8, device="cuda"))
+    assert out.shape == (0, 5)
+
+
+# ---- DQT pack / REDQ unpack ---------------------------------------------------
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("qkind", ["pow2", "general"])
+def test_pack(p, k, P, qkind):
+    q = fqt.params(p, k, 1, pow2=(qkind == "pow2"))[0]
+    note(f"pack GF({p}^{k}) q={q}")
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(5)
+    n = 3001
+    c = rng.integers(0, p, size=(n, k), dtype=np.uint8)
+    out = host(fqt.pack(f, q, dev(c)))
+    want = np.array([float(gf.dqt(row.tolist(), q)) for row in c])
+    assert np.array_equal(out, want)
+
+
+def _random_packed(rng, n, nd, q):
+    digits = rng.integers(0, q, size=(n, nd), dtype=np.int64)
+    digits[0] = q - 1
+    vals = [gf.dqt(row.tolist(), q) for row in digits]
+    return digits, vals
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("qkind", ["pow2", "general"])
+def test_unpack_poly_and_field(p, k, P, qkind):
+    q = fqt.params(p, k, 1, pow2=(qkind == "pow2"))[0]
+    nd = 2 * k - 1
+    note(f"unpack GF({p}^{k}) q={q} nd={nd}")
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(7)
+    digits, vals = _random_packed(rng, 2500, nd, q)
+    assert max(vals) < 2 ** 53
+    packed = dev(np.array(vals, dtype=np.float64))
+    poly = host(fqt.unpack_redq(f, q, packed, nd, fqt.UNPACK_POLY))
+    want_poly = np.array([gf.dqt_inverse(v, q, nd, p) for v in vals], dtype=np.uint8)
+    assert np.array_equal(poly, want_poly)
+    field = host(fqt.unpack_redq(f, q, packed, nd, fqt.UNPACK_FIELD))
+    want_field = np.array([gf.poly_rem(row.tolist(), P, p) for row in want_poly], dtype=np.uint8)
+    assert np.array_equal(field, want_field)
+    # the uint64 variant agrees on the same values
+    packed64 = dev(np.array(vals, dtype=np.int64))
+    assert np.array_equal(host(fqt.unpack_redq(f, q, packed64, nd, fqt.UNPACK_POLY)), want_poly)
+    assert np.array_equal(host(fqt.unpack_redq(f, q, packed64, nd, fqt.UNPACK_FIELD)), want_field)
+
+
+def test_unpack_example2_uint64():
+    note("unpack example 2 (uint64, q=10^4)")
+    from golden_io import load
+    g = load("ex2_redq_p_divides_q.txt")
+    f = fqt.Field(5, 3, (3, 3, 0))
+    packed = dev(np.array([g["product"]], dtype=np.int64))
+    out = host(fqt.unpack_redq(f, g["q"], packed, 5, fqt.UNPACK_POLY))
+    assert out.tolist() == [g["result"]]
+
+
+def test_unpack_near_2_53():
+    # q^nd = 2^53 exactly: the largest binary64 values
+    p, k, P = 3, 2, (1, 0)
+    f = fqt.Field(p, k, P)
+    q, nd = 2 ** 53, 1
+    note("unpack near 2^53")
+    vals = [2 ** 53 - 1, 2 ** 53 - 2, 2 ** 52, 2 ** 52 + 1, 0, 1, 2]
+    out = host(fqt.unpack_redq(f, q, dev(np.array(vals, dtype=np.float64)), nd, fqt.UNPACK_POLY))
+    assert out[:, 0].tolist() == [v % p for v in vals]
+
+
+# ---- GEMM over GF(p^k) ----------------------------------------------------------
+
+def _gemm_case(p, k, P, M, N, K, seed, path="packed", opts=None, adversarial=False):
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(seed)
+    if adversarial:
+        A = np.full((M, K, k), p - 1, dtype=np.uint8)
+        B = np.full((K, N, k), p - 1, dtype=np.uint8)
+    else:
+        A = rng.integers(0, p, size=(M, K, k), dtype=np.uint8)
+        B = rng.integers(0, p, size=(K, N, k), dtype=np.uint8)
+    C = host(fqt.gemm(f, dev(A), dev(B), path=path, opts=opts))
+    want = gf.gemm_gfpk_planes(A, B, p, P)
+    return C, want
+
+
+SHAPES = [(1, 1, 1), (17, 33, 45), (64, 64, 64), (100, 70, 300), (33, 130, 16), (5, 7, 0)]
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+def test_gemm_packed_shapes(p, k, P, tile):
+    for (M, N, K) in SHAPES:
+        note(f"gemm packed GF({p}^{k}) tile={tile} {M}x{N}x{K}")
+        C, want = _gemm_case(p, k, P, M, N, K, seed=M + N + K, opts={"tile": tile})
+        assert np.array_equal(C, want), (M, N, K)
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("nq", [4, 8, 12, 20])
+def test_gemm_packed_multiblock(p, k, P, nq):
+    q, nqmax = fqt.params(p, k, 1)
+    if nq > nqmax:
+        pytest.skip("n_q above the bound")
+    for (M, N, K) in [(40, 50, 97), (64, 64, 256)]:
+        note(f"gemm packed multiblock GF({p}^{k}) n_q={nq} {M}x{N}x{K}")
+        C, want = _gemm_case(p, k, P, M, N, K, seed=nq, opts={"n_q": nq, "tile": 2})
+        assert np.array_equal(C, want), (M, N, K)
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+def test_gemm_adversarial_bound(p, k, P):
+    q, nqmax = fqt.params(p, k, 1)
+    nq4 = nqmax - nqmax % 4
+    for K in [nq4, 3 * nq4 + 5]:
+        K = min(K, 3000)
+        note(f"gemm adversarial GF({p}^{k}) K={K} n_q={nq4}")
+        C, want = _gemm_case(p, k, P, 32, 48, K, seed=0, adversarial=True, opts={"tile": 2})
+        assert np.array_equal(C, want)
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+def test_gemm_plain(p, k, P):
+    for (M, N, K) in [(17, 33, 45), (64, 80, 130)]:
+        note(f"gemm plain GF({p}^{k}) {M}x{N}x{K}")
+        C, want = _gemm_case(p, k, P, M, N, K, seed=3, path="plain")
+        assert np.array_equal(C, want)
+
+
+def test_gemm_strided_and_unaligned():
+    p, k, P = 7, 2, (1, 0)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(9)
+    Abig = rng.integers(0, p, size=(70, 91, k), dtype=np.uint8)   # odd ld: unaligned rows
+    Bbig = rng.integers(0, p, size=(91, 75, k), dtype=np.uint8)
+    A = dev(Abig)[:50, :61]
+    B = dev(Bbig)[:61, :40]
+    note("gemm strided/unaligned")
+    C = host(fqt.gemm(f, A, B, path="packed"))
+    want = gf.gemm_gfpk_planes(Abig[:50, :61], Bbig[:61, :40], p, P)
+    assert np.array_equal(C, want)
+
+
+def test_gemm_cross_path_identity_medium():
+    p, k, P = 5, 3, (3, 3, 0)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(12)
+    A = dev(rng.integers(0, p, size=(300, 700, k), dtype=np.uint8))
+    B = dev(rng.integers(0, p, size=(700, 260, k), dtype=np.uint8))
+    note("gemm cross-path 300x260x700")
+    outs = [host(fqt.gemm(f, A, B, path="plain"))]
+    for tile in (1, 2, 3, 4):
+        outs.append(host(fqt.gemm(f, A, B, path="packed", opts={"tile": tile})))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    want = gf.gemm_gfpk_planes(host(A), host(B), p, P)
+    assert np.array_equal(outs[0], want)
+
+
+# ---- batched --------------------------------------------------------------------
+
+def test_gemm_batched_replay():
+    p, k, P = 3, 4, (2, 0, 0, 2)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(31)
+    shapes = rng.integers(1, 90, size=(40, 3))
+    shapes[0] = (200, 150, 256)
+    As, Bs, Cs, hostA, hostB = [], [], [], [], []
+    for (M, N, K) in shapes.tolist():
+        a = rng.integers(0, p, size=(M, K, k), dtype=np.uint8)
+        b = rng.integers(0, p, size=(K, N, k), dtype=np.uint8)
+        hostA.append(a)
+        hostB.append(b)
+        As.append(dev(a))
+        Bs.append(dev(b))
+        Cs.append(torch.zeros((M, N, k), dtype=torch.uint8, device="cuda"))
+    descs = fqt.make_descs(f, As, Bs, Cs)
+    wants = [gf.gemm_gfpk_planes(a, b, p, P) for a, b in zip(hostA, hostB)]
+    for rep in range(3):
+        note(f"batched replay {rep}")
+        for c in Cs:
+            c.zero_()
+        fqt.gemm_batched(f, descs, path="packed")
+        torch.cuda.synchronize()
+        for c, w in zip(Cs, wants):
+            assert np.array_equal(host(c), w)
+    note("batched plain")
+    for c in Cs:
+        c.zero_()
+    fqt.gemm_batched(f, descs, path="plain")
+    for c, w in zip(Cs, wants):
+        assert np.array_equal(host(c), w)

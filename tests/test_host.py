@@ -1,0 +1,186 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The library must load, export every entry point that include/fqt.h declares,
+and reject every invalid argument synchronously, before touching a device.
+Its Thm. 3 tables are compared with the oracle's, built independently.
+"""
+import ctypes
+import itertools
+import os
+import re
+
+import pytest
+
+from oracle import gf
+from paper_0710_0510_amd import fqt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CONFIG_FIELDS = [(7, 2, (1, 0)), (3, 4, (2, 0, 0, 2)), (5, 3, (3, 3, 0)), (3, 2, (1, 0))]
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "fqt.h")).read()
+    return sorted(set(re.findall(r"\b(fqt_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fqt.lib()
+    declared = header_functions()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(fqt.EXPORTED)
+
+
+def test_version_string():
+    assert "gfx950" in fqt.version()
+
+
+@pytest.mark.parametrize("p,k", [(7, 2), (3, 4), (5, 3), (3, 2), (5, 3), (2, 3), (11, 1)])
+def test_params_match_oracle(p, k):
+    q, nq = fqt.params(p, k, 1, pow2=True)
+    assert (q, nq) == gf.max_pow2_q(p, k)
+    assert gf.eq2_holds(p, k, q, nq) and not gf.eq2_holds(p, k, q, nq + 1)
+    st, _, _ = fqt.params_raw(p, k, nq + 1, pow2=True)
+    assert fqt.STATUS_NAMES[st] == "FQT_ERR_BOUNDS"
+    # general q: largest integer q with q^(2k-1) < 2^53
+    qg, nqg = fqt.params(p, k, 1, pow2=False)
+    assert qg ** (2 * k - 1) < 2 ** 53 <= (qg + 1) ** (2 * k - 1)
+    assert gf.eq2_holds(p, k, qg, nqg) and not gf.eq2_holds(p, k, qg, nqg + 1)
+
+
+def test_params_survey_values():
+    assert fqt.params(7, 2, 1)[0] == 2 ** 17 and fqt.params(7, 2, 1)[1] == 1820
+    assert fqt.params(3, 4, 1) == (128, 7)
+    assert fqt.params(3, 4, 1, pow2=False) == (190, 11)
+    assert fqt.params(5, 3, 1) == (1024, 21)
+    assert fqt.params(5, 3, 1, pow2=False) == (1552, 32)
+    assert fqt.params(3, 2, 1) == (2 ** 17, 16383)
+
+
+def test_params_carry_in():
+    q, nq = fqt.params(5, 3, 1, pow2=True, carry_in=True)
+    assert q > nq * 3 * 16 + 4 and not q > (nq + 1) * 3 * 16 + 4
+
+
+def test_params_errors():
+    st, _, _ = fqt.params_raw(4, 2, 1)
+    assert fqt.STATUS_NAMES[st] == "FQT_ERR_NOT_PRIME"
+    st, _, _ = fqt.params_raw(7, 2, 0)
+    assert fqt.STATUS_NAMES[st] == "FQT_ERR_INVALID_ARG"
+    assert "n_q" in fqt.last_error()
+
+
+@pytest.mark.parametrize("p,k,P,want", [
+    (4, 2, (1, 0), "FQT_ERR_NOT_PRIME"),
+    (9, 2, (1, 0), "FQT_ERR_NOT_PRIME"),
+    (3, 2, (2, 0), "FQT_ERR_REDUCIBLE"),      # X^2 + 2 = (X+1)(X+2)
+    (5, 3, (0, 0, 1), "FQT_ERR_REDUCIBLE"),   # X^3 + X^2
+    (7, 2, (6, 0), "FQT_ERR_REDUCIBLE"),      # X^2 - 1
+    (3, 5, (1, 2, 0, 0, 0), "FQT_ERR_UNSUPPORTED"),
+    (131, 2, (1, 0), "FQT_ERR_UNSUPPORTED"),
+    (7, 2, (7, 0), "FQT_ERR_INVALID_ARG"),
+    (3, 0, (), "FQT_ERR_UNSUPPORTED"),
+])
+def test_field_create_errors(p, k, P, want):
+    assert fqt.STATUS_NAMES[fqt.create_field_status(p, k, P)] == want
+
+
+def test_field_create_accepts_every_irreducible_quadratic_gf5():
+    for low in itertools.product(range(5), repeat=2):
+        st = fqt.create_field_status(5, 2, low)
+        assert (st == 0) == gf.is_irreducible(list(low), 5), low
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("which_q", ["pow2", "general", "other"])
+def test_tables_match_oracle(p, k, P, which_q):
+    f = fqt.Field(p, k, P)
+    q = {"pow2": fqt.params(p, k, 1)[0], "general": fqt.params(p, k, 1, pow2=False)[0],
+         "other": 10 ** 6}[which_q]
+    L, H = f.tables(q)
+    cb = max(1, (p - 1).bit_length())
+    assert len(L) == len(H) == 1 << (k * cb)
+    seen = set()
+    for w in itertools.product(range(p), repeat=k):
+        idx = gf.binary_index(w, p)
+        seen.add(idx)
+        want_L = gf.table_L(list(w), q, p)
+        want_H = gf.table_H(list(w), q, p, P)
+        assert [(L[idx] >> (8 * s)) & 0xFF for s in range(k)] == want_L
+        assert [(H[idx] >> (8 * s)) & 0xFF for s in range(k)] == want_H
+        assert L[idx] >> (8 * k) == 0 and H[idx] >> (8 * k) == 0
+    for idx in range(len(L)):
+        if idx not in seen:
+            assert L[idx] == 0 and H[idx] == 0
+
+
+def test_k1_prime_field_tables():
+    f = fqt.Field(11, 1, (0,))
+    L, H = f.tables(2 ** 52)
+    for u in range(11):
+        assert L[u] == 0 and H[u] == u
+
+
+# ---- argument validation happens before any device work -------------------------
+
+BOGUS = 0x1000  # never dereferenced: every call below must fail validation first
+
+
+def _gemm_status(field, path, M, N, K, lda, ldb, ldc, A=BOGUS, B=BOGUS + (1 << 30),
+                 C=BOGUS + (1 << 31), opts=None):
+    L = fqt.lib()
+    return fqt.STATUS_NAMES[L.fqt_gemm_gfpk_ex(
+        field.handle, fqt.PATHS[path], fqt._opts(opts), M, N, K, ctypes.c_void_p(A), lda,
+        ctypes.c_void_p(B), ldb, ctypes.c_void_p(C), ldc, None)]
+
+
+def test_gemm_validation_errors():
+    f = fqt.Field(7, 2, (1, 0))
+    assert _gemm_status(f, "packed", -1, 4, 4, 4, 4, 4) == "FQT_ERR_INVALID_ARG"
+    assert _gemm_status(f, "packed", 4, 4, 8, 4, 4, 4) == "FQT_ERR_INVALID_ARG"   # lda < K
+    assert _gemm_status(f, "packed", 4, 8, 4, 4, 4, 8) == "FQT_ERR_INVALID_ARG"   # ldb < N
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, A=0) == "FQT_ERR_INVALID_ARG"
+    # C overlapping A
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, A=BOGUS, C=BOGUS + 8) == "FQT_ERR_INVALID_ARG"
+    # eq. (2): n_q above the bound for q = 2^17 (1820) and q above 2^17
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"n_q": 1821}) == "FQT_ERR_BOUNDS"
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"log2q": 18}) == "FQT_ERR_BOUNDS"
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"tile": 99}) == "FQT_ERR_INVALID_ARG"
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4,
+                        opts={"log2q": 3}) in ("FQT_ERR_BOUNDS", "FQT_ERR_UNSUPPORTED")
+
+
+def test_gemm_n_q_bound_cfg4():
+    f = fqt.Field(5, 3, (3, 3, 0))
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"log2q": 10, "n_q": 22}) == "FQT_ERR_BOUNDS"
+
+
+def test_polymul_validation_errors():
+    L = fqt.lib()
+    v = ctypes.c_void_p(BOGUS)
+    w = ctypes.c_void_p(BOGUS + (1 << 30))
+    o = ctypes.c_void_p(BOGUS + (1 << 31))
+    name = lambda st: fqt.STATUS_NAMES[st]
+    # q = 48 = k (p-1)^2 breaks q > n_q k (p-1)^2 for p = 5, k = 3
+    assert name(L.fqt_polymul_batch(5, 3, 48, v, w, 10, o, None)) == "FQT_ERR_BOUNDS"
+    # q^(2k-1) >= 2^53
+    assert name(L.fqt_polymul_batch(5, 3, 2 ** 11, v, w, 10, o, None)) == "FQT_ERR_BOUNDS"
+    assert name(L.fqt_polymul_batch(6, 3, 64, v, w, 10, o, None)) == "FQT_ERR_NOT_PRIME"
+    assert name(L.fqt_polymul_batch(5, 3, 64, v, w, 10, v, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_polymul_batch(5, 9, 64, v, w, 10, o, None)) == "FQT_ERR_UNSUPPORTED"
+
+
+def test_unpack_pack_validation_errors():
+    f = fqt.Field(5, 3, (3, 3, 0))
+    L = fqt.lib()
+    v = ctypes.c_void_p(BOGUS)
+    o = ctypes.c_void_p(BOGUS + (1 << 30))
+    name = lambda st: fqt.STATUS_NAMES[st]
+    # (10^4)^5 > 2^53: the binary64 path refuses; the uint64 path needs q^(ndigits-1) < 2^64
+    assert name(L.fqt_unpack_redq(f.handle, 10 ** 4, v, 4, 5, 0, o, None)) == "FQT_ERR_BOUNDS"
+    assert name(L.fqt_unpack_redq_u64(f.handle, 10 ** 4, v, 4, 7, 0, o, None)) == "FQT_ERR_BOUNDS"
+    assert name(L.fqt_unpack_redq(f.handle, 64, v, 4, 6, 1, o, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_unpack_redq(f.handle, 64, v, 4, 0, 0, o, None)) == "FQT_ERR_UNSUPPORTED"
+    assert name(L.fqt_pack(f.handle, 2 ** 30, v, 4, o, None)) == "FQT_ERR_BOUNDS"
+    assert name(L.fqt_pack(f.handle, 1, v, 4, o, None)) == "FQT_ERR_INVALID_ARG"
