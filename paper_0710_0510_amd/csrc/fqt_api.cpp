@@ -326,9 +326,19 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   uint32_t tile = (o && o->tile) ? o->tile : 0;
   if (tile > (uint32_t)kPackedTiles) return fail(FQT_ERR_INVALID_ARG, "unknown tile id %u", tile);
   if (!tile) {
-    // default: the largest tile that still gives at least one wave per SIMD
-    const int64_t mn = M * N;
-    tile = mn >= (int64_t)4096 * 4096 ? 4 : (mn >= (int64_t)1024 * 2048 ? 3 : (mn >= 256 * 256 ? 2 : 1));
+    // default: the largest tile that still gives every CU two workgroups
+    static const int pref[] = {4, 3, 2, 5, 6, 1};
+    tile = 1;
+    for (int id : pref) {
+      if (id == 4 && k == 4 && multi) continue;  // 4x4 blocks + k = 4 lanes spill registers
+      int bm, bn;
+      packed_tile_shape(id, &bm, &bn);
+      const int64_t nt = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+      if (nt >= 512) {
+        tile = (uint32_t)id;
+        break;
+      }
+    }
   }
   pc->b = b;
   pc->nq = (uint32_t)nq;

@@ -35,12 +35,15 @@ struct TileItem {
   int32_t pad;
 };
 
-// Tile configurations of the packed path (WG of 256 threads = 2x2 waves).
-// id -> (TM, TN): wave tile 16TM x 16TN, workgroup tile 32TM x 32TN.
-constexpr int kPackedTiles = 4;
+// Tile configurations of the packed path (WG of 256 threads = 2x2 waves):
+// X(id, TM, TN, BK): wave tile 16TM x 16TN, workgroup tile 32TM x 32TN,
+// K-tiles of BK elements.
+#define FQT_PACKED_TILES(X) \
+  X(1, 1, 1, 32) X(2, 2, 2, 32) X(3, 2, 4, 16) X(4, 4, 4, 16) X(5, 2, 1, 32) X(6, 1, 2, 32)
+constexpr int kPackedTiles = 6;
 inline void packed_tile_shape(int id, int* bm, int* bn) {
-  static const int tm[kPackedTiles] = {1, 2, 2, 4};
-  static const int tn[kPackedTiles] = {1, 2, 4, 4};
+  static const int tm[kPackedTiles] = {1, 2, 2, 4, 2, 1};
+  static const int tn[kPackedTiles] = {1, 2, 4, 4, 1, 2};
   *bm = 32 * tm[id - 1];
   *bn = 32 * tn[id - 1];
 }

@@ -31,21 +31,24 @@ namespace fqt {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int KE, int TM, int TN>
+template <int KE, int TM, int TN, int BK_>
 struct PT {
   static constexpr int BM = 32 * TM;
   static constexpr int BN = 32 * TN;
-  static constexpr int BK = 16;
-  static constexpr int SA = BK + 1;    // A row stride (doubles): conflict-free reads
-  static constexpr int SB = BN + 16;   // B row stride (doubles)
+  static constexpr int BK = BK_;
+  // Row strides in doubles chosen so that the 32 lanes of one ds_read_b64 of
+  // an MFMA operand hit distinct LDS banks.
+  static constexpr int SA = BK == 32 ? BK + 2 : BK + 1;
+  static constexpr int SB = BN + 16;
   static constexpr int ND = 2 * KE - 1;
   static constexpr int NW = (ND + 1) / 2;  // 16-bit-lane words per output element
   static constexpr int NCA = BM * BK / 4;  // A chunks: 4 consecutive k of one row
   static constexpr int NCB = BK * BN / 4;  // B chunks: 4 consecutive n of one k-row
-  static constexpr int RA = (NCA + 255) / 256;
-  static constexpr int RB = (NCB + 255) / 256;
+  static constexpr int RA = NCA / 256;
+  static constexpr int RB = NCB / 256;
   static constexpr int LDS_A = BM * SA;
   static constexpr int LDS_B = BK * SB;
+  static_assert(NCA % 256 == 0 && NCB % 256 == 0, "every thread loads whole chunks");
 };
 
 // Raw bytes of a 4-element chunk (4*KE bytes) from a row segment starting at
@@ -86,13 +89,13 @@ __device__ __forceinline__ uint32_t chunk_elem(const uint32_t (&raw)[KE], int e)
   return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
 }
 
-template <int KE, int TM, int TN, bool MULTI>
+template <int KE, int TM, int TN, int BK, bool MULTI>
 __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int tile_n,
                                             const PackedParams& pp, double* __restrict__ As,
                                             double* __restrict__ Bs,
                                             const uint32_t* __restrict__ Ls,
                                             const uint32_t* __restrict__ Hs) {
-  using T = PT<KE, TM, TN>;
+  using T = PT<KE, TM, TN, BK>;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -102,6 +105,8 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   const int64_t n0 = (int64_t)tile_n * T::BN;
   const bool aligned = pp.aligned != 0;
   const uint32_t b = pp.b;
+  // Interior tiles (and full K-tiles) load without bounds checks.
+  const bool interior = aligned && m0 + T::BM <= g.M && n0 + T::BN <= g.N;
 
   const v4d bias = {kTwo52, kTwo52, kTwo52, kTwo52};
   v4d acc[TM][TN];
@@ -122,55 +127,62 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
           for (int w = 0; w < T::NW; ++w) W[i][j][v][w] = 0;
   }
 
+  // Fixed chunk geometry of this thread: A chunk r covers row arow + r*(1024/BK),
+  // k = 4*akc..4*akc+3 of the K-tile; B chunk r covers k-row bkr + r*(1024/BN),
+  // n = 4*bnc..4*bnc+3.
+  const int arow = tid / (T::BK / 4), akc = tid % (T::BK / 4);
+  const int bkr = tid / (T::BN / 4), bnc = tid % (T::BN / 4);
+  constexpr int ARS = 1024 / T::BK, BRS = 1024 / T::BN;
+  const uint8_t* pa = g.A + ((m0 + arow) * g.lda + 4 * akc) * KE;
+  const uint8_t* pb = g.B + ((int64_t)bkr * g.ldb + n0 + 4 * bnc) * KE;
+  const int64_t a_rstep = (int64_t)ARS * g.lda * KE;  // bytes between chunk rows
+  const int64_t b_rstep = (int64_t)BRS * g.ldb * KE;
+  const int64_t b_kstep = (int64_t)T::BK * g.ldb * KE;  // bytes per K-tile
+
   uint32_t ra[T::RA][KE];
   uint32_t rb[T::RB][KE];
 
   auto gload = [&](int64_t k0) {
+    if (interior && k0 + T::BK <= g.K) {
+      const uint8_t* a0 = pa + k0 * KE;
+      const uint8_t* b0 = pb + (k0 / T::BK) * b_kstep;
 #pragma unroll
-    for (int r = 0; r < T::RA; ++r) {
-      const int c = tid + 256 * r;
-      if (c < T::NCA) {
-        const int row = c / (T::BK / 4);
-        const int kc = c % (T::BK / 4);
-        load_chunk<KE>(g.A, m0 + row, k0 + 4 * kc, g.M, g.K, g.lda, aligned, ra[r]);
+      for (int r = 0; r < T::RA; ++r) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(a0 + r * a_rstep);
+#pragma unroll
+        for (int j = 0; j < KE; ++j) ra[r][j] = src[j];
       }
+#pragma unroll
+      for (int r = 0; r < T::RB; ++r) {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(b0 + r * b_rstep);
+#pragma unroll
+        for (int j = 0; j < KE; ++j) rb[r][j] = src[j];
+      }
+      return;
     }
 #pragma unroll
-    for (int r = 0; r < T::RB; ++r) {
-      const int c = tid + 256 * r;
-      if (c < T::NCB) {
-        const int kr = c / (T::BN / 4);
-        const int nc = c % (T::BN / 4);
-        load_chunk<KE>(g.B, k0 + kr, n0 + 4 * nc, g.K, g.N, g.ldb, aligned, rb[r]);
-      }
-    }
+    for (int r = 0; r < T::RA; ++r)
+      load_chunk<KE>(g.A, m0 + arow + r * ARS, k0 + 4 * akc, g.M, g.K, g.lda, aligned, ra[r]);
+#pragma unroll
+    for (int r = 0; r < T::RB; ++r)
+      load_chunk<KE>(g.B, k0 + bkr + r * BRS, n0 + 4 * bnc, g.K, g.N, g.ldb, aligned, rb[r]);
   };
 
   auto lstore = [&](int buf) {
     double* as = As + buf * T::LDS_A;
     double* bs = Bs + buf * T::LDS_B;
 #pragma unroll
-    for (int r = 0; r < T::RA; ++r) {
-      const int c = tid + 256 * r;
-      if (c < T::NCA) {
-        const int row = c / (T::BK / 4);
-        const int kc = c % (T::BK / 4);
+    for (int r = 0; r < T::RA; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          as[row * T::SA + 4 * kc + e] = (double)dqt_shift<KE>(chunk_elem<KE>(ra[r], e), b);
-      }
-    }
+      for (int e = 0; e < 4; ++e)
+        as[(arow + r * ARS) * T::SA + 4 * akc + e] =
+            (double)dqt_shift<KE>(chunk_elem<KE>(ra[r], e), b);
 #pragma unroll
-    for (int r = 0; r < T::RB; ++r) {
-      const int c = tid + 256 * r;
-      if (c < T::NCB) {
-        const int kr = c / (T::BN / 4);
-        const int nc = c % (T::BN / 4);
+    for (int r = 0; r < T::RB; ++r)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          bs[kr * T::SB + 4 * nc + e] = (double)dqt_shift<KE>(chunk_elem<KE>(rb[r], e), b);
-      }
-    }
+      for (int e = 0; e < 4; ++e)
+        bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] =
+            (double)dqt_shift<KE>(chunk_elem<KE>(rb[r], e), b);
   };
 
   auto boundary = [&]() {
@@ -271,7 +283,6 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
       }
 }
 
-template <int KE, int TM, int TN>
 __device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls, uint32_t* Hs) {
   const int n = 1 << pp.tbl_log2;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -280,36 +291,36 @@ __device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls
   }
 }
 
-template <int KE, int TM, int TN, bool MULTI>
+template <int KE, int TM, int TN, int BK, bool MULTI>
 __global__ __launch_bounds__(256) void gemm_packed_kernel(GemmArgs g, PackedParams pp,
                                                           int tiles_n, int ntiles) {
-  using T = PT<KE, TM, TN>;
+  using T = PT<KE, TM, TN, BK>;
   __shared__ double As[2 * T::LDS_A];
   __shared__ double Bs[2 * T::LDS_B];
   extern __shared__ uint32_t tabs[];
   uint32_t* Ls = tabs;
   uint32_t* Hs = tabs + (1 << pp.tbl_log2);
-  load_tables<KE, TM, TN>(pp, Ls, Hs);
+  load_tables(pp, Ls, Hs);
   __syncthreads();
   // XCD-aware order: the 8 XCDs receive workgroups round-robin; give each XCD
   // a contiguous run of tiles so that its L2 serves shared A rows / B columns.
   int tile = blockIdx.x;
   if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-  packed_tile<KE, TM, TN, MULTI>(g, tile / tiles_n, tile % tiles_n, pp, As, Bs, Ls, Hs);
+  packed_tile<KE, TM, TN, BK, MULTI>(g, tile / tiles_n, tile % tiles_n, pp, As, Bs, Ls, Hs);
 }
 
-template <int KE, int TM, int TN, bool MULTI>
+template <int KE, int TM, int TN, int BK, bool MULTI>
 __global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
     const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items, int32_t n_items,
     uint32_t* counter, PackedParams pp) {
-  using T = PT<KE, TM, TN>;
+  using T = PT<KE, TM, TN, BK>;
   __shared__ double As[2 * T::LDS_A];
   __shared__ double Bs[2 * T::LDS_B];
   __shared__ int32_t cur;
   extern __shared__ uint32_t tabs[];
   uint32_t* Ls = tabs;
   uint32_t* Hs = tabs + (1 << pp.tbl_log2);
-  load_tables<KE, TM, TN>(pp, Ls, Hs);
+  load_tables(pp, Ls, Hs);
   for (;;) {
     if (threadIdx.x == 0) cur = (int32_t)atomicAdd(&counter[0], 1u);
     __syncthreads();
@@ -318,7 +329,7 @@ __global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
     if (it >= n_items) break;
     const TileItem ti = items[it];
     const GemmArgs g = descs[ti.gemm];
-    packed_tile<KE, TM, TN, MULTI>(g, ti.tm, ti.tn, pp, As, Bs, Ls, Hs);
+    packed_tile<KE, TM, TN, BK, MULTI>(g, ti.tm, ti.tn, pp, As, Bs, Ls, Hs);
   }
   // The last workgroup to leave resets the queue for the next launch (every
   // workgroup has made its final counter[0] increment before counter[1]).
@@ -332,80 +343,101 @@ __global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
   }
 }
 
-template <int KE, int TM, int TN, bool MULTI>
+template <int KE, int TM, int TN, int BK, bool MULTI>
 static hipError_t launch_one(const GemmArgs& g, const PackedParams& pp, hipStream_t s) {
-  using T = PT<KE, TM, TN>;
+  using T = PT<KE, TM, TN, BK>;
   const int tiles_m = (int)((g.M + T::BM - 1) / T::BM);
   const int tiles_n = (int)((g.N + T::BN - 1) / T::BN);
   const int ntiles = tiles_m * tiles_n;
   if (ntiles == 0) return hipSuccess;
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_packed_kernel<KE, TM, TN, MULTI>), dim3(ntiles), dim3(256), dyn, s,
-                     g, pp, tiles_n, ntiles);
+  hipLaunchKernelGGL((gemm_packed_kernel<KE, TM, TN, BK, MULTI>), dim3(ntiles), dim3(256), dyn,
+                     s, g, pp, tiles_n, ntiles);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, bool MULTI>
+template <int KE, int TM, int TN, int BK, bool MULTI>
 static hipError_t launch_batched(const GemmArgs* descs, const TileItem* items, int32_t n_items,
                                  uint32_t* counter, int grid, const PackedParams& pp,
                                  hipStream_t s) {
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_packed_batched_kernel<KE, TM, TN, MULTI>), dim3(grid), dim3(256), dyn,
-                     s, descs, items, n_items, counter, pp);
+  hipLaunchKernelGGL((gemm_packed_batched_kernel<KE, TM, TN, BK, MULTI>), dim3(grid), dim3(256),
+                     dyn, s, descs, items, n_items, counter, pp);
   return hipGetLastError();
 }
 
-// Dispatch over (k, tile id, multi-block).
-#define FQT_TILE_SWITCH(FN, KE, MULTI, ...)                   \
-  switch (tile) {                                             \
-    case 1: return FN<KE, 1, 1, MULTI>(__VA_ARGS__);          \
-    case 2: return FN<KE, 2, 2, MULTI>(__VA_ARGS__);          \
-    case 3: return FN<KE, 2, 4, MULTI>(__VA_ARGS__);          \
-    case 4: return FN<KE, 4, 4, MULTI>(__VA_ARGS__);          \
-    default: return hipErrorInvalidValue;                     \
-  }
+template <int KE, int TM, int TN, int BK, bool MULTI>
+static int occupancy(uint32_t tbl_log2) {
+  int blocks = 0;
+  const size_t dyn = 2u * (1u << tbl_log2) * sizeof(uint32_t);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, (const void*)gemm_packed_batched_kernel<KE, TM, TN, BK, MULTI>, 256, dyn) !=
+      hipSuccess)
+    blocks = 1;
+  return blocks > 0 ? blocks : 1;
+}
 
-#define FQT_K_SWITCH(FN, ...)                                                         \
-  switch (k) {                                                                        \
-    case 1: if (multi) { FQT_TILE_SWITCH(FN, 1, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 1, false, __VA_ARGS__) } \
-    case 2: if (multi) { FQT_TILE_SWITCH(FN, 2, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 2, false, __VA_ARGS__) } \
-    case 3: if (multi) { FQT_TILE_SWITCH(FN, 3, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 3, false, __VA_ARGS__) } \
-    case 4: if (multi) { FQT_TILE_SWITCH(FN, 4, true, __VA_ARGS__) } else { FQT_TILE_SWITCH(FN, 4, false, __VA_ARGS__) } \
-    default: return hipErrorInvalidValue;                                             \
+// Dispatch over (k, tile id, multi-block); the tile list is FQT_PACKED_TILES.
+#define FQT_TILE_CASE(ID, TM, TN, BK) \
+  case ID: return FN<KE, TM, TN, BK, MULTI>(ARGS);
+
+template <int KE, bool MULTI>
+static hipError_t dispatch_one(int tile, const GemmArgs& g, const PackedParams& pp,
+                               hipStream_t s) {
+#define FN launch_one
+#define ARGS g, pp, s
+  switch (tile) { FQT_PACKED_TILES(FQT_TILE_CASE) default: return hipErrorInvalidValue; }
+#undef FN
+#undef ARGS
+}
+
+template <int KE, bool MULTI>
+static hipError_t dispatch_batched(int tile, const GemmArgs* descs, const TileItem* items,
+                                   int32_t n_items, uint32_t* counter, int grid,
+                                   const PackedParams& pp, hipStream_t s) {
+#define FN launch_batched
+#define ARGS descs, items, n_items, counter, grid, pp, s
+  switch (tile) { FQT_PACKED_TILES(FQT_TILE_CASE) default: return hipErrorInvalidValue; }
+#undef FN
+#undef ARGS
+}
+
+template <int KE, bool MULTI>
+static int dispatch_occupancy(int tile, uint32_t tbl_log2) {
+#define FN occupancy
+#define ARGS tbl_log2
+  switch (tile) { FQT_PACKED_TILES(FQT_TILE_CASE) default: return 1; }
+#undef FN
+#undef ARGS
+}
+#undef FQT_TILE_CASE
+
+#define FQT_K_DISPATCH(F, ...)                                           \
+  switch (k) {                                                           \
+    case 1: return multi ? F<1, true>(__VA_ARGS__) : F<1, false>(__VA_ARGS__); \
+    case 2: return multi ? F<2, true>(__VA_ARGS__) : F<2, false>(__VA_ARGS__); \
+    case 3: return multi ? F<3, true>(__VA_ARGS__) : F<3, false>(__VA_ARGS__); \
+    case 4: return multi ? F<4, true>(__VA_ARGS__) : F<4, false>(__VA_ARGS__); \
+    default: break;                                                      \
   }
 
 hipError_t launch_gemm_packed(int k, int tile, bool multi, const GemmArgs& g,
                               const PackedParams& pp, hipStream_t s) {
-  FQT_K_SWITCH(launch_one, g, pp, s)
+  FQT_K_DISPATCH(dispatch_one, tile, g, pp, s)
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArgs* descs,
                                       const TileItem* items, int32_t n_items, uint32_t* counter,
                                       int grid, const PackedParams& pp, hipStream_t s) {
-  FQT_K_SWITCH(launch_batched, descs, items, n_items, counter, grid, pp, s)
+  FQT_K_DISPATCH(dispatch_batched, tile, descs, items, n_items, counter, grid, pp, s)
+  return hipErrorInvalidValue;
 }
 
 // Occupancy of the batched kernel (workgroups per CU) for the persistent grid.
 int packed_batched_occupancy(int k, int tile, bool multi, uint32_t tbl_log2) {
-  int blocks = 0;
-  const size_t dyn = 2u * (1u << tbl_log2) * sizeof(uint32_t);
-#define FQT_OCC(KE, TM, TN, MU)                                                              \
-  if (k == KE && tile_tm == TM && tile_tn == TN && multi == MU) {                           \
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(                                       \
-            &blocks, (const void*)gemm_packed_batched_kernel<KE, TM, TN, MU>, 256, dyn) !=  \
-        hipSuccess)                                                                          \
-      blocks = 1;                                                                            \
-  }
-  static const int tms[kPackedTiles] = {1, 2, 2, 4};
-  static const int tns[kPackedTiles] = {1, 2, 4, 4};
-  const int tile_tm = tms[tile - 1], tile_tn = tns[tile - 1];
-#define FQT_OCC_K(KE) FQT_OCC(KE, 1, 1, true) FQT_OCC(KE, 2, 2, true) FQT_OCC(KE, 2, 4, true) \
-  FQT_OCC(KE, 4, 4, true) FQT_OCC(KE, 1, 1, false) FQT_OCC(KE, 2, 2, false)                  \
-  FQT_OCC(KE, 2, 4, false) FQT_OCC(KE, 4, 4, false)
-  FQT_OCC_K(1) FQT_OCC_K(2) FQT_OCC_K(3) FQT_OCC_K(4)
-#undef FQT_OCC_K
-#undef FQT_OCC
-  return blocks > 0 ? blocks : 1;
+  FQT_K_DISPATCH(dispatch_occupancy, tile, tbl_log2)
+  return 1;
 }
 
 }  // namespace fqt

@@ -180,7 +180,7 @@ SHAPES = [(1, 1, 1), (17, 33, 45), (64, 64, 64), (100, 70, 300), (33, 130, 16), 
 
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-@pytest.mark.parametrize("tile", [1, 2, 3, 4])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 def test_gemm_packed_shapes(p, k, P, tile):
     for (M, N, K) in SHAPES:
         note(f"gemm packed GF({p}^{k}) tile={tile} {M}x{N}x{K}")
@@ -241,7 +241,7 @@ def test_gemm_cross_path_identity_medium():
     B = dev(rng.integers(0, p, size=(700, 260, k), dtype=np.uint8))
     note("gemm cross-path 300x260x700")
     outs = [host(fqt.gemm(f, A, B, path="plain"))]
-    for tile in (1, 2, 3, 4):
+    for tile in (1, 2, 3, 4, 5, 6):
         outs.append(host(fqt.gemm(f, A, B, path="packed", opts={"tile": tile})))
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
