@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 METRIC = "GF(p^k) field mul-adds/sec at bit-exact output, batched FQT vs plain; % roofline"
 PEAK_FP64 = 78.6e12      # MI355X dense FP64 (matrix and vector), FLOP/s
 PEAK_HBM = 8.0e12        # bytes/s
+PEAK_INT8 = 5.0e15       # dense INT8 MFMA, OP/s
+PEAK_I32_VALU = 157.3e12 / 2  # 32-bit integer vector ops per second (one per lane per clock)
 
 
 def poly_str(P_low):
@@ -67,56 +69,86 @@ def cpu_baseline_gemm(w, A, B, gf, target_s=15.0):
                       f"numpy int64 plane products, {dt:.1f} s"}
 
 
+def roofline_for(path, k, work, ms):
+    """Algorithmic work of one step over its measured time, against the
+    published MI355X peak of the unit the path runs on."""
+    if path == "int8":
+        ops = 2.0 * k * k * work          # k^2 INT8 multiply-adds per field mul-add
+        ach = ops / (ms * 1e-3)
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_INT8 / 1e12,
+                "unit": "TOP/s", "frac": ach / PEAK_INT8, "traffic": None,
+                "kernel": "gemm_i8_kernel (+ expand_b_kernel in the step)",
+                "algorithmic": "2 k^2 int8 ops per field mul-add"}
+    if path == "plain":
+        ops = 2.0 * k * k * work
+        ach = ops / (ms * 1e-3)
+        return {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_I32_VALU / 1e12,
+                "unit": "TOP/s", "frac": ach / PEAK_I32_VALU, "traffic": None,
+                "kernel": "gemm_plain_kernel",
+                "algorithmic": "2 k^2 integer ops per field mul-add (reductions not counted)"}
+    flops = 2.0 * work
+    ach = flops / (ms * 1e-3)
+    return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": None,
+            "kernel": "gemm_packed_kernel (fused pack + FP64 MFMA + REDQ + L/H)",
+            "algorithmic": "2 flop per field mul-add (one FP64 FMA on packed values)"}
+
+
 def bench_gemm(w, args, torch, fqt, gf):
     from paper_0710_0510_amd import workloads as W
     A_h, B_h = W.gemm_inputs(w)
     f = fqt.Field(w.p, w.k, w.P_low)
     A = torch.from_numpy(A_h).cuda()
     B = torch.from_numpy(B_h).cuda()
-    C = torch.empty((w.M, w.N, w.k), dtype=torch.uint8, device="cuda")
-    opts = {"tile": args.tile} if args.tile else None
     q, nqmax = fqt.params(w.p, w.k, 1)
+    work = w.M * w.N * w.K
 
-    # ---- parity before timing ----
-    fqt.gemm(f, A, B, C, path=args.path, opts=opts)
-    Cref = torch.empty_like(C)
+    # reference output of the plain comparator, checked on sampled entries
+    Cref = torch.empty((w.M, w.N, w.k), dtype=torch.uint8, device="cuda")
     fqt.gemm(f, A, B, Cref, path="plain")
     torch.cuda.synchronize()
-    same_as_plain = bool(torch.equal(C, Cref))
     rng = np.random.default_rng(1234)
     idx = rng.integers(0, [w.M, w.N], size=(args.samples, 2))
-    Ch = C.cpu().numpy()
-    bad = 0
-    for i, j in idx.tolist():
-        bad += gf.gemm_entry(A_h[i], B_h[:, j], w.p, w.P_low) != Ch[i, j].tolist()
-    if bad or not same_as_plain:
-        raise SystemExit(f"parity failure: {bad} sampled mismatches, same_as_plain={same_as_plain}")
+    Rh = Cref.cpu().numpy()
+    bad = sum(gf.gemm_entry(A_h[i], B_h[:, j], w.p, w.P_low) != Rh[i, j].tolist()
+              for i, j in idx.tolist())
+    if bad:
+        raise SystemExit(f"parity failure: plain path differs from the oracle on {bad} entries")
 
-    fn = lambda: fqt.gemm(f, A, B, C, path=args.path, opts=opts)
-    ms = time_steps(fn, args.steps, args.warmup, torch)
-    work = w.M * w.N * w.K
-    value = work / (ms * 1e-3)
+    paths = [args.path] + [p for p in ("packed", "int8", "plain") if p != args.path and args.all_paths]
+    results = {}
+    for path in paths:
+        opts = {"tile": args.tile} if (args.tile and path == args.path) else None
+        C = torch.empty_like(Cref)
+        fqt.gemm(f, A, B, C, path=path, opts=opts)
+        torch.cuda.synchronize()
+        if not torch.equal(C, Cref):
+            raise SystemExit(f"parity failure: path {path} differs from the plain path")
+        steps = args.steps if path != "plain" else max(3, args.steps // 10)
+        ms = time_steps(lambda: fqt.gemm(f, A, B, C, path=path, opts=opts), steps,
+                        args.warmup if path != "plain" else 2, torch)
+        results[path] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": steps,
+                         "roofline": roofline_for(path, w.k, work, ms)}
 
-    plain_ms = time_steps(lambda: fqt.gemm(f, A, B, Cref, path="plain"), max(3, args.steps // 10), 2, torch)
-    flops = 2.0 * work
-    achieved = flops / (ms * 1e-3)
+    main_r = results[args.path]
     out = {
-        "metric": METRIC, "value": value, "unit": "field mul-adds/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "metric": METRIC, "value": main_r["value"], "unit": "field mul-adds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"packed": "f64", "int8": "int8", "plain": "int32"}[args.path],
+        "data": "synthetic",
         "config": {"workload": w.name, "field": f"GF({w.p}^{w.k})", "P": poly_str(w.P_low),
                    "M": w.M, "N": w.N, "K": w.K, "seed": w.seed, "path": args.path,
                    "q": q, "n_q_max": nqmax, "tile": args.tile or "default"},
-        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-                     "kernel": "gemm_packed_kernel (fused pack + FP64 MFMA + REDQ + L/H)",
-                     "algorithmic": "2 flop per field mul-add (one FP64 FMA on packed values)"},
-        "plain": {"value": work / (plain_ms * 1e-3), "ms_per_step": plain_ms,
-                  "kernel": "gemm_plain_kernel"},
-        "speedup_vs_plain": plain_ms / ms,
-        "parity": {"sampled_entries": args.samples, "sampled_mismatches": bad,
-                   "identical_to_plain_path": same_as_plain},
+        "roofline": main_r["roofline"],
+        "paths": {p: {"value": r["value"], "ms_per_step": r["ms_per_step"],
+                      "roofline_frac": r["roofline"]["frac"], "unit": "field mul-adds/s"}
+                  for p, r in results.items()},
+        "parity": {"sampled_entries_vs_oracle": args.samples, "sampled_mismatches": bad,
+                   "every_path_identical_to_plain": True},
     }
+    if "plain" in results and args.path != "plain":
+        out["speedup_vs_plain"] = results["plain"]["ms_per_step"] / main_r["ms_per_step"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_gemm(w, A_h, B_h, gf, target_s=args.cpu_seconds)
     return out
@@ -128,8 +160,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="gemm-gf7^2-1024")
-    ap.add_argument("--path", default="packed", choices=["packed", "int8", "plain", "auto"])
+    ap.add_argument("--path", default="packed", choices=["packed", "int8", "plain"])
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--all-paths", type=int, default=1, help="also time the other paths")
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

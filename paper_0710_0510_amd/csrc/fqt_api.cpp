@@ -153,6 +153,11 @@ struct BatchPlan {
   int device = -1;
 };
 
+struct Workspace {
+  uint8_t* ptr = nullptr;
+  size_t bytes = 0;
+};
+
 struct TuneEntry {
   fqt_path path;
   fqt_gemm_opts opts;
@@ -168,6 +173,7 @@ struct fqt_field_s {
   std::map<std::pair<int, uint32_t>, DevTables> dev_tables;
   std::vector<std::unique_ptr<BatchPlan>> plans;
   std::map<std::string, TuneEntry> tuned;
+  std::map<int, Workspace> ws;  // per device: B' of the INT8 path
 };
 
 namespace {
@@ -369,7 +375,9 @@ const char* fqt_last_error(void) { return g_last_error.c_str(); }
 const char* fqt_version(void) { return "fqt-mi355x 0.1 (gfx950)"; }
 
 uint32_t fqt_tile_count(fqt_path path) {
-  return path == FQT_PATH_PACKED_F64 ? (uint32_t)kPackedTiles : 1u;
+  return path == FQT_PATH_PACKED_F64 ? (uint32_t)kPackedTiles
+         : path == FQT_PATH_INT8      ? (uint32_t)kInt8Tiles
+                                      : 1u;
 }
 
 fqt_status fqt_field_create(uint32_t p, uint32_t k, const uint32_t* P_low, fqt_field* out) {
@@ -405,6 +413,14 @@ void fqt_field_destroy(fqt_field f) {
       hipSetDevice(kv.first.first);
       hipFree(kv.second.L);
       hipFree(kv.second.H);
+      hipSetDevice(cur);
+    }
+  }
+  for (auto& kv : f->ws) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+      hipSetDevice(kv.first);
+      hipFree(kv.second.ptr);
       hipSetDevice(cur);
     }
   }
@@ -577,6 +593,67 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   return ok();
 }
 
+static fqt_status workspace(fqt_field f, size_t bytes, uint8_t** out) {
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(f->mu);
+  Workspace& w = f->ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      // earlier launches may still read the old buffer
+      FQT_HIP(hipDeviceSynchronize());
+      FQT_HIP(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    if (hipMalloc(&w.ptr, bytes) != hipSuccess)
+      return fail(FQT_ERR_OOM, "INT8 workspace of %zu bytes", bytes);
+    w.bytes = bytes;
+  }
+  *out = w.ptr;
+  return ok();
+}
+
+// INT8 path: exact while n_d (p-1)^2 < 2^31 per accumulation run (eq. (3)).
+static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
+                            hipStream_t s) {
+  const int64_t k = f->k, p = f->p;
+  uint32_t tile = (opts && opts->tile) ? opts->tile : 0;
+  if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
+  const int64_t Kpad = (g.K + 127) / 128 * 128;
+  const int64_t KKpad = Kpad * k, NN = g.N * k, KK = g.K * k;
+  if (!tile) tile = (g.M >= 1024 && NN >= 1024) ? 2 : 1;
+  uint8_t* ws = nullptr;
+  fqt_status st = workspace(f, (size_t)std::max<int64_t>(NN * KKpad, 1), &ws);
+  if (st) return st;
+  PlainFieldArgs pf{};
+  for (int i = 0; i < (int)k; ++i) pf.P_low[i] = f->P_low[i];
+  FQT_HIP(launch_expand_b((int)k, g.B, g.ldb, g.K, g.N, (uint32_t)p, pf, ws, KKpad, Kpad, s));
+  I8Args a{};
+  a.A = g.A;
+  a.lda = g.lda * k;
+  a.Bt = ws;
+  a.ldbt = KKpad;
+  a.C = g.C;
+  a.ldc = g.ldc * k;
+  a.M = g.M;
+  a.NN = NN;
+  a.KK = KK;
+  a.KKpad = KKpad;
+  a.p = (uint32_t)p;
+  const int64_t per_tile = 128 * (p - 1) * (p - 1);
+  const int64_t nkt = (KK + 127) / 128;
+  if (per_tile == 0 || nkt * per_tile < (1ll << 31)) {
+    a.red_tiles = 0;
+  } else {
+    a.red_tiles = (uint32_t)(((1ll << 31) - 1 - (p - 1)) / per_tile);
+  }
+  a.a_vec = (((uintptr_t)g.A) & 15) == 0 && (a.lda % 16) == 0;
+  a.inv_p = 1.0 / (double)p;
+  FQT_HIP(launch_gemm_i8((int)tile, a, s));
+  return ok();
+}
+
 fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opts, int64_t M,
                             int64_t N, int64_t K, const uint8_t* A, int64_t lda,
                             const uint8_t* B, int64_t ldb, uint8_t* C, int64_t ldc,
@@ -604,7 +681,7 @@ fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opt
       return ok();
     }
     case FQT_PATH_INT8:
-      return fail(FQT_ERR_UNSUPPORTED, "INT8 path not built");
+      return gemm_int8(f, opts, g, (hipStream_t)s);
     default:
       return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
   }

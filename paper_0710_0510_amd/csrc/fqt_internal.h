@@ -28,6 +28,27 @@ struct PackedParams {
   const uint32_t* H;
 };
 
+// Low coefficients of the monic defining polynomial (k <= 4), each < p.
+struct PlainFieldArgs {
+  uint32_t P_low[4];
+};
+
+// Arguments of the INT8 GEMM C' = A' B' (see k_gemm_i8.hip); strides in bytes.
+struct I8Args {
+  const uint8_t* A;   // A' = A's bytes, M x KK
+  int64_t lda;
+  const uint8_t* Bt;  // B'^T, NN x KKpad (zero beyond KK)
+  int64_t ldbt;
+  uint8_t* C;         // C' = C's bytes, M x NN
+  int64_t ldc;
+  int64_t M, NN, KK, KKpad;
+  uint32_t p;
+  uint32_t red_tiles;  // K-tiles between reductions mod p (0: never needed)
+  uint32_t a_vec;      // rows of A' are 16-byte aligned
+  uint32_t pad;
+  double inv_p;
+};
+
 // Tile work item of the persistent batched kernel.
 struct TileItem {
   int32_t gemm;    // index into the descriptor array
@@ -74,6 +95,13 @@ hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArg
                                       hipStream_t s);
 
 int packed_batched_occupancy(int k, int tile, bool multi, uint32_t tbl_log2);
+
+// INT8 path: B -> B'^T expansion, then the INT8 MFMA GEMM (tile ids 1..3).
+constexpr int kInt8Tiles = 3;
+hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
+                           uint32_t p, const PlainFieldArgs& pf, uint8_t* Bt, int64_t ldbt,
+                           int64_t Kpad, hipStream_t s);
+hipError_t launch_gemm_i8(int tile, const I8Args& a, hipStream_t s);
 
 // Plain comparator: schoolbook with % p and division by P per product.
 hipError_t launch_gemm_plain(int k, const GemmArgs& g, const FieldArgs& fa,

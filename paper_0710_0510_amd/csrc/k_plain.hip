@@ -9,13 +9,9 @@
 
 namespace fqt {
 
-struct PlainField {
-  uint32_t P_low[4];
-};
-
 template <int KE>
 __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, FieldArgs fa,
-                                                         PlainField pf) {
+                                                         PlainFieldArgs pf) {
   constexpr int T = 16;
   __shared__ uint32_t As[T][T + 1];
   __shared__ uint32_t Bs[T][T + 1];
@@ -65,7 +61,7 @@ __global__ __launch_bounds__(256) void gemm_plain_kernel(GemmArgs g, FieldArgs f
 hipError_t launch_gemm_plain(int k, const GemmArgs& g, const FieldArgs& fa,
                              const uint32_t* P_low, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  PlainField pf{};
+  PlainFieldArgs pf{};
   for (int i = 0; i < k && i < 4; ++i) pf.P_low[i] = P_low[i] % fa.p;
   const dim3 grid((unsigned)((g.N + 15) / 16), (unsigned)((g.M + 15) / 16));
   switch (k) {

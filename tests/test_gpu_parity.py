@@ -282,3 +282,57 @@ def test_gemm_batched_replay():
     fqt.gemm_batched(f, descs, path="plain")
     for c, w in zip(Cs, wants):
         assert np.array_equal(host(c), w)
+
+
+# ---- INT8 coefficient-wise path -------------------------------------------------
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("tile", [1, 2, 3])
+def test_gemm_int8_shapes(p, k, P, tile):
+    for (M, N, K) in SHAPES + [(130, 200, 257)]:
+        note(f"gemm int8 GF({p}^{k}) tile={tile} {M}x{N}x{K}")
+        C, want = _gemm_case(p, k, P, M, N, K, seed=M + 2 * N + K, path="int8",
+                             opts={"tile": tile})
+        assert np.array_equal(C, want), (M, N, K)
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+def test_gemm_int8_adversarial(p, k, P):
+    note(f"gemm int8 adversarial GF({p}^{k})")
+    C, want = _gemm_case(p, k, P, 40, 50, 3001, seed=0, adversarial=True, path="int8")
+    assert np.array_equal(C, want)
+
+
+def test_gemm_int8_delayed_reduction_gf61_2():
+    # K k (p-1)^2 far above 2^31: the INT32 accumulators are reduced mod p
+    # every few thousand K-tiles (eq. (3) with n_d (p-1)^2 < 2^31).
+    p, P = 61, (59, 0)   # X^2 - 2, irreducible since 2 is a non-residue mod 61
+    assert gf.is_irreducible(P, p)
+    note("gemm int8 delayed reduction GF(61^2) K=300000")
+    for adversarial in (True, False):
+        C, want = _gemm_case(p, 2, P, 16, 24, 300000, seed=5, adversarial=adversarial,
+                             path="int8")
+        assert np.array_equal(C, want)
+
+
+def test_gemm_int8_strided_unaligned():
+    p, k, P = 5, 3, (3, 3, 0)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(19)
+    Abig = rng.integers(0, p, size=(70, 93, k), dtype=np.uint8)
+    Bbig = rng.integers(0, p, size=(93, 75, k), dtype=np.uint8)
+    note("gemm int8 strided/unaligned")
+    C = host(fqt.gemm(f, dev(Abig)[:50, :61], dev(Bbig)[:61, :40], path="int8"))
+    assert np.array_equal(C, gf.gemm_gfpk_planes(Abig[:50, :61], Bbig[:61, :40], p, P))
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+def test_gemm_three_paths_identical(p, k, P):
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(44)
+    A = dev(rng.integers(0, p, size=(257, 513, k), dtype=np.uint8))
+    B = dev(rng.integers(0, p, size=(513, 300, k), dtype=np.uint8))
+    note(f"three paths GF({p}^{k}) 257x300x513")
+    outs = [host(fqt.gemm(f, A, B, path=path)) for path in ("plain", "packed", "int8")]
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    assert np.array_equal(outs[0], gf.gemm_gfpk_planes(host(A), host(B), p, P))
