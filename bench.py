@@ -29,6 +29,15 @@ PEAK_INT8 = 5.0e15       # dense INT8 MFMA, OP/s
 PEAK_I32_VALU = 157.3e12 / 2  # 32-bit integer vector ops per second (one per lane per clock)
 
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE scaled by a plain-copy calibration (profiles/ holds the summary).
+# Keyed by (workload, path, tile); valid only for the kernel version profiled.
+MEASURED_TRAFFIC = {
+    ("gemm-gf7^2-1024", "packed", 0): {"bytes": 21121024,
+                                        "source": "profiles/gemm_packed_gf7-2_1024.md"},
+}
+
+
 def poly_str(P_low):
     k = len(P_low)
     terms = [f"X^{k}"]
@@ -131,6 +140,11 @@ def bench_gemm(w, args, torch, fqt, gf):
                          "roofline": roofline_for(path, w.k, work, ms)}
 
     main_r = results[args.path]
+    tr = MEASURED_TRAFFIC.get((w.name, args.path, args.tile))
+    if tr:
+        main_r["roofline"]["traffic"] = tr["bytes"]
+        main_r["roofline"]["traffic_source"] = tr["source"]
+        main_r["roofline"]["algorithmic_bytes"] = (w.M * w.K + w.K * w.N + w.M * w.N) * w.k
     out = {
         "metric": METRIC, "value": main_r["value"], "unit": "field mul-adds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
@@ -154,6 +168,112 @@ def bench_gemm(w, args, torch, fqt, gf):
     return out
 
 
+def _aligned_views(torch, arrays, align=256):
+    """Pack a list of uint8 arrays into one device buffer; return (buffer,
+    list of (offset, shape))."""
+    offs, total = [], 0
+    for a in arrays:
+        offs.append(total)
+        total += (a.nbytes + align - 1) // align * align
+    host = np.zeros(max(total, 1), dtype=np.uint8)
+    for a, o in zip(arrays, offs):
+        host[o:o + a.nbytes] = a.reshape(-1)
+    return torch.from_numpy(host).cuda(), offs
+
+
+def bench_batched(w, args, torch, fqt, gf):
+    from paper_0710_0510_amd import workloads as W
+    mnk, As, Bs = W.batched_inputs(w)
+    f = fqt.Field(w.p, w.k, w.P_low)
+    k = w.k
+    dA, offA = _aligned_views(torch, As)
+    dB, offB = _aligned_views(torch, Bs)
+    Cshapes = [np.zeros((M, N, k), dtype=np.uint8) for (M, N, K) in mnk.tolist()]
+    dC, offC = _aligned_views(torch, Cshapes)
+    dR = torch.zeros_like(dC)
+
+    def descs_for(out):
+        arr = (fqt.GemmDesc * len(As))()
+        for i, (M, N, K) in enumerate(mnk.tolist()):
+            arr[i] = fqt.GemmDesc(M, N, K, K, N, N, dA.data_ptr() + offA[i],
+                                  dB.data_ptr() + offB[i], out.data_ptr() + offC[i])
+        return arr
+
+    dC_descs, dR_descs = descs_for(dC), descs_for(dR)
+    work = int((mnk[:, 0] * mnk[:, 1] * mnk[:, 2]).sum())
+
+    # plain comparator (one launch per product) is the reference
+    fqt.gemm_batched(f, dR_descs, path="plain")
+    torch.cuda.synchronize()
+    Rh = dR.cpu().numpy()
+    rng = np.random.default_rng(99)
+    bad = 0
+    picks = rng.integers(0, len(As), size=args.samples // 4 + 1)
+    for g in picks.tolist():
+        M, N, K = mnk[g]
+        C_g = Rh[offC[g]:offC[g] + M * N * k].reshape(M, N, k)
+        for i, j in rng.integers(0, [M, N], size=(4, 2)).tolist():
+            bad += gf.gemm_entry(As[g][i], Bs[g][:, j], w.p, w.P_low) != C_g[i, j].tolist()
+    if bad:
+        raise SystemExit(f"parity failure: plain path differs from the oracle on {bad} entries")
+
+    opts = {"tile": args.tile} if args.tile else None
+    fqt.gemm_batched(f, dC_descs, path="packed", opts=opts)
+    torch.cuda.synchronize()
+    if not torch.equal(dC, dR):
+        raise SystemExit("parity failure: batched packed path differs from the plain path")
+    ms = time_steps(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=opts),
+                    args.steps, args.warmup, torch)
+    plain_ms = time_steps(lambda: fqt.gemm_batched(f, dR_descs, path="plain"),
+                          max(2, args.steps // 10), 1, torch)
+    q, nqmax = fqt.params(w.p, w.k, 1)
+    out = {
+        "metric": METRIC, "value": work / (ms * 1e-3), "unit": "field mul-adds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "field": f"GF({w.p}^{w.k})", "P": poly_str(w.P_low),
+                   "count": len(As), "MNK_range": [w.lo, w.hi], "sum_MNK": work, "seed": w.seed,
+                   "path": "packed (persistent, hipGraph replay)", "q": q, "n_q_max": nqmax,
+                   "tile": args.tile or "default"},
+        "roofline": roofline_for("packed", k, work, ms),
+        "paths": {"packed": {"value": work / (ms * 1e-3), "ms_per_step": ms},
+                  "plain": {"value": work / (plain_ms * 1e-3), "ms_per_step": plain_ms,
+                            "launches_per_step": len(As)}},
+        "speedup_vs_plain": plain_ms / ms,
+        "parity": {"sampled_entries_vs_oracle": int(len(picks) * 4), "sampled_mismatches": bad,
+                   "identical_to_plain_path": True},
+    }
+    out["roofline"]["kernel"] = "gemm_packed_batched_kernel (persistent, fused pack + FP64 MFMA + REDQ + L/H)"
+    return out
+
+
+def bench_polymul(w, args, torch, fqt, gf):
+    from paper_0710_0510_amd import workloads as W
+    a_h, b_h = W.polymul_inputs(w)
+    a, b = torch.from_numpy(a_h).cuda(), torch.from_numpy(b_h).cuda()
+    c = fqt.polymul_batch(w.p, w.k, w.q, a, b)
+    torch.cuda.synchronize()
+    want = gf.polymul_batch(a_h, b_h, w.p)
+    if not np.array_equal(c.cpu().numpy(), want):
+        raise SystemExit("parity failure: polymul differs from the oracle")
+    ms = time_steps(lambda: fqt.polymul_batch(w.p, w.k, w.q, a, b, out=c), args.steps,
+                    args.warmup, torch)
+    work = w.n * w.k * w.k
+    nbytes = w.n * (2 * w.k + 2 * w.k - 1)
+    ach = nbytes / (ms * 1e-3)
+    return {
+        "metric": METRIC, "value": work / (ms * 1e-3), "unit": "GF(p) mul-adds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "p": w.p, "k": w.k, "q": w.q, "n": w.n, "seed": w.seed},
+        "products_per_s": w.n / (ms * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM, "traffic": None, "kernel": "polymul_kernel",
+                     "algorithmic": f"{2 * w.k} B in + {2 * w.k - 1} B out per product"},
+        "parity": {"full_output_vs_oracle": True},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,6 +286,8 @@ def main():
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
@@ -179,11 +301,23 @@ def main():
 
     if not torch.cuda.is_available():
         raise SystemExit("no GPU visible")
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
     fqt.lib()
     w = W.WORKLOADS[args.workload]
-    if w.kind != "gemm":
-        raise SystemExit(f"workload kind {w.kind} not benchmarked by this entry point yet")
-    out = bench_gemm(w, args, torch, fqt, gf)
+    if w.kind == "gemm":
+        out = bench_gemm(w, args, torch, fqt, gf)
+    elif w.kind == "batched":
+        out = bench_batched(w, args, torch, fqt, gf)
+    else:
+        out = bench_polymul(w, args, torch, fqt, gf)
     print(json.dumps(out), flush=True)
 
 
