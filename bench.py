@@ -224,6 +224,14 @@ def bench_batched(w, args, torch, fqt, gf):
         raise SystemExit("parity failure: batched packed path differs from the plain path")
     ms = time_steps(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=opts),
                     args.steps, args.warmup, torch)
+    dI = torch.zeros_like(dC)
+    dI_descs = descs_for(dI)
+    fqt.gemm_batched(f, dI_descs, path="int8")
+    torch.cuda.synchronize()
+    if not torch.equal(dI, dR):
+        raise SystemExit("parity failure: batched INT8 path differs from the plain path")
+    i8_ms = time_steps(lambda: fqt.gemm_batched(f, dI_descs, path="int8"), args.steps,
+                       args.warmup, torch)
     plain_ms = time_steps(lambda: fqt.gemm_batched(f, dR_descs, path="plain"),
                           max(2, args.steps // 10), 1, torch)
     q, nqmax = fqt.params(w.p, w.k, 1)
@@ -237,6 +245,8 @@ def bench_batched(w, args, torch, fqt, gf):
                    "tile": args.tile or "default"},
         "roofline": roofline_for("packed", k, work, ms),
         "paths": {"packed": {"value": work / (ms * 1e-3), "ms_per_step": ms},
+                  "int8": {"value": work / (i8_ms * 1e-3), "ms_per_step": i8_ms,
+                           "roofline_frac": roofline_for("int8", k, work, i8_ms)["frac"]},
                   "plain": {"value": work / (plain_ms * 1e-3), "ms_per_step": plain_ms,
                             "launches_per_step": len(As)}},
         "speedup_vs_plain": plain_ms / ms,

@@ -151,6 +151,10 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
   int device = -1;
+  // INT8 plans only
+  I8Batch* d_i8 = nullptr;
+  ExpandItem* d_exp = nullptr;
+  uint8_t* d_ws = nullptr;
 };
 
 struct Workspace {
@@ -431,6 +435,9 @@ void fqt_field_destroy(fqt_field f) {
     hipFree(pl->d_descs);
     hipFree(pl->d_items);
     hipFree(pl->d_counter);
+    hipFree(pl->d_i8);
+    hipFree(pl->d_exp);
+    hipFree(pl->d_ws);
   }
   delete f;
 }
@@ -614,6 +621,23 @@ static fqt_status workspace(fqt_field f, size_t bytes, uint8_t** out) {
   return ok();
 }
 
+// Alignment (16, 4 or 1 bytes) shared by every row start of a matrix.
+static uint32_t row_align(const void* base, int64_t row_bytes) {
+  const uintptr_t b = (uintptr_t)base;
+  if ((b & 15) == 0 && (row_bytes & 15) == 0) return 16;
+  if ((b & 3) == 0 && (row_bytes & 3) == 0) return 4;
+  return 1;
+}
+
+// K-tiles (128 bytes of K) between reductions mod p, 0 when the whole sum fits:
+// (p-1) + n (128 (p-1)^2) < 2^31 keeps every INT32 partial sum exact.
+static uint32_t i8_red_tiles(int64_t KK, int64_t p) {
+  const int64_t per_tile = 128 * (p - 1) * (p - 1);
+  const int64_t nkt = (KK + 127) / 128;
+  if (per_tile == 0 || nkt * per_tile < (1ll << 31)) return 0;
+  return (uint32_t)(((1ll << 31) - 1 - (p - 1)) / per_tile);
+}
+
 // INT8 path: exact while n_d (p-1)^2 < 2^31 per accumulation run (eq. (3)).
 static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
                             hipStream_t s) {
@@ -641,14 +665,8 @@ static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmAr
   a.KK = KK;
   a.KKpad = KKpad;
   a.p = (uint32_t)p;
-  const int64_t per_tile = 128 * (p - 1) * (p - 1);
-  const int64_t nkt = (KK + 127) / 128;
-  if (per_tile == 0 || nkt * per_tile < (1ll << 31)) {
-    a.red_tiles = 0;
-  } else {
-    a.red_tiles = (uint32_t)(((1ll << 31) - 1 - (p - 1)) / per_tile);
-  }
-  a.a_vec = (((uintptr_t)g.A) & 15) == 0 && (a.lda % 16) == 0;
+  a.red_tiles = i8_red_tiles(KK, p);
+  a.a_vec = row_align(g.A, a.lda);
   a.inv_p = 1.0 / (double)p;
   FQT_HIP(launch_gemm_i8((int)tile, a, s));
   return ok();
@@ -786,6 +804,112 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
   return ok();
 }
 
+static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t count,
+                               const fqt_gemm_desc* descs, hipStream_t s) {
+  const int64_t k = f->k, p = f->p;
+  uint32_t tile = (opts && opts->tile) ? opts->tile : 1;
+  if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + 2 * sizeof(int));
+  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
+  const int tag[2] = {-(int)tile, dev};  // negative: INT8 plans never match packed ones
+  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, tag, sizeof tag);
+
+  std::lock_guard<std::mutex> lk(f->mu);
+  BatchPlan* plan = nullptr;
+  for (auto& pp : f->plans)
+    if (pp->key == key) plan = pp.get();
+  if (!plan) {
+    const int bm = tile == 2 ? 128 : 64, bn = tile == 1 ? 64 : 128;
+    std::vector<I8Batch> gs(count);
+    std::vector<ExpandItem> exps;
+    std::vector<TileItem> items;
+    size_t ws_total = 0;
+    std::vector<size_t> ws_off(count);
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      const int64_t Kpad = (d.K + 127) / 128 * 128;
+      ws_off[i] = ws_total;
+      ws_total += ((size_t)(d.N * k) * (size_t)(Kpad * k) + 255) / 256 * 256;
+    }
+    auto pl = std::make_unique<BatchPlan>();
+    pl->key = key;
+    pl->device = dev;
+    if (hipMalloc(&pl->d_ws, std::max<size_t>(ws_total, 256)) != hipSuccess)
+      return fail(FQT_ERR_OOM, "INT8 batch workspace of %zu bytes", ws_total);
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      const int64_t Kpad = (d.K + 127) / 128 * 128;
+      I8Batch& b = gs[i];
+      b.a.A = d.A;
+      b.a.lda = d.lda * k;
+      b.a.Bt = pl->d_ws + ws_off[i];
+      b.a.ldbt = Kpad * k;
+      b.a.C = d.C;
+      b.a.ldc = d.ldc * k;
+      b.a.M = d.M;
+      b.a.NN = d.N * k;
+      b.a.KK = d.K * k;
+      b.a.KKpad = Kpad * k;
+      b.a.p = (uint32_t)p;
+      b.a.red_tiles = i8_red_tiles(d.K * k, p);
+      b.a.a_vec = row_align(d.A, d.lda * k);
+      b.a.inv_p = 1.0 / (double)p;
+      b.B = d.B;
+      b.ldb = d.ldb;
+      b.K = d.K;
+      b.N = d.N;
+      if (d.K && d.N)
+        for (int32_t lb = 0; lb < (int32_t)(Kpad / 32); ++lb)
+          for (int32_t nb = 0; nb < (int32_t)((d.N + 31) / 32); ++nb)
+            exps.push_back(ExpandItem{(int32_t)i, lb, nb, 0});
+      const int tm = (int)((d.M + bm - 1) / bm), tn = (int)((d.N * k + bn - 1) / bn);
+      for (int a = 0; a < tm; ++a)
+        for (int c = 0; c < tn; ++c) items.push_back(TileItem{(int32_t)i, a, c, 0});
+    }
+    std::stable_sort(items.begin(), items.end(), [&](const TileItem& x, const TileItem& y) {
+      return descs[x.gemm].K > descs[y.gemm].K;
+    });
+    pl->n_items = (int32_t)items.size();
+    FQT_HIP(hipMalloc(&pl->d_i8, sizeof(I8Batch) * count));
+    FQT_HIP(hipMalloc(&pl->d_exp, sizeof(ExpandItem) * std::max<size_t>(exps.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_items, sizeof(TileItem) * std::max<size_t>(items.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_counter, 2 * sizeof(uint32_t)));
+    FQT_HIP(hipMemcpy(pl->d_i8, gs.data(), sizeof(I8Batch) * count, hipMemcpyHostToDevice));
+    if (!exps.empty())
+      FQT_HIP(hipMemcpy(pl->d_exp, exps.data(), sizeof(ExpandItem) * exps.size(),
+                        hipMemcpyHostToDevice));
+    if (!items.empty())
+      FQT_HIP(hipMemcpy(pl->d_items, items.data(), sizeof(TileItem) * items.size(),
+                        hipMemcpyHostToDevice));
+    FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
+    hipDeviceProp_t prop;
+    FQT_HIP(hipGetDeviceProperties(&prop, dev));
+    pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * i8_batched_occupancy((int)tile),
+                                         std::max<int32_t>(pl->n_items, 1)));
+    PlainFieldArgs pf{};
+    for (int i = 0; i < (int)k; ++i) pf.P_low[i] = f->P_low[i];
+    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = launch_expand_b_batched((int)k, pl->d_i8, pl->d_exp, (int32_t)exps.size(),
+                                            (uint32_t)p, pf, pl->cap_stream);
+    if (le == hipSuccess && pl->n_items > 0)
+      le = launch_gemm_i8_batched((int)tile, pl->d_i8, pl->d_items, pl->n_items, pl->d_counter,
+                                  pl->grid, pl->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (le != hipSuccess) return hip_fail(le, "INT8 batched launch (capture)");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    pl->graph = graph;
+    FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
+    plan = pl.get();
+    f->plans.push_back(std::move(pl));
+  }
+  FQT_HIP(hipGraphLaunch(plan->exec, s));
+  return ok();
+}
+
 fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opts,
                                     int64_t count, const fqt_gemm_desc* descs, fqt_stream_t s) {
   if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
@@ -796,7 +920,21 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_o
     if (st) return fail(st, "descriptor %lld: %s", (long long)i, g_last_error.c_str());
   }
   if (count == 0) return ok();
-  if (path == FQT_PATH_AUTO) path = FQT_PATH_PACKED_F64;
+  if (path == FQT_PATH_AUTO) {
+    int64_t Mmax = 0, Nmax = 0, Kmax = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      Mmax = std::max(Mmax, descs[i].M);
+      Nmax = std::max(Nmax, descs[i].N);
+      Kmax = std::max(Kmax, descs[i].K);
+    }
+    std::lock_guard<std::mutex> lk(f->mu);
+    auto it = f->tuned.find(shape_key(f, count, Mmax, Nmax, Kmax));
+    path = FQT_PATH_PACKED_F64;
+    if (it != f->tuned.end()) {
+      path = it->second.path;
+      if (!opts) opts = &it->second.opts;
+    }
+  }
   switch (path) {
     case FQT_PATH_PACKED_F64:
       return batched_packed(f, opts, count, descs, (hipStream_t)s);
@@ -810,7 +948,7 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_o
       return ok();
     }
     case FQT_PATH_INT8:
-      return fail(FQT_ERR_UNSUPPORTED, "INT8 path not built");
+      return batched_int8(f, opts, count, descs, (hipStream_t)s);
     default:
       return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
   }
@@ -821,11 +959,179 @@ fqt_status fqt_gemm_gfpk_batched(fqt_field f, fqt_path path, int64_t count,
   return fqt_gemm_gfpk_batched_ex(f, path, nullptr, count, descs, s);
 }
 
+// ---- autotuner ---------------------------------------------------------------
+
+namespace {
+
+struct Candidate {
+  fqt_path path;
+  fqt_gemm_opts opts;
+};
+
+// Host copy of every C of the batch (rows of N*k bytes).
+fqt_status snapshot(const fqt_field_s* f, int64_t count, const fqt_gemm_desc* d,
+                    hipStream_t s, std::vector<uint8_t>* out) {
+  size_t total = 0;
+  for (int64_t i = 0; i < count; ++i) total += (size_t)(d[i].M * d[i].N) * f->k;
+  out->resize(total);
+  FQT_HIP(hipStreamSynchronize(s));
+  size_t off = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const size_t row = (size_t)d[i].N * f->k;
+    if (d[i].M && row) {
+      FQT_HIP(hipMemcpy2D(out->data() + off, row, d[i].C, (size_t)d[i].ldc * f->k, row,
+                          (size_t)d[i].M, hipMemcpyDeviceToHost));
+    }
+    off += row * (size_t)d[i].M;
+  }
+  return ok();
+}
+
+bool read_cache(const char* path, const std::string& key, TuneEntry* e) {
+  if (!path) return false;
+  FILE* fp = std::fopen(path, "r");
+  if (!fp) return false;
+  char line[512];
+  bool found = false;
+  while (std::fgets(line, sizeof line, fp)) {
+    char k[256];
+    int pth = 0;
+    unsigned lq = 0, nq = 0, tile = 0;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u",
+                    k, &pth, &lq, &nq, &tile) == 5 &&
+        key == k) {
+      e->path = (fqt_path)pth;
+      e->opts = fqt_gemm_opts{lq, nq, tile, 0};
+      found = true;  // the last matching line wins
+    }
+  }
+  std::fclose(fp);
+  return found;
+}
+
+}  // namespace
+
 fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
                         const char* cache_path, fqt_path* best_path, fqt_gemm_opts* best,
                         fqt_stream_t s) {
-  (void)f; (void)count; (void)descs; (void)cache_path; (void)best_path; (void)best; (void)s;
-  return fail(FQT_ERR_UNSUPPORTED, "autotuner not built");
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (count < 1 || !descs) return fail(FQT_ERR_INVALID_ARG, "empty problem");
+  int64_t Mmax = 0, Nmax = 0, Kmax = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const fqt_gemm_desc& d = descs[i];
+    fqt_status st = check_gemm_args(f, d.M, d.N, d.K, d.A, d.lda, d.B, d.ldb, d.C, d.ldc);
+    if (st) return fail(st, "descriptor %lld: %s", (long long)i, g_last_error.c_str());
+    Mmax = std::max(Mmax, d.M);
+    Nmax = std::max(Nmax, d.N);
+    Kmax = std::max(Kmax, d.K);
+  }
+  const std::string key = shape_key(f, count, Mmax, Nmax, Kmax);
+  TuneEntry cached;
+  if (read_cache(cache_path, key, &cached)) {
+    std::lock_guard<std::mutex> lk(f->mu);
+    f->tuned[key] = cached;
+    if (best_path) *best_path = cached.path;
+    if (best) *best = cached.opts;
+    return ok();
+  }
+
+  // Candidates: every packed tile at the largest q and one q below (fewer
+  // products per K-block), and every INT8 tile for single products.
+  std::vector<Candidate> cands;
+  const uint32_t bmax = max_pow2_b(f->k);
+  for (uint32_t b : {bmax, bmax - 1}) {
+    if (b < 1) continue;
+    for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t) {
+      fqt_gemm_opts o{b, 0, t, 0};
+      PackedChoice pc;
+      if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) != FQT_OK) continue;
+      if (t == 4 && f->k == 4 && pc.multi) continue;  // that variant spills registers
+      cands.push_back({FQT_PATH_PACKED_F64, o});
+    }
+  }
+  for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
+      cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0}});
+  if (cands.empty()) return fail(FQT_ERR_UNSUPPORTED, "no admissible candidate");
+
+  hipStream_t st = (hipStream_t)s;
+  auto run = [&](const Candidate& c) -> fqt_status {
+    if (count == 1) {
+      const fqt_gemm_desc& d = descs[0];
+      return fqt_gemm_gfpk_ex(f, c.path, &c.opts, d.M, d.N, d.K, d.A, d.lda, d.B, d.ldb, d.C,
+                              d.ldc, s);
+    }
+    return fqt_gemm_gfpk_batched_ex(f, c.path, &c.opts, count, descs, s);
+  };
+
+  hipEvent_t e0, e1;
+  FQT_HIP(hipEventCreate(&e0));
+  FQT_HIP(hipEventCreate(&e1));
+  std::vector<uint8_t> ref, cur;
+  double best_ms = 1e30;
+  size_t best_i = 0;
+  std::vector<double> times(cands.size(), 0.0);
+  fqt_status status = FQT_OK;
+  for (size_t i = 0; i < cands.size() && status == FQT_OK; ++i) {
+    status = run(cands[i]);  // warm-up: builds plans and graphs
+    if (status) break;
+    status = snapshot(f, count, descs, st, i == 0 ? &ref : &cur);
+    if (status) break;
+    if (i > 0 && cur != ref) {
+      status = fail(FQT_ERR_DEVICE, "autotune candidate %zu (path %d, q = 2^%u, tile %u) is not "
+                    "byte-identical to candidate 0", i, (int)cands[i].path, cands[i].opts.log2q,
+                    cands[i].opts.tile);
+      break;
+    }
+    // time enough replays to cover about 20 ms, at least three
+    int reps = 3;
+    if (hipEventRecord(e0, st) != hipSuccess) { status = fail(FQT_ERR_DEVICE, "event"); break; }
+    for (int r = 0; r < reps && status == FQT_OK; ++r) status = run(cands[i]);
+    if (status) break;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      status = fail(FQT_ERR_DEVICE, "event");
+      break;
+    }
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    double per = ms / reps;
+    if (per * reps < 20.0) {
+      reps = (int)std::min(200.0, std::ceil(20.0 / std::max(per, 1e-3)));
+      hipEventRecord(e0, st);
+      for (int r = 0; r < reps && status == FQT_OK; ++r) status = run(cands[i]);
+      if (status) break;
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      hipEventElapsedTime(&ms, e0, e1);
+      per = ms / reps;
+    }
+    times[i] = per;
+    if (per < best_ms) {
+      best_ms = per;
+      best_i = i;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (status) return status;
+
+  const Candidate& w = cands[best_i];
+  {
+    std::lock_guard<std::mutex> lk(f->mu);
+    f->tuned[key] = TuneEntry{w.path, w.opts};
+  }
+  if (cache_path) {
+    if (FILE* fp = std::fopen(cache_path, "a")) {
+      std::fprintf(fp,
+                   "{\"key\": \"%s\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u, "
+                   "\"ms\": %.6f, \"candidates\": %zu}\n",
+                   key.c_str(), (int)w.path, w.opts.log2q, w.opts.n_q, w.opts.tile, best_ms,
+                   cands.size());
+      std::fclose(fp);
+    }
+  }
+  if (best_path) *best_path = w.path;
+  if (best) *best = w.opts;
+  return ok();
 }
 
 }  // extern "C"

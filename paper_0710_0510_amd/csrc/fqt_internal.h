@@ -44,9 +44,21 @@ struct I8Args {
   int64_t M, NN, KK, KKpad;
   uint32_t p;
   uint32_t red_tiles;  // K-tiles between reductions mod p (0: never needed)
-  uint32_t a_vec;      // rows of A' are 16-byte aligned
+  uint32_t a_vec;      // alignment of A' rows and 16-byte columns: 16, 4 or 1
   uint32_t pad;
   double inv_p;
+};
+
+// One product of an INT8 batch: the GEMM arguments plus its source B.
+struct I8Batch {
+  I8Args a;
+  const uint8_t* B;
+  int64_t ldb, K, N;  // B is K x N elements, ldb elements per row
+};
+
+// One 32 x 32 block of the B -> B'^T expansion of a batch.
+struct ExpandItem {
+  int32_t gemm, lb, nb, pad;
 };
 
 // Tile work item of the persistent batched kernel.
@@ -102,6 +114,12 @@ hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int6
                            uint32_t p, const PlainFieldArgs& pf, uint8_t* Bt, int64_t ldbt,
                            int64_t Kpad, hipStream_t s);
 hipError_t launch_gemm_i8(int tile, const I8Args& a, hipStream_t s);
+hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* items,
+                                   int32_t n_items, uint32_t p, const PlainFieldArgs& pf,
+                                   hipStream_t s);
+hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* items,
+                                  int32_t n_items, uint32_t* counter, int grid, hipStream_t s);
+int i8_batched_occupancy(int tile);
 
 // Plain comparator: schoolbook with % p and division by P per product.
 hipError_t launch_gemm_plain(int k, const GemmArgs& g, const FieldArgs& fa,

@@ -29,15 +29,13 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ---- B -> B'^T expansion ------------------------------------------------------
 
-// One workgroup expands a 32 (l) x 32 (n) block of B.  Output row n*k+s holds,
+// Expand the 32 (l) x 32 (n) block of B at (l0, n0): output row n*k+s holds,
 // at column l*k+i, coefficient s of X^i * B[l][n] mod P.
 template <int KE>
-__global__ __launch_bounds__(256) void expand_b_kernel(const uint8_t* __restrict__ B, int64_t ldb,
-                                                       int64_t K, int64_t N, uint32_t p,
-                                                       PlainFieldArgs pf,
-                                                       uint8_t* __restrict__ Bt, int64_t ldbt) {
-  __shared__ uint8_t tile[32 * KE][32 * KE + 4];
-  const int64_t l0 = (int64_t)blockIdx.x * 32, n0 = (int64_t)blockIdx.y * 32;
+__device__ __forceinline__ void expand_block(const uint8_t* __restrict__ B, int64_t ldb, int64_t K,
+                                             int64_t N, uint32_t p, const PlainFieldArgs& pf,
+                                             uint8_t* __restrict__ Bt, int64_t ldbt, int64_t l0,
+                                             int64_t n0, uint8_t (*tile)[32 * KE + 4]) {
   for (int e = threadIdx.x; e < 32 * 32; e += 256) {
     const int ll = e >> 5, nl = e & 31;  // consecutive threads -> consecutive n (coalesced)
     const int64_t l = l0 + ll, n = n0 + nl;
@@ -62,12 +60,33 @@ __global__ __launch_bounds__(256) void expand_b_kernel(const uint8_t* __restrict
     }
   }
   __syncthreads();
-  // 32*KE output rows of 32*KE bytes each
   for (int e = threadIdx.x; e < 32 * KE * 32 * KE; e += 256) {
     const int r = e / (32 * KE), cc = e % (32 * KE);
     const int64_t orow = n0 * KE + r;
     if (orow < N * KE) Bt[orow * ldbt + l0 * KE + cc] = tile[r][cc];
   }
+}
+
+template <int KE>
+__global__ __launch_bounds__(256) void expand_b_kernel(const uint8_t* __restrict__ B, int64_t ldb,
+                                                       int64_t K, int64_t N, uint32_t p,
+                                                       PlainFieldArgs pf,
+                                                       uint8_t* __restrict__ Bt, int64_t ldbt) {
+  __shared__ uint8_t tile[32 * KE][32 * KE + 4];
+  expand_block<KE>(B, ldb, K, N, p, pf, Bt, ldbt, (int64_t)blockIdx.x * 32,
+                   (int64_t)blockIdx.y * 32, tile);
+}
+
+// Batched expansion: one workgroup per (product, 32 x 32 block) item.
+template <int KE>
+__global__ __launch_bounds__(256) void expand_b_batched_kernel(const I8Batch* __restrict__ gs,
+                                                               const ExpandItem* __restrict__ items,
+                                                               uint32_t p, PlainFieldArgs pf) {
+  __shared__ uint8_t tile[32 * KE][32 * KE + 4];
+  const ExpandItem it = items[blockIdx.x];
+  const I8Batch g = gs[it.gemm];
+  expand_block<KE>(g.B, g.ldb, g.K, g.N, p, pf, const_cast<uint8_t*>(g.a.Bt), g.a.ldbt,
+                   (int64_t)it.lb * 32, (int64_t)it.nb * 32, tile);
 }
 
 template <int KE>
@@ -117,10 +136,18 @@ __device__ __forceinline__ uint32_t mod_p_i32(int32_t x, uint32_t p, double inv_
 
 // 16 bytes of row `row` starting at byte column `col` of a matrix with `ld`
 // bytes per row and `rows` x `cols` valid bytes; missing bytes read as 0.
+// align: 16 or 4 when every row start and every 16-byte column offset is
+// aligned that far, else 1.
 __device__ __forceinline__ uint4 load16(const uint8_t* base, int64_t ld, int64_t row, int64_t col,
-                                        int64_t rows, int64_t cols, bool vec) {
-  if (vec && row < rows && col + 15 < cols)
-    return *reinterpret_cast<const uint4*>(base + row * ld + col);
+                                        int64_t rows, int64_t cols, uint32_t align) {
+  if (row < rows && col + 15 < cols) {
+    const uint8_t* src = base + row * ld + col;
+    if (align >= 16) return *reinterpret_cast<const uint4*>(src);
+    if (align >= 4) {
+      const uint32_t* w = reinterpret_cast<const uint32_t*>(src);
+      return make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  }
   uint32_t w[4] = {0, 0, 0, 0};
   if (row < rows) {
     const uint8_t* src = base + row * ld;
@@ -131,16 +158,12 @@ __device__ __forceinline__ uint4 load16(const uint8_t* base, int64_t ld, int64_t
 }
 
 template <int TM, int TN>
-__global__ __launch_bounds__(256) void gemm_i8_kernel(I8Args a, int tiles_n, int ntiles) {
+__device__ __forceinline__ void i8_tile(const I8Args& a, int64_t m0, int64_t n0,
+                                        uint8_t (*As)[I8T<TM, TN>::BM * I8T<TM, TN>::S],
+                                        uint8_t (*Bs)[I8T<TM, TN>::BN * I8T<TM, TN>::S]) {
   using T = I8T<TM, TN>;
-  __shared__ __attribute__((aligned(16))) uint8_t As[2][T::BM * T::S];
-  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][T::BN * T::S];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * 16 * TM, wn0 = (wave & 1) * 16 * TN;
-  int tile = blockIdx.x;
-  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-  const int64_t m0 = (int64_t)(tile / tiles_n) * T::BM;
-  const int64_t n0 = (int64_t)(tile % tiles_n) * T::BN;
   const int crow = tid >> 3, ccol = (tid & 7) * 16;  // chunk r: row crow + 32r, bytes ccol..+15
 
   v4i acc[TM][TN];
@@ -156,7 +179,7 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(I8Args a, int tiles_n, int
       ra[r] = load16(a.A, a.lda, m0 + crow + 32 * r, k0 + ccol, a.M, a.KK, a.a_vec);
 #pragma unroll
     for (int r = 0; r < T::RB; ++r)
-      rb[r] = load16(a.Bt, a.ldbt, n0 + crow + 32 * r, k0 + ccol, a.NN, a.KKpad, true);
+      rb[r] = load16(a.Bt, a.ldbt, n0 + crow + 32 * r, k0 + ccol, a.NN, a.KKpad, 16u);
   };
   auto lstore = [&](int buf) {
 #pragma unroll
@@ -222,6 +245,46 @@ __global__ __launch_bounds__(256) void gemm_i8_kernel(I8Args a, int tiles_n, int
 }
 
 template <int TM, int TN>
+__global__ __launch_bounds__(256) void gemm_i8_kernel(I8Args a, int tiles_n, int ntiles) {
+  using T = I8T<TM, TN>;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][T::BM * T::S];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][T::BN * T::S];
+  int tile = blockIdx.x;
+  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  i8_tile<TM, TN>(a, (int64_t)(tile / tiles_n) * T::BM, (int64_t)(tile % tiles_n) * T::BN, As, Bs);
+}
+
+// Persistent INT8 kernel over the tiles of a whole batch (atomic queue, the
+// last workgroup out resets it for the next launch).
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void gemm_i8_batched_kernel(const I8Batch* __restrict__ gs,
+                                                              const TileItem* __restrict__ items,
+                                                              int32_t n_items, uint32_t* counter) {
+  using T = I8T<TM, TN>;
+  __shared__ __attribute__((aligned(16))) uint8_t As[2][T::BM * T::S];
+  __shared__ __attribute__((aligned(16))) uint8_t Bs[2][T::BN * T::S];
+  __shared__ int32_t cur;
+  for (;;) {
+    if (threadIdx.x == 0) cur = (int32_t)atomicAdd(&counter[0], 1u);
+    __syncthreads();
+    const int32_t it = cur;
+    __syncthreads();
+    if (it >= n_items) break;
+    const TileItem ti = items[it];
+    const I8Args a = gs[ti.gemm].a;
+    i8_tile<TM, TN>(a, (int64_t)ti.tm * T::BM, (int64_t)ti.tn * T::BN, As, Bs);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t done = atomicAdd(&counter[1], 1u);
+    if (done == gridDim.x - 1) {
+      atomicExch(&counter[0], 0u);
+      atomicExch(&counter[1], 0u);
+    }
+  }
+}
+
+template <int TM, int TN>
 static hipError_t launch_i8(const I8Args& a, hipStream_t s) {
   using T = I8T<TM, TN>;
   const int tiles_m = (int)((a.M + T::BM - 1) / T::BM);
@@ -229,6 +292,56 @@ static hipError_t launch_i8(const I8Args& a, hipStream_t s) {
   const int ntiles = tiles_m * tiles_n;
   if (ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL((gemm_i8_kernel<TM, TN>), dim3(ntiles), dim3(256), 0, s, a, tiles_n, ntiles);
+  return hipGetLastError();
+}
+
+template <int TM, int TN>
+static hipError_t launch_i8_batched(const I8Batch* gs, const TileItem* items, int32_t n,
+                                    uint32_t* counter, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((gemm_i8_batched_kernel<TM, TN>), dim3(grid), dim3(256), 0, s, gs, items, n,
+                     counter);
+  return hipGetLastError();
+}
+
+template <int TM, int TN>
+static int occ_i8() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, (const void*)gemm_i8_batched_kernel<TM, TN>, 256, 0) != hipSuccess)
+    blocks = 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+int i8_batched_occupancy(int tile) {
+  switch (tile) {
+    case 1: return occ_i8<2, 2>();
+    case 2: return occ_i8<4, 4>();
+    case 3: return occ_i8<2, 4>();
+    default: return 1;
+  }
+}
+
+hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* items,
+                                  int32_t n_items, uint32_t* counter, int grid, hipStream_t s) {
+  switch (tile) {
+    case 1: return launch_i8_batched<2, 2>(gs, items, n_items, counter, grid, s);
+    case 2: return launch_i8_batched<4, 4>(gs, items, n_items, counter, grid, s);
+    case 3: return launch_i8_batched<2, 4>(gs, items, n_items, counter, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* items,
+                                   int32_t n_items, uint32_t p, const PlainFieldArgs& pf,
+                                   hipStream_t s) {
+  if (n_items == 0) return hipSuccess;
+  switch (k) {
+    case 1: hipLaunchKernelGGL(expand_b_batched_kernel<1>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
+    case 2: hipLaunchKernelGGL(expand_b_batched_kernel<2>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
+    case 3: hipLaunchKernelGGL(expand_b_batched_kernel<3>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
+    case 4: hipLaunchKernelGGL(expand_b_batched_kernel<4>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -276,6 +276,15 @@ def test_gemm_batched_replay():
         torch.cuda.synchronize()
         for c, w in zip(Cs, wants):
             assert np.array_equal(host(c), w)
+    for tile in (1, 2, 3):
+        for rep in range(2):
+            note(f"batched int8 tile {tile} replay {rep}")
+            for c in Cs:
+                c.zero_()
+            fqt.gemm_batched(f, descs, path="int8", opts={"tile": tile})
+            torch.cuda.synchronize()
+            for c, w in zip(Cs, wants):
+                assert np.array_equal(host(c), w)
     note("batched plain")
     for c in Cs:
         c.zero_()
@@ -336,3 +345,53 @@ def test_gemm_three_paths_identical(p, k, P):
     outs = [host(fqt.gemm(f, A, B, path=path)) for path in ("plain", "packed", "int8")]
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
     assert np.array_equal(outs[0], gf.gemm_gfpk_planes(host(A), host(B), p, P))
+
+
+# ---- autotuner ------------------------------------------------------------------
+
+def test_autotune_single_and_cache(tmp_path):
+    p, k, P = 5, 3, (3, 3, 0)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(61)
+    Ah = rng.integers(0, p, size=(200, 300, k), dtype=np.uint8)
+    Bh = rng.integers(0, p, size=(300, 150, k), dtype=np.uint8)
+    A, B = dev(Ah), dev(Bh)
+    C = torch.zeros((200, 150, k), dtype=torch.uint8, device="cuda")
+    descs = fqt.make_descs(f, [A], [B], [C])
+    cache = str(tmp_path / "tune.jsonl")
+    note("autotune single GEMM")
+    path, opts = fqt.autotune(f, descs, cache)
+    assert path in ("packed", "int8") and opts["tile"] >= 1
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"key"' in lines[0]
+    # second tuning reads the cache, writes nothing new
+    f2 = fqt.Field(p, k, P)
+    assert fqt.autotune(f2, fqt.make_descs(f2, [A], [B], [C]), cache) == (path, opts)
+    assert len(open(cache).read().strip().splitlines()) == 1
+    want = gf.gemm_gfpk_planes(Ah, Bh, p, P)
+    for field in (f, f2):
+        out = host(fqt.gemm(field, A, B, path="auto"))
+        assert np.array_equal(out, want)
+
+
+def test_autotune_batched():
+    p, k, P = 3, 4, (2, 0, 0, 2)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(62)
+    shapes = rng.integers(16, 120, size=(24, 3))
+    As, Bs, Cs, wants = [], [], [], []
+    for (M, N, K) in shapes.tolist():
+        a = rng.integers(0, p, size=(M, K, k), dtype=np.uint8)
+        b = rng.integers(0, p, size=(K, N, k), dtype=np.uint8)
+        As.append(dev(a)); Bs.append(dev(b))
+        Cs.append(torch.zeros((M, N, k), dtype=torch.uint8, device="cuda"))
+        wants.append(gf.gemm_gfpk_planes(a, b, p, P))
+    descs = fqt.make_descs(f, As, Bs, Cs)
+    note("autotune batched")
+    path, opts = fqt.autotune(f, descs)
+    assert path in ("packed", "int8") and opts["tile"] >= 1
+    for c in Cs:
+        c.zero_()
+    fqt.gemm_batched(f, descs, path="auto")
+    for c, w in zip(Cs, wants):
+        assert np.array_equal(host(c), w)

@@ -184,3 +184,18 @@ def test_unpack_pack_validation_errors():
     assert name(L.fqt_unpack_redq(f.handle, 64, v, 4, 0, 0, o, None)) == "FQT_ERR_UNSUPPORTED"
     assert name(L.fqt_pack(f.handle, 2 ** 30, v, 4, o, None)) == "FQT_ERR_BOUNDS"
     assert name(L.fqt_pack(f.handle, 1, v, 4, o, None)) == "FQT_ERR_INVALID_ARG"
+
+
+def test_autotune_argument_errors():
+    f = fqt.Field(7, 2, (1, 0))
+    L = fqt.lib()
+    name = lambda st: fqt.STATUS_NAMES[st]
+    assert name(L.fqt_autotune(f.handle, 0, None, None, None, None, None)) == "FQT_ERR_INVALID_ARG"
+    bad = (fqt.GemmDesc * 1)()
+    bad[0] = fqt.GemmDesc(4, 4, 8, 4, 4, 4, BOGUS, BOGUS + (1 << 30), BOGUS + (1 << 31))  # lda < K
+    assert name(L.fqt_autotune(f.handle, 1, bad, None, None, None, None)) == "FQT_ERR_INVALID_ARG"
+
+
+def test_tile_counts():
+    assert fqt.tile_count("packed") == 6
+    assert fqt.tile_count("int8") == 3
