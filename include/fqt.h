@@ -225,12 +225,17 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path,
 /* Time every admissible (path, q, n_q, tile) candidate on the given problem
  * (a single GEMM when count == 1, else a batch), require byte-identical
  * outputs across candidates (FQT_ERR_DEVICE with a message otherwise), and
- * remember the fastest for FQT_PATH_AUTO on this field and shape class.  The
- * winner is written to best (may be NULL) and appended to the JSON cache
- * file cache_path (may be NULL).  C buffers are overwritten. */
-fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
-                        const char* cache_path, fqt_path* best_path,
-                        fqt_gemm_opts* best, fqt_stream_t s);
+ * remember the fastest for FQT_PATH_AUTO on this field and shape class.
+ *   only        FQT_PATH_AUTO: candidates of every path; FQT_PATH_PACKED_F64 or
+ *               FQT_PATH_INT8: that path's candidates only (the tuned entry
+ *               is then stored for that path, and for AUTO only if none is).
+ *   cache_path  JSON-lines file (may be NULL): an entry with the same key is
+ *               reused without timing; a new winner is appended.
+ * The winner is written to best_path / best (may be NULL).  The C buffers of
+ * the descriptors are overwritten.  Timing uses HIP events on stream s. */
+fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count,
+                        const fqt_gemm_desc* descs, const char* cache_path,
+                        fqt_path* best_path, fqt_gemm_opts* best, fqt_stream_t s);
 
 /* Number of tile configurations of a path (ids 1..count). */
 uint32_t fqt_tile_count(fqt_path path);

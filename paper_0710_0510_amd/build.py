@@ -24,6 +24,8 @@ SOURCES = ["fqt_api.cpp", "k_transform.hip", "k_gemm_f64.hip", "k_gemm_i8.hip", 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep MFMA accumulators in VGPRs: no per-iteration AGPR copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]

@@ -344,7 +344,7 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
       int bm, bn;
       packed_tile_shape(id, &bm, &bn);
       const int64_t nt = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
-      if (nt >= 512) {
+      if (nt >= 256) {
         tile = (uint32_t)id;
         break;
       }
@@ -690,6 +690,12 @@ fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opt
       path = FQT_PATH_PACKED_F64;
     }
   }
+  if (!opts && (path == FQT_PATH_PACKED_F64 || path == FQT_PATH_INT8)) {
+    std::lock_guard<std::mutex> lk(f->mu);
+    auto it = f->tuned.find(shape_key(f, 1, M, N, K) +
+                            (path == FQT_PATH_INT8 ? "_int8" : "_packed"));
+    if (it != f->tuned.end()) opts = &it->second.opts;
+  }
   switch (path) {
     case FQT_PATH_PACKED_F64:
       return gemm_packed(f, opts, g, (hipStream_t)s);
@@ -935,6 +941,18 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_o
       if (!opts) opts = &it->second.opts;
     }
   }
+  if (!opts && (path == FQT_PATH_PACKED_F64 || path == FQT_PATH_INT8)) {
+    int64_t Mmax = 0, Nmax = 0, Kmax = 0;
+    for (int64_t i = 0; i < count; ++i) {
+      Mmax = std::max(Mmax, descs[i].M);
+      Nmax = std::max(Nmax, descs[i].N);
+      Kmax = std::max(Kmax, descs[i].K);
+    }
+    std::lock_guard<std::mutex> lk(f->mu);
+    auto it = f->tuned.find(shape_key(f, count, Mmax, Nmax, Kmax) +
+                            (path == FQT_PATH_INT8 ? "_int8" : "_packed"));
+    if (it != f->tuned.end()) opts = &it->second.opts;
+  }
   switch (path) {
     case FQT_PATH_PACKED_F64:
       return batched_packed(f, opts, count, descs, (hipStream_t)s);
@@ -1011,10 +1029,12 @@ bool read_cache(const char* path, const std::string& key, TuneEntry* e) {
 
 }  // namespace
 
-fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
+fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gemm_desc* descs,
                         const char* cache_path, fqt_path* best_path, fqt_gemm_opts* best,
                         fqt_stream_t s) {
   if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (only != FQT_PATH_AUTO && only != FQT_PATH_PACKED_F64 && only != FQT_PATH_INT8)
+    return fail(FQT_ERR_INVALID_ARG, "autotune covers the packed and INT8 paths");
   if (count < 1 || !descs) return fail(FQT_ERR_INVALID_ARG, "empty problem");
   int64_t Mmax = 0, Nmax = 0, Kmax = 0;
   for (int64_t i = 0; i < count; ++i) {
@@ -1025,11 +1045,14 @@ fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
     Nmax = std::max(Nmax, d.N);
     Kmax = std::max(Kmax, d.K);
   }
-  const std::string key = shape_key(f, count, Mmax, Nmax, Kmax);
+  const std::string key = shape_key(f, count, Mmax, Nmax, Kmax) +
+                          (only == FQT_PATH_AUTO ? "" : only == FQT_PATH_INT8 ? "_int8" : "_packed");
+  const std::string auto_key = shape_key(f, count, Mmax, Nmax, Kmax);
   TuneEntry cached;
   if (read_cache(cache_path, key, &cached)) {
     std::lock_guard<std::mutex> lk(f->mu);
     f->tuned[key] = cached;
+    if (!f->tuned.count(auto_key)) f->tuned[auto_key] = cached;
     if (best_path) *best_path = cached.path;
     if (best) *best = cached.opts;
     return ok();
@@ -1040,6 +1063,7 @@ fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
   std::vector<Candidate> cands;
   const uint32_t bmax = max_pow2_b(f->k);
   for (uint32_t b : {bmax, bmax - 1}) {
+    if (only == FQT_PATH_INT8) break;
     if (b < 1) continue;
     for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t) {
       fqt_gemm_opts o{b, 0, t, 0};
@@ -1049,7 +1073,8 @@ fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
       cands.push_back({FQT_PATH_PACKED_F64, o});
     }
   }
-  for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
+  if (only != FQT_PATH_PACKED_F64)
+    for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
       cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0}});
   if (cands.empty()) return fail(FQT_ERR_UNSUPPORTED, "no admissible candidate");
 
@@ -1118,6 +1143,7 @@ fqt_status fqt_autotune(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
   {
     std::lock_guard<std::mutex> lk(f->mu);
     f->tuned[key] = TuneEntry{w.path, w.opts};
+    if (only == FQT_PATH_AUTO || !f->tuned.count(auto_key)) f->tuned[auto_key] = TuneEntry{w.path, w.opts};
   }
   if (cache_path) {
     if (FILE* fp = std::fopen(cache_path, "a")) {

@@ -80,7 +80,7 @@ def lib() -> ctypes.CDLL:
         "fqt_gemm_gfpk_batched": (c_int, [vp, c_int, c_i64, ctypes.POINTER(GemmDesc), vp]),
         "fqt_gemm_gfpk_batched_ex": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_i64,
                                              ctypes.POINTER(GemmDesc), vp]),
-        "fqt_autotune": (c_int, [vp, c_i64, ctypes.POINTER(GemmDesc), ctypes.c_char_p,
+        "fqt_autotune": (c_int, [vp, c_int, c_i64, ctypes.POINTER(GemmDesc), ctypes.c_char_p,
                                  ctypes.POINTER(c_int), ctypes.POINTER(GemmOpts), vp]),
         "fqt_tile_count": (c_u32, [c_int]),
         "fqt_last_error": (ctypes.c_char_p, []),
@@ -250,10 +250,13 @@ def gemm_batched(field: Field, descs, path: str = "auto", opts=None, stream=None
                                           descs, _stream(stream)))
 
 
-def autotune(field: Field, descs, cache_path: Optional[str] = None, stream=None):
+def autotune(field: Field, descs, cache_path: Optional[str] = None, only: str = "auto",
+             stream=None):
+    """Tune (path, q, tile) on the problem described by ``descs``; ``only``
+    restricts the candidates to one path ("packed" or "int8")."""
     path = ctypes.c_int(0)
     best = GemmOpts()
-    _check(lib().fqt_autotune(field.handle, len(descs), descs,
+    _check(lib().fqt_autotune(field.handle, PATHS[only], len(descs), descs,
                               cache_path.encode() if cache_path else None, ctypes.byref(path),
                               ctypes.byref(best), _stream(stream)))
     return PATH_NAMES[path.value], {"log2q": best.log2q, "n_q": best.n_q, "tile": best.tile}

@@ -390,6 +390,8 @@ def test_autotune_batched():
     note("autotune batched")
     path, opts = fqt.autotune(f, descs)
     assert path in ("packed", "int8") and opts["tile"] >= 1
+    assert fqt.autotune(f, descs, only="packed")[0] == "packed"
+    assert fqt.autotune(f, descs, only="int8")[0] == "int8"
     for c in Cs:
         c.zero_()
     fqt.gemm_batched(f, descs, path="auto")

@@ -190,12 +190,19 @@ def test_autotune_argument_errors():
     f = fqt.Field(7, 2, (1, 0))
     L = fqt.lib()
     name = lambda st: fqt.STATUS_NAMES[st]
-    assert name(L.fqt_autotune(f.handle, 0, None, None, None, None, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_autotune(f.handle, 0, 0, None, None, None, None, None)) == "FQT_ERR_INVALID_ARG"
     bad = (fqt.GemmDesc * 1)()
     bad[0] = fqt.GemmDesc(4, 4, 8, 4, 4, 4, BOGUS, BOGUS + (1 << 30), BOGUS + (1 << 31))  # lda < K
-    assert name(L.fqt_autotune(f.handle, 1, bad, None, None, None, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_autotune(f.handle, 0, 1, bad, None, None, None, None)) == "FQT_ERR_INVALID_ARG"
 
 
 def test_tile_counts():
     assert fqt.tile_count("packed") == 6
     assert fqt.tile_count("int8") == 3
+
+
+def test_autotune_rejects_plain_only():
+    f = fqt.Field(7, 2, (1, 0))
+    d = (fqt.GemmDesc * 1)()
+    d[0] = fqt.GemmDesc(4, 4, 4, 4, 4, 4, BOGUS, BOGUS + (1 << 30), BOGUS + (1 << 31))
+    assert fqt.STATUS_NAMES[fqt.lib().fqt_autotune(f.handle, 3, 1, d, None, None, None, None)] == "FQT_ERR_INVALID_ARG"
