@@ -96,7 +96,12 @@ typedef struct {
                       largest eq. (2) allows for q */
   uint32_t tile;   /* kernel tile configuration id (see fqt_tile_count); 0 =
                       default for the shape */
-  uint32_t reserved;
+  uint32_t boundary; /* packed path, K > n_q: step at each K-block boundary.
+                        0 = default (1); 1 = REDQ residues of the block (Alg. 2,
+                        first part); 2 = the block's q-adic digits (Alg. 1's
+                        radix conversion, bit fields for q = 2^b) with the
+                        reduction mod p delayed to the end (Section 6).  Both
+                        give identical bytes. */
 } fqt_gemm_opts;
 
 /* ---- field handle (Section 7: GF(p^k) = GF(p)[X]/(P)) ------------------- */

@@ -304,6 +304,8 @@ struct PackedChoice {
   uint32_t nq;        // products per K-block actually used (multiple of 4)
   uint32_t tile;
   bool multi;
+  int mode;           // 0 single block, 1 REDQ residues, 2 digit sums
+  uint32_t fold;      // boundaries between folds of the 16-bit lanes (0: never)
 };
 
 fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t K, int64_t M,
@@ -327,11 +329,18 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   if (nq < 4)
     return fail(FQT_ERR_UNSUPPORTED, "n_q below 4 (q = 2^%u, p = %u, k = %u)", b, p, k);
   const bool multi = (uint64_t)K > nq;
+  const uint32_t bmode = (o && o->boundary) ? o->boundary : 1;
+  if (bmode > 2) return fail(FQT_ERR_INVALID_ARG, "unknown boundary mode %u", bmode);
+  uint32_t fold = 0;
   if (multi) {
+    // lanes grow by < 2p (residues) or by at most one block's digit bound per
+    // boundary; keep (p-1) + (fold+1) * growth below 2^16 (the +1 is the
+    // last block, added in the epilogue)
+    const uint64_t growth = bmode == 1 ? 2 * (uint64_t)p - 1 : nq * unit;
     const uint64_t nblocks = ((uint64_t)K + 15) / 16 * 16 / nq + 1;
-    if (nblocks * (2 * p - 1) >= 65536)
-      return fail(FQT_ERR_UNSUPPORTED, "too many K-blocks (%" PRIu64 ") for the residue lanes",
-                  nblocks);
+    const uint64_t cap = (65535 - (p - 1)) / std::max<uint64_t>(growth, 1);
+    if (cap < 2) return fail(FQT_ERR_UNSUPPORTED, "residue lanes too narrow for n_q = %" PRIu64, nq);
+    if (nblocks + 1 > cap) fold = (uint32_t)(cap - 1);
   }
   uint32_t tile = (o && o->tile) ? o->tile : 0;
   if (tile > (uint32_t)kPackedTiles) return fail(FQT_ERR_INVALID_ARG, "unknown tile id %u", tile);
@@ -354,6 +363,8 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   pc->nq = (uint32_t)nq;
   pc->tile = tile;
   pc->multi = multi;
+  pc->mode = multi ? (int)bmode : 0;
+  pc->fold = fold;
   return ok();
 }
 
@@ -593,10 +604,13 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   pp.tbl_log2 = f->tbl_log2;
   pp.aligned = ((((uintptr_t)g.A) | ((uintptr_t)g.B)) & 3) == 0 && (g.lda * f->k) % 4 == 0 &&
                (g.ldb * f->k) % 4 == 0;
+  pp.fold_blocks = pc.fold;
+  pp.qmask = (uint32_t)(q - 1);
+  pp.qmod = (uint32_t)(q % f->p);
   pp.fa = field_args(f, q);
   pp.L = dt.L;
   pp.H = dt.H;
-  FQT_HIP(launch_gemm_packed((int)f->k, (int)pc.tile, pc.multi, g, pp, s));
+  FQT_HIP(launch_gemm_packed((int)f->k, (int)pc.tile, pc.mode, g, pp, s));
   return ok();
 }
 
@@ -780,20 +794,23 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
     hipDeviceProp_t prop;
     FQT_HIP(hipGetDeviceProperties(&prop, dev));
-    const int occ = packed_batched_occupancy((int)f->k, (int)pc.tile, pc.multi, f->tbl_log2);
+    const int occ = packed_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2);
     pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * occ, pl->n_items));
     PackedParams pp{};
     pp.b = pc.b;
     pp.nq_groups = pc.nq / 4;
     pp.tbl_log2 = f->tbl_log2;
     pp.aligned = aligned;
+    pp.fold_blocks = pc.fold;
+    pp.qmask = (uint32_t)(q - 1);
+    pp.qmod = (uint32_t)(q % f->p);
     pp.fa = field_args(f, q);
     pp.L = dt.L;
     pp.H = dt.H;
     // Capture the persistent launch once; later calls replay the graph.
     FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.multi, pl->d_descs,
+    hipError_t le = launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
                                                pl->d_items, pl->n_items, pl->d_counter, pl->grid,
                                                pp, pl->cap_stream);
     hipGraph_t graph = nullptr;
@@ -1014,12 +1031,12 @@ bool read_cache(const char* path, const std::string& key, TuneEntry* e) {
   while (std::fgets(line, sizeof line, fp)) {
     char k[256];
     int pth = 0;
-    unsigned lq = 0, nq = 0, tile = 0;
-    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u",
-                    k, &pth, &lq, &nq, &tile) == 5 &&
+    unsigned lq = 0, nq = 0, tile = 0, bnd = 0;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u, \"boundary\": %u",
+                    k, &pth, &lq, &nq, &tile, &bnd) == 6 &&
         key == k) {
       e->path = (fqt_path)pth;
-      e->opts = fqt_gemm_opts{lq, nq, tile, 0};
+      e->opts = fqt_gemm_opts{lq, nq, tile, bnd};
       found = true;  // the last matching line wins
     }
   }
@@ -1065,13 +1082,15 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   for (uint32_t b : {bmax, bmax - 1}) {
     if (only == FQT_PATH_INT8) break;
     if (b < 1) continue;
-    for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t) {
-      fqt_gemm_opts o{b, 0, t, 0};
-      PackedChoice pc;
-      if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) != FQT_OK) continue;
-      if (t == 4 && f->k == 4 && pc.multi) continue;  // that variant spills registers
-      cands.push_back({FQT_PATH_PACKED_F64, o});
-    }
+    for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t)
+      for (uint32_t bm : {1u, 2u}) {
+        fqt_gemm_opts o{b, 0, t, bm};
+        PackedChoice pc;
+        if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) != FQT_OK) continue;
+        if (t == 4 && f->k == 4 && pc.multi) continue;  // that variant spills registers
+        if (!pc.multi && bm == 2) continue;              // one block: no boundary step
+        cands.push_back({FQT_PATH_PACKED_F64, o});
+      }
   }
   if (only != FQT_PATH_PACKED_F64)
     for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
@@ -1149,9 +1168,9 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
     if (FILE* fp = std::fopen(cache_path, "a")) {
       std::fprintf(fp,
                    "{\"key\": \"%s\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u, "
-                   "\"ms\": %.6f, \"candidates\": %zu}\n",
-                   key.c_str(), (int)w.path, w.opts.log2q, w.opts.n_q, w.opts.tile, best_ms,
-                   cands.size());
+                   "\"boundary\": %u, \"ms\": %.6f, \"candidates\": %zu}\n",
+                   key.c_str(), (int)w.path, w.opts.log2q, w.opts.n_q, w.opts.tile, w.opts.boundary,
+                   best_ms, cands.size());
       std::fclose(fp);
     }
   }

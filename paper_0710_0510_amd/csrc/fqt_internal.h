@@ -23,6 +23,10 @@ struct PackedParams {
   uint32_t nq_groups;  // K-block = 4*nq_groups products (MFMA k-groups of 4)
   uint32_t tbl_log2;   // each table has 2^tbl_log2 entries (k*cb)
   uint32_t aligned;    // rows of A and B start on 4-byte boundaries
+  uint32_t fold_blocks;  // block boundaries between folds of the lanes mod p (0: never)
+  uint32_t qmask;      // q - 1
+  uint32_t qmod;       // q mod p
+  uint32_t pad;
   FieldArgs fa;
   const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)
   const uint32_t* H;
@@ -98,15 +102,15 @@ hipError_t launch_polymul(int k, uint64_t q, int pow2, uint32_t b, const FieldAr
                           const uint8_t* a, const uint8_t* bb, size_t n, uint8_t* c,
                           hipStream_t s);
 
-hipError_t launch_gemm_packed(int k, int tile, bool multi, const GemmArgs& g,
+hipError_t launch_gemm_packed(int k, int tile, int mode, const GemmArgs& g,
                               const PackedParams& pp, hipStream_t s);
 
-hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArgs* descs,
+hipError_t launch_gemm_packed_batched(int k, int tile, int mode, const GemmArgs* descs,
                                       const TileItem* items, int32_t n_items,
                                       uint32_t* counter, int grid, const PackedParams& pp,
                                       hipStream_t s);
 
-int packed_batched_occupancy(int k, int tile, bool multi, uint32_t tbl_log2);
+int packed_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2);
 
 // INT8 path: B -> B'^T expansion, then the INT8 MFMA GEMM (tile ids 1..3).
 constexpr int kInt8Tiles = 3;

@@ -13,10 +13,17 @@
 // Delayed reduction across K-blocks (Section 6: the reduction "can be
 // delayed" while eq. (2) holds; how blocks combine is left open).  The
 // residue vector is linear in the digits modulo p (Thm. 2: u_i = sum_{j>=i}
-// mu_j q^(j-i) mod p), and L + H is linear in u, so block residues are summed
-// in 16-bit lanes and the tables are applied once at the end.  A block
-// boundary therefore costs one FMA for rop plus a shift and a 24-bit
-// multiply-add per digit; the accumulator restarts at the 2^52 bias.
+// mu_j q^(j-i) mod p), and L + H is linear in u, so the blocks' contributions
+// are summed in 16-bit lanes (folded mod p before they could overflow) and
+// the tables are applied once at the end.  Two exact boundary steps:
+//   MODE 1 (REDQ residues): Alg. 2's first part per block -- one FMA for rop,
+//     then a shift and a 24-bit multiply-add per digit; lanes sum u'_i.
+//   MODE 2 (digit sums): the radix conversion of Alg. 1 per block -- with
+//     q = 2^b the digits are bit fields of the accumulator, no division at
+//     all; lanes sum the digits, and at the end Horner's rule mod p turns the
+//     digit sums D_i into u_i = sum_{j>=i} D_j q^(j-i) mod p.
+// Either way the accumulator restarts at the 2^52 bias after a boundary.
+// MODE 0 is a single block (K <= n_q): no lanes at all.
 //
 // Layout: workgroup = 256 threads = 2 x 2 waves; wave tile 16TM x 16TN made of
 // TM x TN MFMA blocks of 16 x 16; workgroup tile BM x BN = 32TM x 32TN;
@@ -89,13 +96,14 @@ __device__ __forceinline__ uint32_t chunk_elem(const uint32_t (&raw)[KE], int e)
   return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
 }
 
-template <int KE, int TM, int TN, int BK, bool MULTI>
+template <int KE, int TM, int TN, int BK, int MODE>
 __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int tile_n,
                                             const PackedParams& pp, double* __restrict__ As,
                                             double* __restrict__ Bs,
                                             const uint32_t* __restrict__ Ls,
                                             const uint32_t* __restrict__ Hs) {
   using T = PT<KE, TM, TN, BK>;
+  constexpr bool MULTI = MODE != 0;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -185,6 +193,30 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
             (double)dqt_shift<KE>(chunk_elem<KE>(rb[r], e), b);
   };
 
+  // Lane words of one element: digit 2w in the low half, 2w+1 in the high.
+  auto digits_words = [&](double acc_v, uint32_t (&wd)[T::NW]) {
+    if constexpr (MODE == 2) {
+      const uint64_t rb = bits64(acc_v);
+#pragma unroll
+      for (int w = 0; w < T::NW; ++w) {
+        const uint32_t d0 = (uint32_t)(rb >> (b * (uint32_t)(2 * w))) & pp.qmask;
+        const uint32_t d1 =
+            (2 * w + 1 < T::ND) ? (uint32_t)(rb >> (b * (uint32_t)(2 * w + 1))) & pp.qmask : 0u;
+        wd[w] = d0 | (d1 << 16);
+      }
+    } else {
+      uint32_t t[T::ND];
+      redq_residues_biased<T::ND>(acc_v, b, pp.fa, t);
+#pragma unroll
+      for (int w = 0; w < T::NW; ++w) {
+        const uint32_t lo = t[2 * w];
+        const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
+        wd[w] = perm_b32(hi, lo, 0x0c040c00u);
+      }
+    }
+  };
+
+  uint32_t nbound = 0;
   auto boundary = [&]() {
     if constexpr (MULTI) {
 #pragma unroll
@@ -193,17 +225,28 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
         for (int j = 0; j < TN; ++j) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            uint32_t t[T::ND];
-            redq_residues_biased<T::ND>(acc[i][j][v], b, pp.fa, t);
+            uint32_t wd[T::NW];
+            digits_words(acc[i][j][v], wd);
 #pragma unroll
-            for (int w = 0; w < T::NW; ++w) {
-              const uint32_t lo = t[2 * w];
-              const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
-              W[i][j][v][w] += perm_b32(hi, lo, 0x0c040c00u);
-            }
+            for (int w = 0; w < T::NW; ++w) W[i][j][v][w] += wd[w];
           }
           acc[i][j] = bias;
         }
+      // fold the lanes mod p before another block could overflow them
+      if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
+        nbound = 0;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+              for (int w = 0; w < T::NW; ++w) {
+                const uint32_t x = W[i][j][v][w];
+                W[i][j][v][w] = mod_p_small(x & 0xffffu, pp.fa) | (mod_p_small(x >> 16, pp.fa) << 16);
+              }
+      }
     }
   };
 
@@ -250,19 +293,29 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        uint32_t t[T::ND];
-        redq_residues_biased<T::ND>(acc[i][j][v], b, fa, t);
         uint32_t u[T::ND];
         if constexpr (MULTI) {
+          uint32_t wd[T::NW];
+          digits_words(acc[i][j][v], wd);
+          uint32_t D[T::ND];
 #pragma unroll
           for (int w = 0; w < T::NW; ++w) {
-            const uint32_t lo = t[2 * w];
-            const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
-            const uint32_t tot = W[i][j][v][w] + perm_b32(hi, lo, 0x0c040c00u);
-            u[2 * w] = mod_p_small(tot & 0xffffu, fa);
-            if (2 * w + 1 < T::ND) u[2 * w + 1] = mod_p_small(tot >> 16, fa);
+            const uint32_t tot = W[i][j][v][w] + wd[w];
+            D[2 * w] = tot & 0xffffu;
+            if (2 * w + 1 < T::ND) D[2 * w + 1] = tot >> 16;
+          }
+          if constexpr (MODE == 2) {
+            // residues of the digit sums: u_i = (D_i + q u_{i+1}) mod p
+            u[T::ND - 1] = mod_p_small(D[T::ND - 1], fa);
+#pragma unroll
+            for (int d = T::ND - 2; d >= 0; --d) u[d] = mod_p_small(D[d] + pp.qmod * u[d + 1], fa);
+          } else {
+#pragma unroll
+            for (int d = 0; d < T::ND; ++d) u[d] = mod_p_small(D[d], fa);
           }
         } else {
+          uint32_t t[T::ND];
+          redq_residues_biased<T::ND>(acc[i][j][v], b, fa, t);
 #pragma unroll
           for (int d = 0; d < T::ND; ++d) {
             const uint32_t x = t[d] & 0xffu;
@@ -291,7 +344,7 @@ __device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls
   }
 }
 
-template <int KE, int TM, int TN, int BK, bool MULTI>
+template <int KE, int TM, int TN, int BK, int MODE>
 __global__ __launch_bounds__(256) void gemm_packed_kernel(GemmArgs g, PackedParams pp,
                                                           int tiles_n, int ntiles) {
   using T = PT<KE, TM, TN, BK>;
@@ -306,10 +359,10 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(GemmArgs g, PackedPara
   // a contiguous run of tiles so that its L2 serves shared A rows / B columns.
   int tile = blockIdx.x;
   if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-  packed_tile<KE, TM, TN, BK, MULTI>(g, tile / tiles_n, tile % tiles_n, pp, As, Bs, Ls, Hs);
+  packed_tile<KE, TM, TN, BK, MODE>(g, tile / tiles_n, tile % tiles_n, pp, As, Bs, Ls, Hs);
 }
 
-template <int KE, int TM, int TN, int BK, bool MULTI>
+template <int KE, int TM, int TN, int BK, int MODE>
 __global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
     const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items, int32_t n_items,
     uint32_t* counter, PackedParams pp) {
@@ -329,7 +382,7 @@ __global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
     if (it >= n_items) break;
     const TileItem ti = items[it];
     const GemmArgs g = descs[ti.gemm];
-    packed_tile<KE, TM, TN, BK, MULTI>(g, ti.tm, ti.tn, pp, As, Bs, Ls, Hs);
+    packed_tile<KE, TM, TN, BK, MODE>(g, ti.tm, ti.tn, pp, As, Bs, Ls, Hs);
   }
   // The last workgroup to leave resets the queue for the next launch (every
   // workgroup has made its final counter[0] increment before counter[1]).
@@ -343,7 +396,7 @@ __global__ __launch_bounds__(256) void gemm_packed_batched_kernel(
   }
 }
 
-template <int KE, int TM, int TN, int BK, bool MULTI>
+template <int KE, int TM, int TN, int BK, int MODE>
 static hipError_t launch_one(const GemmArgs& g, const PackedParams& pp, hipStream_t s) {
   using T = PT<KE, TM, TN, BK>;
   const int tiles_m = (int)((g.M + T::BM - 1) / T::BM);
@@ -351,27 +404,27 @@ static hipError_t launch_one(const GemmArgs& g, const PackedParams& pp, hipStrea
   const int ntiles = tiles_m * tiles_n;
   if (ntiles == 0) return hipSuccess;
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_packed_kernel<KE, TM, TN, BK, MULTI>), dim3(ntiles), dim3(256), dyn,
+  hipLaunchKernelGGL((gemm_packed_kernel<KE, TM, TN, BK, MODE>), dim3(ntiles), dim3(256), dyn,
                      s, g, pp, tiles_n, ntiles);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, int BK, bool MULTI>
+template <int KE, int TM, int TN, int BK, int MODE>
 static hipError_t launch_batched(const GemmArgs* descs, const TileItem* items, int32_t n_items,
                                  uint32_t* counter, int grid, const PackedParams& pp,
                                  hipStream_t s) {
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_packed_batched_kernel<KE, TM, TN, BK, MULTI>), dim3(grid), dim3(256),
+  hipLaunchKernelGGL((gemm_packed_batched_kernel<KE, TM, TN, BK, MODE>), dim3(grid), dim3(256),
                      dyn, s, descs, items, n_items, counter, pp);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, int BK, bool MULTI>
+template <int KE, int TM, int TN, int BK, int MODE>
 static int occupancy(uint32_t tbl_log2) {
   int blocks = 0;
   const size_t dyn = 2u * (1u << tbl_log2) * sizeof(uint32_t);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, (const void*)gemm_packed_batched_kernel<KE, TM, TN, BK, MULTI>, 256, dyn) !=
+          &blocks, (const void*)gemm_packed_batched_kernel<KE, TM, TN, BK, MODE>, 256, dyn) !=
       hipSuccess)
     blocks = 1;
   return blocks > 0 ? blocks : 1;
@@ -379,9 +432,9 @@ static int occupancy(uint32_t tbl_log2) {
 
 // Dispatch over (k, tile id, multi-block); the tile list is FQT_PACKED_TILES.
 #define FQT_TILE_CASE(ID, TM, TN, BK) \
-  case ID: return FN<KE, TM, TN, BK, MULTI>(ARGS);
+  case ID: return FN<KE, TM, TN, BK, MODE>(ARGS);
 
-template <int KE, bool MULTI>
+template <int KE, int MODE>
 static hipError_t dispatch_one(int tile, const GemmArgs& g, const PackedParams& pp,
                                hipStream_t s) {
 #define FN launch_one
@@ -391,7 +444,7 @@ static hipError_t dispatch_one(int tile, const GemmArgs& g, const PackedParams& 
 #undef ARGS
 }
 
-template <int KE, bool MULTI>
+template <int KE, int MODE>
 static hipError_t dispatch_batched(int tile, const GemmArgs* descs, const TileItem* items,
                                    int32_t n_items, uint32_t* counter, int grid,
                                    const PackedParams& pp, hipStream_t s) {
@@ -402,7 +455,7 @@ static hipError_t dispatch_batched(int tile, const GemmArgs* descs, const TileIt
 #undef ARGS
 }
 
-template <int KE, bool MULTI>
+template <int KE, int MODE>
 static int dispatch_occupancy(int tile, uint32_t tbl_log2) {
 #define FN occupancy
 #define ARGS tbl_log2
@@ -412,22 +465,29 @@ static int dispatch_occupancy(int tile, uint32_t tbl_log2) {
 }
 #undef FQT_TILE_CASE
 
-#define FQT_K_DISPATCH(F, ...)                                           \
-  switch (k) {                                                           \
-    case 1: return multi ? F<1, true>(__VA_ARGS__) : F<1, false>(__VA_ARGS__); \
-    case 2: return multi ? F<2, true>(__VA_ARGS__) : F<2, false>(__VA_ARGS__); \
-    case 3: return multi ? F<3, true>(__VA_ARGS__) : F<3, false>(__VA_ARGS__); \
-    case 4: return multi ? F<4, true>(__VA_ARGS__) : F<4, false>(__VA_ARGS__); \
-    default: break;                                                      \
+#define FQT_MODE_DISPATCH(F, KE, ...)                                         \
+  switch (mode) {                                                             \
+    case 0: return F<KE, 0>(__VA_ARGS__);                                     \
+    case 1: return F<KE, 1>(__VA_ARGS__);                                     \
+    case 2: return F<KE, 2>(__VA_ARGS__);                                     \
+    default: break;                                                           \
+  }
+#define FQT_K_DISPATCH(F, ...)                                                \
+  switch (k) {                                                                \
+    case 1: FQT_MODE_DISPATCH(F, 1, __VA_ARGS__) break;                       \
+    case 2: FQT_MODE_DISPATCH(F, 2, __VA_ARGS__) break;                       \
+    case 3: FQT_MODE_DISPATCH(F, 3, __VA_ARGS__) break;                       \
+    case 4: FQT_MODE_DISPATCH(F, 4, __VA_ARGS__) break;                       \
+    default: break;                                                           \
   }
 
-hipError_t launch_gemm_packed(int k, int tile, bool multi, const GemmArgs& g,
+hipError_t launch_gemm_packed(int k, int tile, int mode, const GemmArgs& g,
                               const PackedParams& pp, hipStream_t s) {
   FQT_K_DISPATCH(dispatch_one, tile, g, pp, s)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArgs* descs,
+hipError_t launch_gemm_packed_batched(int k, int tile, int mode, const GemmArgs* descs,
                                       const TileItem* items, int32_t n_items, uint32_t* counter,
                                       int grid, const PackedParams& pp, hipStream_t s) {
   FQT_K_DISPATCH(dispatch_batched, tile, descs, items, n_items, counter, grid, pp, s)
@@ -435,7 +495,7 @@ hipError_t launch_gemm_packed_batched(int k, int tile, bool multi, const GemmArg
 }
 
 // Occupancy of the batched kernel (workgroups per CU) for the persistent grid.
-int packed_batched_occupancy(int k, int tile, bool multi, uint32_t tbl_log2) {
+int packed_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2) {
   FQT_K_DISPATCH(dispatch_occupancy, tile, tbl_log2)
   return 1;
 }

@@ -40,7 +40,7 @@ class FqtError(RuntimeError):
 
 class GemmOpts(ctypes.Structure):
     _fields_ = [("log2q", ctypes.c_uint32), ("n_q", ctypes.c_uint32),
-                ("tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("tile", ctypes.c_uint32), ("boundary", ctypes.c_uint32)]
 
 
 class GemmDesc(ctypes.Structure):
@@ -210,7 +210,7 @@ def _opts(opts) -> Optional[ctypes.POINTER(GemmOpts)]:
     if isinstance(opts, GemmOpts):
         return ctypes.pointer(opts)
     return ctypes.pointer(GemmOpts(int(opts.get("log2q", 0)), int(opts.get("n_q", 0)),
-                                   int(opts.get("tile", 0)), 0))
+                                   int(opts.get("tile", 0)), int(opts.get("boundary", 0))))
 
 
 def _ld(t, k: int) -> int:
@@ -259,7 +259,8 @@ def autotune(field: Field, descs, cache_path: Optional[str] = None, only: str = 
     _check(lib().fqt_autotune(field.handle, PATHS[only], len(descs), descs,
                               cache_path.encode() if cache_path else None, ctypes.byref(path),
                               ctypes.byref(best), _stream(stream)))
-    return PATH_NAMES[path.value], {"log2q": best.log2q, "n_q": best.n_q, "tile": best.tile}
+    return PATH_NAMES[path.value], {"log2q": best.log2q, "n_q": best.n_q, "tile": best.tile,
+                                    "boundary": best.boundary}
 
 
 def tile_count(path: str) -> int:

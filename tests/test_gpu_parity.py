@@ -190,24 +190,47 @@ def test_gemm_packed_shapes(p, k, P, tile):
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
 @pytest.mark.parametrize("nq", [4, 8, 12, 20])
-def test_gemm_packed_multiblock(p, k, P, nq):
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_gemm_packed_multiblock(p, k, P, nq, boundary):
     q, nqmax = fqt.params(p, k, 1)
     if nq > nqmax:
         pytest.skip("n_q above the bound")
     for (M, N, K) in [(40, 50, 97), (64, 64, 256)]:
-        note(f"gemm packed multiblock GF({p}^{k}) n_q={nq} {M}x{N}x{K}")
-        C, want = _gemm_case(p, k, P, M, N, K, seed=nq, opts={"n_q": nq, "tile": 2})
+        note(f"gemm packed multiblock GF({p}^{k}) n_q={nq} boundary={boundary} {M}x{N}x{K}")
+        C, want = _gemm_case(p, k, P, M, N, K, seed=nq,
+                             opts={"n_q": nq, "tile": 2, "boundary": boundary})
         assert np.array_equal(C, want), (M, N, K)
 
 
+@pytest.mark.parametrize("boundary", [1, 2])
+@pytest.mark.parametrize("tile", [1, 4])
+def test_gemm_packed_lane_folding(boundary, tile):
+    # 10000 K-blocks of 4 products: the 16-bit lanes must be folded mod p
+    p, k, P = 7, 2, (1, 0)
+    for adversarial in (True, False):
+        note(f"gemm packed folding boundary={boundary} tile={tile} adversarial={adversarial}")
+        C, want = _gemm_case(p, k, P, 33, 40, 40000, seed=7, adversarial=adversarial,
+                             opts={"n_q": 4, "tile": tile, "boundary": boundary})
+        assert np.array_equal(C, want)
+
+
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-def test_gemm_adversarial_bound(p, k, P):
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_gemm_adversarial_bound(p, k, P, boundary):
     q, nqmax = fqt.params(p, k, 1)
     nq4 = nqmax - nqmax % 4
     for K in [nq4, 3 * nq4 + 5]:
         K = min(K, 3000)
-        note(f"gemm adversarial GF({p}^{k}) K={K} n_q={nq4}")
-        C, want = _gemm_case(p, k, P, 32, 48, K, seed=0, adversarial=True, opts={"tile": 2})
+        note(f"gemm adversarial GF({p}^{k}) K={K} n_q={nq4} boundary={boundary}")
+        if boundary == 2 and K > nq4 and nq4 * k * (p - 1) ** 2 + p > 65535:
+            # one block's digit sums do not fit the 16-bit lanes: refused on the host
+            with pytest.raises(fqt.FqtError) as ei:
+                _gemm_case(p, k, P, 32, 48, K, seed=0, adversarial=True,
+                           opts={"tile": 2, "boundary": boundary})
+            assert ei.value.name == "FQT_ERR_UNSUPPORTED"
+            continue
+        C, want = _gemm_case(p, k, P, 32, 48, K, seed=0, adversarial=True,
+                             opts={"tile": 2, "boundary": boundary})
         assert np.array_equal(C, want)
 
 
