@@ -97,7 +97,8 @@ typedef struct {
   uint32_t tile;   /* kernel tile configuration id (see fqt_tile_count); 0 =
                       default for the shape */
   uint32_t boundary; /* packed path, K > n_q: step at each K-block boundary.
-                        0 = default (1); 1 = REDQ residues of the block (Alg. 2,
+                        0 = default (2 when q <= 2^12, else 1); 1 = REDQ
+                        residues of the block (Alg. 2,
                         first part); 2 = the block's q-adic digits (Alg. 1's
                         radix conversion, bit fields for q = 2^b) with the
                         reduction mod p delayed to the end (Section 6).  Both

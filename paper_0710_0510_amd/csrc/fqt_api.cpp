@@ -301,7 +301,8 @@ fqt_status check_gemm_args(const fqt_field_s* f, int64_t M, int64_t N, int64_t K
 // Resolved parameters of the packed path.
 struct PackedChoice {
   uint32_t b;
-  uint32_t nq;        // products per K-block actually used (multiple of 4)
+  uint32_t nq;        // MFMA slots per K-block (multiple of 4)
+  uint32_t nq_real;   // products per K-block (<= nq; the rest are zero slots)
   uint32_t tile;
   bool multi;
   int mode;           // 0 single block, 1 REDQ residues, 2 digit sums
@@ -325,20 +326,37 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   uint64_t nq = (o && o->n_q) ? o->n_q : nq_max;
   if (nq > nq_max)
     return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks q > n_q k (p-1)^2 for q = 2^%u", nq, b);
-  nq = std::min<uint64_t>(nq, 1u << 30) & ~3ull;  // whole MFMA k-groups
-  if (nq < 4)
+  nq = std::min<uint64_t>(nq, 1u << 30);
+  // Blocks are whole MFMA k-groups of 4 slots.  A block of n_q % 4 != 0
+  // products is padded with zero slots when the slot count divides every
+  // K-tile (8 or 16); otherwise n_q is rounded down to a multiple of 4.
+  uint64_t slots = nq & ~3ull, real = slots;
+  if (nq % 4 && (K > (int64_t)nq) && ((nq + 3) / 4 * 4 == 8 || (nq + 3) / 4 * 4 == 16)) {
+    slots = (nq + 3) / 4 * 4;
+    real = nq;
+  }
+  if (slots < 4)
     return fail(FQT_ERR_UNSUPPORTED, "n_q below 4 (q = 2^%u, p = %u, k = %u)", b, p, k);
-  const bool multi = (uint64_t)K > nq;
-  const uint32_t bmode = (o && o->boundary) ? o->boundary : 1;
+  const bool multi = (uint64_t)K > real;
+  if (multi && b != bmax)
+    return fail(FQT_ERR_UNSUPPORTED, "several K-blocks need the largest q = 2^%u", bmax);
+  nq = slots;
+  // default: digit sums where their fields fit (2b <= 24), else REDQ residues
+  const uint32_t bmode = (o && o->boundary) ? o->boundary : (2 * b <= 24 ? 2u : 1u);
   if (bmode > 2) return fail(FQT_ERR_INVALID_ARG, "unknown boundary mode %u", bmode);
   uint32_t fold = 0;
   if (multi) {
     // lanes grow by < 2p (residues) or by at most one block's digit bound per
     // boundary; keep (p-1) + (fold+1) * growth below 2^16 (the +1 is the
     // last block, added in the epilogue)
-    const uint64_t growth = bmode == 1 ? 2 * (uint64_t)p - 1 : nq * unit;
-    const uint64_t nblocks = ((uint64_t)K + 15) / 16 * 16 / nq + 1;
-    const uint64_t cap = (65535 - (p - 1)) / std::max<uint64_t>(growth, 1);
+    // REDQ residues: 16-bit lanes grow by < 2p per block.  Digit sums: fields
+    // of 2b bits grow by at most the block's digit bound; they need 2b <= 24.
+    if (bmode == 2 && 2 * b > 24)
+      return fail(FQT_ERR_UNSUPPORTED, "digit-sum boundaries need q <= 2^12 (q = 2^%u)", b);
+    const uint64_t width = bmode == 1 ? 65535 : (1ull << (2 * b)) - 1;
+    const uint64_t growth = bmode == 1 ? 2 * (uint64_t)p - 1 : real * unit;
+    const uint64_t nblocks = ((uint64_t)K + real - 1) / real + 8;
+    const uint64_t cap = (width - (p - 1)) / std::max<uint64_t>(growth, 1);
     if (cap < 2) return fail(FQT_ERR_UNSUPPORTED, "residue lanes too narrow for n_q = %" PRIu64, nq);
     if (nblocks + 1 > cap) fold = (uint32_t)(cap - 1);
   }
@@ -349,7 +367,7 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
     static const int pref[] = {4, 3, 2, 5, 6, 1};
     tile = 1;
     for (int id : pref) {
-      if (id == 4 && k == 4 && multi) continue;  // 4x4 blocks + k = 4 lanes spill registers
+      if (id == 4 && k >= 3 && multi && bmode == 1) continue;  // that variant spills registers
       int bm, bn;
       packed_tile_shape(id, &bm, &bn);
       const int64_t nt = ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
@@ -361,6 +379,7 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   }
   pc->b = b;
   pc->nq = (uint32_t)nq;
+  pc->nq_real = (uint32_t)real;
   pc->tile = tile;
   pc->multi = multi;
   pc->mode = multi ? (int)bmode : 0;
@@ -607,6 +626,7 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   pp.fold_blocks = pc.fold;
   pp.qmask = (uint32_t)(q - 1);
   pp.qmod = (uint32_t)(q % f->p);
+  pp.blk_real = pc.nq_real;
   pp.fa = field_args(f, q);
   pp.L = dt.L;
   pp.H = dt.H;
@@ -804,6 +824,7 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     pp.fold_blocks = pc.fold;
     pp.qmask = (uint32_t)(q - 1);
     pp.qmod = (uint32_t)(q % f->p);
+    pp.blk_real = pc.nq_real;
     pp.fa = field_args(f, q);
     pp.L = dt.L;
     pp.H = dt.H;
@@ -1082,12 +1103,16 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   for (uint32_t b : {bmax, bmax - 1}) {
     if (only == FQT_PATH_INT8) break;
     if (b < 1) continue;
+    const uint64_t unit_nq = (uint64_t)f->k * (f->p - 1) * (f->p - 1);
+    const uint32_t nq_top = unit_nq ? (uint32_t)std::min<uint64_t>(((1ull << b) - 1) / unit_nq, 1u << 30) : 0;
     for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t)
-      for (uint32_t bm : {1u, 2u}) {
-        fqt_gemm_opts o{b, 0, t, bm};
+      for (uint32_t bm : {1u, 2u})
+      for (uint32_t nqc : {0u, nq_top & ~3u}) {
+        if (nqc && nqc == nq_top) continue;  // same as the default
+        fqt_gemm_opts o{b, nqc, t, bm};
         PackedChoice pc;
         if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) != FQT_OK) continue;
-        if (t == 4 && f->k == 4 && pc.multi) continue;  // that variant spills registers
+        if (t == 4 && f->k >= 3 && pc.mode == 1) continue;  // that variant spills registers
         if (!pc.multi && bm == 2) continue;              // one block: no boundary step
         cands.push_back({FQT_PATH_PACKED_F64, o});
       }

@@ -26,7 +26,7 @@ struct PackedParams {
   uint32_t fold_blocks;  // block boundaries between folds of the lanes mod p (0: never)
   uint32_t qmask;      // q - 1
   uint32_t qmod;       // q mod p
-  uint32_t pad;
+  uint32_t blk_real;   // products per K-block (< 4*nq_groups: padded blocks)
   FieldArgs fa;
   const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)
   const uint32_t* H;

@@ -20,8 +20,11 @@
 //     then a shift and a 24-bit multiply-add per digit; lanes sum u'_i.
 //   MODE 2 (digit sums): the radix conversion of Alg. 1 per block -- with
 //     q = 2^b the digits are bit fields of the accumulator, no division at
-//     all; lanes sum the digits, and at the end Horner's rule mod p turns the
-//     digit sums D_i into u_i = sum_{j>=i} D_j q^(j-i) mod p.
+//     all.  The block's bits masked to its even digits are added into one
+//     64-bit integer E, those of its odd digits into O: every digit field then
+//     has b empty bits above it, so digit sums up to q^2 - 1 never carry into
+//     the next field (2b <= 24 here).  At the end Horner's rule mod p turns
+//     the digit sums D_i into u_i = sum_{j>=i} D_j q^(j-i) mod p.
 // Either way the accumulator restarts at the 2^52 bias after a boundary.
 // MODE 0 is a single block (K <= n_q): no lanes at all.
 //
@@ -112,9 +115,15 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   const int64_t m0 = (int64_t)tile_m * T::BM;
   const int64_t n0 = (int64_t)tile_n * T::BN;
   const bool aligned = pp.aligned != 0;
-  const uint32_t b = pp.b;
+  // Several K-blocks: q is the largest power of two eq. (2) admits, fixed at
+  // compile time so that digit windows become constant bit-field extracts.
+  constexpr uint32_t BQ = MODE ? 52u / (2u * KE - 1u) : 0u;
+  const uint32_t b = BQ ? BQ : pp.b;
   // Interior tiles (and full K-tiles) load without bounds checks.
   const bool interior = aligned && m0 + T::BM <= g.M && n0 + T::BN <= g.N;
+  // Padded K-blocks: blk_real products in blk_slots = 4 * nq_groups MFMA
+  // slots, the last slots of a block zero (blk_slots divides BK).
+  const bool padded = MULTI && pp.blk_real != 4 * pp.nq_groups;
 
   const v4d bias = {kTwo52, kTwo52, kTwo52, kTwo52};
   v4d acc[TM][TN];
@@ -123,8 +132,30 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = bias;
 
-  uint32_t W[MULTI ? TM : 1][MULTI ? TN : 1][4][MULTI ? T::NW : 1];
-  if constexpr (MULTI) {
+  // MODE 2: gapped digit sums, even digits in E, odd digits in O.
+  constexpr bool GAPPED = MODE == 2;
+  constexpr uint64_t QM = BQ ? (1ull << BQ) - 1 : 0;
+  constexpr uint64_t EM = [] {
+    uint64_t m = 0;
+    for (int d = 0; d < T::ND; d += 2) m |= QM << (BQ * d);
+    return m;
+  }();
+  constexpr uint64_t OM = [] {
+    uint64_t m = 0;
+    for (int d = 1; d < T::ND; d += 2) m |= QM << (BQ * d);
+    return m;
+  }();
+  uint64_t E[GAPPED ? TM : 1][GAPPED ? TN : 1][4], O[GAPPED ? TM : 1][GAPPED ? TN : 1][4];
+  if constexpr (GAPPED) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) E[i][j][v] = O[i][j][v] = 0;
+  }
+  uint32_t W[MODE == 1 ? TM : 1][MODE == 1 ? TN : 1][4][MODE == 1 ? T::NW : 1];
+  if constexpr (MODE == 1) {
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -150,7 +181,51 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   uint32_t ra[T::RA][KE];
   uint32_t rb[T::RB][KE];
 
+  // Padded mode: this thread's A chunk starts at slot offset 4*akc of the
+  // K-tile, i.e. block a_blk of the tile, offset a_off in it; its B rows sit
+  // at slot offsets bkr + r*BRS.
+  const uint32_t slots = 4 * pp.nq_groups, real = pp.blk_real;
+  const uint32_t a_blk = padded ? (4u * akc) / slots : 0u, a_off = padded ? (4u * akc) % slots : 0u;
+  const int a_cnt = padded ? (int)min(4u, real - a_off) : 4;
+  auto gload_padded = [&](int64_t kt) {
+    const int64_t blk0 = kt * (T::BK / slots);  // first block of this K-tile
+    const int64_t ka = (blk0 + a_blk) * real + a_off;
+#pragma unroll
+    for (int r = 0; r < T::RA; ++r) {
+      const int64_t row = m0 + arow + r * ARS;
+#pragma unroll
+      for (int j = 0; j < KE; ++j) ra[r][j] = 0;
+      if (row < g.M) {
+        const uint8_t* src = g.A + row * g.lda * KE;
+        for (int e = 0; e < a_cnt; ++e) {
+          if (ka + e >= g.K) break;
+#pragma unroll
+          for (int c = 0; c < KE; ++c) {
+            const int jb = e * KE + c;
+            ra[r][jb >> 2] |= (uint32_t)src[(ka + e) * KE + c] << (8 * (jb & 3));
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < T::RB; ++r) {
+      const uint32_t sl = (uint32_t)(bkr + r * BRS);
+      const uint32_t off = sl % slots;
+      const int64_t krow = (blk0 + sl / slots) * real + off;
+      if (off < real) {
+        load_chunk<KE>(g.B, krow, n0 + 4 * bnc, g.K, g.N, g.ldb, aligned, rb[r]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < KE; ++j) rb[r][j] = 0;
+      }
+    }
+  };
+
   auto gload = [&](int64_t k0) {
+    if (padded) {
+      gload_padded(k0 / T::BK);
+      return;
+    }
     if (interior && k0 + T::BK <= g.K) {
       const uint8_t* a0 = pa + k0 * KE;
       const uint8_t* b0 = pb + (k0 / T::BK) * b_kstep;
@@ -193,27 +268,20 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
             (double)dqt_shift<KE>(chunk_elem<KE>(rb[r], e), b);
   };
 
-  // Lane words of one element: digit 2w in the low half, 2w+1 in the high.
-  auto digits_words = [&](double acc_v, uint32_t (&wd)[T::NW]) {
-    if constexpr (MODE == 2) {
-      const uint64_t rb = bits64(acc_v);
+  // REDQ residues of one element as lane words: digit 2w low, 2w+1 high.
+  auto residue_words = [&](double acc_v, uint32_t (&wd)[T::NW]) {
+    uint32_t t[T::ND];
+    redq_residues_biased<T::ND>(acc_v, b, pp.fa, t);
 #pragma unroll
-      for (int w = 0; w < T::NW; ++w) {
-        const uint32_t d0 = (uint32_t)(rb >> (b * (uint32_t)(2 * w))) & pp.qmask;
-        const uint32_t d1 =
-            (2 * w + 1 < T::ND) ? (uint32_t)(rb >> (b * (uint32_t)(2 * w + 1))) & pp.qmask : 0u;
-        wd[w] = d0 | (d1 << 16);
-      }
-    } else {
-      uint32_t t[T::ND];
-      redq_residues_biased<T::ND>(acc_v, b, pp.fa, t);
-#pragma unroll
-      for (int w = 0; w < T::NW; ++w) {
-        const uint32_t lo = t[2 * w];
-        const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
-        wd[w] = perm_b32(hi, lo, 0x0c040c00u);
-      }
+    for (int w = 0; w < T::NW; ++w) {
+      const uint32_t lo = t[2 * w];
+      const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
+      wd[w] = perm_b32(hi, lo, 0x0c040c00u);
     }
+  };
+  // digit field d of a gapped sum: bits [d*b, d*b + 2b)
+  auto field = [&](uint64_t x, int d) -> uint32_t {
+    return (uint32_t)(x >> (BQ * d)) & (uint32_t)((1ull << (2 * BQ)) - 1);
   };
 
   uint32_t nbound = 0;
@@ -225,14 +293,20 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
         for (int j = 0; j < TN; ++j) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            uint32_t wd[T::NW];
-            digits_words(acc[i][j][v], wd);
+            if constexpr (GAPPED) {
+              const uint64_t rb = bits64(acc[i][j][v]);
+              E[i][j][v] += rb & EM;
+              O[i][j][v] += rb & OM;
+            } else {
+              uint32_t wd[T::NW];
+              residue_words(acc[i][j][v], wd);
 #pragma unroll
-            for (int w = 0; w < T::NW; ++w) W[i][j][v][w] += wd[w];
+              for (int w = 0; w < T::NW; ++w) W[i][j][v][w] += wd[w];
+            }
           }
           acc[i][j] = bias;
         }
-      // fold the lanes mod p before another block could overflow them
+      // fold the sums mod p before another block could overflow them
       if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
         nbound = 0;
 #pragma unroll
@@ -240,17 +314,33 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
           for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
+            for (int v = 0; v < 4; ++v) {
+              if constexpr (GAPPED) {
+                uint64_t e = 0, o = 0;
 #pragma unroll
-              for (int w = 0; w < T::NW; ++w) {
-                const uint32_t x = W[i][j][v][w];
-                W[i][j][v][w] = mod_p_small(x & 0xffffu, pp.fa) | (mod_p_small(x >> 16, pp.fa) << 16);
+                for (int d = 0; d < T::ND; ++d) {
+                  const uint64_t r = mod_p_small(field((d & 1) ? O[i][j][v] : E[i][j][v], d), pp.fa);
+                  if (d & 1) o |= r << (BQ * d);
+                  else e |= r << (BQ * d);
+                }
+                E[i][j][v] = e;
+                O[i][j][v] = o;
+              } else {
+#pragma unroll
+                for (int w = 0; w < T::NW; ++w) {
+                  const uint32_t x = W[i][j][v][w];
+                  W[i][j][v][w] =
+                      mod_p_small(x & 0xffffu, pp.fa) | (mod_p_small(x >> 16, pp.fa) << 16);
+                }
               }
+            }
       }
     }
   };
 
-  const int64_t nkt = (g.K + T::BK - 1) / T::BK;
+  // K-tiles cover K products, or ceil(K / real) padded blocks of `slots`.
+  const int64_t kslots = padded ? (g.K + real - 1) / real * slots : g.K;
+  const int64_t nkt = (kslots + T::BK - 1) / T::BK;
   uint32_t gcnt = 0;
   if (nkt > 0) {
     gload(0);
@@ -294,24 +384,23 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         uint32_t u[T::ND];
-        if constexpr (MULTI) {
+        if constexpr (GAPPED) {
+          // digit sums D_d of all blocks (the last one included), then
+          // residues u_d = (D_d + q u_{d+1}) mod p
+          const uint64_t rb = bits64(acc[i][j][v]);
+          const uint64_t e = E[i][j][v] + (rb & EM), o = O[i][j][v] + (rb & OM);
+          u[T::ND - 1] = mod_p_small(field(((T::ND - 1) & 1) ? o : e, T::ND - 1), fa);
+#pragma unroll
+          for (int d = T::ND - 2; d >= 0; --d)
+            u[d] = mod_p_small(field((d & 1) ? o : e, d) + pp.qmod * u[d + 1], fa);
+        } else if constexpr (MODE == 1) {
           uint32_t wd[T::NW];
-          digits_words(acc[i][j][v], wd);
-          uint32_t D[T::ND];
+          residue_words(acc[i][j][v], wd);
 #pragma unroll
           for (int w = 0; w < T::NW; ++w) {
             const uint32_t tot = W[i][j][v][w] + wd[w];
-            D[2 * w] = tot & 0xffffu;
-            if (2 * w + 1 < T::ND) D[2 * w + 1] = tot >> 16;
-          }
-          if constexpr (MODE == 2) {
-            // residues of the digit sums: u_i = (D_i + q u_{i+1}) mod p
-            u[T::ND - 1] = mod_p_small(D[T::ND - 1], fa);
-#pragma unroll
-            for (int d = T::ND - 2; d >= 0; --d) u[d] = mod_p_small(D[d] + pp.qmod * u[d + 1], fa);
-          } else {
-#pragma unroll
-            for (int d = 0; d < T::ND; ++d) u[d] = mod_p_small(D[d], fa);
+            u[2 * w] = mod_p_small(tot & 0xffffu, fa);
+            if (2 * w + 1 < T::ND) u[2 * w + 1] = mod_p_small(tot >> 16, fa);
           }
         } else {
           uint32_t t[T::ND];

@@ -195,6 +195,8 @@ def test_gemm_packed_multiblock(p, k, P, nq, boundary):
     q, nqmax = fqt.params(p, k, 1)
     if nq > nqmax:
         pytest.skip("n_q above the bound")
+    if boundary == 2 and q > 2 ** 12:
+        pytest.skip("digit-sum boundaries need q <= 2^12")
     for (M, N, K) in [(40, 50, 97), (64, 64, 256)]:
         note(f"gemm packed multiblock GF({p}^{k}) n_q={nq} boundary={boundary} {M}x{N}x{K}")
         C, want = _gemm_case(p, k, P, M, N, K, seed=nq,
@@ -202,15 +204,26 @@ def test_gemm_packed_multiblock(p, k, P, nq, boundary):
         assert np.array_equal(C, want), (M, N, K)
 
 
-@pytest.mark.parametrize("boundary", [1, 2])
 @pytest.mark.parametrize("tile", [1, 4])
-def test_gemm_packed_lane_folding(boundary, tile):
-    # 10000 K-blocks of 4 products: the 16-bit lanes must be folded mod p
+def test_gemm_packed_lane_folding_residues(tile):
+    # 10000 K-blocks of 4 products: the 16-bit residue lanes must be folded
     p, k, P = 7, 2, (1, 0)
     for adversarial in (True, False):
-        note(f"gemm packed folding boundary={boundary} tile={tile} adversarial={adversarial}")
+        note(f"gemm packed folding residues tile={tile} adversarial={adversarial}")
         C, want = _gemm_case(p, k, P, 33, 40, 40000, seed=7, adversarial=adversarial,
-                             opts={"n_q": 4, "tile": tile, "boundary": boundary})
+                             opts={"n_q": 4, "tile": tile, "boundary": 1})
+        assert np.array_equal(C, want)
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_gemm_packed_field_folding_digits(tile):
+    # GF(3^4), q = 2^7, blocks of 7: 14-bit digit fields hold 146 blocks of
+    # digit sums (7*16 each); K = 3000 is 429 blocks, so the fields are folded
+    p, k, P = 3, 4, (2, 0, 0, 2)
+    for adversarial in (True, False):
+        note(f"gemm packed folding digits tile={tile} adversarial={adversarial}")
+        C, want = _gemm_case(p, k, P, 33, 40, 3000, seed=8, adversarial=adversarial,
+                             opts={"tile": tile, "boundary": 2})
         assert np.array_equal(C, want)
 
 
@@ -222,8 +235,8 @@ def test_gemm_adversarial_bound(p, k, P, boundary):
     for K in [nq4, 3 * nq4 + 5]:
         K = min(K, 3000)
         note(f"gemm adversarial GF({p}^{k}) K={K} n_q={nq4} boundary={boundary}")
-        if boundary == 2 and K > nq4 and nq4 * k * (p - 1) ** 2 + p > 65535:
-            # one block's digit sums do not fit the 16-bit lanes: refused on the host
+        if boundary == 2 and K > nq4 and 2 * (q.bit_length() - 1) > 24:
+            # digit sums of q = 2^b need fields of 2b <= 24 bits: refused on the host
             with pytest.raises(fqt.FqtError) as ei:
                 _gemm_case(p, k, P, 32, 48, K, seed=0, adversarial=True,
                            opts={"tile": 2, "boundary": boundary})
@@ -420,3 +433,31 @@ def test_autotune_batched():
     fqt.gemm_batched(f, descs, path="auto")
     for c, w in zip(Cs, wants):
         assert np.array_equal(host(c), w)
+
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
+@pytest.mark.parametrize("nq", [5, 6, 7, 13, 15])
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_gemm_packed_padded_blocks(p, k, P, nq, boundary):
+    # n_q not a multiple of 4: blocks of n_q products padded to 8 or 16 MFMA slots
+    q, nqmax = fqt.params(p, k, 1)
+    if nq > nqmax:
+        pytest.skip("n_q above the bound")
+    if boundary == 2 and q > 2 ** 12:
+        pytest.skip("digit-sum boundaries need q <= 2^12")
+    for tile in (1, 3):
+        for (M, N, K) in [(40, 50, 97), (64, 64, 256), (17, 9, 7 * nq + 3)]:
+            note(f"gemm padded GF({p}^{k}) n_q={nq} boundary={boundary} tile={tile} {M}x{N}x{K}")
+            C, want = _gemm_case(p, k, P, M, N, K, seed=nq + K,
+                                 opts={"n_q": nq, "tile": tile, "boundary": boundary})
+            assert np.array_equal(C, want), (M, N, K)
+
+
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_gemm_padded_adversarial_gf81(boundary):
+    # GF(3^4), q = 2^7: n_q = 7 is the largest block eq. (2) admits
+    p, k, P = 3, 4, (2, 0, 0, 2)
+    note(f"gemm padded adversarial GF(3^4) boundary={boundary}")
+    C, want = _gemm_case(p, k, P, 48, 40, 256, seed=0, adversarial=True,
+                         opts={"n_q": 7, "boundary": boundary})
+    assert np.array_equal(C, want)
