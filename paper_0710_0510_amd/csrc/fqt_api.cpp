@@ -1024,22 +1024,46 @@ struct Candidate {
   fqt_gemm_opts opts;
 };
 
-// Host copy of every C of the batch (rows of N*k bytes).
+// Pinned host buffer (hipHostMalloc) that frees itself.
+struct PinnedBuf {
+  uint8_t* p = nullptr;
+  size_t n = 0;
+  ~PinnedBuf() {
+    if (p) hipHostFree(p);
+  }
+  fqt_status resize(size_t bytes) {
+    if (bytes <= n) return ok();
+    if (p) hipHostFree(p);
+    p = nullptr;
+    n = 0;
+    if (hipHostMalloc((void**)&p, std::max<size_t>(bytes, 1), hipHostMallocDefault) != hipSuccess)
+      return fail(FQT_ERR_OOM, "pinned host buffer of %zu bytes", bytes);
+    n = bytes;
+    return ok();
+  }
+};
+
+// Host copy of every C of the batch (rows of N*k bytes) into pinned memory.
 fqt_status snapshot(const fqt_field_s* f, int64_t count, const fqt_gemm_desc* d,
-                    hipStream_t s, std::vector<uint8_t>* out) {
+                    hipStream_t s, PinnedBuf* out, size_t* total_out) {
   size_t total = 0;
   for (int64_t i = 0; i < count; ++i) total += (size_t)(d[i].M * d[i].N) * f->k;
-  out->resize(total);
-  FQT_HIP(hipStreamSynchronize(s));
+  fqt_status st = out->resize(total);
+  if (st) return st;
+  *total_out = total;
+  std::memset(out->p, 0, total);
+  // Copies are ordered after the candidate's kernels on the same stream, then
+  // the stream is drained: no reliance on null-stream ordering.
   size_t off = 0;
   for (int64_t i = 0; i < count; ++i) {
     const size_t row = (size_t)d[i].N * f->k;
     if (d[i].M && row) {
-      FQT_HIP(hipMemcpy2D(out->data() + off, row, d[i].C, (size_t)d[i].ldc * f->k, row,
-                          (size_t)d[i].M, hipMemcpyDeviceToHost));
+      FQT_HIP(hipMemcpy2DAsync(out->p + off, row, d[i].C, (size_t)d[i].ldc * f->k, row,
+                               (size_t)d[i].M, hipMemcpyDeviceToHost, s));
     }
     off += row * (size_t)d[i].M;
   }
+  FQT_HIP(hipStreamSynchronize(s));
   return ok();
 }
 
@@ -1135,7 +1159,8 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   hipEvent_t e0, e1;
   FQT_HIP(hipEventCreate(&e0));
   FQT_HIP(hipEventCreate(&e1));
-  std::vector<uint8_t> ref, cur;
+  PinnedBuf ref, cur;
+  size_t ref_n = 0, cur_n = 0;
   double best_ms = 1e30;
   size_t best_i = 0;
   std::vector<double> times(cands.size(), 0.0);
@@ -1143,12 +1168,19 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   for (size_t i = 0; i < cands.size() && status == FQT_OK; ++i) {
     status = run(cands[i]);  // warm-up: builds plans and graphs
     if (status) break;
-    status = snapshot(f, count, descs, st, i == 0 ? &ref : &cur);
+    status = i == 0 ? snapshot(f, count, descs, st, &ref, &ref_n)
+                    : snapshot(f, count, descs, st, &cur, &cur_n);
     if (status) break;
-    if (i > 0 && cur != ref) {
-      status = fail(FQT_ERR_DEVICE, "autotune candidate %zu (path %d, q = 2^%u, tile %u) is not "
-                    "byte-identical to candidate 0", i, (int)cands[i].path, cands[i].opts.log2q,
-                    cands[i].opts.tile);
+    if (i > 0 && std::memcmp(cur.p, ref.p, ref_n) != 0) {
+      size_t at = 0;
+      while (at < ref_n && cur.p[at] == ref.p[at]) ++at;
+      size_t nbad = 0;
+      for (size_t j = 0; j < ref_n; ++j) nbad += cur.p[j] != ref.p[j];
+      status = fail(FQT_ERR_DEVICE, "autotune candidate %zu (path %d, q = 2^%u, tile %u, boundary "
+                    "%u) is not byte-identical to candidate 0: %zu of %zu bytes differ, first at "
+                    "byte %zu (%u vs %u)", i, (int)cands[i].path, cands[i].opts.log2q,
+                    cands[i].opts.tile, cands[i].opts.boundary, nbad, ref_n, at,
+                    (unsigned)cur.p[at], (unsigned)ref.p[at]);
       break;
     }
     // time enough replays to cover about 20 ms, at least three
