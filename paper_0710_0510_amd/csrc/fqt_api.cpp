@@ -330,8 +330,11 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   // Blocks are whole MFMA k-groups of 4 slots.  A block of n_q % 4 != 0
   // products is padded with zero slots when the slot count divides every
   // K-tile (8 or 16); otherwise n_q is rounded down to a multiple of 4.
+  // Register-direct tiles take no padded blocks.
+  const bool direct = o && o->tile && is_direct_tile((int)o->tile);
   uint64_t slots = nq & ~3ull, real = slots;
-  if (nq % 4 && (K > (int64_t)nq) && ((nq + 3) / 4 * 4 == 8 || (nq + 3) / 4 * 4 == 16)) {
+  if (!direct && nq % 4 && (K > (int64_t)nq) &&
+      ((nq + 3) / 4 * 4 == 8 || (nq + 3) / 4 * 4 == 16)) {
     slots = (nq + 3) / 4 * 4;
     real = nq;
   }
@@ -362,6 +365,11 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   }
   uint32_t tile = (o && o->tile) ? o->tile : 0;
   if (tile > (uint32_t)kPackedTiles) return fail(FQT_ERR_INVALID_ARG, "unknown tile id %u", tile);
+  if (tile && is_direct_tile((int)tile)) {
+    if (multi && !direct_tile_multi_ok((int)tile))
+      return fail(FQT_ERR_UNSUPPORTED, "tile %u takes single-block problems only (K <= n_q)",
+                  tile);
+  }
   if (!tile) {
     // default: the largest tile that still gives every CU two workgroups
     static const int pref[] = {4, 3, 2, 5, 6, 1};
@@ -630,7 +638,10 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   pp.fa = field_args(f, q);
   pp.L = dt.L;
   pp.H = dt.H;
-  FQT_HIP(launch_gemm_packed((int)f->k, (int)pc.tile, pc.mode, g, pp, s));
+  if (is_direct_tile((int)pc.tile))
+    FQT_HIP(launch_gemm_direct((int)f->k, (int)pc.tile, pc.mode, g, pp, s));
+  else
+    FQT_HIP(launch_gemm_packed((int)f->k, (int)pc.tile, pc.mode, g, pp, s));
   return ok();
 }
 
@@ -814,7 +825,9 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
     hipDeviceProp_t prop;
     FQT_HIP(hipGetDeviceProperties(&prop, dev));
-    const int occ = packed_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2);
+    const bool direct = is_direct_tile((int)pc.tile);
+    const int occ = direct ? direct_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2)
+                           : packed_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2);
     pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * occ, pl->n_items));
     PackedParams pp{};
     pp.b = pc.b;
@@ -831,9 +844,13 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     // Capture the persistent launch once; later calls replay the graph.
     FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t le = launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
-                                               pl->d_items, pl->n_items, pl->d_counter, pl->grid,
-                                               pp, pl->cap_stream);
+    hipError_t le =
+        direct ? launch_gemm_direct_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
+                                            pl->d_items, pl->n_items, pl->d_counter, pl->grid, pp,
+                                            pl->cap_stream)
+               : launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
+                                            pl->d_items, pl->n_items, pl->d_counter, pl->grid, pp,
+                                            pl->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
     if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");

@@ -72,17 +72,35 @@ struct TileItem {
   int32_t pad;
 };
 
-// Tile configurations of the packed path (WG of 256 threads = 2x2 waves):
+// Tile configurations of the packed path, ids 1..kPackedTiles.
+// LDS-staged kernels (k_gemm_f64.hip), WG of 256 threads = 2x2 waves:
 // X(id, TM, TN, BK): wave tile 16TM x 16TN, workgroup tile 32TM x 32TN,
 // K-tiles of BK elements.
 #define FQT_PACKED_TILES(X) \
   X(1, 1, 1, 32) X(2, 2, 2, 32) X(3, 2, 4, 16) X(4, 4, 4, 16) X(5, 2, 1, 32) X(6, 1, 2, 32)
-constexpr int kPackedTiles = 6;
+constexpr int kStagedTiles = 6;
+// Register-direct kernels (k_gemm_direct.hip), WG of 4 waves = 4/SK waves side
+// by side x SK waves splitting K: X(id, TM, TN, SK, MULTI_OK); MULTI_OK = 0
+// tiles take single-block problems only (their per-element block state would
+// not fit in registers).
+#define FQT_DIRECT_TILES(X) \
+  X(7, 4, 4, 4, 0) X(8, 2, 4, 2, 0) X(9, 4, 4, 1, 0) X(10, 2, 4, 1, 0) X(11, 1, 4, 1, 1)
+constexpr int kPackedTiles = 11;
+#ifndef FQT_DIRECT_STAGES
+#define FQT_DIRECT_STAGES 2
+#endif
+constexpr int kDirectStages = FQT_DIRECT_STAGES;  // K-steps in flight per wave
+inline bool is_direct_tile(int id) { return id > kStagedTiles; }
+inline bool direct_tile_multi_ok(int id) { return id == 11; }
 inline void packed_tile_shape(int id, int* bm, int* bn) {
-  static const int tm[kPackedTiles] = {1, 2, 2, 4, 2, 1};
-  static const int tn[kPackedTiles] = {1, 2, 4, 4, 1, 2};
-  *bm = 32 * tm[id - 1];
-  *bn = 32 * tn[id - 1];
+  //                               1  2  3  4  5  6  7  8  9 10 11
+  static const int tm[kPackedTiles] = {1, 2, 2, 4, 2, 1, 4, 2, 4, 2, 1};
+  static const int tn[kPackedTiles] = {1, 2, 4, 4, 1, 2, 4, 4, 4, 4, 4};
+  static const int sk[kPackedTiles] = {1, 1, 1, 1, 1, 1, 4, 2, 1, 1, 1};
+  // side-by-side waves: 2x2 (SK 1), 2x1 (SK 2), 1x1 (SK 4)
+  const int s = sk[id - 1];
+  *bm = 16 * tm[id - 1] * (s == 4 ? 1 : 2);
+  *bn = 16 * tn[id - 1] * (s == 1 ? 2 : 1);
 }
 
 // ---- launchers (each returns the launch's hipError_t) ----------------------
@@ -111,6 +129,15 @@ hipError_t launch_gemm_packed_batched(int k, int tile, int mode, const GemmArgs*
                                       hipStream_t s);
 
 int packed_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2);
+
+// Register-direct packed kernels (tile ids > kStagedTiles).
+hipError_t launch_gemm_direct(int k, int tile, int mode, const GemmArgs& g,
+                              const PackedParams& pp, hipStream_t s);
+hipError_t launch_gemm_direct_batched(int k, int tile, int mode, const GemmArgs* descs,
+                                      const TileItem* items, int32_t n_items,
+                                      uint32_t* counter, int grid, const PackedParams& pp,
+                                      hipStream_t s);
+int direct_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2);
 
 // INT8 path: B -> B'^T expansion, then the INT8 MFMA GEMM (tile ids 1..3).
 constexpr int kInt8Tiles = 3;

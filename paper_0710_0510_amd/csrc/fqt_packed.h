@@ -1,0 +1,191 @@
+// Device pieces shared by the two packed-FP64 GEMM kernel families (LDS-staged
+// in k_gemm_f64.hip, register-direct in k_gemm_direct.hip): operand bytes ->
+// packed doubles, the per-element state carried across K-blocks, and the
+// final REDQ + table step of Alg. 4.
+//
+// K-block state (Section 6 delays the reduction while eq. (2) holds; how the
+// blocks combine is a reading of Thm. 2): the residue vector u of a block is
+// linear in its digits modulo p, and L + H is linear in u, so blocks are
+// summed before the tables are applied once.
+//   MODE 0: one block (K <= n_q); the biased accumulator is the whole state.
+//   MODE 1: REDQ residues u'_i < 2p of every block summed in 16-bit lanes,
+//           two residues per word (digit 2w low, 2w+1 high).
+//   MODE 2: digit sums.  With q = 2^b the digits of a block are bit fields of
+//           its accumulator; the bits of its even digits are added into E,
+//           those of its odd digits into O, so every field has b spare bits
+//           above it and sums below q^2 never carry (needs 2b <= 24).  At the
+//           end Horner's rule mod p gives u_i = sum_{j>=i} D_j q^(j-i) mod p.
+// Lanes and fields are folded mod p every fold_blocks boundaries, before they
+// could overflow.  In modes 1 and 2, q is the largest power of two eq. (2)
+// admits and is fixed at compile time.
+#pragma once
+
+#include "fqt_internal.h"
+
+namespace fqt {
+
+// q = 2^b of the multi-block modes.
+template <int KE>
+constexpr uint32_t multi_block_b() {
+  return 52u / (2u * KE - 1u);
+}
+
+// Digit-sum boundaries (mode 2) need fields of 2b <= 24 bits.
+template <int KE>
+constexpr bool digit_sums_fit() {
+  return 2 * multi_block_b<KE>() <= 24;
+}
+
+constexpr uint64_t digit_mask(int nd, uint32_t b, int parity) {
+  uint64_t m = 0;
+  for (int d = parity; d < nd; d += 2) m |= ((1ull << b) - 1) << (b * d);
+  return m;
+}
+
+// Element e (0..NWD*4/KE - 1) of a little-endian run of NWD words holding
+// consecutive KE-byte elements: its bytes in the low bytes of the result
+// (higher bytes are whatever follows; dqt_shift reads only the low KE).
+template <int KE, int NWD>
+__device__ __forceinline__ uint32_t seg_elem(const uint32_t (&raw)[NWD], int e) {
+  const int o = e * KE;
+  const uint32_t lo = raw[o >> 2];
+  if ((o & 3) == 0) return lo;
+  const uint32_t hi = ((o >> 2) + 1 < NWD) ? raw[(o >> 2) + 1] : 0u;
+  return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+}
+
+// DQT of one element straight to binary64 (exact: the value is < 2^32).
+template <int KE>
+__device__ __forceinline__ double packed_value(uint32_t bytes, uint32_t b) {
+  return (double)dqt_shift<KE>(bytes, b);
+}
+
+template <int KE, int MODE>
+struct BlockLanes {
+  static constexpr int ND = 2 * KE - 1;
+  static constexpr int NW = KE;  // 16-bit lane words, (ND + 1) / 2
+  static constexpr uint32_t BQ = MODE ? multi_block_b<KE>() : 0u;
+  static constexpr uint64_t EM = MODE == 2 ? digit_mask(ND, BQ, 0) : 0;
+  static constexpr uint64_t OM = MODE == 2 ? digit_mask(ND, BQ, 1) : 0;
+
+  uint64_t E, O;   // MODE 2
+  uint32_t W[NW];  // MODE 1
+
+  __device__ __forceinline__ void clear() {
+    E = O = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) W[w] = 0;
+  }
+
+  // digit field d of a gapped sum: bits [d*b, d*b + 2b)
+  static __device__ __forceinline__ uint32_t field(uint64_t x, int d) {
+    return (uint32_t)(x >> (BQ * d)) & (uint32_t)((1ull << (2 * BQ)) - 1);
+  }
+
+  // REDQ residues of a block as lane words.
+  static __device__ __forceinline__ void residue_words(double acc, const FieldArgs& fa,
+                                                       uint32_t (&wd)[NW]) {
+    uint32_t t[ND];
+    redq_residues_biased<ND>(acc, BQ, fa, t);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const uint32_t lo = t[2 * w];
+      const uint32_t hi = (2 * w + 1 < ND) ? t[2 * w + 1] : 0u;
+      wd[w] = perm_b32(hi, lo, 0x0c040c00u);
+    }
+  }
+
+  // A block boundary: take the block's contribution out of its accumulator.
+  __device__ __forceinline__ void add(double acc, const FieldArgs& fa) {
+    if constexpr (MODE == 2) {
+      const uint64_t rb = bits64(acc);
+      E += rb & EM;
+      O += rb & OM;
+    } else if constexpr (MODE == 1) {
+      uint32_t wd[NW];
+      residue_words(acc, fa, wd);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) W[w] += wd[w];
+    }
+  }
+
+  // Reduce every lane or field mod p.
+  __device__ __forceinline__ void fold(const FieldArgs& fa) {
+    if constexpr (MODE == 2) {
+      uint64_t e = 0, o = 0;
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const uint64_t r = mod_p_small(field((d & 1) ? O : E, d), fa);
+        if (d & 1) o |= r << (BQ * d);
+        else e |= r << (BQ * d);
+      }
+      E = e;
+      O = o;
+    } else if constexpr (MODE == 1) {
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t x = W[w];
+        W[w] = mod_p_small(x & 0xffffu, fa) | (mod_p_small(x >> 16, fa) << 16);
+      }
+    }
+  }
+
+  // Final residues u_0..u_{2k-2} in [0, p) of all blocks, the last block
+  // still in its accumulator.  b is q's exponent for MODE 0.
+  __device__ __forceinline__ void residues(double acc, uint32_t b, const PackedParams& pp,
+                                           uint32_t (&u)[ND]) const {
+    const FieldArgs& fa = pp.fa;
+    if constexpr (MODE == 2) {
+      const uint64_t rb = bits64(acc);
+      const uint64_t e = E + (rb & EM), o = O + (rb & OM);
+      u[ND - 1] = mod_p_small(field(((ND - 1) & 1) ? o : e, ND - 1), fa);
+#pragma unroll
+      for (int d = ND - 2; d >= 0; --d)
+        u[d] = mod_p_small(field((d & 1) ? o : e, d) + pp.qmod * u[d + 1], fa);
+    } else if constexpr (MODE == 1) {
+      uint32_t wd[NW];
+      residue_words(acc, fa, wd);
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const uint32_t tot = W[w] + wd[w];
+        u[2 * w] = mod_p_small(tot & 0xffffu, fa);
+        if (2 * w + 1 < ND) u[2 * w + 1] = mod_p_small(tot >> 16, fa);
+      }
+    } else {
+      uint32_t t[ND];
+      redq_residues_biased<ND>(acc, b, fa, t);
+#pragma unroll
+      for (int d = 0; d < ND; ++d) {
+        const uint32_t x = t[d] & 0xffu;
+        u[d] = x >= fa.p ? x - fa.p : x;
+      }
+    }
+  }
+};
+
+// Thm. 3: the field element of residues u as L[u_0..u_{k-1}] + H[u_{k-1}..u_{2k-2}]
+// (binary table index, Section 5.3), one coefficient per byte.
+template <int KE>
+__device__ __forceinline__ uint32_t lh_combine(const uint32_t (&u)[2 * KE - 1],
+                                               const PackedParams& pp,
+                                               const uint32_t* __restrict__ Ls,
+                                               const uint32_t* __restrict__ Hs) {
+  uint32_t il = 0, ih = 0;
+#pragma unroll
+  for (int d = 0; d < KE; ++d) {
+    il |= u[d] << (pp.fa.cb * d);
+    ih |= u[KE - 1 + d] << (pp.fa.cb * d);
+  }
+  const uint32_t tmask = (1u << pp.tbl_log2) - 1u;  // keeps lookups inside the tables
+  return add_bytes_mod_p(Ls[il & tmask], Hs[ih & tmask], pp.fa);
+}
+
+__device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls, uint32_t* Hs) {
+  const int n = 1 << pp.tbl_log2;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    Ls[i] = pp.L[i];
+    Hs[i] = pp.H[i];
+  }
+}
+
+}  // namespace fqt

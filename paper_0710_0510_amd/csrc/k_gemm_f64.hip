@@ -10,32 +10,17 @@
 //   4. Two table lookups L[u_0..u_{k-1}] + H[u_{k-1}..u_{2k-2}] (Thm. 3) and
 //      one coefficient-wise addition mod p.
 //
-// Delayed reduction across K-blocks (Section 6: the reduction "can be
-// delayed" while eq. (2) holds; how blocks combine is left open).  The
-// residue vector is linear in the digits modulo p (Thm. 2: u_i = sum_{j>=i}
-// mu_j q^(j-i) mod p), and L + H is linear in u, so the blocks' contributions
-// are summed in 16-bit lanes (folded mod p before they could overflow) and
-// the tables are applied once at the end.  Two exact boundary steps:
-//   MODE 1 (REDQ residues): Alg. 2's first part per block -- one FMA for rop,
-//     then a shift and a 24-bit multiply-add per digit; lanes sum u'_i.
-//   MODE 2 (digit sums): the radix conversion of Alg. 1 per block -- with
-//     q = 2^b the digits are bit fields of the accumulator, no division at
-//     all.  The block's bits masked to its even digits are added into one
-//     64-bit integer E, those of its odd digits into O: every digit field then
-//     has b empty bits above it, so digit sums up to q^2 - 1 never carry into
-//     the next field (2b <= 24 here).  At the end Horner's rule mod p turns
-//     the digit sums D_i into u_i = sum_{j>=i} D_j q^(j-i) mod p.
-// Either way the accumulator restarts at the 2^52 bias after a boundary.
-// MODE 0 is a single block (K <= n_q): no lanes at all.
+// Several K-blocks (delayed reduction, Section 6) carry a per-element state
+// between blocks: modes 0/1/2 of BlockLanes in fqt_packed.h.
 //
 // Layout: workgroup = 256 threads = 2 x 2 waves; wave tile 16TM x 16TN made of
 // TM x TN MFMA blocks of 16 x 16; workgroup tile BM x BN = 32TM x 32TN;
-// K-tiles of BK = 16 elements, double-buffered in LDS as packed doubles.
+// K-tiles of BK (16 or 32) elements, double-buffered in LDS as packed doubles.
 // MFMA 16x16x4 f64 operand layout (per lane l of the wave):
 //   A: row l%16, k l/16;  B: k l/16, column l%16;
 //   D: element v in 0..3 at row l/16 + 4v, column l%16 (checked on gfx950).
 
-#include "fqt_internal.h"
+#include "fqt_packed.h"
 
 namespace fqt {
 
@@ -89,16 +74,6 @@ __device__ __forceinline__ void load_chunk(const uint8_t* base, int64_t row, int
   }
 }
 
-// Element e (0..3) of a raw chunk: its KE bytes in the low bytes of a word.
-template <int KE>
-__device__ __forceinline__ uint32_t chunk_elem(const uint32_t (&raw)[KE], int e) {
-  const int o = e * KE;
-  if ((o & 3) == 0) return raw[o >> 2];
-  const uint32_t lo = raw[o >> 2];
-  const uint32_t hi = ((o >> 2) + 1 < KE) ? raw[(o >> 2) + 1] : 0u;
-  return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
-}
-
 template <int KE, int TM, int TN, int BK, int MODE>
 __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int tile_n,
                                             const PackedParams& pp, double* __restrict__ As,
@@ -117,8 +92,7 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   const bool aligned = pp.aligned != 0;
   // Several K-blocks: q is the largest power of two eq. (2) admits, fixed at
   // compile time so that digit windows become constant bit-field extracts.
-  constexpr uint32_t BQ = MODE ? 52u / (2u * KE - 1u) : 0u;
-  const uint32_t b = BQ ? BQ : pp.b;
+  const uint32_t b = MODE ? multi_block_b<KE>() : pp.b;
   // Interior tiles (and full K-tiles) load without bounds checks.
   const bool interior = aligned && m0 + T::BM <= g.M && n0 + T::BN <= g.N;
   // Padded K-blocks: blk_real products in blk_slots = 4 * nq_groups MFMA
@@ -132,38 +106,14 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = bias;
 
-  // MODE 2: gapped digit sums, even digits in E, odd digits in O.
-  constexpr bool GAPPED = MODE == 2;
-  constexpr uint64_t QM = BQ ? (1ull << BQ) - 1 : 0;
-  constexpr uint64_t EM = [] {
-    uint64_t m = 0;
-    for (int d = 0; d < T::ND; d += 2) m |= QM << (BQ * d);
-    return m;
-  }();
-  constexpr uint64_t OM = [] {
-    uint64_t m = 0;
-    for (int d = 1; d < T::ND; d += 2) m |= QM << (BQ * d);
-    return m;
-  }();
-  uint64_t E[GAPPED ? TM : 1][GAPPED ? TN : 1][4], O[GAPPED ? TM : 1][GAPPED ? TN : 1][4];
-  if constexpr (GAPPED) {
+  BlockLanes<KE, MODE> st[MULTI ? TM : 1][MULTI ? TN : 1][4];
+  if constexpr (MULTI) {
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int j = 0; j < TN; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) E[i][j][v] = O[i][j][v] = 0;
-  }
-  uint32_t W[MODE == 1 ? TM : 1][MODE == 1 ? TN : 1][4][MODE == 1 ? T::NW : 1];
-  if constexpr (MODE == 1) {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int j = 0; j < TN; ++j)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int w = 0; w < T::NW; ++w) W[i][j][v][w] = 0;
+        for (int v = 0; v < 4; ++v) st[i][j][v].clear();
   }
 
   // Fixed chunk geometry of this thread: A chunk r covers row arow + r*(1024/BK),
@@ -259,29 +209,13 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         as[(arow + r * ARS) * T::SA + 4 * akc + e] =
-            (double)dqt_shift<KE>(chunk_elem<KE>(ra[r], e), b);
+            (double)dqt_shift<KE>(seg_elem<KE, KE>(ra[r], e), b);
 #pragma unroll
     for (int r = 0; r < T::RB; ++r)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] =
-            (double)dqt_shift<KE>(chunk_elem<KE>(rb[r], e), b);
-  };
-
-  // REDQ residues of one element as lane words: digit 2w low, 2w+1 high.
-  auto residue_words = [&](double acc_v, uint32_t (&wd)[T::NW]) {
-    uint32_t t[T::ND];
-    redq_residues_biased<T::ND>(acc_v, b, pp.fa, t);
-#pragma unroll
-    for (int w = 0; w < T::NW; ++w) {
-      const uint32_t lo = t[2 * w];
-      const uint32_t hi = (2 * w + 1 < T::ND) ? t[2 * w + 1] : 0u;
-      wd[w] = perm_b32(hi, lo, 0x0c040c00u);
-    }
-  };
-  // digit field d of a gapped sum: bits [d*b, d*b + 2b)
-  auto field = [&](uint64_t x, int d) -> uint32_t {
-    return (uint32_t)(x >> (BQ * d)) & (uint32_t)((1ull << (2 * BQ)) - 1);
+            (double)dqt_shift<KE>(seg_elem<KE, KE>(rb[r], e), b);
   };
 
   uint32_t nbound = 0;
@@ -292,18 +226,7 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            if constexpr (GAPPED) {
-              const uint64_t rb = bits64(acc[i][j][v]);
-              E[i][j][v] += rb & EM;
-              O[i][j][v] += rb & OM;
-            } else {
-              uint32_t wd[T::NW];
-              residue_words(acc[i][j][v], wd);
-#pragma unroll
-              for (int w = 0; w < T::NW; ++w) W[i][j][v][w] += wd[w];
-            }
-          }
+          for (int v = 0; v < 4; ++v) st[i][j][v].add(acc[i][j][v], pp.fa);
           acc[i][j] = bias;
         }
       // fold the sums mod p before another block could overflow them
@@ -314,26 +237,7 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
           for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              if constexpr (GAPPED) {
-                uint64_t e = 0, o = 0;
-#pragma unroll
-                for (int d = 0; d < T::ND; ++d) {
-                  const uint64_t r = mod_p_small(field((d & 1) ? O[i][j][v] : E[i][j][v], d), pp.fa);
-                  if (d & 1) o |= r << (BQ * d);
-                  else e |= r << (BQ * d);
-                }
-                E[i][j][v] = e;
-                O[i][j][v] = o;
-              } else {
-#pragma unroll
-                for (int w = 0; w < T::NW; ++w) {
-                  const uint32_t x = W[i][j][v][w];
-                  W[i][j][v][w] =
-                      mod_p_small(x & 0xffffu, pp.fa) | (mod_p_small(x >> 16, pp.fa) << 16);
-                }
-              }
-            }
+            for (int v = 0; v < 4; ++v) st[i][j][v].fold(pp.fa);
       }
     }
   };
@@ -376,7 +280,6 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   }
 
   // Epilogue: final residues, L + H (Thm. 3), store k bytes per element.
-  const FieldArgs& fa = pp.fa;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -384,53 +287,12 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         uint32_t u[T::ND];
-        if constexpr (GAPPED) {
-          // digit sums D_d of all blocks (the last one included), then
-          // residues u_d = (D_d + q u_{d+1}) mod p
-          const uint64_t rb = bits64(acc[i][j][v]);
-          const uint64_t e = E[i][j][v] + (rb & EM), o = O[i][j][v] + (rb & OM);
-          u[T::ND - 1] = mod_p_small(field(((T::ND - 1) & 1) ? o : e, T::ND - 1), fa);
-#pragma unroll
-          for (int d = T::ND - 2; d >= 0; --d)
-            u[d] = mod_p_small(field((d & 1) ? o : e, d) + pp.qmod * u[d + 1], fa);
-        } else if constexpr (MODE == 1) {
-          uint32_t wd[T::NW];
-          residue_words(acc[i][j][v], wd);
-#pragma unroll
-          for (int w = 0; w < T::NW; ++w) {
-            const uint32_t tot = W[i][j][v][w] + wd[w];
-            u[2 * w] = mod_p_small(tot & 0xffffu, fa);
-            if (2 * w + 1 < T::ND) u[2 * w + 1] = mod_p_small(tot >> 16, fa);
-          }
-        } else {
-          uint32_t t[T::ND];
-          redq_residues_biased<T::ND>(acc[i][j][v], b, fa, t);
-#pragma unroll
-          for (int d = 0; d < T::ND; ++d) {
-            const uint32_t x = t[d] & 0xffu;
-            u[d] = x >= fa.p ? x - fa.p : x;
-          }
-        }
-        uint32_t il = 0, ih = 0;
-#pragma unroll
-        for (int d = 0; d < KE; ++d) {
-          il |= u[d] << (fa.cb * d);
-          ih |= u[KE - 1 + d] << (fa.cb * d);
-        }
-        const uint32_t tmask = (1u << pp.tbl_log2) - 1u;  // keeps lookups inside the tables
-        const uint32_t e = add_bytes_mod_p(Ls[il & tmask], Hs[ih & tmask], fa);
+        st[MULTI ? i : 0][MULTI ? j : 0][v].residues(acc[i][j][v], b, pp, u);
+        const uint32_t e = lh_combine<KE>(u, pp, Ls, Hs);
         const int64_t row = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
         const int64_t col = n0 + wn0 + 16 * j + (lane & 15);
         if (row < g.M && col < g.N) store_elem<KE>(g.C + (row * g.ldc + col) * KE, e);
       }
-}
-
-__device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls, uint32_t* Hs) {
-  const int n = 1 << pp.tbl_log2;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    Ls[i] = pp.L[i];
-    Hs[i] = pp.H[i];
-  }
 }
 
 template <int KE, int TM, int TN, int BK, int MODE>
@@ -520,17 +382,24 @@ static int occupancy(uint32_t tbl_log2) {
 }
 
 // Dispatch over (k, tile id, multi-block); the tile list is FQT_PACKED_TILES.
-#define FQT_TILE_CASE(ID, TM, TN, BK) \
-  case ID: return FN<KE, TM, TN, BK, MODE>(ARGS);
+// (digit-sum boundaries only where 2b <= 24: the host never asks for others)
+#define FQT_TILE_CASE(ID, TM, TN, BK)                                    \
+  case ID:                                                                \
+    if constexpr (MODE != 2 || digit_sums_fit<KE>())                      \
+      return FN<KE, TM, TN, BK, MODE>(ARGS);                              \
+    else                                                                  \
+      return FAIL;
 
 template <int KE, int MODE>
 static hipError_t dispatch_one(int tile, const GemmArgs& g, const PackedParams& pp,
                                hipStream_t s) {
 #define FN launch_one
 #define ARGS g, pp, s
+#define FAIL hipErrorInvalidValue
   switch (tile) { FQT_PACKED_TILES(FQT_TILE_CASE) default: return hipErrorInvalidValue; }
 #undef FN
 #undef ARGS
+#undef FAIL
 }
 
 template <int KE, int MODE>
@@ -539,18 +408,22 @@ static hipError_t dispatch_batched(int tile, const GemmArgs* descs, const TileIt
                                    const PackedParams& pp, hipStream_t s) {
 #define FN launch_batched
 #define ARGS descs, items, n_items, counter, grid, pp, s
+#define FAIL hipErrorInvalidValue
   switch (tile) { FQT_PACKED_TILES(FQT_TILE_CASE) default: return hipErrorInvalidValue; }
 #undef FN
 #undef ARGS
+#undef FAIL
 }
 
 template <int KE, int MODE>
 static int dispatch_occupancy(int tile, uint32_t tbl_log2) {
 #define FN occupancy
 #define ARGS tbl_log2
+#define FAIL 1
   switch (tile) { FQT_PACKED_TILES(FQT_TILE_CASE) default: return 1; }
 #undef FN
 #undef ARGS
+#undef FAIL
 }
 #undef FQT_TILE_CASE
 

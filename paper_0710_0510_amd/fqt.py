@@ -222,6 +222,19 @@ def _ld(t, k: int) -> int:
     return t.stride(0) // k
 
 
+def _matrix(t, k: int, name: str):
+    """A rows x cols x k uint8 device tensor whose elements are k consecutive
+    bytes and whose rows are equally spaced (any row stride)."""
+    import torch
+    if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != k:
+        raise ValueError(f"{name}: expected a uint8 tensor of shape (rows, cols, {k})")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: expected a device tensor")
+    if t.numel() and ((t.shape[2] > 1 and t.stride(2) != 1) or
+                      (t.shape[1] > 1 and t.stride(1) != k)):
+        raise ValueError(f"{name}: elements within a row must be contiguous")
+
+
 def gemm(field: Field, A, B, C=None, path: str = "auto", opts=None, stream=None):
     """C = A B over the field; A is M x K x k, B is K x N x k (uint8)."""
     import torch
@@ -229,6 +242,11 @@ def gemm(field: Field, A, B, C=None, path: str = "auto", opts=None, stream=None)
     N = B.shape[1]
     if C is None:
         C = torch.empty((M, N, field.k), dtype=torch.uint8, device=A.device)
+    for t, name in ((A, "A"), (B, "B"), (C, "C")):
+        _matrix(t, field.k, name)
+    if B.shape[0] != K or tuple(C.shape[:2]) != (M, N):
+        raise ValueError(f"shapes do not chain: A {tuple(A.shape)}, B {tuple(B.shape)}, "
+                         f"C {tuple(C.shape)}")
     lda, ldb, ldc = _ld(A, field.k), _ld(B, field.k), _ld(C, field.k)
     _check(lib().fqt_gemm_gfpk_ex(field.handle, PATHS[path], _opts(opts), M, N, K, _ptr(A),
                                   lda, _ptr(B), ldb, _ptr(C), ldc, _stream(stream)))
@@ -238,6 +256,10 @@ def gemm(field: Field, A, B, C=None, path: str = "auto", opts=None, stream=None)
 def make_descs(field: Field, As, Bs, Cs):
     arr = (GemmDesc * len(As))()
     for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        for t, name in ((A, "A"), (B, "B"), (C, "C")):
+            _matrix(t, field.k, f"{name}[{i}]")
+        if B.shape[0] != A.shape[1] or tuple(C.shape[:2]) != (A.shape[0], B.shape[1]):
+            raise ValueError(f"product {i}: shapes do not chain")
         arr[i] = GemmDesc(A.shape[0], B.shape[1], A.shape[1], _ld(A, field.k),
                           _ld(B, field.k), _ld(C, field.k),
                           A.data_ptr(), B.data_ptr(), C.data_ptr())
