@@ -32,7 +32,11 @@ PEAK_I32_VALU = 157.3e12 / 2  # 32-bit integer vector ops per second (one per la
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE scaled by a plain-copy calibration (profiles/ holds the summary).
 # Keyed by (workload, path, tile); valid only for the kernel version profiled.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    ("gemm-gf7^2-1024", "packed", 7): {
+        "bytes": 15_269_888,  # FETCH 6432 KiB x 2.000 + WRITE 2048 KiB x 1.000
+        "source": "profiles/gemm_direct_gf7-2_1024.md"},
+}
 
 
 def poly_str(P_low):
@@ -75,7 +79,15 @@ def cpu_baseline_gemm(w, A, B, gf, target_s=15.0):
                       f"numpy int64 plane products, {dt:.1f} s"}
 
 
-def roofline_for(path, k, work, ms):
+# Kernel that carries a packed step, by tile id (1..6 LDS-staged, 7..12 direct).
+def packed_kernel_name(tile):
+    if tile and tile >= 7:
+        return (f"gemm_direct_kernel, tile {tile} (DQT on load into MFMA registers + "
+                "FP64 MFMA + REDQ + L/H)")
+    return f"gemm_packed_kernel, tile {tile} (DQT into LDS + FP64 MFMA + REDQ + L/H)"
+
+
+def roofline_for(path, k, work, ms, tile=0):
     """Algorithmic work of one step over its measured time, against the
     published MI355X peak of the unit the path runs on."""
     if path == "int8":
@@ -96,7 +108,7 @@ def roofline_for(path, k, work, ms):
     ach = flops / (ms * 1e-3)
     return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
             "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": None,
-            "kernel": "gemm_packed_kernel (fused pack + FP64 MFMA + REDQ + L/H)",
+            "kernel": packed_kernel_name(tile),
             "algorithmic": "2 flop per field mul-add (one FP64 FMA on packed values)"}
 
 
@@ -138,11 +150,12 @@ def bench_gemm(w, args, torch, fqt, gf):
         steps = args.steps if path != "plain" else max(3, args.steps // 10)
         ms = time_steps(lambda: fqt.gemm(f, A, B, C, path=path, opts=opts), steps,
                         args.warmup if path != "plain" else 2, torch)
+        tile = (opts or tuned.get(path) or {}).get("tile", 0)
         results[path] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": steps,
-                         "roofline": roofline_for(path, w.k, work, ms)}
+                         "tile": tile, "roofline": roofline_for(path, w.k, work, ms, tile)}
 
     main_r = results[args.path]
-    tr = MEASURED_TRAFFIC.get((w.name, args.path, args.tile))
+    tr = MEASURED_TRAFFIC.get((w.name, args.path, main_r["tile"]))
     if tr:
         main_r["roofline"]["traffic"] = tr["bytes"]
         main_r["roofline"]["traffic_source"] = tr["source"]
@@ -250,7 +263,7 @@ def bench_batched(w, args, torch, fqt, gf):
                    "count": len(As), "MNK_range": [w.lo, w.hi], "sum_MNK": work, "seed": w.seed,
                    "path": "packed (persistent, hipGraph replay)", "q": q, "n_q_max": nqmax,
                    "tile": args.tile or "autotuned", "tuned": tuned},
-        "roofline": roofline_for("packed", k, work, ms),
+        "roofline": roofline_for("packed", k, work, ms, (opts or tuned.get("packed") or {}).get("tile", 0)),
         "paths": {"packed": {"value": work / (ms * 1e-3), "ms_per_step": ms},
                   "int8": {"value": work / (i8_ms * 1e-3), "ms_per_step": i8_ms,
                            "roofline_frac": roofline_for("int8", k, work, i8_ms)["frac"]},
@@ -260,7 +273,7 @@ def bench_batched(w, args, torch, fqt, gf):
         "parity": {"sampled_entries_vs_oracle": int(len(picks) * 4), "sampled_mismatches": bad,
                    "identical_to_plain_path": True},
     }
-    out["roofline"]["kernel"] = "gemm_packed_batched_kernel (persistent, fused pack + FP64 MFMA + REDQ + L/H)"
+    out["roofline"]["kernel"] = "persistent batched " + out["roofline"]["kernel"]
     return out
 
 

@@ -96,10 +96,11 @@ typedef struct {
                       largest eq. (2) allows for q */
   uint32_t tile;   /* kernel tile configuration id (see fqt_tile_count); 0 =
                       default for the shape.  Packed path: ids 1..6 stage
-                      operands through LDS; ids 7..11 load them straight
-                      into MFMA registers (7..10 need K <= n_q and return
-                      FQT_ERR_UNSUPPORTED otherwise; these ids never pad a
-                      K-block: n_q is rounded down to a multiple of 4). */
+                      operands through LDS; ids 7..12 load them straight
+                      into MFMA registers (all but 11 need K <= n_q and
+                      return FQT_ERR_UNSUPPORTED otherwise; these ids never
+                      pad a K-block: n_q is rounded down to a multiple of
+                      4). */
   uint32_t boundary; /* packed path, K > n_q: step at each K-block boundary.
                         0 = default (2 when q <= 2^12, else 1); 1 = REDQ
                         residues of the block (Alg. 2,

@@ -79,28 +79,27 @@ struct TileItem {
 #define FQT_PACKED_TILES(X) \
   X(1, 1, 1, 32) X(2, 2, 2, 32) X(3, 2, 4, 16) X(4, 4, 4, 16) X(5, 2, 1, 32) X(6, 1, 2, 32)
 constexpr int kStagedTiles = 6;
-// Register-direct kernels (k_gemm_direct.hip), WG of 4 waves = 4/SK waves side
-// by side x SK waves splitting K: X(id, TM, TN, SK, MULTI_OK); MULTI_OK = 0
-// tiles take single-block problems only (their per-element block state would
-// not fit in registers).
-#define FQT_DIRECT_TILES(X) \
-  X(7, 4, 4, 4, 0) X(8, 2, 4, 2, 0) X(9, 4, 4, 1, 0) X(10, 2, 4, 1, 0) X(11, 1, 4, 1, 1)
-constexpr int kPackedTiles = 11;
+// Register-direct kernels (k_gemm_direct.hip), WG of NWV waves = NWV/SK waves
+// side by side x SK waves splitting K: X(id, TM, TN, SK, NWV, MULTI_OK);
+// MULTI_OK = 0 tiles take single-block problems only (their per-element block
+// state would not fit in registers).
+#define FQT_DIRECT_TILES(X)                                                     \
+  X(7, 4, 4, 4, 4, 0) X(8, 2, 4, 2, 4, 0) X(9, 4, 4, 1, 4, 0) X(10, 2, 4, 1, 4, 0) \
+  X(11, 1, 4, 1, 4, 1) X(12, 2, 4, 4, 8, 0)
+constexpr int kPackedTiles = 12;
 #ifndef FQT_DIRECT_STAGES
 #define FQT_DIRECT_STAGES 2
 #endif
 constexpr int kDirectStages = FQT_DIRECT_STAGES;  // K-steps in flight per wave
 inline bool is_direct_tile(int id) { return id > kStagedTiles; }
 inline bool direct_tile_multi_ok(int id) { return id == 11; }
+// Workgroup tile (rows x columns of C) of every tile id.
 inline void packed_tile_shape(int id, int* bm, int* bn) {
-  //                               1  2  3  4  5  6  7  8  9 10 11
-  static const int tm[kPackedTiles] = {1, 2, 2, 4, 2, 1, 4, 2, 4, 2, 1};
-  static const int tn[kPackedTiles] = {1, 2, 4, 4, 1, 2, 4, 4, 4, 4, 4};
-  static const int sk[kPackedTiles] = {1, 1, 1, 1, 1, 1, 4, 2, 1, 1, 1};
-  // side-by-side waves: 2x2 (SK 1), 2x1 (SK 2), 1x1 (SK 4)
-  const int s = sk[id - 1];
-  *bm = 16 * tm[id - 1] * (s == 4 ? 1 : 2);
-  *bn = 16 * tn[id - 1] * (s == 1 ? 2 : 1);
+  //                                     1   2    3    4   5   6   7   8    9   10   11  12
+  static const int m[kPackedTiles] = {32, 64, 64, 128, 64, 32, 64, 64, 128, 64, 32, 64};
+  static const int n[kPackedTiles] = {32, 64, 128, 128, 32, 64, 64, 64, 128, 128, 128, 64};
+  *bm = m[id - 1];
+  *bn = n[id - 1];
 }
 
 // ---- launchers (each returns the launch's hipError_t) ----------------------

@@ -180,6 +180,29 @@ __device__ __forceinline__ uint32_t lh_combine(const uint32_t (&u)[2 * KE - 1],
   return add_bytes_mod_p(Ls[il & tmask], Hs[ih & tmask], pp.fa);
 }
 
+// Workgroup -> output tile.  Workgroups reach the 8 XCDs round-robin
+// (workgroup i runs on XCD i % 8), and every XCD has its own L2; each XCD is
+// handed one rectangular block of the tile grid (2 x 4 or 4 x 2 blocks), so it
+// reads one band of A rows and one band of B columns instead of all of B.
+// Grids that do not split that way fall back to contiguous runs of tiles.
+__device__ __forceinline__ int xcd_tile(int bid, int tiles_m, int tiles_n) {
+  const int ntiles = tiles_m * tiles_n;
+  if (ntiles & 7) return bid;
+  const int x = bid & 7, r = bid >> 3;  // XCD, rank within the XCD
+  int gm, gn;
+  if (tiles_m % 2 == 0 && tiles_n % 4 == 0) {
+    gm = 2;
+    gn = 4;
+  } else if (tiles_m % 4 == 0 && tiles_n % 2 == 0) {
+    gm = 4;
+    gn = 2;
+  } else {
+    return x * (ntiles >> 3) + r;
+  }
+  const int bm = tiles_m / gm, bn = tiles_n / gn;  // block of bm x bn tiles
+  return ((x / gn) * bm + r / bn) * tiles_n + (x % gn) * bn + r % bn;
+}
+
 __device__ __forceinline__ void load_tables(const PackedParams& pp, uint32_t* Ls, uint32_t* Hs) {
   const int n = 1 << pp.tbl_log2;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {

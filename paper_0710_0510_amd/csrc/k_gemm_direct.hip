@@ -16,12 +16,15 @@
 // For k = 2 and TN = 4 every operand load is 8 bytes per lane, and 16 lanes
 // read one 128-byte run of a B row.
 //
-// Workgroup = 4 waves = SP waves side by side x SK waves splitting the
-// K-steps (SK = 1, 2, 4).  With SK > 1 the waves of one output tile run
+// Workgroup = 4 or 8 waves = SP waves side by side x SK waves splitting the
+// K-steps (SK = 1, 2, 4); with 8 waves every SIMD runs two, so one wave's
+// DQT and loads issue while the other's MFMAs occupy the matrix core.  With SK > 1 the waves of one output tile run
 // through disjoint K ranges and combine their (single-block, biased)
 // accumulators in LDS at the end: partial sums r_w are exact integers and
-// 2^52 + sum r_w stays exact while the total obeys eq. (2).  The owner of
-// MFMA row-block i is wave i % SK, which then finishes those outputs.
+// 2^52 + sum r_w stays exact while the total obeys eq. (2).  Accumulator
+// element v of MFMA row-block i (output rows 16i + l/16 + 4v) is owned by
+// split-K wave (4i + v) % SK, which adds the others' partials and finishes
+// those outputs.
 //
 // MFMA 16x16x4 f64 lane layout: A row l%16, k l/16; B k l/16, column l%16;
 // D element v at row l/16 + 4v, column l%16.
@@ -34,9 +37,9 @@ namespace fqt {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int KE, int TM, int TN, int SK>
+template <int KE, int TM, int TN, int SK, int NWV>
 struct DT {
-  static constexpr int SP = 4 / SK;            // waves side by side
+  static constexpr int SP = NWV / SK;          // waves side by side
   static constexpr int WGM = SP >= 2 ? 2 : 1;  // ... as WGM x WGN wave tiles
   static constexpr int WGN = SP / WGM;
   static constexpr int WM = 16 * TM, WN = 16 * TN;
@@ -46,8 +49,8 @@ struct DT {
   // LDS doubles for combining split-K partial accumulators
   static constexpr int RED = SK > 1 ? SP * TM * TN * (SK - 1) * 256 : 1;
   static_assert((TN * KE) % 4 == 0, "B row segments are whole words");
-  static_assert(SK == 1 || SK == 2 || SK == 4, "4 waves per workgroup");
-  static_assert(TM % SK == 0, "every wave finishes whole MFMA row-blocks");
+  static_assert((NWV == 4 || NWV == 8) && (SK == 1 || SK == 2 || SK == 4) && SP <= 4,
+                "4 or 8 waves: up to 4 side by side, up to 4 splitting K");
 };
 
 // Raw operand bytes of one K-step of one lane.
@@ -57,12 +60,12 @@ struct DStage {
   uint32_t b[4][TN * KE / 4];  // B rows 16s+4g+gk, columns wn0+TN*c .. +TN-1
 };
 
-template <int KE, int TM, int TN, int SK, int MODE, int PD>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD>
 __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int tile_n,
                                             const PackedParams& pp, double* __restrict__ red,
                                             const uint32_t* __restrict__ Ls,
                                             const uint32_t* __restrict__ Hs) {
-  using T = DT<KE, TM, TN, SK>;
+  using T = DT<KE, TM, TN, SK, NWV>;
   using St = DStage<KE, TM, TN>;
   constexpr bool MULTI = MODE != 0;
   static_assert(!(MULTI && SK > 1), "split-K waves combine single-block accumulators");
@@ -257,34 +260,34 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
     kloop(std::false_type{}, s_begin, s_end);
   }
 
-  // Split-K: hand the row-blocks this wave does not own to their owner.
+  // Split-K: hand the accumulator rows this wave does not own to their owner.
   if constexpr (SK > 1) {
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      const int own = i % SK;
-      if (own != kw) {
-        const int slot = (kw - own + SK) % SK - 1;
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            red[((((sw * TM + i) * (SK - 1) + slot) * TN + j) * 4 + v) * 64 + lane] =
-                acc[i][j][v] - kTwo52;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      if (i % SK == kw) {
-#pragma unroll
-        for (int slot = 0; slot < SK - 1; ++slot)
+      for (int v = 0; v < 4; ++v) {
+        const int own = (4 * i + v) % SK;
+        if (own != kw) {
+          const int slot = (kw - own + SK) % SK - 1;
 #pragma unroll
           for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-              acc[i][j][v] += red[((((sw * TM + i) * (SK - 1) + slot) * TN + j) * 4 + v) * 64 + lane];
+            red[(((((sw * TM + i) * 4 + v) * (SK - 1) + slot) * TN) + j) * 64 + lane] =
+                acc[i][j][v] - kTwo52;
+        }
       }
-    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        if ((4 * i + v) % SK == kw) {
+#pragma unroll
+          for (int slot = 0; slot < SK - 1; ++slot)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j][v] += red[(((((sw * TM + i) * 4 + v) * (SK - 1) + slot) * TN) + j) * 64 + lane];
+        }
+      }
   }
 
   // Epilogue: residues, L + H (Thm. 3), TN consecutive outputs per lane.
@@ -292,9 +295,9 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
   const int64_t col0 = wn0 + TN * c;
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
-    if (SK > 1 && i % SK != kw) continue;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
+      if (SK > 1 && (4 * i + v) % SK != kw) continue;
       uint32_t e[TN];
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
@@ -328,28 +331,25 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
   }
 }
 
-template <int KE, int TM, int TN, int SK, int MODE, int PD>
-__global__ __launch_bounds__(256) void gemm_direct_kernel(GemmArgs g, PackedParams pp,
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD>
+__global__ __launch_bounds__(64 * NWV) void gemm_direct_kernel(GemmArgs g, PackedParams pp,
                                                           int tiles_n, int ntiles) {
-  using T = DT<KE, TM, TN, SK>;
+  using T = DT<KE, TM, TN, SK, NWV>;
   __shared__ double red[T::RED];
   extern __shared__ uint32_t tabs[];
   uint32_t* Ls = tabs;
   uint32_t* Hs = tabs + (1 << pp.tbl_log2);
   load_tables(pp, Ls, Hs);
   __syncthreads();
-  // XCD-aware order: workgroups reach the 8 XCDs round-robin; give each XCD
-  // a contiguous run of tiles so that its L2 serves shared A rows / B columns.
-  int tile = blockIdx.x;
-  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-  direct_tile<KE, TM, TN, SK, MODE, PD>(g, tile / tiles_n, tile % tiles_n, pp, red, Ls, Hs);
+  const int tile = xcd_tile((int)blockIdx.x, ntiles / tiles_n, tiles_n);
+  direct_tile<KE, TM, TN, SK, NWV, MODE, PD>(g, tile / tiles_n, tile % tiles_n, pp, red, Ls, Hs);
 }
 
-template <int KE, int TM, int TN, int SK, int MODE, int PD>
-__global__ __launch_bounds__(256) void gemm_direct_batched_kernel(
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD>
+__global__ __launch_bounds__(64 * NWV) void gemm_direct_batched_kernel(
     const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items, int32_t n_items,
     uint32_t* counter, PackedParams pp) {
-  using T = DT<KE, TM, TN, SK>;
+  using T = DT<KE, TM, TN, SK, NWV>;
   __shared__ double red[T::RED];
   __shared__ int32_t cur;
   extern __shared__ uint32_t tabs[];
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void gemm_direct_batched_kernel(
     if (it >= n_items) break;
     const TileItem ti = items[it];
     const GemmArgs g = descs[ti.gemm];
-    direct_tile<KE, TM, TN, SK, MODE, PD>(g, ti.tm, ti.tn, pp, red, Ls, Hs);
+    direct_tile<KE, TM, TN, SK, NWV, MODE, PD>(g, ti.tm, ti.tn, pp, red, Ls, Hs);
   }
   // The last workgroup to leave resets the queue for the next launch (every
   // workgroup has made its final counter[0] increment before counter[1]).
@@ -381,36 +381,36 @@ __global__ __launch_bounds__(256) void gemm_direct_batched_kernel(
 
 // ---- dispatch ----------------------------------------------------------------
 
-template <int KE, int TM, int TN, int SK, int MODE>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE>
 static hipError_t direct_one(const GemmArgs& g, const PackedParams& pp, hipStream_t s) {
-  using T = DT<KE, TM, TN, SK>;
+  using T = DT<KE, TM, TN, SK, NWV>;
   const int tiles_m = (int)((g.M + T::BM - 1) / T::BM);
   const int tiles_n = (int)((g.N + T::BN - 1) / T::BN);
   const int ntiles = tiles_m * tiles_n;
   if (ntiles == 0) return hipSuccess;
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_direct_kernel<KE, TM, TN, SK, MODE, kDirectStages>), dim3(ntiles),
-                     dim3(256), dyn, s, g, pp, tiles_n, ntiles);
+  hipLaunchKernelGGL((gemm_direct_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages>), dim3(ntiles),
+                     dim3(64 * NWV), dyn, s, g, pp, tiles_n, ntiles);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, int SK, int MODE>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE>
 static hipError_t direct_batched(const GemmArgs* descs, const TileItem* items, int32_t n_items,
                                  uint32_t* counter, int grid, const PackedParams& pp,
                                  hipStream_t s) {
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_direct_batched_kernel<KE, TM, TN, SK, MODE, kDirectStages>),
-                     dim3(grid), dim3(256), dyn, s, descs, items, n_items, counter, pp);
+  hipLaunchKernelGGL((gemm_direct_batched_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages>),
+                     dim3(grid), dim3(64 * NWV), dyn, s, descs, items, n_items, counter, pp);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, int SK, int MODE>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE>
 static int direct_occupancy(uint32_t tbl_log2) {
   int blocks = 0;
   const size_t dyn = 2u * (1u << tbl_log2) * sizeof(uint32_t);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &blocks,
-          (const void*)gemm_direct_batched_kernel<KE, TM, TN, SK, MODE, kDirectStages>, 256,
+          (const void*)gemm_direct_batched_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages>, 64 * NWV,
           dyn) != hipSuccess)
     blocks = 1;
   return blocks > 0 ? blocks : 1;
@@ -418,10 +418,10 @@ static int direct_occupancy(uint32_t tbl_log2) {
 
 // Only the (tile, mode) pairs the host can ask for are instantiated: several
 // K-blocks only on MULTI_OK tiles, digit sums only where 2b <= 24.
-#define FQT_DIRECT_CASE(ID, TM, TN, SK, MULTI_OK)                            \
+#define FQT_DIRECT_CASE(ID, TM, TN, SK, NWV, MULTI_OK)                       \
   case ID:                                                                    \
     if constexpr ((MODE == 0 || MULTI_OK) && (MODE != 2 || digit_sums_fit<KE>())) \
-      return FN<KE, TM, TN, SK, MODE>(ARGS);                                  \
+      return FN<KE, TM, TN, SK, NWV, MODE>(ARGS);                             \
     else                                                                      \
       return FAIL;
 

@@ -306,10 +306,7 @@ __global__ __launch_bounds__(256) void gemm_packed_kernel(GemmArgs g, PackedPara
   uint32_t* Hs = tabs + (1 << pp.tbl_log2);
   load_tables(pp, Ls, Hs);
   __syncthreads();
-  // XCD-aware order: the 8 XCDs receive workgroups round-robin; give each XCD
-  // a contiguous run of tiles so that its L2 serves shared A rows / B columns.
-  int tile = blockIdx.x;
-  if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+  const int tile = xcd_tile((int)blockIdx.x, ntiles / tiles_n, tiles_n);
   packed_tile<KE, TM, TN, BK, MODE>(g, tile / tiles_n, tile % tiles_n, pp, As, Bs, Ls, Hs);
 }
 

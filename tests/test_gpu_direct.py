@@ -1,10 +1,11 @@
-"""Parity of the register-direct packed kernels (tile ids 7..11) with the
+"""Parity of the register-direct packed kernels (tile ids 7..12) with the
 oracle, through the C ABI.  Bit-exact: the canonical field element is unique.
 
-Tiles 7 and 8 split the K-steps across the waves of a workgroup (4 and 2
-ways) and combine the partial accumulators at the end; tiles 9..11 give every
-wave its own output tile.  Tiles 7..10 take one K-block (K <= n_q); tile 11
-also carries several (both boundary modes).
+Tiles 7, 8 and 12 split the K-steps across the waves of a workgroup (4, 2
+and 4 ways; tile 12 runs 8 waves, two per SIMD) and combine the partial
+accumulators at the end; tiles 9..11 give every wave its own output tile.
+All but tile 11 take one K-block (K <= n_q); tile 11 also carries several
+(both boundary modes).
 """
 import sys
 
@@ -20,8 +21,8 @@ torch = pytest.importorskip("torch")
 
 FIELDS = [(7, 2, (1, 0)), (3, 4, (2, 0, 0, 2)), (5, 3, (3, 3, 0)), (3, 2, (1, 0)),
           (2, 1, (1,)), (13, 1, (11,))]
-DIRECT = [7, 8, 9, 10, 11]
-SINGLE_ONLY = {7, 8, 9, 10}
+DIRECT = [7, 8, 9, 10, 11, 12]
+SINGLE_ONLY = {7, 8, 9, 10, 12}
 
 
 def note(msg):
@@ -87,10 +88,10 @@ def test_direct_shapes(p, k, P, tile):
         assert np.array_equal(C, want), (M, N, K)
 
 
-@pytest.mark.parametrize("tile", [7, 8, 11])
+@pytest.mark.parametrize("tile", [7, 8, 11, 12])
 def test_direct_split_k_edges(tile):
-    # K-steps of 16 shared by 4 (tile 7) or 2 (tile 8) waves: fewer steps than
-    # waves, a ragged last step, steps that do not divide evenly
+    # K-steps of 16 shared by 4 (tiles 7, 12) or 2 (tile 8) waves: fewer steps
+    # than waves, a ragged last step, steps that do not divide evenly
     p, k, P = 7, 2, (1, 0)
     for K in [0, 1, 3, 15, 16, 17, 31, 32, 48, 63, 64, 65, 80, 127, 1819, 1820]:
         note(f"direct split-K edges tile={tile} K={K}")
@@ -99,7 +100,7 @@ def test_direct_split_k_edges(tile):
 
 
 @pytest.mark.parametrize("p,k,P", FIELDS[:4])
-@pytest.mark.parametrize("tile", [7, 8, 9, 11])
+@pytest.mark.parametrize("tile", [7, 8, 9, 11, 12])
 def test_direct_adversarial_single_block(p, k, P, tile):
     # every coefficient p-1 and K = n_q: the packed sums reach eq. (2)'s bound
     nq = min(nq_direct(p, k), 3000)

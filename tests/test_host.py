@@ -152,10 +152,10 @@ def test_gemm_validation_errors():
 
 
 def test_direct_tiles_refuse_several_blocks():
-    # register-direct tiles 7..10 hold no per-element block state: K > n_q is
-    # refused on the host; tile 11 carries it
+    # register-direct tiles other than 11 hold no per-element block state:
+    # K > n_q is refused on the host; tile 11 carries it
     f = fqt.Field(3, 4, (2, 0, 0, 2))          # q = 2^7, n_q <= 7
-    for tile in (7, 8, 9, 10):
+    for tile in (7, 8, 9, 10, 12):
         assert _gemm_status(f, "packed", 4, 4, 64, 64, 4, 4,
                             opts={"tile": tile}) == "FQT_ERR_UNSUPPORTED"
     g = fqt.Field(7, 2, (1, 0))                # q = 2^17, n_q <= 1820
@@ -209,7 +209,7 @@ def test_autotune_argument_errors():
 
 
 def test_tile_counts():
-    assert fqt.tile_count("packed") == 11
+    assert fqt.tile_count("packed") == 12
     assert fqt.tile_count("int8") == 3
 
 
