@@ -115,14 +115,4 @@ __device__ __forceinline__ uint32_t load_elem(const uint8_t* src) {
   }
 }
 
-// DQT of one element (Section 2, shifts for q = 2^b, Section 2's remark):
-// sum_j coeff_j << (b*j).  The host guarantees the sum is below 2^32.
-template <int KE>
-__device__ __forceinline__ uint32_t dqt_shift(uint32_t e, uint32_t b) {
-  uint32_t v = e & 0xffu;
-#pragma unroll
-  for (int j = 1; j < KE; ++j) v |= ((e >> (8 * j)) & 0xffu) << (b * (uint32_t)j);
-  return v;
-}
-
 }  // namespace fqt

@@ -42,22 +42,74 @@ constexpr uint64_t digit_mask(int nd, uint32_t b, int parity) {
   return m;
 }
 
-// Element e (0..NWD*4/KE - 1) of a little-endian run of NWD words holding
-// consecutive KE-byte elements: its bytes in the low bytes of the result
-// (higher bytes are whatever follows; dqt_shift reads only the low KE).
-template <int KE, int NWD>
-__device__ __forceinline__ uint32_t seg_elem(const uint32_t (&raw)[NWD], int e) {
-  const int o = e * KE;
-  const uint32_t lo = raw[o >> 2];
-  if ((o & 3) == 0) return lo;
-  const uint32_t hi = ((o >> 2) + 1 < NWD) ? raw[(o >> 2) + 1] : 0u;
-  return __builtin_amdgcn_alignbyte(hi, lo, o & 3);
+// Byte-select forms of a shift and an add (gfx9 SDWA: an operand can be one
+// zero-extended byte of a register), so that a coefficient byte enters the
+// DQT sum without a separate extract instruction.
+#define FQT_SDWA_BYTE(S)                                                            \
+  __device__ __forceinline__ uint32_t byte_shl_##S(uint32_t w, uint32_t s) {      \
+    uint32_t r;                                                                     \
+    asm("v_lshlrev_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD "        \
+        "src0_sel:DWORD src1_sel:BYTE_" #S                                          \
+        : "=v"(r)                                                                   \
+        : "v"(s), "v"(w));                                                          \
+    return r;                                                                       \
+  }                                                                                 \
+  __device__ __forceinline__ uint32_t add_byte_##S(uint32_t v, uint32_t w) {      \
+    uint32_t r;                                                                     \
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD "            \
+        "src0_sel:DWORD src1_sel:BYTE_" #S                                          \
+        : "=v"(r)                                                                   \
+        : "v"(v), "v"(w));                                                          \
+    return r;                                                                       \
+  }
+FQT_SDWA_BYTE(0)
+FQT_SDWA_BYTE(1)
+FQT_SDWA_BYTE(2)
+FQT_SDWA_BYTE(3)
+#undef FQT_SDWA_BYTE
+
+// byte `sel` (a constant after unrolling) of w, shifted left by s
+__device__ __forceinline__ uint32_t byte_shl(uint32_t w, int sel, uint32_t s) {
+  switch (sel) {
+    case 0: return byte_shl_0(w, s);
+    case 1: return byte_shl_1(w, s);
+    case 2: return byte_shl_2(w, s);
+    default: return byte_shl_3(w, s);
+  }
+}
+// v + byte `sel` of w
+__device__ __forceinline__ uint32_t add_byte(uint32_t v, uint32_t w, int sel) {
+  switch (sel) {
+    case 0: return add_byte_0(v, w);
+    case 1: return add_byte_1(v, w);
+    case 2: return add_byte_2(v, w);
+    default: return add_byte_3(v, w);
+  }
 }
 
-// DQT of one element straight to binary64 (exact: the value is < 2^32).
-template <int KE>
-__device__ __forceinline__ double packed_value(uint32_t bytes, uint32_t b) {
-  return (double)dqt_shift<KE>(bytes, b);
+// Shift amounts j*b of the DQT at q = 2^b (Section 2: multiplication by q^j
+// is a shift), j < 4.
+struct DqtShifts {
+  uint32_t s[4];
+  __device__ __forceinline__ explicit DqtShifts(uint32_t b) : s{0u, b, 2u * b, 3u * b} {}
+};
+
+// DQT of element e of a little-endian run of NWD words holding consecutive
+// KE-byte elements, straight to binary64: sum_j c_j << (j*b), exact since the
+// host keeps it below 2^32.  KE - 1 byte-select shifts and adds (KE = 1: one
+// extract) and one conversion; elements that straddle words need no realign.
+template <int KE, int NWD>
+__device__ __forceinline__ double packed_elem(const uint32_t (&raw)[NWD], int e,
+                                              const DqtShifts& sh) {
+  const int o = e * KE;
+  if constexpr (KE == 1) {
+    return (double)((raw[o >> 2] >> (8 * (o & 3))) & 0xffu);
+  } else {
+    uint32_t v = add_byte(byte_shl(raw[(o + 1) >> 2], (o + 1) & 3, sh.s[1]), raw[o >> 2], o & 3);
+#pragma unroll
+    for (int j = 2; j < KE; ++j) v += byte_shl(raw[(o + j) >> 2], (o + j) & 3, sh.s[j]);
+    return (double)v;
+  }
 }
 
 template <int KE, int MODE>

@@ -76,6 +76,7 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
   const int64_t wm0 = (int64_t)tile_m * T::BM + (sw / T::WGN) * T::WM;
   const int64_t wn0 = (int64_t)tile_n * T::BN + (sw % T::WGN) * T::WN;
   const uint32_t b = MODE ? multi_block_b<KE>() : pp.b;
+  const DqtShifts sh(b);
   const bool inner = pp.aligned != 0 && wm0 + T::WM <= g.M && wn0 + T::WN <= g.N;
 
   const int64_t nks = (g.K + 15) / 16;  // K-steps
@@ -194,11 +195,11 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int gk = 0; gk < 4; ++gk) av[i][gk] = packed_value<KE>(seg_elem<KE, KE>(x.a[i], gk), b);
+      for (int gk = 0; gk < 4; ++gk) av[i][gk] = packed_elem<KE, KE>(x.a[i], gk, sh);
 #pragma unroll
     for (int gk = 0; gk < 4; ++gk)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) bv[gk][j] = packed_value<KE>(seg_elem<KE, T::BW>(x.b[gk], j), b);
+      for (int j = 0; j < TN; ++j) bv[gk][j] = packed_elem<KE, T::BW>(x.b[gk], j, sh);
   };
   auto mfma_step = [&](const double (&av)[TM][4], const double (&bv)[4][TN]) {
 #pragma unroll

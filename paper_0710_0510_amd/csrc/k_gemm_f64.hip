@@ -93,6 +93,7 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   // Several K-blocks: q is the largest power of two eq. (2) admits, fixed at
   // compile time so that digit windows become constant bit-field extracts.
   const uint32_t b = MODE ? multi_block_b<KE>() : pp.b;
+  const DqtShifts sh(b);
   // Interior tiles (and full K-tiles) load without bounds checks.
   const bool interior = aligned && m0 + T::BM <= g.M && n0 + T::BN <= g.N;
   // Padded K-blocks: blk_real products in blk_slots = 4 * nq_groups MFMA
@@ -209,13 +210,13 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         as[(arow + r * ARS) * T::SA + 4 * akc + e] =
-            (double)dqt_shift<KE>(seg_elem<KE, KE>(ra[r], e), b);
+            packed_elem<KE, KE>(ra[r], e, sh);
 #pragma unroll
     for (int r = 0; r < T::RB; ++r)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] =
-            (double)dqt_shift<KE>(seg_elem<KE, KE>(rb[r], e), b);
+            packed_elem<KE, KE>(rb[r], e, sh);
   };
 
   uint32_t nbound = 0;
