@@ -178,6 +178,7 @@ struct fqt_field_s {
   std::vector<std::unique_ptr<BatchPlan>> plans;
   std::map<std::string, TuneEntry> tuned;
   std::map<int, Workspace> ws;  // per device: B' of the INT8 path
+  std::map<int, uint8_t*> dev_mt;  // per device: multiplication-matrix table
 };
 
 namespace {
@@ -261,6 +262,50 @@ fqt_status device_tables(fqt_field_s* f, uint64_t q, DevTables* out) {
   FQT_HIP(hipMemcpy(dt.H, ht.second.data(), bytes, hipMemcpyHostToDevice));
   f->dev_tables[key] = dt;
   *out = dt;
+  return ok();
+}
+
+// Multiplication-matrix table of the INT8 path: for every binary index
+// idx = sum_j c_j << (cb j) of an element b (Section 5.3's indexing), entry
+// idx holds at byte s*k + i coefficient s of X^i * b mod P (the matrix of
+// a -> a*b, transposed), mt_stride(k) bytes per entry; indices with a digit
+// >= p hold zeros.
+
+fqt_status device_mt(fqt_field_s* f, uint8_t** out) {
+  std::lock_guard<std::mutex> lk(f->mu);
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  auto it = f->dev_mt.find(dev);
+  if (it != f->dev_mt.end()) {
+    *out = it->second;
+    return ok();
+  }
+  const uint32_t k = f->k, p = f->p, cb = f->cb, stride = mt_stride(k);
+  const size_t n = (size_t)1 << f->tbl_log2;
+  std::vector<uint8_t> mt(n * stride, 0);
+  for (size_t idx = 0; idx < n; ++idx) {
+    std::vector<uint32_t> b(k);
+    bool valid = true;
+    for (uint32_t j = 0; j < k; ++j) {
+      b[j] = (uint32_t)(idx >> (cb * j)) & ((1u << cb) - 1);
+      valid = valid && b[j] < p;
+    }
+    if (!valid) continue;
+    std::vector<uint32_t> row = b;  // X^i * b mod P, i = 0, 1, ...
+    for (uint32_t i = 0; i < k; ++i) {
+      for (uint32_t sidx = 0; sidx < k; ++sidx) mt[idx * stride + sidx * k + i] = (uint8_t)row[sidx];
+      // row <- X * row mod P: shift up, then X^k = -sum P_low[s] X^s
+      const uint32_t top = row[k - 1];
+      for (uint32_t sidx = k - 1; sidx > 0; --sidx)
+        row[sidx] = (row[sidx - 1] + top * (p - f->P_low[sidx] % p)) % p;
+      row[0] = (top * (p - f->P_low[0] % p)) % p;
+    }
+  }
+  uint8_t* d = nullptr;
+  FQT_HIP(hipMalloc(&d, mt.size()));
+  FQT_HIP(hipMemcpy(d, mt.data(), mt.size(), hipMemcpyHostToDevice));
+  f->dev_mt[dev] = d;
+  *out = d;
   return ok();
 }
 
@@ -463,6 +508,14 @@ void fqt_field_destroy(fqt_field f) {
     if (hipGetDevice(&cur) == hipSuccess) {
       hipSetDevice(kv.first);
       hipFree(kv.second.ptr);
+      hipSetDevice(cur);
+    }
+  }
+  for (auto& kv : f->dev_mt) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+      hipSetDevice(kv.first);
+      hipFree(kv.second);
       hipSetDevice(cur);
     }
   }
@@ -689,15 +742,17 @@ static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmAr
   const int64_t k = f->k, p = f->p;
   uint32_t tile = (opts && opts->tile) ? opts->tile : 0;
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
-  const int64_t Kpad = (g.K + 127) / 128 * 128;
-  const int64_t KKpad = Kpad * k, NN = g.N * k, KK = g.K * k;
+  // B'^T rows are padded to whole 128-byte K-tiles of the INT8 GEMM
+  const int64_t NN = g.N * k, KK = g.K * k, KKpad = (KK + 127) / 128 * 128;
   if (!tile) tile = (g.M >= 1024 && NN >= 1024) ? 2 : 1;
   uint8_t* ws = nullptr;
   fqt_status st = workspace(f, (size_t)std::max<int64_t>(NN * KKpad, 1), &ws);
   if (st) return st;
-  PlainFieldArgs pf{};
-  for (int i = 0; i < (int)k; ++i) pf.P_low[i] = f->P_low[i];
-  FQT_HIP(launch_expand_b((int)k, g.B, g.ldb, g.K, g.N, (uint32_t)p, pf, ws, KKpad, Kpad, s));
+  uint8_t* mt = nullptr;
+  st = device_mt(f, &mt);
+  if (st) return st;
+  FQT_HIP(launch_expand_b((int)k, g.B, g.ldb, g.K, g.N, mt, f->cb, f->tbl_log2, ws, KKpad, KKpad,
+                          s));
   I8Args a{};
   a.A = g.A;
   a.lda = g.lda * k;
@@ -877,6 +932,9 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
   const int tag[2] = {-(int)tile, dev};  // negative: INT8 plans never match packed ones
   std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, tag, sizeof tag);
 
+  uint8_t* mt = nullptr;  // before taking the field lock (device_mt takes it)
+  fqt_status mst = device_mt(f, &mt);
+  if (mst) return mst;
   std::lock_guard<std::mutex> lk(f->mu);
   BatchPlan* plan = nullptr;
   for (auto& pp : f->plans)
@@ -890,9 +948,9 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
     std::vector<size_t> ws_off(count);
     for (int64_t i = 0; i < count; ++i) {
       const fqt_gemm_desc& d = descs[i];
-      const int64_t Kpad = (d.K + 127) / 128 * 128;
+      const int64_t KKpad = (d.K * k + 127) / 128 * 128;
       ws_off[i] = ws_total;
-      ws_total += ((size_t)(d.N * k) * (size_t)(Kpad * k) + 255) / 256 * 256;
+      ws_total += ((size_t)(d.N * k) * (size_t)KKpad + 255) / 256 * 256;
     }
     auto pl = std::make_unique<BatchPlan>();
     pl->key = key;
@@ -901,18 +959,18 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
       return fail(FQT_ERR_OOM, "INT8 batch workspace of %zu bytes", ws_total);
     for (int64_t i = 0; i < count; ++i) {
       const fqt_gemm_desc& d = descs[i];
-      const int64_t Kpad = (d.K + 127) / 128 * 128;
+      const int64_t KKpad = (d.K * k + 127) / 128 * 128;
       I8Batch& b = gs[i];
       b.a.A = d.A;
       b.a.lda = d.lda * k;
       b.a.Bt = pl->d_ws + ws_off[i];
-      b.a.ldbt = Kpad * k;
+      b.a.ldbt = KKpad;
       b.a.C = d.C;
       b.a.ldc = d.ldc * k;
       b.a.M = d.M;
       b.a.NN = d.N * k;
       b.a.KK = d.K * k;
-      b.a.KKpad = Kpad * k;
+      b.a.KKpad = KKpad;
       b.a.p = (uint32_t)p;
       b.a.red_tiles = i8_red_tiles(d.K * k, p);
       b.a.a_vec = row_align(d.A, d.lda * k);
@@ -921,9 +979,11 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
       b.ldb = d.ldb;
       b.K = d.K;
       b.N = d.N;
+      // 32 x 64-element expansion blocks covering the padded row
+      const int64_t lcols = (KKpad + k - 1) / k;
       if (d.K && d.N)
-        for (int32_t lb = 0; lb < (int32_t)(Kpad / 32); ++lb)
-          for (int32_t nb = 0; nb < (int32_t)((d.N + 31) / 32); ++nb)
+        for (int32_t lb = 0; lb < (int32_t)((lcols + 31) / 32); ++lb)
+          for (int32_t nb = 0; nb < (int32_t)((d.N + 63) / 64); ++nb)
             exps.push_back(ExpandItem{(int32_t)i, lb, nb, 0});
       const int tm = (int)((d.M + bm - 1) / bm), tn = (int)((d.N * k + bn - 1) / bn);
       for (int a = 0; a < tm; ++a)
@@ -949,12 +1009,10 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
     FQT_HIP(hipGetDeviceProperties(&prop, dev));
     pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * i8_batched_occupancy((int)tile),
                                          std::max<int32_t>(pl->n_items, 1)));
-    PlainFieldArgs pf{};
-    for (int i = 0; i < (int)k; ++i) pf.P_low[i] = f->P_low[i];
     FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_expand_b_batched((int)k, pl->d_i8, pl->d_exp, (int32_t)exps.size(),
-                                            (uint32_t)p, pf, pl->cap_stream);
+                                            mt, f->cb, f->tbl_log2, pl->cap_stream);
     if (le == hipSuccess && pl->n_items > 0)
       le = launch_gemm_i8_batched((int)tile, pl->d_i8, pl->d_items, pl->n_items, pl->d_counter,
                                   pl->grid, pl->cap_stream);

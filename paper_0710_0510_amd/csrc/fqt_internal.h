@@ -60,7 +60,11 @@ struct I8Batch {
   int64_t ldb, K, N;  // B is K x N elements, ldb elements per row
 };
 
-// One 32 x 32 block of the B -> B'^T expansion of a batch.
+// Bytes per entry of the INT8 path's multiplication-matrix table (k^2 bytes
+// padded to 4 or 16).
+__host__ __device__ constexpr uint32_t mt_stride(uint32_t k) { return k <= 2 ? 4u : 16u; }
+
+// One 32 (K) x 64 (N) block of the B -> B'^T expansion of a batch.
 struct ExpandItem {
   int32_t gemm, lb, nb, pad;
 };
@@ -141,12 +145,12 @@ int direct_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2);
 // INT8 path: B -> B'^T expansion, then the INT8 MFMA GEMM (tile ids 1..3).
 constexpr int kInt8Tiles = 3;
 hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
-                           uint32_t p, const PlainFieldArgs& pf, uint8_t* Bt, int64_t ldbt,
-                           int64_t Kpad, hipStream_t s);
+                           const uint8_t* mt, uint32_t cb, uint32_t tbl_log2, uint8_t* Bt,
+                           int64_t ldbt, int64_t Kpad, hipStream_t s);
 hipError_t launch_gemm_i8(int tile, const I8Args& a, hipStream_t s);
 hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* items,
-                                   int32_t n_items, uint32_t p, const PlainFieldArgs& pf,
-                                   hipStream_t s);
+                                   int32_t n_items, const uint8_t* mt, uint32_t cb,
+                                   uint32_t tbl_log2, hipStream_t s);
 hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* items,
                                   int32_t n_items, uint32_t* counter, int grid, hipStream_t s);
 int i8_batched_occupancy(int tile);

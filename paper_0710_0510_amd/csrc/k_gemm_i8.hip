@@ -28,85 +28,158 @@ namespace fqt {
 typedef int v4i __attribute__((ext_vector_type(4)));
 
 // ---- B -> B'^T expansion ------------------------------------------------------
+//
+// Row n*k + s of B'^T holds, at columns l*k .. l*k + k-1, coefficient s of
+// X^i * B[l][n] mod P for i = 0..k-1: k bytes of the element's multiplication
+// matrix, read from a table indexed like L and H (mt, stride mt_stride(k)).
+// A workgroup expands a block of 32 (l) x 64 (n) elements: it stages the
+// block's B bytes in LDS (rows l, coalesced loads), then every thread writes
+// whole runs of E consecutive elements (16 bytes; 12 for k = 3) of one output
+// row, so consecutive threads store consecutive pieces of a row.  Columns at
+// or beyond KKpad (the padded row length) are not written; elements l >= K
+// expand to zeros.
 
-// Expand the 32 (l) x 32 (n) block of B at (l0, n0): output row n*k+s holds,
-// at column l*k+i, coefficient s of X^i * B[l][n] mod P.
+template <int KE>
+struct EXP {
+  static constexpr int L = 32, NB = 64;
+  static constexpr int RB = NB * KE;               // B bytes of one block row
+  static constexpr int RS = RB + 4;                // LDS row stride (bytes)
+  static constexpr int E = KE == 3 ? 4 : 16 / KE;  // elements per output run
+  static constexpr int RUN = E * KE;               // bytes per output run
+  static constexpr int NRUN = L / E;               // runs per block row of B'^T
+  static constexpr int MTS = (int)mt_stride(KE);
+};
+
+__device__ __forceinline__ void load_mt(const uint8_t* __restrict__ mt, uint32_t tbl_log2,
+                                        uint32_t mts, uint8_t* __restrict__ lds) {
+  const int words = (int)(((size_t)1 << tbl_log2) * mts / 4);
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(mt);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(lds);
+  for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+}
+
 template <int KE>
 __device__ __forceinline__ void expand_block(const uint8_t* __restrict__ B, int64_t ldb, int64_t K,
-                                             int64_t N, uint32_t p, const PlainFieldArgs& pf,
-                                             uint8_t* __restrict__ Bt, int64_t ldbt, int64_t l0,
-                                             int64_t n0, uint8_t (*tile)[32 * KE + 4]) {
-  for (int e = threadIdx.x; e < 32 * 32; e += 256) {
-    const int ll = e >> 5, nl = e & 31;  // consecutive threads -> consecutive n (coalesced)
-    const int64_t l = l0 + ll, n = n0 + nl;
-    uint32_t c[KE];
+                                             int64_t N, const uint8_t* __restrict__ mts,
+                                             uint32_t cb, uint32_t tmask, uint8_t* __restrict__ Bt,
+                                             int64_t ldbt, int64_t KKpad, int64_t l0, int64_t n0,
+                                             uint8_t* __restrict__ tile) {
+  using X = EXP<KE>;
+  // the block's B bytes, zero beyond row K and column N
+  const bool al = ((((uintptr_t)B) | (uintptr_t)(ldb * KE)) & 3) == 0;
+  const int64_t rowbytes = N * KE;
+  for (int e = threadIdx.x; e < X::L * (X::RB / 4); e += blockDim.x) {
+    const int r = e / (X::RB / 4), c4 = (e % (X::RB / 4)) * 4;
+    const int64_t l = l0 + r, col = n0 * KE + c4;
+    uint32_t w = 0;
+    if (l < K) {
+      const uint8_t* src = B + l * ldb * KE + col;
+      if (al && col + 4 <= rowbytes) {
+        w = *reinterpret_cast<const uint32_t*>(src);
+      } else {
 #pragma unroll
-    for (int s = 0; s < KE; ++s) c[s] = 0;
-    if (l < K && n < N) {
-      const uint8_t* src = B + (l * ldb + n) * KE;
-#pragma unroll
-      for (int s = 0; s < KE; ++s) c[s] = src[s];
+        for (int j = 0; j < 4; ++j)
+          if (col + j < rowbytes) w |= (uint32_t)src[j] << (8 * j);
+      }
     }
-    // row i of the multiplication matrix: X^i * b mod P, by repeated X-shifts
-#pragma unroll
-    for (int i = 0; i < KE; ++i) {
-#pragma unroll
-      for (int s = 0; s < KE; ++s) tile[nl * KE + s][ll * KE + i] = (uint8_t)c[s];
-      // c <- X*c mod P: shift up, then X^k = -sum P_low[s] X^s
-      const uint32_t top = c[KE - 1];
-#pragma unroll
-      for (int s = KE - 1; s > 0; --s) c[s] = (c[s - 1] + top * (p - pf.P_low[s])) % p;
-      c[0] = (top * (p - pf.P_low[0])) % p;
-    }
+    *reinterpret_cast<uint32_t*>(tile + r * X::RS + c4) = w;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 32 * KE * 32 * KE; e += 256) {
-    const int r = e / (32 * KE), cc = e % (32 * KE);
-    const int64_t orow = n0 * KE + r;
-    if (orow < N * KE) Bt[orow * ldbt + l0 * KE + cc] = tile[r][cc];
+  for (int t = threadIdx.x; t < X::NB * X::NRUN; t += blockDim.x) {
+    const int n = t / X::NRUN, run = t % X::NRUN;
+    const int64_t col0 = (l0 + run * X::E) * KE;  // first byte column of the run
+    if (n0 + n >= N || col0 >= KKpad) continue;
+    uint32_t ent[X::E][X::MTS / 4];
+#pragma unroll
+    for (int e = 0; e < X::E; ++e) {
+      const uint8_t* eb = tile + (run * X::E + e) * X::RS + n * KE;
+      uint32_t idx = 0;
+#pragma unroll
+      for (int j = 0; j < KE; ++j) idx |= (uint32_t)eb[j] << (cb * j);
+      const uint32_t* m = reinterpret_cast<const uint32_t*>(mts + (size_t)(idx & tmask) * X::MTS);
+#pragma unroll
+      for (int w = 0; w < X::MTS / 4; ++w) ent[e][w] = m[w];
+    }
+#pragma unroll
+    for (int s = 0; s < KE; ++s) {
+      uint32_t out[X::RUN / 4];
+#pragma unroll
+      for (int w = 0; w < X::RUN / 4; ++w) out[w] = 0;
+#pragma unroll
+      for (int e = 0; e < X::E; ++e)
+#pragma unroll
+        for (int i = 0; i < KE; ++i) {
+          const int src = s * KE + i, pos = e * KE + i;
+          const uint32_t byte = (ent[e][src >> 2] >> (8 * (src & 3))) & 0xffu;
+          out[pos >> 2] |= byte << (8 * (pos & 3));
+        }
+      uint8_t* dst = Bt + ((n0 + n) * KE + s) * ldbt + col0;
+      if constexpr (X::RUN == 16) {
+        // 16-byte runs never straddle the 128-byte padding
+        *reinterpret_cast<uint4*>(dst) = make_uint4(out[0], out[1], out[2], out[3]);
+      } else {
+#pragma unroll
+        for (int w = 0; w < X::RUN / 4; ++w)
+          if (col0 + 4 * w < KKpad) reinterpret_cast<uint32_t*>(dst)[w] = out[w];
+      }
+    }
   }
 }
 
 template <int KE>
 __global__ __launch_bounds__(256) void expand_b_kernel(const uint8_t* __restrict__ B, int64_t ldb,
-                                                       int64_t K, int64_t N, uint32_t p,
-                                                       PlainFieldArgs pf,
-                                                       uint8_t* __restrict__ Bt, int64_t ldbt) {
-  __shared__ uint8_t tile[32 * KE][32 * KE + 4];
-  expand_block<KE>(B, ldb, K, N, p, pf, Bt, ldbt, (int64_t)blockIdx.x * 32,
-                   (int64_t)blockIdx.y * 32, tile);
+                                                       int64_t K, int64_t N,
+                                                       const uint8_t* __restrict__ mt,
+                                                       uint32_t cb, uint32_t tbl_log2,
+                                                       uint8_t* __restrict__ Bt, int64_t ldbt,
+                                                       int64_t KKpad) {
+  using X = EXP<KE>;
+  __shared__ __align__(16) uint8_t tile[X::L * X::RS];
+  extern __shared__ __align__(16) uint8_t mts[];
+  load_mt(mt, tbl_log2, X::MTS, mts);
+  expand_block<KE>(B, ldb, K, N, mts, cb, (1u << tbl_log2) - 1u, Bt, ldbt, KKpad,
+                   (int64_t)blockIdx.x * X::L, (int64_t)blockIdx.y * X::NB, tile);
 }
 
-// Batched expansion: one workgroup per (product, 32 x 32 block) item.
+// Batched expansion: one workgroup per (product, 64 x 64 block) item.
 template <int KE>
 __global__ __launch_bounds__(256) void expand_b_batched_kernel(const I8Batch* __restrict__ gs,
                                                                const ExpandItem* __restrict__ items,
-                                                               uint32_t p, PlainFieldArgs pf) {
-  __shared__ uint8_t tile[32 * KE][32 * KE + 4];
+                                                               const uint8_t* __restrict__ mt,
+                                                               uint32_t cb, uint32_t tbl_log2) {
+  using X = EXP<KE>;
+  __shared__ __align__(16) uint8_t tile[X::L * X::RS];
+  extern __shared__ __align__(16) uint8_t mts[];
+  load_mt(mt, tbl_log2, X::MTS, mts);
   const ExpandItem it = items[blockIdx.x];
   const I8Batch g = gs[it.gemm];
-  expand_block<KE>(g.B, g.ldb, g.K, g.N, p, pf, const_cast<uint8_t*>(g.a.Bt), g.a.ldbt,
-                   (int64_t)it.lb * 32, (int64_t)it.nb * 32, tile);
+  expand_block<KE>(g.B, g.ldb, g.K, g.N, mts, cb, (1u << tbl_log2) - 1u,
+                   const_cast<uint8_t*>(g.a.Bt), g.a.ldbt, g.a.KKpad, (int64_t)it.lb * X::L,
+                   (int64_t)it.nb * X::NB, tile);
 }
 
 template <int KE>
-static hipError_t launch_expand(const uint8_t* B, int64_t ldb, int64_t K, int64_t N, uint32_t p,
-                                const PlainFieldArgs& pf, uint8_t* Bt, int64_t ldbt,
-                                int64_t Kpad, hipStream_t s) {
-  const dim3 grid((unsigned)(Kpad / 32), (unsigned)((N + 31) / 32));
-  hipLaunchKernelGGL(expand_b_kernel<KE>, grid, dim3(256), 0, s, B, ldb, K, N, p, pf, Bt, ldbt);
+static hipError_t launch_expand(const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
+                                const uint8_t* mt, uint32_t cb, uint32_t tbl_log2, uint8_t* Bt,
+                                int64_t ldbt, int64_t KKpad, hipStream_t s) {
+  using X = EXP<KE>;
+  const int64_t lcols = (KKpad + KE - 1) / KE;  // elements covering the padded row
+  const dim3 grid((unsigned)((lcols + X::L - 1) / X::L), (unsigned)((N + X::NB - 1) / X::NB));
+  const size_t dyn = ((size_t)1 << tbl_log2) * X::MTS;
+  hipLaunchKernelGGL(expand_b_kernel<KE>, grid, dim3(256), dyn, s, B, ldb, K, N, mt, cb, tbl_log2,
+                     Bt, ldbt, KKpad);
   return hipGetLastError();
 }
 
 hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
-                           uint32_t p, const PlainFieldArgs& pf, uint8_t* Bt, int64_t ldbt,
-                           int64_t Kpad, hipStream_t s) {
-  if (K == 0 || N == 0) return hipSuccess;
+                           const uint8_t* mt, uint32_t cb, uint32_t tbl_log2, uint8_t* Bt,
+                           int64_t ldbt, int64_t KKpad, hipStream_t s) {
+  if (N == 0 || KKpad == 0) return hipSuccess;
   switch (k) {
-    case 1: return launch_expand<1>(B, ldb, K, N, p, pf, Bt, ldbt, Kpad, s);
-    case 2: return launch_expand<2>(B, ldb, K, N, p, pf, Bt, ldbt, Kpad, s);
-    case 3: return launch_expand<3>(B, ldb, K, N, p, pf, Bt, ldbt, Kpad, s);
-    case 4: return launch_expand<4>(B, ldb, K, N, p, pf, Bt, ldbt, Kpad, s);
+    case 1: return launch_expand<1>(B, ldb, K, N, mt, cb, tbl_log2, Bt, ldbt, KKpad, s);
+    case 2: return launch_expand<2>(B, ldb, K, N, mt, cb, tbl_log2, Bt, ldbt, KKpad, s);
+    case 3: return launch_expand<3>(B, ldb, K, N, mt, cb, tbl_log2, Bt, ldbt, KKpad, s);
+    case 4: return launch_expand<4>(B, ldb, K, N, mt, cb, tbl_log2, Bt, ldbt, KKpad, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -332,14 +405,18 @@ hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* i
 }
 
 hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* items,
-                                   int32_t n_items, uint32_t p, const PlainFieldArgs& pf,
-                                   hipStream_t s) {
+                                   int32_t n_items, const uint8_t* mt, uint32_t cb,
+                                   uint32_t tbl_log2, hipStream_t s) {
   if (n_items == 0) return hipSuccess;
+  const size_t dyn = ((size_t)1 << tbl_log2) * mt_stride((uint32_t)k);
   switch (k) {
-    case 1: hipLaunchKernelGGL(expand_b_batched_kernel<1>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
-    case 2: hipLaunchKernelGGL(expand_b_batched_kernel<2>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
-    case 3: hipLaunchKernelGGL(expand_b_batched_kernel<3>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
-    case 4: hipLaunchKernelGGL(expand_b_batched_kernel<4>, dim3(n_items), dim3(256), 0, s, gs, items, p, pf); break;
+#define FQT_EXP_CASE(KE)                                                                   \
+  case KE:                                                                                 \
+    hipLaunchKernelGGL(expand_b_batched_kernel<KE>, dim3(n_items), dim3(256), dyn, s, gs, \
+                       items, mt, cb, tbl_log2);                                           \
+    break;
+    FQT_EXP_CASE(1) FQT_EXP_CASE(2) FQT_EXP_CASE(3) FQT_EXP_CASE(4)
+#undef FQT_EXP_CASE
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
