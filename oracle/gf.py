@@ -419,3 +419,68 @@ def binary_index(uw: Sequence[int], p: int) -> int:
     u_0 least significant."""
     c = max(1, (p - 1).bit_length())
     return sum(int(x) << (c * i) for i, x in enumerate(uw))
+
+
+# ---------------------------------------------------------------------------
+# d-FQT: long polynomials in chunks of d+1 coefficients (Section 6)
+# ---------------------------------------------------------------------------
+
+
+def polymul_long(a: Sequence[int], b: Sequence[int], p: int) -> List[int]:
+    """Definition of the product of two polynomials over GF(p) of any length:
+    the convolution of the coefficient lists reduced mod p (numpy convolve
+    on int64 as the library step; exact while len * (p-1)^2 < 2^63)."""
+    if len(a) == 0 or len(b) == 0:
+        return []
+    c = np.convolve(np.asarray(a, dtype=np.int64), np.asarray(b, dtype=np.int64))
+    return [int(x) % p for x in c]
+
+
+def dfqt_degree(n_coeffs: int, d: int) -> int:
+    """Section 6: a polynomial with n_coeffs = N + 1 coefficients becomes one
+    of degree D_q = ceil((N+1)/(d+1)) - 1 in Y = X^(d+1)."""
+    return -(-n_coeffs // (d + 1)) - 1
+
+
+def dfqt_chunks(a: Sequence[int], d: int) -> List[List[int]]:
+    """P = sum_i P_i Y^i with Y = X^(d+1): chunk i holds coefficients
+    i(d+1) .. i(d+1)+d of P (the last chunk zero-padded)."""
+    n = dfqt_degree(len(a), d) + 1
+    padded = list(a) + [0] * (n * (d + 1) - len(a))
+    return [padded[i * (d + 1):(i + 1) * (d + 1)] for i in range(n)]
+
+
+def dfqt_polymul(a: Sequence[int], b: Sequence[int], p: int, d: int, q: int,
+                 n_q: int) -> List[int]:
+    """The d-FQT product of Section 6, step by step, in big integers.
+
+    1. Split both operands into chunks of d+1 coefficients (degree <= d
+       polynomials P_i, Q_j in X; the operands become polynomials in
+       Y = X^(d+1)).
+    2. Pack every chunk at q (DQT, eq. (1)).
+    3. For every t, S_t = sum_i P_i(q) Q_{t-i}(q) is accumulated in blocks of
+       at most n_q products; each block's integer sum is reduced by REDQ_{2d+1}
+       (Alg. 2 on its 2d+1 q-adic digits, exact while eq. (2) holds with
+       k = d+1, i.e. q > n_q (d+1)(p-1)^2 and q^(2d+1) below the mantissa
+       bound) and the blocks' reduced digits are added mod p.
+    4. Digit j of S_t is the coefficient of X^(t(d+1)+j); digits of
+       consecutive t overlap (2d+1 > d+1) and are added mod p.
+    """
+    if len(a) == 0 or len(b) == 0:
+        return []
+    P = [dqt(ch, q) for ch in dfqt_chunks(a, d)]
+    Q = [dqt(ch, q) for ch in dfqt_chunks(b, d)]
+    nd = 2 * d + 1
+    out = [0] * (len(a) + len(b) - 1)
+    for t in range(len(P) + len(Q) - 1):
+        terms = [P[i] * Q[t - i] for i in range(len(P)) if 0 <= t - i < len(Q)]
+        mu_t = [0] * nd
+        for s in range(0, len(terms), n_q):
+            r = sum(terms[s:s + n_q])
+            _, _, mu, _ = redq_steps(r, p, q, nd - 1)
+            mu_t = [(x + y) % p for x, y in zip(mu_t, mu)]
+        for j, m in enumerate(mu_t):
+            n = t * (d + 1) + j
+            if n < len(out):
+                out[n] = (out[n] + m) % p
+    return out

@@ -333,3 +333,106 @@ def test_block_bound_is_tight_for_dot_products():
 def test_binary_index_layout():
     assert gf.binary_index([1, 2, 0, 1], 3) == 1 + (2 << 2) + (1 << 6)
     assert gf.binary_index([4, 4, 4], 5) == 4 + (4 << 3) + (4 << 6)
+
+
+# --- d-FQT: long polynomials in chunks of d+1 coefficients (Section 6) ----
+
+def _binomial_row_mod_p(n, p):
+    """Coefficients of (1 + X)^n mod p from exact binomial coefficients."""
+    from math import comb
+    return [comb(n, i) % p for i in range(n + 1)]
+
+
+@pytest.mark.parametrize("p", [2, 3, 5, 7])
+def test_polymul_long_binomial_closed_form(p):
+    # (1 + X)^m (1 + X)^n = (1 + X)^(m+n): a closed form for every coefficient
+    for m, n in [(0, 0), (1, 4), (7, 9), (30, 41), (500, 500)]:
+        a = _binomial_row_mod_p(m, p)
+        b = _binomial_row_mod_p(n, p)
+        assert gf.polymul_long(a, b, p) == _binomial_row_mod_p(m + n, p)
+
+
+def test_polymul_long_frobenius():
+    # over GF(p), (1 + X)^p = 1 + X^p (freshman's dream), squared via the product
+    for p in (3, 5, 7, 11):
+        f = _binomial_row_mod_p(p, p)
+        assert f == [1] + [0] * (p - 1) + [1]
+        sq = gf.polymul_long(f, f, p)
+        assert sq == _binomial_row_mod_p(2 * p, p)
+        want = [0] * (2 * p + 1)
+        want[0] = 1
+        want[p] = 2 % p
+        want[2 * p] = 1
+        assert sq == want
+
+
+def test_polymul_long_agrees_with_schoolbook():
+    rng = random.Random(3)
+    for p in (2, 3, 13, 127):
+        for la, lb in [(1, 1), (3, 8), (64, 65), (200, 17)]:
+            a = [rng.randrange(p) for _ in range(la)]
+            b = [rng.randrange(p) for _ in range(lb)]
+            assert gf.polymul_long(a, b, p) == gf.poly_mul_mod_p(a, b, p)
+
+
+def test_dfqt_degree_of_the_papers_example():
+    # p = 3, N = 500, d = 4: D_q = ceil(501 / 5) - 1 = 100 chunks beyond the first
+    assert gf.dfqt_degree(501, 4) == 100
+    assert gf.dfqt_degree(1, 0) == 0 and gf.dfqt_degree(5, 4) == 0 and gf.dfqt_degree(6, 4) == 1
+    # chunks: the last one zero-padded, concatenation restores the operand
+    a = list(range(13))
+    ch = gf.dfqt_chunks(a, 4)
+    assert [len(c) for c in ch] == [5, 5, 5] and sum(ch, [])[:13] == a and ch[-1][3:] == [0, 0]
+
+
+def _eq2_params(p, d):
+    """(q, n_q max) at the largest q = 2^b with q^(2d+1) < 2^53."""
+    return gf.max_pow2_q(p, d + 1)
+
+
+@pytest.mark.parametrize("p,d", [(2, 1), (3, 0), (3, 1), (3, 2), (3, 4), (5, 3), (7, 2), (13, 1)])
+def test_dfqt_equals_the_product_definition(p, d):
+    q, nq = _eq2_params(p, d)
+    rng = random.Random(p * 10 + d)
+    for la, lb in [(1, 1), (d + 1, d + 1), (d + 2, 3 * d + 4), (37, 29), (101, 101)]:
+        a = [rng.randrange(p) for _ in range(la)]
+        b = [rng.randrange(p) for _ in range(lb)]
+        want = gf.polymul_long(a, b, p)
+        for n_q in sorted({1, max(1, nq // 2), nq}):
+            assert gf.dfqt_polymul(a, b, p, d, q, n_q) == want, (la, lb, n_q)
+        # all (p-1): every block's digits reach their largest value
+        amax, bmax = [p - 1] * la, [p - 1] * lb
+        assert gf.dfqt_polymul(amax, bmax, p, d, q, nq) == gf.polymul_long(amax, bmax, p)
+
+
+def test_dfqt_general_q():
+    # eq. (2) with a q that is not a power of two (Section 2 allows any q)
+    p, d = 3, 4
+    q = 59                      # q^9 < 2^53 and q > 2 * 5 * 2^2
+    assert q ** 9 < 2 ** 53 and q > 2 * (d + 1) * (p - 1) ** 2
+    rng = random.Random(9)
+    a = [rng.randrange(p) for _ in range(501)]
+    b = [rng.randrange(p) for _ in range(501)]
+    assert gf.dfqt_polymul(a, b, p, d, q, 2) == gf.polymul_long(a, b, p)
+
+
+def test_dfqt_exhaustive_tiny():
+    # every pair of polynomials with 3 coefficients over GF(2) and GF(3), d = 1
+    for p in (2, 3):
+        q, nq = _eq2_params(p, 1)
+        for a in itertools.product(range(p), repeat=3):
+            for b in itertools.product(range(p), repeat=3):
+                assert gf.dfqt_polymul(list(a), list(b), p, 1, q, nq) == \
+                    gf.poly_mul_mod_p(list(a), list(b), p)
+
+
+def test_dfqt_block_bound_is_tight():
+    # q = 16, p = 3, d = 1: eq. (2) allows n_q = 1 (16 > 8) but not 2 (16 = 16);
+    # with every coefficient 2 a block of two products has a middle digit of
+    # 2 * 2 * 4 = 16 = q, which carries into the next digit and breaks the result
+    p, d, q = 3, 1, 16
+    a = [2] * 8
+    b = [2] * 8
+    want = gf.polymul_long(a, b, p)
+    assert gf.dfqt_polymul(a, b, p, d, q, 1) == want
+    assert gf.dfqt_polymul(a, b, p, d, q, 2) != want
