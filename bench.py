@@ -304,6 +304,79 @@ def bench_polymul(w, args, torch, fqt, gf):
     }
 
 
+def bench_dfqt(w, args, torch, fqt, gf):
+    """d-FQT products of long polynomials (Section 6) against the classical
+    product with delayed reduction (eq. (3)); work = count * len^2 GF(p)
+    mul-adds (the classical count, the same for every method)."""
+    from paper_0710_0510_amd import workloads as W
+    a_h, b_h = W.poly_long_inputs(w)
+    a, b = torch.from_numpy(a_h).cuda(), torch.from_numpy(b_h).cuda()
+    ref = fqt.polymul_delayed(w.p, a, b)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    picks = rng.integers(0, w.count, size=max(4, args.samples // 16))
+    ref_h = ref.cpu().numpy()
+    bad = sum(gf.polymul_long(a_h[i].tolist(), b_h[i].tolist(), w.p) != ref_h[i].tolist()
+              for i in picks.tolist())
+    if bad:
+        raise SystemExit(f"parity failure: the delayed comparator differs from the oracle on {bad}")
+    work = w.count * w.length * w.length
+    variants = {}
+    for d in sorted({w.d, 1, 2, 3}):
+        out = fqt.polymul_dfqt(w.p, d, a, b)
+        torch.cuda.synchronize()
+        if not torch.equal(out, ref):
+            raise SystemExit(f"parity failure: d-FQT with d = {d} differs from the comparator")
+        ms = time_steps(lambda: fqt.polymul_dfqt(w.p, d, a, b, out=out), args.steps,
+                        args.warmup, torch)
+        nch = -(-w.length // (d + 1))
+        fl = 2.0 * w.count * nch * nch / (ms * 1e-3)  # one FP64 FMA per chunk product
+        q, nq = gf.max_pow2_q(w.p, d + 1)
+        variants[d] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "q": q, "n_q": nq,
+                       "chunks": nch, "fp64_tflops": fl / 1e12}
+    dms = time_steps(lambda: fqt.polymul_delayed(w.p, a, b, out=ref), args.steps, args.warmup,
+                     torch)
+    main_v = variants[w.d]
+    out = {
+        "metric": METRIC, "value": main_v["value"], "unit": "GF(p) mul-adds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_v["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "p": w.p, "degree": w.length - 1, "d": w.d,
+                   "count": w.count, "seed": w.seed, "q": main_v["q"], "n_q": main_v["n_q"]},
+        "products_per_s": w.count / (main_v["ms_per_step"] * 1e-3),
+        "roofline": {"bound": "alu", "achieved": main_v["fp64_tflops"], "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": main_v["fp64_tflops"] * 1e12 / PEAK_FP64,
+                     "traffic": None, "kernel": "dfqt_kernel (DQT + FP64 FMA convolution + "
+                     "block digits + overlap-add)",
+                     "algorithmic": "2 flop per product of packed chunks, ceil(len/(d+1))^2 "
+                                    "per polynomial product"},
+        "paths": {f"dfqt_d{d}": {"value": v["value"], "ms_per_step": v["ms_per_step"],
+                                 "q": v["q"], "n_q": v["n_q"]} for d, v in variants.items()},
+        "comparator": {"kind": "classical, delayed reduction (eq. (3))",
+                       "value": work / (dms * 1e-3), "ms_per_step": dms},
+        "speedup_vs_delayed": dms / main_v["ms_per_step"],
+        "parity": {"sampled_products_vs_oracle": int(len(picks)), "sampled_mismatches": bad,
+                   "every_d_identical_to_comparator": True},
+    }
+    if not args.no_cpu:
+        n = 4
+        t0 = time.time()
+        for i in range(n):
+            gf.polymul_long(a_h[i].tolist(), b_h[i].tolist(), w.p)
+        dt = max(time.time() - t0, 1e-6)
+        n = int(max(4, min(w.count, n * args.cpu_seconds / dt)))
+        t0 = time.time()
+        for i in range(n):
+            gf.polymul_long(a_h[i].tolist(), b_h[i].tolist(), w.p)
+        dt = time.time() - t0
+        out["cpu_baseline"] = {"value": n * w.length * w.length / dt, "unit": "GF(p) mul-adds/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"first {n} of the {w.count} products, numpy int64 "
+                                         f"convolution, {dt:.1f} s"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -344,6 +417,8 @@ def main():
     w = W.WORKLOADS[args.workload]
     if w.kind == "gemm":
         out = bench_gemm(w, args, torch, fqt, gf)
+    elif w.kind == "dfqt":
+        out = bench_dfqt(w, args, torch, fqt, gf)
     elif w.kind == "batched":
         out = bench_batched(w, args, torch, fqt, gf)
     else:

@@ -192,6 +192,40 @@ fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q,
                              const uint8_t* a, const uint8_t* b, size_t n,
                              uint8_t* c, fqt_stream_t s);
 
+/* ---- d-FQT: long polynomials over GF(p) (Section 6) --------------------- */
+
+/* c[i] = a[i] * b[i] in GF(p)[X] for i < count, each operand len
+ * coefficients (degree len - 1): the d-FQT of Section 6.  Every operand is
+ * split into ceil(len/(d+1)) chunks of d+1 coefficients (a polynomial in
+ * Y = X^(d+1)), each chunk packed at q = 2^log2q into one binary64 (DQT,
+ * eq. (1)); the packed chunks are convolved exactly in FP64, in blocks of at
+ * most n_q products, each block reduced by REDQ_{2d+1} (or, with q <= 2^12,
+ * by summing its q-adic digit fields); the 2d+1 digits of every packed
+ * product are the coefficients of X^(t(d+1)+j), and overlapping digits of
+ * consecutive ones are added mod p.
+ *   a, b   device, count*len bytes, every byte in [0, p);
+ *   c      device, count*(2 len - 1) bytes; must not overlap a or b.
+ *   p      prime <= 127; d in [0, 7]; 1 <= len <= 1024 (d+1)
+ *          (FQT_ERR_UNSUPPORTED beyond).
+ *   log2q  0 = the largest q with q^(2d+1) < 2^53 ((2d+1) log2q <= 52);
+ *          smaller q only while one block holds every product of a chunk
+ *          pair sum (n_q >= ceil(len/(d+1))), else FQT_ERR_UNSUPPORTED.
+ *   n_q    products per block; 0 = the largest eq. (2) allows,
+ *          q > n_q (d+1)(p-1)^2 (FQT_ERR_BOUNDS when q cannot hold one).
+ *   boundary  as fqt_gemm_opts.boundary (0 default, 1 REDQ residues,
+ *          2 digit sums, q <= 2^12); identical bytes. */
+fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                            uint32_t boundary, const uint8_t* a, const uint8_t* b,
+                            int64_t count, int64_t len, uint8_t* c, fqt_stream_t s);
+
+/* The comparator of Section 6: the classical product with delayed reduction
+ * (eq. (3)): every coefficient accumulated in 32-bit integers and reduced
+ * mod p once (or every n_d products if len (p-1)^2 could overflow).
+ *   Same buffers as fqt_polymul_dfqt; p prime <= 127; 1 <= len <= 8192. */
+fqt_status fqt_polymul_delayed(uint32_t p, const uint8_t* a, const uint8_t* b,
+                               int64_t count, int64_t len, uint8_t* c,
+                               fqt_stream_t s);
+
 /* ---- GEMM over GF(p^k) (Alg. 4 for every entry, Section 7) -------------- */
 
 /* C = A * B over the field; A is M x K, B is K x N, C is M x N elements.

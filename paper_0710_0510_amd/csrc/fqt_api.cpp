@@ -669,6 +669,97 @@ fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q, const uint8_t* 
   return ok();
 }
 
+fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                            uint32_t boundary, const uint8_t* a, const uint8_t* b, int64_t count,
+                            int64_t len, uint8_t* c, fqt_stream_t s) {
+  if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
+  if (p > 127) return fail(FQT_ERR_UNSUPPORTED, "p = %u above 127", p);
+  if (d > 7) return fail(FQT_ERR_UNSUPPORTED, "d = %u above 7 (chunks of at most 8 coefficients)", d);
+  if (count < 0 || len < 1) return fail(FQT_ERR_INVALID_ARG, "count < 0 or len < 1");
+  if (count && (!a || !b || !c)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  const uint32_t ke = d + 1;
+  const int64_t nch = (len + ke - 1) / ke;
+  if (nch > kDfqtMaxChunks)
+    return fail(FQT_ERR_UNSUPPORTED, "len = %lld needs %lld chunks, above %d", (long long)len,
+                (long long)nch, kDfqtMaxChunks);
+  if (boundary > 2) return fail(FQT_ERR_INVALID_ARG, "unknown boundary mode %u", boundary);
+  // eq. (2) with k = d+1 coefficients per packed number: q^(2d+1) < 2^53,
+  // q > n_q (d+1)(p-1)^2; q = 2^b with (2d+1) b <= 52 so that the biased
+  // accumulator holds the sum, and the residue bytes stay below bit 52
+  const uint32_t bmax = 52 / (2 * ke - 1);
+  const uint32_t bq = log2q ? log2q : bmax;
+  if (bq < 1 || bq > bmax)
+    return fail(FQT_ERR_BOUNDS, "q = 2^%u breaks q^(2d+1) < 2^53 (d = %u)", bq, d);
+  if (bq * (2 * ke - 2) + 8 > 52)
+    return fail(FQT_ERR_UNSUPPORTED, "q = 2^%u leaves no room for the residue bytes", bq);
+  const uint64_t q = 1ull << bq;
+  const uint64_t unit = (uint64_t)ke * (p - 1) * (p - 1);
+  const uint64_t nq_max = unit ? (q - 1) / unit : (uint64_t)1 << 30;
+  if (nq_max < 1)
+    return fail(FQT_ERR_BOUNDS, "q = 2^%u is not above (d+1)(p-1)^2 = %" PRIu64, bq, unit);
+  const uint64_t nq = n_q ? n_q : std::min<uint64_t>(nq_max, (uint64_t)1 << 30);
+  if (nq > nq_max)
+    return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks q > n_q (d+1)(p-1)^2", nq);
+  const bool multi = (uint64_t)nch > nq;  // the longest S_t has nch products
+  if (multi && bq != bmax)
+    return fail(FQT_ERR_UNSUPPORTED, "several blocks need the largest q = 2^%u", bmax);
+  int mode = 0;
+  uint32_t fold = 0;
+  if (multi) {
+    mode = boundary ? (int)boundary : (2 * bq <= 24 ? 2 : 1);
+    if (mode == 2 && 2 * bq > 24)
+      return fail(FQT_ERR_UNSUPPORTED, "digit-sum boundaries need q <= 2^12 (q = 2^%u)", bq);
+    const uint64_t width = mode == 1 ? 65535 : q * q - 1;
+    const uint64_t growth = mode == 1 ? 2 * (uint64_t)p - 1 : nq * unit;
+    const uint64_t nblocks = ((uint64_t)nch + nq - 1) / nq + 1;
+    const uint64_t cap = (width - (p - 1)) / std::max<uint64_t>(growth, 1);
+    if (cap < 2) return fail(FQT_ERR_UNSUPPORTED, "residue lanes too narrow for n_q = %" PRIu64, nq);
+    if (nblocks + 1 > cap) fold = (uint32_t)(cap - 1);
+  }
+  const size_t nc = (size_t)count * (size_t)(2 * len - 1), ni = (size_t)count * (size_t)len;
+  if (overlap(c, nc, a, ni) || overlap(c, nc, b, ni))
+    return fail(FQT_ERR_INVALID_ARG, "output overlaps an input");
+  fqt_field_s tmp;
+  tmp.p = p;
+  tmp.k = ke;
+  tmp.cb = std::max(1u, ceil_log2(p));
+  DfqtArgs g{};
+  g.a = a;
+  g.b = b;
+  g.c = c;
+  g.count = count;
+  g.len = (int32_t)len;
+  g.nch = (int32_t)nch;
+  g.nq = (uint32_t)nq;
+  g.lg2q = bq;
+  g.pp.fa = field_args(&tmp, q);
+  g.pp.qmod = (uint32_t)(q % p);
+  g.pp.fold_blocks = fold;
+  g.pp.b = bq;
+  FQT_HIP(launch_dfqt((int)ke, mode, g, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_polymul_delayed(uint32_t p, const uint8_t* a, const uint8_t* b, int64_t count,
+                               int64_t len, uint8_t* c, fqt_stream_t s) {
+  if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
+  if (p > 127) return fail(FQT_ERR_UNSUPPORTED, "p = %u above 127", p);
+  if (count < 0 || len < 1) return fail(FQT_ERR_INVALID_ARG, "count < 0 or len < 1");
+  if (count && (!a || !b || !c)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (len > kDelayedMaxLen)
+    return fail(FQT_ERR_UNSUPPORTED, "len = %lld above %d", (long long)len, kDelayedMaxLen);
+  const size_t nc = (size_t)count * (size_t)(2 * len - 1), ni = (size_t)count * (size_t)len;
+  if (overlap(c, nc, a, ni) || overlap(c, nc, b, ni))
+    return fail(FQT_ERR_INVALID_ARG, "output overlaps an input");
+  // eq. (3), unsigned: a reduced value below p plus n_d (p-1)^2 stays below 2^32
+  const uint64_t sq = (uint64_t)(p - 1) * (p - 1);
+  const uint64_t lim = 0xffffffffull - p;
+  DelayedArgs g{a, b, c, count, (int32_t)len, p, 0};
+  if (sq && (uint64_t)len * sq > lim) g.nd = (uint32_t)(lim / sq);
+  FQT_HIP(launch_polymul_delayed(g, (hipStream_t)s));
+  return ok();
+}
+
 static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
                               hipStream_t s) {
   PackedChoice pc;

@@ -32,6 +32,28 @@ struct PackedParams {
   const uint32_t* H;
 };
 
+// d-FQT product of long polynomials (k_dfqt.hip): count pairs of len
+// coefficients, chunks of d+1 = KE coefficients packed at q = 2^lg2q.
+struct DfqtArgs {
+  const uint8_t* a;
+  const uint8_t* b;
+  uint8_t* c;            // count x (2 len - 1)
+  int64_t count;
+  int32_t len, nch;      // coefficients, chunks per operand
+  uint32_t nq, lg2q;     // products per block; q = 2^lg2q
+  PackedParams pp;       // fa, qmod and fold_blocks are used
+};
+
+// Classical product with delayed reduction (eq. (3)), the comparator.
+struct DelayedArgs {
+  const uint8_t* a;
+  const uint8_t* b;
+  uint8_t* c;
+  int64_t count;
+  int32_t len;
+  uint32_t p, nd;        // nd: products between reductions (0: once at the end)
+};
+
 // Low coefficients of the monic defining polynomial (k <= 4), each < p.
 struct PlainFieldArgs {
   uint32_t P_low[4];
@@ -154,6 +176,12 @@ hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* i
 hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* items,
                                   int32_t n_items, uint32_t* counter, int grid, hipStream_t s);
 int i8_batched_occupancy(int tile);
+
+// d-FQT (ke = d + 1 in 1..8, mode 0/1/2 as in fqt_packed.h) and its comparator.
+hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s);
+hipError_t launch_polymul_delayed(const DelayedArgs& g, hipStream_t s);
+constexpr int kDfqtMaxChunks = 1024;  // chunks of one operand (in LDS)
+constexpr int kDelayedMaxLen = 8192;  // coefficients of one operand (in LDS)
 
 // Plain comparator: schoolbook with % p and division by P per product.
 hipError_t launch_gemm_plain(int k, const GemmArgs& g, const FieldArgs& fa,

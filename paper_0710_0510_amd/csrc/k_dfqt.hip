@@ -1,0 +1,242 @@
+// d-FQT products of long polynomials over GF(p) on gfx950 (Section 6), and
+// the classical product with delayed reduction it is compared with.
+//
+// d-FQT: a polynomial of len coefficients is split into nch = ceil(len/(d+1))
+// chunks of d+1 coefficients, each packed at q = 2^b into one binary64 (DQT,
+// eq. (1)).  The product is the convolution S_t = sum_i P_i Q_{t-i} of the
+// packed chunks (t = 0..2nch-2), accumulated exactly in FP64 in blocks of at
+// most n_q products (eq. (2) with k = d+1); each block leaves its 2d+1 digits
+// in the per-element state of fqt_packed.h (one block: REDQ_{2d+1} of the
+// biased accumulator; several: residue lanes or digit sums), which yields
+// Thm. 2's residues u_i of S_t; the Q_d correction turns them into the digits
+// mod p.  Digit j of S_t is the coefficient of X^(t(d+1)+j); consecutive S_t
+// overlap in d digits, which are added mod p.
+//
+// One wave per product, four per workgroup.  The packed chunks of both
+// operands sit in LDS.  Lane l accumulates S_t for the four consecutive
+// t = t0 + 4l .. t0 + 4l + 3 over a chunk index i that runs in step across
+// the wave (so P_i is one broadcast read), keeping Q_{t-i} .. Q_{t+3-i} as a
+// sliding window (one more read per i); out-of-range chunks read as zero,
+// which only adds zero products to a block.  Passes t0 = 0, 256, ... cover
+// t = 0..2nch-1 (the last t has no products of its own and only receives the
+// overlapping digits of the one before).  The digits that overlap into t come
+// from t-1: the same lane for r > 0, the previous lane (a shuffle) for r = 0,
+// lane 63 of the previous pass for the first lane.
+
+#include "fqt_packed.h"
+
+namespace fqt {
+
+template <int KE, int MODE>
+__global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
+  constexpr int ND = 2 * KE - 1;
+  constexpr bool MULTI = MODE != 0;
+  __shared__ double sh[4][2][kDfqtMaxChunks];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t prod = (int64_t)blockIdx.x * 4 + w;
+  const bool live = prod < g.count;  // idle waves still reach every barrier
+  double* P = sh[w][0];
+  double* Q = sh[w][1];
+  const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
+  const int len = g.len, nch = g.nch;
+  const uint8_t* pa = g.a + (live ? prod : 0) * len;
+  const uint8_t* pb = g.b + (live ? prod : 0) * len;
+  uint8_t* pc = g.c + (live ? prod : 0) * (int64_t)(2 * len - 1);
+
+  // DQT of every chunk: sum_j c_j 2^(b j) < 2^52, exact in binary64
+  if (live) {
+    for (int i = lane; i < nch; i += 64) {
+      uint64_t va = 0, vb = 0;
+#pragma unroll
+      for (int j = 0; j < KE; ++j) {
+        const int idx = i * KE + j;
+        if (idx < len) {
+          va |= (uint64_t)pa[idx] << (b * j);
+          vb |= (uint64_t)pb[idx] << (b * j);
+        }
+      }
+      P[i] = (double)va;
+      Q[i] = (double)vb;
+    }
+  }
+  __syncthreads();
+  if (!live) return;  // no barrier below
+
+  const PackedParams& pp = g.pp;
+  const int nt = 2 * nch;  // t = 0 .. 2nch-1
+  uint32_t carry[KE > 1 ? KE - 1 : 1];
+#pragma unroll
+  for (int j = 0; j < KE - 1; ++j) carry[j] = 0;
+  for (int t0 = 0; t0 < nt; t0 += 256) {
+    const int tb = t0 + 4 * lane;
+    double acc[4];
+    BlockLanes<KE, MODE> st[MULTI ? 4 : 1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = kTwo52;
+    if constexpr (MULTI) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) st[r].clear();
+    }
+    const int ilo = max(0, t0 - (nch - 1)), ihi = min(nch - 1, t0 + 255);
+    double qw[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = tb + r - ilo;
+      qw[r] = (j >= 0 && j < nch) ? Q[j] : 0.0;
+    }
+    uint32_t cnt = 0, nbound = 0;
+    for (int i = ilo; i <= ihi; ++i) {
+      const double pi = P[i];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = __builtin_fma(pi, qw[r], acc[r]);
+      if constexpr (MULTI) {
+        if (++cnt == g.nq) {
+          cnt = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            st[r].add(acc[r], pp.fa);
+            acc[r] = kTwo52;
+          }
+          if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
+            nbound = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) st[r].fold(pp.fa);
+          }
+        }
+      }
+      // slide the window one chunk down Q
+      qw[3] = qw[2];
+      qw[2] = qw[1];
+      qw[1] = qw[0];
+      const int j = tb - i - 1;
+      qw[0] = (j >= 0 && j < nch) ? Q[j] : 0.0;
+    }
+
+    // Thm. 2's residues u_i, then Alg. 2's second part (the Q_d correction of
+    // Section 5.1): digit i mod p is (u_i - q u_{i+1}) mod p, the top one u_2d
+    uint32_t u[4][ND];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      st[MULTI ? r : 0].residues(acc[r], b, pp, u[r]);
+#pragma unroll
+      for (int i = 0; i < ND - 1; ++i) u[r][i] = mod_p_small(u[r][i] + pp.fa.c * u[r][i + 1], pp.fa);
+    }
+    // digits d+1..2d of S_{tb-1}: previous lane's last t, or the carried ones
+    uint32_t prev[KE > 1 ? KE - 1 : 1];
+#pragma unroll
+    for (int j = 0; j < KE - 1; ++j) {
+      const uint32_t up = (uint32_t)__shfl_up((int)u[3][KE + j], 1, 64);
+      prev[j] = lane == 0 ? carry[j] : up;
+      carry[j] = (uint32_t)__shfl((int)u[3][KE + j], 63, 64);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int t = tb + r;
+      if (t >= nt) break;
+#pragma unroll
+      for (int j = 0; j < KE; ++j) {
+        const int n = t * KE + j;
+        if (n >= 2 * len - 1) break;
+        uint32_t v = u[r][j];
+        if (j < KE - 1) v += r ? u[r - 1][KE + j] : prev[j];
+        pc[n] = (uint8_t)(v >= pp.fa.p ? v - pp.fa.p : v);
+      }
+    }
+  }
+}
+
+// Classical product, delayed reduction (eq. (3)): c_n = sum_i a_i b_{n-i} in
+// INT32, reduced mod p once, or every n_d products when len (p-1)^2 would
+// overflow.  Same wave layout as the d-FQT kernel, on coefficients.
+__global__ __launch_bounds__(256) void polymul_delayed_kernel(DelayedArgs g) {
+  __shared__ uint8_t sh[4][2][kDelayedMaxLen];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t prod = (int64_t)blockIdx.x * 4 + w;
+  const bool live = prod < g.count;
+  uint8_t* A = sh[w][0];
+  uint8_t* B = sh[w][1];
+  const int len = g.len;
+  const uint8_t* pa = g.a + (live ? prod : 0) * len;
+  const uint8_t* pb = g.b + (live ? prod : 0) * len;
+  uint8_t* pc = g.c + (live ? prod : 0) * (int64_t)(2 * len - 1);
+  if (live)
+    for (int i = lane; i < len; i += 64) {
+      A[i] = pa[i];
+      B[i] = pb[i];
+    }
+  __syncthreads();
+  if (!live) return;
+  const int nout = 2 * len - 1;
+  for (int n0 = 0; n0 < nout; n0 += 256) {
+    const int nb = n0 + 4 * lane;
+    uint32_t acc[4] = {0, 0, 0, 0};
+    const int ilo = max(0, n0 - (len - 1)), ihi = min(len - 1, n0 + 255);
+    uint32_t bw[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = nb + r - ilo;
+      bw[r] = (j >= 0 && j < len) ? B[j] : 0u;
+    }
+    uint32_t cnt = 0;
+    for (int i = ilo; i <= ihi; ++i) {
+      const uint32_t ai = A[i];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] += ai * bw[r];
+      if (g.nd && ++cnt == g.nd) {
+        cnt = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] %= g.p;
+      }
+      bw[3] = bw[2];
+      bw[2] = bw[1];
+      bw[1] = bw[0];
+      const int j = nb - i - 1;
+      bw[0] = (j >= 0 && j < len) ? B[j] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (nb + r < nout) pc[nb + r] = (uint8_t)(acc[r] % g.p);
+  }
+}
+
+template <int KE>
+static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
+  const dim3 grid((unsigned)((g.count + 3) / 4));
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((dfqt_kernel<KE, 0>), grid, dim3(256), 0, s, g); break;
+    case 1: hipLaunchKernelGGL((dfqt_kernel<KE, 1>), grid, dim3(256), 0, s, g); break;
+    case 2:
+      if constexpr (digit_sums_fit<KE>()) {
+        hipLaunchKernelGGL((dfqt_kernel<KE, 2>), grid, dim3(256), 0, s, g);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s) {
+  if (g.count == 0) return hipSuccess;
+  switch (ke) {
+    case 1: return dfqt_k<1>(mode, g, s);
+    case 2: return dfqt_k<2>(mode, g, s);
+    case 3: return dfqt_k<3>(mode, g, s);
+    case 4: return dfqt_k<4>(mode, g, s);
+    case 5: return dfqt_k<5>(mode, g, s);
+    case 6: return dfqt_k<6>(mode, g, s);
+    case 7: return dfqt_k<7>(mode, g, s);
+    case 8: return dfqt_k<8>(mode, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_polymul_delayed(const DelayedArgs& g, hipStream_t s) {
+  if (g.count == 0) return hipSuccess;
+  hipLaunchKernelGGL(polymul_delayed_kernel, dim3((unsigned)((g.count + 3) / 4)), dim3(256), 0, s,
+                     g);
+  return hipGetLastError();
+}
+
+}  // namespace fqt

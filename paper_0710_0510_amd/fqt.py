@@ -27,7 +27,7 @@ EXPORTED = [
     "fqt_field_create", "fqt_field_destroy", "fqt_field_tables", "fqt_params", "fqt_pack",
     "fqt_unpack_redq", "fqt_unpack_redq_u64", "fqt_polymul_batch", "fqt_gemm_gfpk",
     "fqt_gemm_gfpk_ex", "fqt_gemm_gfpk_batched", "fqt_gemm_gfpk_batched_ex", "fqt_autotune",
-    "fqt_tile_count", "fqt_last_error", "fqt_version",
+    "fqt_tile_count", "fqt_last_error", "fqt_version", "fqt_polymul_dfqt", "fqt_polymul_delayed",
 ]
 
 
@@ -73,6 +73,9 @@ def lib() -> ctypes.CDLL:
         "fqt_unpack_redq": (c_int, [vp, c_u64, vp, c_sz, c_u32, c_int, vp, vp]),
         "fqt_unpack_redq_u64": (c_int, [vp, c_u64, vp, c_sz, c_u32, c_int, vp, vp]),
         "fqt_polymul_batch": (c_int, [c_u32, c_u32, c_u64, vp, vp, c_sz, vp, vp]),
+        "fqt_polymul_dfqt": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, vp, vp, c_i64, c_i64, vp,
+                                     vp]),
+        "fqt_polymul_delayed": (c_int, [c_u32, vp, vp, c_i64, c_i64, vp, vp]),
         "fqt_gemm_gfpk": (c_int, [vp, c_int, c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp,
                                   c_i64, vp]),
         "fqt_gemm_gfpk_ex": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_i64, c_i64, c_i64,
@@ -201,6 +204,41 @@ def polymul_batch(p: int, k: int, q: int, a, b, out=None, stream=None):
     if out is None:
         out = torch.empty((n, 2 * k - 1), dtype=torch.uint8, device=a.device)
     _check(lib().fqt_polymul_batch(p, k, q, _ptr(a), _ptr(b), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def _poly_operands(a, b, name: str):
+    """count x len uint8 device tensors, rows contiguous."""
+    import torch
+    for t in (a, b):
+        if t.dtype != torch.uint8 or t.dim() != 2 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name}: operands must be contiguous (count, len) uint8 device tensors")
+    if a.shape != b.shape:
+        raise ValueError(f"{name}: operand shapes differ: {tuple(a.shape)} vs {tuple(b.shape)}")
+
+
+def polymul_dfqt(p: int, d: int, a, b, log2q: int = 0, n_q: int = 0, boundary: int = 0,
+                 out=None, stream=None):
+    """d-FQT products of long polynomials (Section 6): out[i] = a[i] * b[i]."""
+    import torch
+    _poly_operands(a, b, "polymul_dfqt")
+    count, length = a.shape
+    if out is None:
+        out = torch.empty((count, max(2 * length - 1, 0)), dtype=torch.uint8, device=a.device)
+    _check(lib().fqt_polymul_dfqt(p, d, log2q, n_q, boundary, _ptr(a), _ptr(b), count, length,
+                                  _ptr(out), _stream(stream)))
+    return out
+
+
+def polymul_delayed(p: int, a, b, out=None, stream=None):
+    """The classical product with delayed reduction (eq. (3)), the comparator."""
+    import torch
+    _poly_operands(a, b, "polymul_delayed")
+    count, length = a.shape
+    if out is None:
+        out = torch.empty((count, max(2 * length - 1, 0)), dtype=torch.uint8, device=a.device)
+    _check(lib().fqt_polymul_delayed(p, _ptr(a), _ptr(b), count, length, _ptr(out),
+                                     _stream(stream)))
     return out
 
 

@@ -37,7 +37,7 @@ GF3_2 = Field(3, 2, (1, 0))          # X^2 + 1
 @dataclass(frozen=True)
 class Workload:
     name: str
-    kind: str                 # "polymul" | "gemm" | "batched"
+    kind: str                 # "polymul" | "gemm" | "batched" | "dfqt"
     p: int
     k: int
     P_low: Tuple[int, ...] = ()
@@ -50,6 +50,8 @@ class Workload:
     count: int = 0            # batched: number of products
     lo: int = 0               # batched: M, N, K uniform in [lo, hi]
     hi: int = 0
+    length: int = 0           # dfqt: coefficients per operand (degree N = length - 1)
+    d: int = 0                # dfqt: chunks of d + 1 coefficients
 
 
 WORKLOADS = {
@@ -62,6 +64,10 @@ WORKLOADS = {
                                 M=4096, N=4096, K=4096),
     "gemm-gf3^2-8192": Workload("gemm-gf3^2-8192", "gemm", 3, 2, GF3_2.P_low, seed=5,
                                 M=8192, N=8192, K=8192),
+    # long polynomials over GF(3): degree N = 500, d = 4 (the paper's Fig. 2 case),
+    # a batch of independent pairs
+    "dfqt-gf3-n500-d4": Workload("dfqt-gf3-n500-d4", "dfqt", 3, 1, (), seed=6, count=16384,
+                                 length=501, d=4),
 }
 
 
@@ -74,6 +80,15 @@ def polymul_inputs(w: Workload):
     rng = np.random.default_rng(w.seed)
     a = coeffs(rng, (w.n,), w.p, w.k)
     b = coeffs(rng, (w.n,), w.p, w.k)
+    return a, b
+
+
+def poly_long_inputs(w: Workload, count: int = 0):
+    """count x length coefficient arrays a, b, i.i.d. uniform in [0, p)."""
+    count = count or w.count
+    rng = np.random.default_rng(w.seed)
+    a = rng.integers(0, w.p, size=(count, w.length), dtype=np.uint8)
+    b = rng.integers(0, w.p, size=(count, w.length), dtype=np.uint8)
     return a, b
 
 

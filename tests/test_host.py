@@ -218,3 +218,48 @@ def test_autotune_rejects_plain_only():
     d = (fqt.GemmDesc * 1)()
     d[0] = fqt.GemmDesc(4, 4, 4, 4, 4, 4, BOGUS, BOGUS + (1 << 30), BOGUS + (1 << 31))
     assert fqt.STATUS_NAMES[fqt.lib().fqt_autotune(f.handle, 3, 1, d, None, None, None, None)] == "FQT_ERR_INVALID_ARG"
+
+
+# ---- d-FQT long polynomials: every refusal happens before device work -------
+
+def _dfqt_status(p, d, log2q, n_q, boundary, count, length, a=BOGUS, b=BOGUS + (1 << 30),
+                 c=BOGUS + (1 << 31)):
+    L = fqt.lib()
+    return fqt.STATUS_NAMES[L.fqt_polymul_dfqt(p, d, log2q, n_q, boundary, ctypes.c_void_p(a),
+                                               ctypes.c_void_p(b), count, length,
+                                               ctypes.c_void_p(c), None)]
+
+
+def test_dfqt_validation_errors():
+    assert _dfqt_status(4, 1, 0, 0, 0, 1, 10) == "FQT_ERR_NOT_PRIME"
+    assert _dfqt_status(131, 1, 0, 0, 0, 1, 10) == "FQT_ERR_UNSUPPORTED"       # p > 127
+    assert _dfqt_status(3, 8, 0, 0, 0, 1, 10) == "FQT_ERR_UNSUPPORTED"         # d > 7
+    assert _dfqt_status(3, 1, 0, 0, 0, -1, 10) == "FQT_ERR_INVALID_ARG"
+    assert _dfqt_status(3, 1, 0, 0, 0, 1, 0) == "FQT_ERR_INVALID_ARG"
+    assert _dfqt_status(3, 1, 0, 0, 0, 1, 10, a=0) == "FQT_ERR_INVALID_ARG"
+    assert _dfqt_status(3, 0, 0, 0, 0, 1, 1025) == "FQT_ERR_UNSUPPORTED"       # > 1024 chunks
+    assert _dfqt_status(3, 1, 0, 0, 3, 1, 10) == "FQT_ERR_INVALID_ARG"         # boundary 3
+    # q^(2d+1) < 2^53: d = 4 allows q up to 2^5
+    assert _dfqt_status(3, 4, 6, 0, 0, 1, 10) == "FQT_ERR_BOUNDS"
+    # q > n_q (d+1)(p-1)^2: p = 3, d = 4, q = 32 allows n_q = 1 only
+    assert _dfqt_status(3, 4, 0, 2, 0, 1, 10) == "FQT_ERR_BOUNDS"
+    # p = 127, d = 4: q = 32 is below (d+1)(p-1)^2, no block fits
+    assert _dfqt_status(127, 4, 0, 0, 0, 1, 10) == "FQT_ERR_BOUNDS"
+    # several blocks need the largest q (d = 1: q = 2^17), and q = 2^16 with
+    # n_q = 2 < 6 chunks would need them
+    assert _dfqt_status(3, 1, 16, 2, 0, 1, 12) == "FQT_ERR_UNSUPPORTED"
+    # digit sums need q <= 2^12: d = 1 has q = 2^17 when several blocks are forced
+    assert _dfqt_status(3, 1, 0, 2, 2, 1, 12) == "FQT_ERR_UNSUPPORTED"
+    # output overlapping an input
+    assert _dfqt_status(3, 1, 0, 0, 0, 4, 10, c=BOGUS + 8) == "FQT_ERR_INVALID_ARG"
+
+
+def test_delayed_validation_errors():
+    L = fqt.lib()
+    v, w, o = (ctypes.c_void_p(BOGUS), ctypes.c_void_p(BOGUS + (1 << 30)),
+               ctypes.c_void_p(BOGUS + (1 << 31)))
+    name = lambda st: fqt.STATUS_NAMES[st]
+    assert name(L.fqt_polymul_delayed(9, v, w, 1, 10, o, None)) == "FQT_ERR_NOT_PRIME"
+    assert name(L.fqt_polymul_delayed(3, v, w, 1, 8193, o, None)) == "FQT_ERR_UNSUPPORTED"
+    assert name(L.fqt_polymul_delayed(3, v, w, 1, 0, o, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_polymul_delayed(3, v, w, 4, 10, v, None)) == "FQT_ERR_INVALID_ARG"
