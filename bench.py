@@ -36,6 +36,9 @@ MEASURED_TRAFFIC = {
     ("gemm-gf7^2-1024", "packed", 7): {
         "bytes": 15_269_888,  # FETCH 6432 KiB x 2.000 + WRITE 2048 KiB x 1.000
         "source": "profiles/gemm_direct_gf7-2_1024.md"},
+    ("dfqt-gf3-n500-d4", "dfqt", 4): {
+        "bytes": 34_072_576,  # FETCH 8573 KiB x 2.000 + WRITE 16128 KiB x 1.000
+        "source": "profiles/dfqt_gf3_n500_d4.md"},
 }
 
 
@@ -359,6 +362,11 @@ def bench_dfqt(w, args, torch, fqt, gf):
         "parity": {"sampled_products_vs_oracle": int(len(picks)), "sampled_mismatches": bad,
                    "every_d_identical_to_comparator": True},
     }
+    tr = MEASURED_TRAFFIC.get((w.name, "dfqt", w.d))
+    if tr:
+        out["roofline"]["traffic"] = tr["bytes"]
+        out["roofline"]["traffic_source"] = tr["source"]
+        out["roofline"]["algorithmic_bytes"] = w.count * (2 * w.length + 2 * w.length - 1)
     if not args.no_cpu:
         n = 4
         t0 = time.time()
