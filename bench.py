@@ -84,6 +84,9 @@ def cpu_baseline_gemm(w, A, B, gf, target_s=15.0):
 
 # Kernel that carries a packed step, by tile id (1..6 LDS-staged, 7..12 direct).
 def packed_kernel_name(tile):
+    if tile and tile >= 13:
+        return (f"gemm_split_kernel, tile {tile} (2-coefficient chunks at q = 2^17, three "
+                "FP64 MFMA chunk-pair sums + REDQ_3 + L/H)")
     if tile and tile >= 7:
         return (f"gemm_direct_kernel, tile {tile} (DQT on load into MFMA registers + "
                 "FP64 MFMA + REDQ + L/H)")
@@ -107,6 +110,13 @@ def roofline_for(path, k, work, ms, tile=0):
                 "unit": "TOP/s", "frac": ach / PEAK_I32_VALU, "traffic": None,
                 "kernel": "gemm_plain_kernel",
                 "algorithmic": "2 k^2 integer ops per field mul-add (reductions not counted)"}
+    if tile and tile >= 13:
+        # d-split: three chunk-pair products per field mul-add
+        ach = 6.0 * work / (ms * 1e-3)
+        return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,
+                "unit": "TFLOP/s", "frac": ach / PEAK_FP64, "traffic": None,
+                "kernel": packed_kernel_name(tile),
+                "algorithmic": "6 flop per field mul-add (three FP64 FMAs on packed chunks)"}
     flops = 2.0 * work
     ach = flops / (ms * 1e-3)
     return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,

@@ -100,7 +100,16 @@ typedef struct {
                       into MFMA registers (all but 11 need K <= n_q and
                       return FQT_ERR_UNSUPPORTED otherwise; these ids never
                       pad a K-block: n_q is rounded down to a multiple of
-                      4). */
+                      4).  Ids 13 and 14 (k = 3 or 4 only, else
+                      FQT_ERR_UNSUPPORTED) split every element into two
+                      chunks of 2 coefficients (Section 6's chunking with
+                      d = 1) packed at q = 2^17 and contract three
+                      chunk-pair sums (three MFMAs per k-group); one block
+                      holds n_q <= (2^17 - 1) / (w (p-1)^2) products, w = 8
+                      for k = 4 and 4 for k = 3 (4095 for GF(3^4)); longer
+                      K runs in blocks of a multiple of 16 products.  They
+                      accept log2q 0 or 17 only (FQT_ERR_INVALID_ARG) and
+                      ignore boundary. */
   uint32_t boundary; /* packed path, K > n_q: step at each K-block boundary.
                         0 = default (2 when q <= 2^12, else 1); 1 = REDQ
                         residues of the block (Alg. 2,

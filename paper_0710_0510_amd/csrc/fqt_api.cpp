@@ -354,9 +354,49 @@ struct PackedChoice {
   uint32_t fold;      // boundaries between folds of the 16-bit lanes (0: never)
 };
 
+// d-split tiles: chunks of 2 coefficients packed at q = 2^17 (q^3 < 2^53).
+// The largest digits are those of S_K = sum (a_lo + a_hi)(b_lo + b_hi), up
+// to w (p-1)^2 per k with w = 8 for k = 4 and 4 for k = 3: one block takes
+// n_q w (p-1)^2 < q.  Longer K is cut into blocks of whole 16-k steps, each
+// starting from digits below p: (p-1) + n w (p-1)^2 < q.
+constexpr uint32_t kSplitB = 17;
+
+uint64_t split_unit(uint32_t p, uint32_t k) {
+  return (uint64_t)(k == 4 ? 8 : 4) * (p - 1) * (p - 1);
+}
+
 fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t K, int64_t M,
                           int64_t N, PackedChoice* pc) {
   const uint32_t p = f->p, k = f->k;
+  if (o && o->tile > (uint32_t)kPackedTiles)
+    return fail(FQT_ERR_INVALID_ARG, "unknown tile id %u", o->tile);
+  if (o && o->tile && is_split_tile((int)o->tile)) {
+    if (k != 3 && k != 4)
+      return fail(FQT_ERR_UNSUPPORTED, "d-split tiles pair coefficients of k = 3 or 4 (k = %u)", k);
+    if (o->log2q && o->log2q != kSplitB)
+      return fail(FQT_ERR_INVALID_ARG, "d-split tiles pack chunks at q = 2^%u", kSplitB);
+    const uint64_t q = 1ull << kSplitB, unit = split_unit(p, k);
+    const uint64_t nq_one = unit ? (q - 1) / unit : (uint64_t)1 << 30;
+    if (o->n_q > nq_one)
+      return fail(FQT_ERR_BOUNDS, "n_q = %u breaks the d-split bound %" PRIu64, o->n_q, nq_one);
+    const uint64_t nq = o->n_q ? o->n_q : nq_one;
+    pc->multi = (uint64_t)K > nq;
+    pc->nq = 0;
+    if (pc->multi) {
+      const uint64_t nq_next = unit ? (q - p) / unit : nq;
+      const uint64_t steps = std::min(nq, nq_next) / 16;
+      if (steps == 0)
+        return fail(FQT_ERR_UNSUPPORTED, "d-split blocks below 16 products (p = %u, n_q = %" PRIu64
+                    ")", p, nq);
+      pc->nq = (uint32_t)std::min<uint64_t>(steps * 16, 1u << 30);
+    }
+    pc->b = kSplitB;
+    pc->nq_real = pc->nq;
+    pc->tile = o->tile;
+    pc->mode = 0;
+    pc->fold = 0;
+    return ok();
+  }
   const uint32_t bmax = max_pow2_b(k);
   uint32_t b = (o && o->log2q) ? o->log2q : bmax;
   if (b > bmax || b < 1)
@@ -766,8 +806,10 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   fqt_status st = resolve_packed(f, opts, g.K, g.M, g.N, &pc);
   if (st) return st;
   const uint64_t q = 1ull << pc.b;
+  const bool split = is_split_tile((int)pc.tile);
   DevTables dt;
-  st = device_tables(f, q, &dt);
+  // d-split: the tables reduce a plain coefficient vector mod P (q = p)
+  st = device_tables(f, split ? f->p : q, &dt);
   if (st) return st;
   PackedParams pp{};
   pp.b = pc.b;
@@ -782,7 +824,9 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   pp.fa = field_args(f, q);
   pp.L = dt.L;
   pp.H = dt.H;
-  if (is_direct_tile((int)pc.tile))
+  if (split)
+    FQT_HIP(launch_gemm_split((int)f->k, (int)pc.tile, g, pp, s));
+  else if (is_direct_tile((int)pc.tile))
     FQT_HIP(launch_gemm_direct((int)f->k, (int)pc.tile, pc.mode, g, pp, s));
   else
     FQT_HIP(launch_gemm_packed((int)f->k, (int)pc.tile, pc.mode, g, pp, s));
@@ -922,8 +966,9 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
   fqt_status st = resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc);
   if (st) return st;
   const uint64_t q = 1ull << pc.b;
+  const bool split = is_split_tile((int)pc.tile);
   DevTables dt;
-  st = device_tables(f, q, &dt);
+  st = device_tables(f, split ? f->p : q, &dt);
   if (st) return st;
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
@@ -972,8 +1017,10 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     hipDeviceProp_t prop;
     FQT_HIP(hipGetDeviceProperties(&prop, dev));
     const bool direct = is_direct_tile((int)pc.tile);
-    const int occ = direct ? direct_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2)
-                           : packed_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2);
+    const int occ =
+        split ? split_batched_occupancy((int)f->k, (int)pc.tile, f->tbl_log2)
+        : direct ? direct_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2)
+                 : packed_batched_occupancy((int)f->k, (int)pc.tile, pc.mode, f->tbl_log2);
     pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * occ, pl->n_items));
     PackedParams pp{};
     pp.b = pc.b;
@@ -991,12 +1038,15 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le =
-        direct ? launch_gemm_direct_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
-                                            pl->d_items, pl->n_items, pl->d_counter, pl->grid, pp,
-                                            pl->cap_stream)
-               : launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
-                                            pl->d_items, pl->n_items, pl->d_counter, pl->grid, pp,
-                                            pl->cap_stream);
+        split    ? launch_gemm_split_batched((int)f->k, (int)pc.tile, pl->d_descs, pl->d_items,
+                                             pl->n_items, pl->d_counter, pl->grid, pp,
+                                             pl->cap_stream)
+        : direct ? launch_gemm_direct_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
+                                              pl->d_items, pl->n_items, pl->d_counter, pl->grid,
+                                              pp, pl->cap_stream)
+                 : launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
+                                              pl->d_items, pl->n_items, pl->d_counter, pl->grid,
+                                              pp, pl->cap_stream);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
     if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");
@@ -1307,6 +1357,14 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
         cands.push_back({FQT_PATH_PACKED_F64, o});
       }
   }
+  // d-split tiles bring their own q (one block, no boundary step)
+  if (only != FQT_PATH_INT8)
+    for (uint32_t t = (uint32_t)kFirstSplitTile; t <= (uint32_t)kPackedTiles; ++t) {
+      fqt_gemm_opts o{0, 0, t, 0};
+      PackedChoice pc;
+      if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) == FQT_OK)
+        cands.push_back({FQT_PATH_PACKED_F64, o});
+    }
   if (only != FQT_PATH_PACKED_F64)
     for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
       cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0}});

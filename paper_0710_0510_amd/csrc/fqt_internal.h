@@ -112,18 +112,23 @@ constexpr int kStagedTiles = 6;
 #define FQT_DIRECT_TILES(X)                                                     \
   X(7, 4, 4, 4, 4, 0) X(8, 2, 4, 2, 4, 0) X(9, 4, 4, 1, 4, 0) X(10, 2, 4, 1, 4, 0) \
   X(11, 1, 4, 1, 4, 1) X(12, 2, 4, 4, 8, 0)
-constexpr int kPackedTiles = 12;
+// d-split kernels (k_gemm_split.hip), k = 3 or 4, wave tile 16 x 64:
+// id kFirstSplitTile = 2 x 2 waves, kFirstSplitTile + 1 = 4 x 1 waves.
+constexpr int kFirstSplitTile = 13;
+constexpr int kPackedTiles = 14;
 #ifndef FQT_DIRECT_STAGES
 #define FQT_DIRECT_STAGES 2
 #endif
 constexpr int kDirectStages = FQT_DIRECT_STAGES;  // K-steps in flight per wave
-inline bool is_direct_tile(int id) { return id > kStagedTiles; }
+inline bool is_direct_tile(int id) { return id > kStagedTiles && id < kFirstSplitTile; }
+inline bool is_split_tile(int id) { return id >= kFirstSplitTile; }
 inline bool direct_tile_multi_ok(int id) { return id == 11; }
 // Workgroup tile (rows x columns of C) of every tile id.
 inline void packed_tile_shape(int id, int* bm, int* bn) {
-  //                                     1   2    3    4   5   6   7   8    9   10   11  12
-  static const int m[kPackedTiles] = {32, 64, 64, 128, 64, 32, 64, 64, 128, 64, 32, 64};
-  static const int n[kPackedTiles] = {32, 64, 128, 128, 32, 64, 64, 64, 128, 128, 128, 64};
+  //                                     1   2    3    4   5   6   7   8    9   10   11  12  13  14
+  static const int m[kPackedTiles] = {32, 64, 64, 128, 64, 32, 64, 64, 128, 64, 32, 64, 32, 64};
+  static const int n[kPackedTiles] = {32, 64, 128, 128, 32, 64, 64, 64, 128, 128, 128, 64, 128,
+                                      64};
   *bm = m[id - 1];
   *bn = n[id - 1];
 }
@@ -163,6 +168,14 @@ hipError_t launch_gemm_direct_batched(int k, int tile, int mode, const GemmArgs*
                                       uint32_t* counter, int grid, const PackedParams& pp,
                                       hipStream_t s);
 int direct_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2);
+
+// d-split kernels (tile ids >= kFirstSplitTile, k = 3 or 4).
+hipError_t launch_gemm_split(int k, int tile, const GemmArgs& g, const PackedParams& pp,
+                             hipStream_t s);
+hipError_t launch_gemm_split_batched(int k, int tile, const GemmArgs* descs,
+                                     const TileItem* items, int32_t n_items, uint32_t* counter,
+                                     int grid, const PackedParams& pp, hipStream_t s);
+int split_batched_occupancy(int k, int tile, uint32_t tbl_log2);
 
 // INT8 path: B -> B'^T expansion, then the INT8 MFMA GEMM (tile ids 1..3).
 constexpr int kInt8Tiles = 3;

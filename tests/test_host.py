@@ -163,6 +163,21 @@ def test_direct_tiles_refuse_several_blocks():
                         opts={"tile": 7}) == "FQT_ERR_UNSUPPORTED"
 
 
+def test_split_tiles_validation():
+    # d-split tiles: k = 3 or 4 only, q = 2^17 only, n_q <= (2^17 - 1) / (w (p-1)^2)
+    # (w = 8 for k = 4: 4095 for p = 3), blocks of at least 16 products
+    g = fqt.Field(7, 2, (1, 0))
+    for tile in (13, 14):
+        assert _gemm_status(g, "packed", 4, 4, 4, 4, 4, 4, opts={"tile": tile}) == "FQT_ERR_UNSUPPORTED"
+    f = fqt.Field(3, 4, (2, 0, 0, 2))
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4,
+                        opts={"tile": 13, "log2q": 16}) == "FQT_ERR_INVALID_ARG"
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4,
+                        opts={"tile": 13, "n_q": 4096}) == "FQT_ERR_BOUNDS"
+    assert _gemm_status(f, "packed", 4, 4, 64, 64, 4, 4,
+                        opts={"tile": 14, "n_q": 8}) == "FQT_ERR_UNSUPPORTED"
+
+
 def test_gemm_n_q_bound_cfg4():
     f = fqt.Field(5, 3, (3, 3, 0))
     assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"log2q": 10, "n_q": 22}) == "FQT_ERR_BOUNDS"
@@ -209,7 +224,7 @@ def test_autotune_argument_errors():
 
 
 def test_tile_counts():
-    assert fqt.tile_count("packed") == 12
+    assert fqt.tile_count("packed") == 14
     assert fqt.tile_count("int8") == 3
 
 
