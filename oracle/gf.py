@@ -484,3 +484,157 @@ def dfqt_polymul(a: Sequence[int], b: Sequence[int], p: int, d: int, q: int,
             if n < len(out):
                 out[n] = (out[n] + m) % p
     return out
+
+
+# ---------------------------------------------------------------------------
+# Discrete-logarithm representation (Section 7, Alg. 4)
+# ---------------------------------------------------------------------------
+#
+# Alg. 4 takes field elements as exponents of a generator g.  The paper leaves
+# the generator and the code of zero open; the readings used here: g is the
+# first element of multiplicative order p^k - 1 in base-p order (element
+# index sum_i c_i p^i), and zero has the code m = p^k - 1, one past the
+# largest exponent m - 1.
+
+
+def elem_index(c: Sequence[int], p: int) -> int:
+    """Base-p index sum_i c_i p^i of an element in coefficient form."""
+    return sum(int(x) * p ** i for i, x in enumerate(c))
+
+
+def elem_from_index(idx: int, p: int, k: int) -> List[int]:
+    return [(idx // p ** i) % p for i in range(k)]
+
+
+def mult_order(a: Sequence[int], p: int, P_low: Sequence[int]) -> int:
+    """Smallest e >= 1 with a^e = 1, by repeated multiplication (a != 0)."""
+    k = len(P_low)
+    one = [1] + [0] * (k - 1)
+    x, e = list(a), 1
+    while x != one:
+        x = field_mul(x, a, p, P_low)
+        e += 1
+        if e > p ** k:
+            raise ValueError("element of infinite order: P is not irreducible")
+    return e
+
+
+def log_generator(p: int, P_low: Sequence[int]) -> int:
+    """Index of the first element of order p^k - 1 in base-p order."""
+    k = len(P_low)
+    m = p ** k - 1
+    for idx in range(1, p ** k):
+        if mult_order(elem_from_index(idx, p, k), p, P_low) == m:
+            return idx
+    raise ValueError("no generator: P is not irreducible")
+
+
+def log_tables(p: int, P_low: Sequence[int]):
+    """(g, expo, logs): expo[e] is the index of g^e for e = 0..m-1, logs maps
+    an element index to its exponent, and logs[0] = m codes zero."""
+    k = len(P_low)
+    m = p ** k - 1
+    g = log_generator(p, P_low)
+    ge = elem_from_index(g, p, k)
+    expo, x = [], [1] + [0] * (k - 1)
+    for _ in range(m):
+        expo.append(elem_index(x, p))
+        x = field_mul(x, ge, p, P_low)
+    logs = {idx: e for e, idx in enumerate(expo)}
+    logs[0] = m
+    return g, expo, logs
+
+
+def zech_table(p: int, P_low: Sequence[int]) -> List[int]:
+    """Z[n] = log(1 + g^n) for n = 0..m-1 (the code m where 1 + g^n = 0):
+    the field addition of the log representation rests on
+    g^a + g^b = g^a (1 + g^(b-a))."""
+    k = len(P_low)
+    _, expo, logs = log_tables(p, P_low)
+    one = [1] + [0] * (k - 1)
+    return [logs[elem_index(field_add(one, elem_from_index(expo[n], p, k), p), p)]
+            for n in range(len(expo))]
+
+
+def to_log(c: Sequence[int], p: int, P_low: Sequence[int], tabs=None) -> int:
+    _, _, logs = tabs or log_tables(p, P_low)
+    return logs[elem_index(c, p)]
+
+
+def from_log(code: int, p: int, P_low: Sequence[int], tabs=None) -> List[int]:
+    k = len(P_low)
+    _, expo, _ = tabs or log_tables(p, P_low)
+    m = len(expo)
+    if code == m:
+        return [0] * k
+    if not 0 <= code < m:
+        raise ValueError(f"code {code} outside 0..{m}")
+    return elem_from_index(expo[code], p, k)
+
+
+def log_add(a: int, b: int, Z: Sequence[int]) -> int:
+    """Field addition on codes: zero is the identity, otherwise
+    a + Z[(b - a) mod m] mod m, and zero where 1 + g^(b-a) vanishes."""
+    m = len(Z)
+    if a == m:
+        return b
+    if b == m:
+        return a
+    z = Z[(b - a) % m]
+    return m if z == m else (a + z) % m
+
+
+def fgdp_log(v1: Sequence[int], v2: Sequence[int], p: int, P_low: Sequence[int], q: int,
+             tabs=None, Z=None) -> int:
+    """Alg. 4 on codes, step by step in big integers: every code becomes the
+    evaluation at q of its element (the tabulated conversion), one integer
+    dot product, rop and the residues u_0..u_{2k-2}, then L and H as codes
+    (the two tables of Thm. 3 followed by the conversion to logarithms), and
+    R = H + L by the field addition of codes."""
+    k = len(P_low)
+    tabs = tabs or log_tables(p, P_low)
+    Z = Z if Z is not None else zech_table(p, P_low)
+    pk = lambda code: dqt(from_log(code, p, P_low, tabs), q)
+    r = sum(pk(a) * pk(b) for a, b in zip(v1, v2))
+    rop = r // p
+    u = [r // q ** i - p * (rop // q ** i) for i in range(2 * k - 1)]
+    L = to_log(table_L(u[0:k], q, p), p, P_low, tabs)
+    H = to_log(table_H(u[k - 1:2 * k - 1], q, p, P_low), p, P_low, tabs)
+    return log_add(H, L, Z)
+
+
+def gemm_log_alg4(A, B, p: int, P_low: Sequence[int], q: int, n_q: int):
+    """C = A B on codes with Alg. 4 per entry, K cut into blocks of at most
+    n_q products (each a dot product under eq. (2)), the block results added
+    with the field addition of codes.  Small cases only (pure Python)."""
+    tabs = log_tables(p, P_low)
+    Z = zech_table(p, P_low)
+    m = len(Z)
+    M, K = len(A), len(A[0]) if len(A) else 0
+    N = len(B[0]) if len(B) else 0
+    C = [[m] * N for _ in range(M)]
+    for i in range(M):
+        for j in range(N):
+            acc = m
+            for s in range(0, K, n_q):
+                part = fgdp_log(A[i][s:s + n_q], [B[l][j] for l in range(s, min(K, s + n_q))],
+                                p, P_low, q, tabs, Z)
+                acc = log_add(acc, part, Z)
+            C[i][j] = acc
+    return C
+
+
+def gemm_log(A: np.ndarray, B: np.ndarray, p: int, P_low: Sequence[int]) -> np.ndarray:
+    """Definition: the product over GF(p^k) of the elements the codes stand
+    for, returned as codes (M x K and K x N arrays of codes; zero = p^k - 1)."""
+    k = len(P_low)
+    _, expo, logs = log_tables(p, P_low)
+    m = len(expo)
+    anti = np.array([elem_from_index(i, p, k) for i in expo] + [[0] * k], dtype=np.uint8)
+    Cc = gemm_gfpk_planes(anti[np.asarray(A, dtype=np.int64)],
+                          anti[np.asarray(B, dtype=np.int64)], p, P_low)
+    lut = np.zeros(p ** k, dtype=np.uint16)
+    for idx, e in logs.items():
+        lut[idx] = e
+    weights = np.array([p ** i for i in range(k)], dtype=np.int64)
+    return lut[(Cc.astype(np.int64) * weights).sum(axis=-1)]

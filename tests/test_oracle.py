@@ -436,3 +436,124 @@ def test_dfqt_block_bound_is_tight():
     want = gf.polymul_long(a, b, p)
     assert gf.dfqt_polymul(a, b, p, d, q, 1) == want
     assert gf.dfqt_polymul(a, b, p, d, q, 2) != want
+
+
+# ---- discrete-log representation (Section 7, Alg. 4) ------------------------
+
+@pytest.mark.parametrize("name", ["log_gf4.txt", "log_gf9.txt"])
+def test_log_tables_hand_derived(name):
+    g = load(name)
+    P_low = tuple(g["P_low"])
+    gen, expo, logs = gf.log_tables(g["p"], P_low)
+    assert gen == g["generator"]
+    assert expo == g["exp_index"]
+    assert gf.zech_table(g["p"], P_low) == g["zech"]
+
+
+LOG_FIELDS = [(2, (1, 1)), (3, (1, 0)), (7, (1, 0)), (3, (2, 0, 0, 2)), (5, (3, 3, 0)),
+              (2, (1, 0, 1)), (13, (2,)), (2, (1,))]
+
+
+@pytest.mark.parametrize("p,P_low", LOG_FIELDS)
+def test_log_generator_is_first_of_full_order(p, P_low):
+    k = len(P_low)
+    m = p ** k - 1
+    g = gf.log_generator(p, P_low)
+    ge = gf.elem_from_index(g, p, k)
+    # brute force: g^e != 1 for 0 < e < m, g^m = 1, and every element of
+    # smaller index has a proper divisor of m as its order
+    one = [1] + [0] * (k - 1)
+    x = list(ge)
+    for e in range(1, m):
+        assert x != one, e
+        x = gf.field_mul(x, ge, p, P_low)
+    assert x == one
+    for idx in range(1, g):
+        o = gf.mult_order(gf.elem_from_index(idx, p, k), p, P_low)
+        assert o < m and m % o == 0
+
+
+def test_x_is_the_generator_of_gf81_and_gf125():
+    # X has order 80 in GF(3)[X]/(X^4 + 2X^3 + 2) and 124 in
+    # GF(5)[X]/(X^3 + 3X + 3); constants have order dividing p - 1, so X
+    # (index p) is the first element of full order
+    assert gf.log_generator(3, (2, 0, 0, 2)) == 3
+    assert gf.log_generator(5, (3, 3, 0)) == 5
+
+
+@pytest.mark.parametrize("p,P_low", LOG_FIELDS)
+def test_log_tables_bijective_and_zech_identities(p, P_low):
+    k = len(P_low)
+    m = p ** k - 1
+    tabs = gf.log_tables(p, P_low)
+    gen, expo, logs = tabs
+    assert sorted(expo) == list(range(1, p ** k))       # g^e runs over every nonzero element
+    assert all(logs[expo[e]] == e for e in range(m))
+    Z = gf.zech_table(p, P_low)
+    for n in range(m):
+        # g^Z[n] = 1 + g^n in coefficient form
+        one_plus = gf.field_add([1] + [0] * (k - 1), gf.from_log(n, p, P_low, tabs), p)
+        assert gf.from_log(Z[n], p, P_low, tabs) == one_plus
+        # Z[-n] = Z[n] - n mod m (multiply 1 + g^n by g^-n)
+        if Z[n] != m:
+            assert Z[(-n) % m] == (Z[n] - n) % m
+    # 1 + g^n = 0 exactly for g^n = -1: n = m/2 for odd p, n = 0 for p = 2
+    assert Z.index(m) == (0 if p == 2 else m // 2)
+    assert Z.count(m) == 1
+
+
+@pytest.mark.parametrize("p,P_low", LOG_FIELDS[:6])
+def test_log_add_is_field_add(p, P_low):
+    k = len(P_low)
+    m = p ** k - 1
+    tabs = gf.log_tables(p, P_low)
+    Z = gf.zech_table(p, P_low)
+    codes = range(m + 1) if m < 130 else random.Random(3).sample(range(m + 1), 130)
+    for a in codes:
+        for b in codes:
+            want = gf.field_add(gf.from_log(a, p, P_low, tabs), gf.from_log(b, p, P_low, tabs), p)
+            assert gf.from_log(gf.log_add(a, b, Z), p, P_low, tabs) == want
+
+
+@pytest.mark.parametrize("p,P_low", [(7, (1, 0)), (3, (2, 0, 0, 2)), (5, (3, 3, 0)),
+                                     (2, (1, 0, 1))])
+def test_alg4_on_logs_matches_the_definition(p, P_low):
+    # Alg. 4 step by step (tabulated conversion, REDQ, L and H as codes, Zech
+    # addition), in blocks of n_q, against the product of the antilogs
+    k = len(P_low)
+    m = p ** k - 1
+    q, nq = gf.max_pow2_q(p, k)
+    rng = np.random.default_rng(p + k)
+    for (M, K, N) in [(3, 1, 2), (4, 9, 3), (2, 2 * nq + 3, 2)]:
+        A = rng.integers(0, m + 1, size=(M, K))
+        B = rng.integers(0, m + 1, size=(K, N))
+        A[0, 0] = m                            # zeros are codes too
+        want = gf.gemm_log(A, B, p, P_low)
+        got = gf.gemm_log_alg4(A.tolist(), B.tolist(), p, P_low, q, nq)
+        assert np.array_equal(np.array(got), want), (M, K, N)
+    # every element p-1 coefficient-wise: the packed sums reach eq. (2)'s bound
+    full = gf.to_log([p - 1] * k, p, P_low)
+    A = np.full((2, nq), full)
+    B = np.full((nq, 2), full)
+    assert np.array_equal(np.array(gf.gemm_log_alg4(A.tolist(), B.tolist(), p, P_low, q, nq)),
+                          gf.gemm_log(A, B, p, P_low))
+
+
+def test_gemm_log_definition_on_small_cases():
+    # the log-form definition against the one-product-at-a-time field
+    # arithmetic on codes: a sum of g^(a+b) terms built with log_add
+    p, P_low = 5, (3, 3, 0)
+    m = p ** 3 - 1
+    Z = gf.zech_table(p, P_low)
+    rng = np.random.default_rng(11)
+    A = rng.integers(0, m + 1, size=(3, 7))
+    B = rng.integers(0, m + 1, size=(7, 4))
+    C = gf.gemm_log(A, B, p, P_low)
+    for i in range(3):
+        for j in range(4):
+            acc = m
+            for l in range(7):
+                a, b = int(A[i, l]), int(B[l, j])
+                prod = m if m in (a, b) else (a + b) % m      # g^a g^b = g^(a+b)
+                acc = gf.log_add(acc, prod, Z)
+            assert C[i, j] == acc
