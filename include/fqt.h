@@ -274,6 +274,51 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path,
                                     const fqt_gemm_desc* descs,
                                     fqt_stream_t s);
 
+/* ---- discrete-log representation (Section 7, Alg. 4) -------------------- */
+
+/* Alg. 4 takes field elements as exponents of a generator g.  A code is a
+ * uint16: e in [0, m-1] stands for g^e, m = p^k - 1 stands for zero, and
+ * every entry point below reads codes above m as zero.  g is the first
+ * element of multiplicative order m in base-p order (element index
+ * sum_i c_i p^i), a choice the paper leaves open.  All buffers are device
+ * pointers; calls are asynchronous on stream s.  Tables are built on first
+ * use on each device (a few KB, held by the field). */
+
+/* Host query: the generator's base-p index and the code of zero (m).
+ * Either pointer may be NULL. */
+fqt_status fqt_log_info(fqt_field f, uint32_t* generator_index, uint32_t* zero_code);
+
+/* codes[i] = log of the element held in coeffs[k*i .. k*i + k-1] (one
+ * coefficient per byte, each in [0, p); an element with a byte >= p is read
+ * as zero).  n >= 0 elements; the buffers must not overlap
+ * (FQT_ERR_INVALID_ARG). */
+fqt_status fqt_to_log(fqt_field f, const uint8_t* coeffs, int64_t n, uint16_t* codes,
+                      fqt_stream_t s);
+
+/* coeffs[k*i ..] = the coefficients of the element with code codes[i]. */
+fqt_status fqt_from_log(fqt_field f, const uint16_t* codes, int64_t n, uint8_t* coeffs,
+                        fqt_stream_t s);
+
+/* c[i] = a[i] + b[i] in the field, on codes, through the Zech table
+ * Z[n] = log(1 + g^n): g^a + g^b = g^(a + Z[b-a]) (Alg. 4's last step).
+ * c may equal a or b; any other overlap is FQT_ERR_INVALID_ARG. */
+fqt_status fqt_log_add(fqt_field f, const uint16_t* a, const uint16_t* b, int64_t n,
+                       uint16_t* c, fqt_stream_t s);
+
+/* C = A * B over the field on codes (Alg. 4 for every entry): each operand
+ * code becomes its element's evaluation at q by one table lookup, the
+ * packed products are contracted exactly on the FP64 MFMA in K-blocks of
+ * n_q (eq. (2)), REDQ gives the residues u, Thm. 3's L and H tables return
+ * codes and R = H + L by the Zech table.  A is M x K, B is K x N, C is
+ * M x N codes, ld* in elements (lda >= K, ldb >= N, ldc >= N); C must not
+ * overlap A or B; K == 0 writes the zero code.  opts as for the packed
+ * path; tile 0 (default), 7, 9 or 11 (else FQT_ERR_UNSUPPORTED); 7 and 9
+ * take one K-block, 11 several; a tile whose split-K buffer and tables do
+ * not fit LDS is FQT_ERR_UNSUPPORTED. */
+fqt_status fqt_gemm_log(fqt_field f, const fqt_gemm_opts* opts, int64_t M, int64_t N,
+                        int64_t K, const uint16_t* A, int64_t lda, const uint16_t* B,
+                        int64_t ldb, uint16_t* C, int64_t ldc, fqt_stream_t s);
+
 /* ---- autotuner ----------------------------------------------------------- */
 
 /* Time every admissible (path, q, n_q, tile) candidate on the given problem

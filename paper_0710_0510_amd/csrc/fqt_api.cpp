@@ -167,6 +167,29 @@ struct TuneEntry {
   fqt_gemm_opts opts;
 };
 
+// Discrete-log representation (Alg. 4).  Codes e < m = p^k - 1 stand for
+// g^e; m codes zero.
+struct LogHost {
+  bool built = false;
+  uint32_t gen = 0;                // base-p index sum c_i p^i of the generator
+  uint32_t m = 0;                  // p^k - 1
+  std::vector<uint32_t> expw;      // code -> coefficient word (byte i = c_i), m + 1 entries
+  std::vector<uint16_t> logt;      // binary index (Section 5.3) -> code
+  std::vector<uint16_t> zech;      // Z[n] = log(1 + g^n), m + 1 entries (Z[m] = m)
+};
+
+struct DevLogBase {  // per device
+  uint32_t* expw = nullptr;
+  uint16_t* logt = nullptr;
+  uint16_t* zech = nullptr;
+};
+
+struct DevLogQ {  // per device and q = 2^b
+  uint32_t* pk = nullptr;  // evaluation at q of every code's element, pk[m] = 0
+  uint32_t* L = nullptr;  // Thm. 3's tables, holding codes
+  uint32_t* H = nullptr;
+};
+
 }  // namespace
 
 struct fqt_field_s {
@@ -179,6 +202,9 @@ struct fqt_field_s {
   std::map<std::string, TuneEntry> tuned;
   std::map<int, Workspace> ws;  // per device: B' of the INT8 path
   std::map<int, uint8_t*> dev_mt;  // per device: multiplication-matrix table
+  LogHost lg;
+  std::map<int, DevLogBase> dev_logb;
+  std::map<std::pair<int, uint32_t>, DevLogQ> dev_logq;  // (device, b)
 };
 
 namespace {
@@ -309,6 +335,178 @@ fqt_status device_mt(fqt_field_s* f, uint8_t** out) {
   return ok();
 }
 
+// ---- discrete-log tables (host, then per device) ----------------------------
+
+// Product of two elements given as k coefficients, reduced mod P.
+std::vector<uint32_t> elem_mul(const fqt_field_s* f, const std::vector<uint32_t>& a,
+                               const std::vector<uint32_t>& b) {
+  const uint32_t k = f->k, p = f->p;
+  std::vector<uint32_t> c(2 * k - 1, 0);
+  for (uint32_t i = 0; i < k; ++i)
+    for (uint32_t j = 0; j < k; ++j) c[i + j] = (c[i + j] + a[i] * b[j]) % p;
+  return poly_mod(c, f->P_low, k, p);
+}
+
+std::vector<uint32_t> elem_pow(const fqt_field_s* f, std::vector<uint32_t> a, uint64_t e) {
+  std::vector<uint32_t> r(f->k, 0);
+  r[0] = 1;
+  while (e) {
+    if (e & 1) r = elem_mul(f, r, a);
+    a = elem_mul(f, a, a);
+    e >>= 1;
+  }
+  return r;
+}
+
+// Generator: the first element in base-p order whose order is m = p^k - 1,
+// i.e. a^(m/r) != 1 for every prime r dividing m.  Then the exponent,
+// binary-index and Zech tables.  Caller holds f->mu.
+void log_host(fqt_field_s* f) {
+  LogHost& lg = f->lg;
+  if (lg.built) return;
+  const uint32_t p = f->p, k = f->k, cb = f->cb;
+  uint32_t pk = 1;
+  for (uint32_t i = 0; i < k; ++i) pk *= p;
+  const uint32_t m = pk - 1;
+  std::vector<uint32_t> primes;
+  for (uint32_t x = m, d = 2; x > 1; ++d) {
+    if (d * d > x) d = x;
+    if (x % d == 0) {
+      primes.push_back(d);
+      while (x % d == 0) x /= d;
+    }
+  }
+  auto coeffs = [&](uint32_t idx) {
+    std::vector<uint32_t> c(k);
+    for (uint32_t i = 0; i < k; ++i, idx /= p) c[i] = idx % p;
+    return c;
+  };
+  auto is_one = [&](const std::vector<uint32_t>& c) {
+    if (c[0] != 1) return false;
+    for (uint32_t i = 1; i < k; ++i)
+      if (c[i]) return false;
+    return true;
+  };
+  uint32_t gen = 0;
+  for (uint32_t idx = 1; idx < pk && !gen; ++idx) {
+    const auto a = coeffs(idx);
+    bool full = true;
+    for (uint32_t r : primes) full = full && !is_one(elem_pow(f, a, m / r));
+    if (full) gen = idx;
+  }
+  auto word = [&](const std::vector<uint32_t>& c) {
+    uint32_t w = 0;
+    for (uint32_t i = 0; i < k; ++i) w |= c[i] << (8 * i);
+    return w;
+  };
+  auto bin = [&](const std::vector<uint32_t>& c) {
+    uint32_t b = 0;
+    for (uint32_t i = 0; i < k; ++i) b |= c[i] << (cb * i);
+    return b;
+  };
+  lg.gen = gen;
+  lg.m = m;
+  lg.expw.assign(m + 1, 0);
+  lg.logt.assign((size_t)1 << (k * cb), (uint16_t)m);
+  lg.zech.assign(m + 1, (uint16_t)m);
+  const auto g = coeffs(gen);
+  std::vector<std::vector<uint32_t>> powers(m);
+  std::vector<uint32_t> x(k, 0);
+  x[0] = 1;
+  for (uint32_t e = 0; e < m; ++e) {
+    powers[e] = x;
+    lg.expw[e] = word(x);
+    lg.logt[bin(x)] = (uint16_t)e;
+    x = elem_mul(f, x, g);
+  }
+  for (uint32_t n = 0; n < m; ++n) {
+    auto y = powers[n];
+    y[0] = (y[0] + 1) % p;
+    lg.zech[n] = lg.logt[bin(y)];
+  }
+  lg.built = true;
+}
+
+template <typename T>
+fqt_status upload(const std::vector<T>& v, T** out) {
+  FQT_HIP(hipMalloc(out, v.size() * sizeof(T)));
+  FQT_HIP(hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return ok();
+}
+
+fqt_status device_log_base(fqt_field_s* f, DevLogBase* out) {
+  std::lock_guard<std::mutex> lk(f->mu);
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  auto it = f->dev_logb.find(dev);
+  if (it != f->dev_logb.end()) {
+    *out = it->second;
+    return ok();
+  }
+  log_host(f);
+  DevLogBase d;
+  fqt_status st = upload(f->lg.expw, &d.expw);
+  if (!st) st = upload(f->lg.logt, &d.logt);
+  if (!st) st = upload(f->lg.zech, &d.zech);
+  if (st) {
+    hipFree(d.expw);
+    hipFree(d.logt);
+    hipFree(d.zech);
+    return st;
+  }
+  f->dev_logb[dev] = d;
+  *out = d;
+  return ok();
+}
+
+// Packed values at q = 2^b and Thm. 3's tables mapped to codes.
+fqt_status device_log_q(fqt_field_s* f, uint32_t b, DevLogQ* out) {
+  std::lock_guard<std::mutex> lk(f->mu);
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  const auto key = std::make_pair(dev, b);
+  auto it = f->dev_logq.find(key);
+  if (it != f->dev_logq.end()) {
+    *out = it->second;
+    return ok();
+  }
+  log_host(f);
+  const LogHost& lg = f->lg;
+  const uint32_t k = f->k, cb = f->cb;
+  const uint64_t q = 1ull << b;
+  std::vector<uint32_t> pk(lg.m + 1, 0);
+  for (uint32_t e = 0; e < lg.m; ++e) {
+    uint64_t v = 0;
+    for (int i = (int)k - 1; i >= 0; --i) v = v * q + ((lg.expw[e] >> (8 * i)) & 0xffu);
+    if (v > UINT32_MAX) return fail(FQT_ERR_UNSUPPORTED, "packed value above 2^32 at q = 2^%u", b);
+    pk[e] = (uint32_t)v;  // below p q^(k-1) < 2^32 for every q eq. (2) admits
+  }
+  const auto& ht = host_tables(f, q);
+  auto to_code = [&](uint32_t w) {
+    uint32_t bi = 0;
+    for (uint32_t i = 0; i < k; ++i) bi |= ((w >> (8 * i)) & 0xffu) << (cb * i);
+    return (uint32_t)lg.logt[bi];
+  };
+  std::vector<uint32_t> Lc(ht.first.size()), Hc(ht.second.size());
+  for (size_t i = 0; i < Lc.size(); ++i) {
+    Lc[i] = to_code(ht.first[i]);
+    Hc[i] = to_code(ht.second[i]);
+  }
+  DevLogQ d;
+  fqt_status st = upload(pk, &d.pk);
+  if (!st) st = upload(Lc, &d.L);
+  if (!st) st = upload(Hc, &d.H);
+  if (st) {
+    hipFree(d.pk);
+    hipFree(d.L);
+    hipFree(d.H);
+    return st;
+  }
+  f->dev_logq[key] = d;
+  *out = d;
+  return ok();
+}
+
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
   return na && nb && x < y + nb && y < x + na;
@@ -324,10 +522,12 @@ size_t mat_bytes(int64_t rows, int64_t cols, int64_t ld, uint32_t k) {
   return (size_t)(((rows - 1) * ld + cols) * (int64_t)k);
 }
 
+// eb = bytes per element (k coefficients, or 2 for a discrete-log code)
 fqt_status check_gemm_args(const fqt_field_s* f, int64_t M, int64_t N, int64_t K,
                            const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb,
-                           uint8_t* C, int64_t ldc) {
+                           uint8_t* C, int64_t ldc, uint32_t eb = 0) {
   if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (!eb) eb = f->k;
   if (M < 0 || N < 0 || K < 0) return fail(FQT_ERR_INVALID_ARG, "negative dimension");
   if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
     return fail(FQT_ERR_UNSUPPORTED, "dimension above 2^31-1");
@@ -337,8 +537,8 @@ fqt_status check_gemm_args(const fqt_field_s* f, int64_t M, int64_t N, int64_t K
   if (M && N && !C) return fail(FQT_ERR_INVALID_ARG, "null C");
   if (M && K && !A) return fail(FQT_ERR_INVALID_ARG, "null A");
   if (K && N && !B) return fail(FQT_ERR_INVALID_ARG, "null B");
-  const size_t nc = mat_bytes(M, N, ldc, f->k);
-  if (overlap(C, nc, A, mat_bytes(M, K, lda, f->k)) || overlap(C, nc, B, mat_bytes(K, N, ldb, f->k)))
+  const size_t nc = mat_bytes(M, N, ldc, eb);
+  if (overlap(C, nc, A, mat_bytes(M, K, lda, eb)) || overlap(C, nc, B, mat_bytes(K, N, ldb, eb)))
     return fail(FQT_ERR_INVALID_ARG, "C overlaps A or B");
   return ok();
 }
@@ -556,6 +756,26 @@ void fqt_field_destroy(fqt_field f) {
     if (hipGetDevice(&cur) == hipSuccess) {
       hipSetDevice(kv.first);
       hipFree(kv.second);
+      hipSetDevice(cur);
+    }
+  }
+  for (auto& kv : f->dev_logb) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+      hipSetDevice(kv.first);
+      hipFree(kv.second.expw);
+      hipFree(kv.second.logt);
+      hipFree(kv.second.zech);
+      hipSetDevice(cur);
+    }
+  }
+  for (auto& kv : f->dev_logq) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+      hipSetDevice(kv.first.first);
+      hipFree(kv.second.pk);
+      hipFree(kv.second.L);
+      hipFree(kv.second.H);
       hipSetDevice(cur);
     }
   }
@@ -797,6 +1017,123 @@ fqt_status fqt_polymul_delayed(uint32_t p, const uint8_t* a, const uint8_t* b, i
   DelayedArgs g{a, b, c, count, (int32_t)len, p, 0};
   if (sq && (uint64_t)len * sq > lim) g.nd = (uint32_t)(lim / sq);
   FQT_HIP(launch_polymul_delayed(g, (hipStream_t)s));
+  return ok();
+}
+
+// ---- discrete-log representation (Alg. 4) -----------------------------------
+
+fqt_status fqt_log_info(fqt_field f, uint32_t* generator_index, uint32_t* zero_code) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  std::lock_guard<std::mutex> lk(f->mu);
+  log_host(f);
+  if (generator_index) *generator_index = f->lg.gen;
+  if (zero_code) *zero_code = f->lg.m;
+  return ok();
+}
+
+fqt_status fqt_to_log(fqt_field f, const uint8_t* coeffs, int64_t n, uint16_t* codes,
+                      fqt_stream_t s) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (n < 0) return fail(FQT_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return ok();
+  if (!coeffs || !codes) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (overlap(coeffs, (size_t)n * f->k, codes, (size_t)n * 2))
+    return fail(FQT_ERR_INVALID_ARG, "output overlaps the input");
+  DevLogBase d;
+  fqt_status st = device_log_base(f, &d);
+  if (st) return st;
+  FQT_HIP(launch_to_log((int)f->k, f->cb, coeffs, n, d.logt, codes, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_from_log(fqt_field f, const uint16_t* codes, int64_t n, uint8_t* coeffs,
+                        fqt_stream_t s) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (n < 0) return fail(FQT_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return ok();
+  if (!coeffs || !codes) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (overlap(coeffs, (size_t)n * f->k, codes, (size_t)n * 2))
+    return fail(FQT_ERR_INVALID_ARG, "output overlaps the input");
+  DevLogBase d;
+  fqt_status st = device_log_base(f, &d);
+  if (st) return st;
+  FQT_HIP(launch_from_log((int)f->k, codes, n, f->lg.m, d.expw, coeffs, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_log_add(fqt_field f, const uint16_t* a, const uint16_t* b, int64_t n, uint16_t* c,
+                       fqt_stream_t s) {
+  if (!f) return fail(FQT_ERR_INVALID_ARG, "null field");
+  if (n < 0) return fail(FQT_ERR_INVALID_ARG, "n < 0");
+  if (n == 0) return ok();
+  if (!a || !b || !c) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  const size_t nb = (size_t)n * 2;
+  // in place (c == a or c == b) is fine; any other overlap is not
+  if ((c != a && overlap(c, nb, a, nb)) || (c != b && overlap(c, nb, b, nb)))
+    return fail(FQT_ERR_INVALID_ARG, "output partly overlaps an input");
+  DevLogBase d;
+  fqt_status st = device_log_base(f, &d);
+  if (st) return st;
+  FQT_HIP(launch_log_add(a, b, n, f->lg.m, d.zech, c, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_gemm_log(fqt_field f, const fqt_gemm_opts* opts, int64_t M, int64_t N, int64_t K,
+                        const uint16_t* A, int64_t lda, const uint16_t* B, int64_t ldb, uint16_t* C,
+                        int64_t ldc, fqt_stream_t s) {
+  const uint8_t* A8 = reinterpret_cast<const uint8_t*>(A);
+  const uint8_t* B8 = reinterpret_cast<const uint8_t*>(B);
+  uint8_t* C8 = reinterpret_cast<uint8_t*>(C);
+  fqt_status st = check_gemm_args(f, M, N, K, A8, lda, B8, ldb, C8, ldc, 2);
+  if (st) return st;
+  if (M == 0 || N == 0) return ok();
+  fqt_gemm_opts o = opts ? *opts : fqt_gemm_opts{0, 0, 0, 0};
+  if (o.tile && !is_log_tile((int)o.tile))
+    return fail(FQT_ERR_UNSUPPORTED, "tile %u: the log form runs tiles 7, 9 and 11", o.tile);
+  uint32_t m;
+  {
+    std::lock_guard<std::mutex> lk(f->mu);
+    log_host(f);
+    m = f->lg.m;
+  }
+  PackedChoice pc;
+  if (!o.tile) {
+    // one block: the split-K tile when its LDS fits, else tile 9; several: 11
+    fqt_gemm_opts probe = o;
+    probe.tile = 11;
+    st = resolve_packed(f, &probe, K, M, N, &pc);
+    if (st) return st;
+    o.tile = pc.multi ? 11 : (log_tile_fits(7, f->tbl_log2, m) ? 7 : 9);
+  }
+  if (!log_tile_fits((int)o.tile, f->tbl_log2, m))
+    return fail(FQT_ERR_UNSUPPORTED, "tile %u: tables of %u codes do not fit LDS", o.tile, m + 1);
+  st = resolve_packed(f, &o, K, M, N, &pc);
+  if (st) return st;
+  DevLogBase lb;
+  st = device_log_base(f, &lb);
+  if (st) return st;
+  DevLogQ lq;
+  st = device_log_q(f, pc.b, &lq);
+  if (st) return st;
+  const uint64_t q = 1ull << pc.b;
+  PackedParams pp{};
+  pp.b = pc.b;
+  pp.nq_groups = pc.nq / 4;
+  pp.tbl_log2 = f->tbl_log2;
+  pp.aligned = ((((uintptr_t)A) | ((uintptr_t)B)) & 3) == 0 && (lda * 2) % 4 == 0 &&
+               (ldb * 2) % 4 == 0;
+  pp.fold_blocks = pc.fold;
+  pp.qmask = (uint32_t)(q - 1);
+  pp.qmod = (uint32_t)(q % f->p);
+  pp.blk_real = pc.nq_real;
+  pp.fa = field_args(f, q);
+  pp.L = lq.L;
+  pp.H = lq.H;
+  pp.pk = lq.pk;
+  pp.Z = lb.zech;
+  pp.zero_code = m;
+  GemmArgs g{A8, B8, C8, M, N, K, lda, ldb, ldc};
+  FQT_HIP(launch_gemm_log((int)f->k, (int)pc.tile, pc.mode, g, pp, (hipStream_t)s));
   return ok();
 }
 

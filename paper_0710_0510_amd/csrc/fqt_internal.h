@@ -30,6 +30,11 @@ struct PackedParams {
   FieldArgs fa;
   const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)
   const uint32_t* H;
+  // discrete-log operands (Alg. 4): packed value of every code at q, Zech
+  // logarithms, and the code of zero m = p^k - 1 (L and H then hold codes)
+  const uint32_t* pk;  // m + 1 entries, pk[m] = 0 (each below 2^32 under eq. (2))
+  const uint16_t* Z;   // m + 1 entries, Z[n] = log(1 + g^n) (m where 1 + g^n = 0)
+  uint32_t zero_code;
 };
 
 // d-FQT product of long polynomials (k_dfqt.hip): count pairs of len
@@ -168,6 +173,21 @@ hipError_t launch_gemm_direct_batched(int k, int tile, int mode, const GemmArgs*
                                       uint32_t* counter, int grid, const PackedParams& pp,
                                       hipStream_t s);
 int direct_batched_occupancy(int k, int tile, int mode, uint32_t tbl_log2);
+
+// Discrete-log operands (k_gemm_log.hip): register-direct tiles on 16-bit
+// codes, X(id, TM, TN, SK, NWV, MULTI_OK) as in FQT_DIRECT_TILES.
+#define FQT_LOG_TILES(X) X(7, 4, 4, 4, 4, 0) X(9, 4, 4, 1, 4, 0) X(11, 1, 4, 1, 4, 1)
+inline bool is_log_tile(int id) { return id == 7 || id == 9 || id == 11; }
+hipError_t launch_gemm_log(int k, int tile, int mode, const GemmArgs& g, const PackedParams& pp,
+                           hipStream_t s);
+// Whether a log tile's split-K buffer and tables fit one workgroup's LDS.
+bool log_tile_fits(int tile, uint32_t tbl_log2, uint32_t zero_code);
+hipError_t launch_to_log(int k, uint32_t cb, const uint8_t* coeffs, int64_t n,
+                         const uint16_t* logt, uint16_t* codes, hipStream_t s);
+hipError_t launch_from_log(int k, const uint16_t* codes, int64_t n, uint32_t zero_code,
+                           const uint32_t* expw, uint8_t* coeffs, hipStream_t s);
+hipError_t launch_log_add(const uint16_t* a, const uint16_t* b, int64_t n, uint32_t zero_code,
+                          const uint16_t* Z, uint16_t* c, hipStream_t s);
 
 // d-split kernels (tile ids >= kFirstSplitTile, k = 3 or 4).
 hipError_t launch_gemm_split(int k, int tile, const GemmArgs& g, const PackedParams& pp,

@@ -232,6 +232,74 @@ __device__ __forceinline__ uint32_t lh_combine(const uint32_t (&u)[2 * KE - 1],
   return add_bytes_mod_p(Ls[il & tmask], Hs[ih & tmask], pp.fa);
 }
 
+// ---- discrete-log operands (Alg. 4) ------------------------------------------
+// A code e < m = p^k - 1 stands for g^e, the code m for zero; larger codes
+// read as zero.
+
+// Packed value of code e of a run of 16-bit codes: one table lookup
+// (Alg. 4's tabulated conversion to the evaluation at q).  Every packed value
+// of an element is below p q^(k-1) < 2^32 under eq. (2), so the table holds
+// 32-bit integers.
+template <int NWD>
+__device__ __forceinline__ double log_elem(const uint32_t (&raw)[NWD], int e, uint32_t zero,
+                                           const uint32_t* __restrict__ pks) {
+  const uint32_t code = (raw[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+  return (double)pks[min(code, zero)];
+}
+
+// Field addition of codes a, b in [0, m]: zero is the identity, otherwise
+// g^a + g^b = g^a (1 + g^(b-a)) = g^(a + Z[b-a]), zero where Z gives m.
+__device__ __forceinline__ uint32_t zech_add(uint32_t a, uint32_t b, uint32_t m,
+                                             const uint16_t* __restrict__ Zs) {
+  const int32_t dd = (int32_t)b - (int32_t)a;
+  const uint32_t d = (uint32_t)(dd < 0 ? dd + (int32_t)m : dd);  // in [0, m]
+  const uint32_t z = Zs[d];
+  const uint32_t s = a + z;
+  uint32_t r = z >= m ? m : (s >= m ? s - m : s);
+  r = a >= m ? b : r;
+  return b >= m ? a : r;
+}
+
+// Alg. 4's last steps on codes: L and H looked up by the binary indices of
+// (u_0..u_{k-1}) and (u_{k-1}..u_{2k-2}) (Thm. 3's tables, holding codes),
+// then R = H + L by the Zech table.
+template <int KE>
+__device__ __forceinline__ uint32_t lh_log(const uint32_t (&u)[2 * KE - 1],
+                                           const PackedParams& pp,
+                                           const uint32_t* __restrict__ Ls,
+                                           const uint32_t* __restrict__ Hs,
+                                           const uint16_t* __restrict__ Zs) {
+  uint32_t il = 0, ih = 0;
+#pragma unroll
+  for (int d = 0; d < KE; ++d) {
+    il |= u[d] << (pp.fa.cb * d);
+    ih |= u[KE - 1 + d] << (pp.fa.cb * d);
+  }
+  const uint32_t tmask = (1u << pp.tbl_log2) - 1u;
+  return zech_add(Hs[ih & tmask], Ls[il & tmask], pp.zero_code, Zs);
+}
+
+// Bytes of dynamic LDS the log kernels need: L, H, the packed values, the
+// Zech table.
+__host__ __device__ inline size_t log_lds_bytes(uint32_t tbl_log2, uint32_t zero_code) {
+  const size_t n = (size_t)1 << tbl_log2, e = (size_t)zero_code + 1;
+  return (2 * n + e) * 4 + (e * 2 + 3) / 4 * 4;
+}
+
+// Copy the packed values and the Zech table into LDS after L and H.
+__device__ __forceinline__ void log_lds_tables(const PackedParams& pp, uint32_t* tabs,
+                                               uint32_t** pks, uint16_t** Zs) {
+  const int n = 1 << pp.tbl_log2, e = (int)pp.zero_code + 1;
+  uint32_t* pk = tabs + 2 * n;
+  uint16_t* z = reinterpret_cast<uint16_t*>(pk + e);
+  for (int i = threadIdx.x; i < e; i += blockDim.x) {
+    pk[i] = pp.pk[i];
+    z[i] = pp.Z[i];
+  }
+  *pks = pk;
+  *Zs = z;
+}
+
 // Workgroup -> output tile.  Workgroups reach the 8 XCDs round-robin
 // (workgroup i runs on XCD i % 8), and every XCD has its own L2; each XCD is
 // handed one rectangular block of the tile grid (2 x 4 or 4 x 2 blocks), so it

@@ -28,6 +28,7 @@ EXPORTED = [
     "fqt_unpack_redq", "fqt_unpack_redq_u64", "fqt_polymul_batch", "fqt_gemm_gfpk",
     "fqt_gemm_gfpk_ex", "fqt_gemm_gfpk_batched", "fqt_gemm_gfpk_batched_ex", "fqt_autotune",
     "fqt_tile_count", "fqt_last_error", "fqt_version", "fqt_polymul_dfqt", "fqt_polymul_delayed",
+    "fqt_log_info", "fqt_to_log", "fqt_from_log", "fqt_log_add", "fqt_gemm_log",
 ]
 
 
@@ -85,6 +86,12 @@ def lib() -> ctypes.CDLL:
                                              ctypes.POINTER(GemmDesc), vp]),
         "fqt_autotune": (c_int, [vp, c_int, c_i64, ctypes.POINTER(GemmDesc), ctypes.c_char_p,
                                  ctypes.POINTER(c_int), ctypes.POINTER(GemmOpts), vp]),
+        "fqt_log_info": (c_int, [vp, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)]),
+        "fqt_to_log": (c_int, [vp, vp, c_i64, vp, vp]),
+        "fqt_from_log": (c_int, [vp, vp, c_i64, vp, vp]),
+        "fqt_log_add": (c_int, [vp, vp, vp, c_i64, vp, vp]),
+        "fqt_gemm_log": (c_int, [vp, ctypes.POINTER(GemmOpts), c_i64, c_i64, c_i64, vp, c_i64,
+                                 vp, c_i64, vp, c_i64, vp]),
         "fqt_tile_count": (c_u32, [c_int]),
         "fqt_last_error": (ctypes.c_char_p, []),
         "fqt_version": (ctypes.c_char_p, []),
@@ -325,3 +332,93 @@ def autotune(field: Field, descs, cache_path: Optional[str] = None, only: str = 
 
 def tile_count(path: str) -> int:
     return lib().fqt_tile_count(PATHS[path])
+
+
+# ---- discrete-log representation (Alg. 4) -------------------------------------
+
+
+def log_info(field: Field) -> Tuple[int, int]:
+    """(base-p index of the generator g, code of zero m = p^k - 1)."""
+    g, m = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    _check(lib().fqt_log_info(field.handle, ctypes.byref(g), ctypes.byref(m)))
+    return g.value, m.value
+
+
+def _codes(t, name: str):
+    import torch
+    if t.dtype != torch.uint16 or not t.is_cuda:
+        raise ValueError(f"{name}: expected a uint16 device tensor")
+
+
+def to_log(field: Field, coeffs, out=None, stream=None):
+    """Codes of the elements of an (..., k) uint8 device tensor."""
+    import torch
+    if coeffs.dtype != torch.uint8 or not coeffs.is_cuda or coeffs.shape[-1] != field.k \
+            or not coeffs.is_contiguous():
+        raise ValueError(f"coeffs: expected a contiguous (..., {field.k}) uint8 device tensor")
+    n = coeffs.numel() // field.k
+    if out is None:
+        out = torch.empty(coeffs.shape[:-1], dtype=torch.uint16, device=coeffs.device)
+    _codes(out, "out")
+    if out.numel() != n or not out.is_contiguous():
+        raise ValueError("out: one contiguous code per element")
+    _check(lib().fqt_to_log(field.handle, _ptr(coeffs), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def from_log(field: Field, codes, out=None, stream=None):
+    """Coefficient form (..., k) uint8 of a uint16 device tensor of codes."""
+    import torch
+    _codes(codes, "codes")
+    if not codes.is_contiguous():
+        raise ValueError("codes: expected a contiguous tensor")
+    n = codes.numel()
+    if out is None:
+        out = torch.empty(tuple(codes.shape) + (field.k,), dtype=torch.uint8, device=codes.device)
+    if out.dtype != torch.uint8 or out.numel() != n * field.k or not out.is_contiguous():
+        raise ValueError(f"out: expected a contiguous uint8 tensor of {n} x {field.k} bytes")
+    _check(lib().fqt_from_log(field.handle, _ptr(codes), n, _ptr(out), _stream(stream)))
+    return out
+
+
+def log_add(field: Field, a, b, out=None, stream=None):
+    """a + b in the field, element-wise on codes (Zech table)."""
+    import torch
+    _codes(a, "a")
+    _codes(b, "b")
+    if a.shape != b.shape or not a.is_contiguous() or not b.is_contiguous():
+        raise ValueError("a, b: contiguous tensors of one shape")
+    if out is None:
+        out = torch.empty_like(a)
+    _codes(out, "out")
+    if out.shape != a.shape or not out.is_contiguous():
+        raise ValueError("out: a contiguous tensor of the operands' shape")
+    _check(lib().fqt_log_add(field.handle, _ptr(a), _ptr(b), a.numel(), _ptr(out),
+                             _stream(stream)))
+    return out
+
+
+def _code_matrix(t, name: str):
+    _codes(t, name)
+    if t.dim() != 2:
+        raise ValueError(f"{name}: expected a 2-D tensor of codes")
+    if t.numel() and t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name}: codes within a row must be contiguous")
+
+
+def gemm_log(field: Field, A, B, C=None, opts=None, stream=None):
+    """C = A B over the field on codes (M x K and K x N uint16 device tensors)."""
+    import torch
+    M, K = A.shape[0], A.shape[1]
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.uint16, device=A.device)
+    for t, name in ((A, "A"), (B, "B"), (C, "C")):
+        _code_matrix(t, name)
+    if B.shape[0] != K or tuple(C.shape) != (M, N):
+        raise ValueError(f"shapes do not chain: A {tuple(A.shape)}, B {tuple(B.shape)}, "
+                         f"C {tuple(C.shape)}")
+    ld = lambda t: max(t.shape[1], 1) if t.numel() == 0 or t.shape[0] <= 1 else t.stride(0)
+    _check(lib().fqt_gemm_log(field.handle, _opts(opts), M, N, K, _ptr(A), ld(A), _ptr(B), ld(B),
+                              _ptr(C), ld(C), _stream(stream)))
+    return C

@@ -278,3 +278,44 @@ def test_delayed_validation_errors():
     assert name(L.fqt_polymul_delayed(3, v, w, 1, 8193, o, None)) == "FQT_ERR_UNSUPPORTED"
     assert name(L.fqt_polymul_delayed(3, v, w, 1, 0, o, None)) == "FQT_ERR_INVALID_ARG"
     assert name(L.fqt_polymul_delayed(3, v, w, 4, 10, v, None)) == "FQT_ERR_INVALID_ARG"
+
+
+# ---- discrete-log representation -------------------------------------------
+
+@pytest.mark.parametrize("p,k,P", CONFIG_FIELDS + [(2, 2, (1, 1)), (13, 3, (1, 0, 4)),
+                                                   (7, 4, (1, 0, 0, 1)), (11, 1, (9,))])
+def test_log_generator_matches_oracle(p, k, P):
+    # host-only query: the library's generator search against the oracle's
+    f = fqt.Field(p, k, P)
+    g, m = fqt.log_info(f)
+    assert m == p ** k - 1
+    assert g == gf.log_generator(p, P)
+
+
+def test_log_validation_errors():
+    f = fqt.Field(5, 3, (3, 3, 0))
+    L = fqt.lib()
+    v = ctypes.c_void_p(BOGUS)
+    w = ctypes.c_void_p(BOGUS + (1 << 30))
+    o = ctypes.c_void_p(BOGUS + (1 << 31))
+    name = lambda st: fqt.STATUS_NAMES[st]
+    assert name(L.fqt_to_log(f.handle, v, -1, o, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_to_log(f.handle, v, 10, None, None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_to_log(f.handle, v, 10, ctypes.c_void_p(BOGUS + 4), None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_from_log(f.handle, v, 10, ctypes.c_void_p(BOGUS + 8), None)) == "FQT_ERR_INVALID_ARG"
+    # log_add: in place is allowed, a partial overlap is not
+    assert name(L.fqt_log_add(f.handle, v, w, 10, ctypes.c_void_p(BOGUS + 2), None)) == "FQT_ERR_INVALID_ARG"
+    assert name(L.fqt_log_add(f.handle, v, w, -3, o, None)) == "FQT_ERR_INVALID_ARG"
+
+    def gemm_log(M, N, K, lda, ldb, ldc, A=BOGUS, B=BOGUS + (1 << 30), C=BOGUS + (1 << 31),
+                 opts=None):
+        return name(L.fqt_gemm_log(f.handle, fqt._opts(opts), M, N, K, ctypes.c_void_p(A), lda,
+                                   ctypes.c_void_p(B), ldb, ctypes.c_void_p(C), ldc, None))
+    assert gemm_log(4, 4, 8, 4, 4, 4) == "FQT_ERR_INVALID_ARG"             # lda < K
+    assert gemm_log(-1, 4, 4, 4, 4, 4) == "FQT_ERR_INVALID_ARG"
+    assert gemm_log(4, 4, 4, 4, 4, 4, C=BOGUS + 6) == "FQT_ERR_INVALID_ARG"  # C overlaps A (2-byte codes)
+    assert gemm_log(4, 4, 4, 4, 4, 4, opts={"tile": 2}) == "FQT_ERR_UNSUPPORTED"
+    assert gemm_log(4, 4, 4, 4, 4, 4, opts={"tile": 13}) == "FQT_ERR_UNSUPPORTED"
+    assert gemm_log(4, 4, 4, 4, 4, 4, opts={"n_q": 100}) == "FQT_ERR_BOUNDS"
+    # tiles 7 and 9 take one K-block (q = 2^10, n_q = 21 for GF(5^3))
+    assert gemm_log(4, 4, 64, 64, 4, 4, opts={"tile": 7}) == "FQT_ERR_UNSUPPORTED"
