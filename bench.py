@@ -167,6 +167,31 @@ def bench_gemm(w, args, torch, fqt, gf):
         results[path] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": steps,
                          "tile": tile, "roofline": roofline_for(path, w.k, work, ms, tile)}
 
+    if args.all_paths:
+        # the same product on discrete-log codes (Alg. 4's representation):
+        # conversions outside the timed region, every log tile that admits K
+        Al, Bl, Rl = fqt.to_log(f, A), fqt.to_log(f, B), fqt.to_log(f, Cref)
+        Cl = torch.empty_like(Rl)
+        best = None
+        for tile in (7, 9, 11):
+            try:
+                fqt.gemm_log(f, Al, Bl, Cl, opts={"tile": tile})
+            except fqt.FqtError:
+                continue
+            torch.cuda.synchronize()
+            if not torch.equal(Cl, Rl):
+                raise SystemExit(f"parity failure: log tile {tile} differs from the plain path")
+            ms = time_steps(lambda: fqt.gemm_log(f, Al, Bl, Cl, opts={"tile": tile}), args.steps,
+                            args.warmup, torch)
+            if best is None or ms < best[1]:
+                best = (tile, ms)
+        if best:
+            tile, ms = best
+            rl = roofline_for("packed", w.k, work, ms, tile)
+            rl["kernel"] = f"gemm_direct_kernel on codes, tile {tile} (pack-table lookup + FP64 MFMA + REDQ + L/H codes + Zech)"
+            results["log"] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": args.steps,
+                              "tile": tile, "roofline": rl}
+
     main_r = results[args.path]
     tr = MEASURED_TRAFFIC.get((w.name, args.path, main_r["tile"]))
     if tr:
@@ -185,7 +210,8 @@ def bench_gemm(w, args, torch, fqt, gf):
                    "tuned": tuned},
         "roofline": main_r["roofline"],
         "paths": {p: {"value": r["value"], "ms_per_step": r["ms_per_step"],
-                      "roofline_frac": r["roofline"]["frac"], "unit": "field mul-adds/s"}
+                      "roofline_frac": r["roofline"]["frac"], "unit": "field mul-adds/s",
+                      "tile": r["tile"]}
                   for p, r in results.items()},
         "parity": {"sampled_entries_vs_oracle": args.samples, "sampled_mismatches": bad,
                    "every_path_identical_to_plain": True},
