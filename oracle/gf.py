@@ -638,3 +638,70 @@ def gemm_log(A: np.ndarray, B: np.ndarray, p: int, P_low: Sequence[int]) -> np.n
         lut[idx] = e
     weights = np.array([p ** i for i in range(k)], dtype=np.int64)
     return lut[(Cc.astype(np.int64) * weights).sum(axis=-1)]
+
+
+# ---------------------------------------------------------------------------
+# Winograd's variant of Strassen's product over GF(p^k) (the setting of the
+# paper's Fig. 3: finite-field Winograd matrix multiplication with the FQT as
+# the base case)
+# ---------------------------------------------------------------------------
+#
+# On a 2 x 2 block partition, seven block products and fifteen block
+# additions (Winograd's schedule):
+#   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2,
+#   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21,
+#   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4,
+#   P5 = S1 T1, P6 = S2 T2, P7 = S3 T3,
+#   C11 = P1 + P2, U2 = P1 + P6, U3 = U2 + P7, U4 = U2 + P5,
+#   C12 = U4 + P3, C21 = U3 - P4, C22 = U3 + P5.
+# Additions of field elements are coefficient-wise mod p.  Odd dimensions are
+# peeled: the even part goes through the recursion, the last row, column or
+# rank-one term through the definition.
+
+
+def _fadd(X: np.ndarray, Y: np.ndarray, p: int) -> np.ndarray:
+    return ((X.astype(np.int64) + Y) % p).astype(np.uint8)
+
+
+def _fsub(X: np.ndarray, Y: np.ndarray, p: int) -> np.ndarray:
+    return ((X.astype(np.int64) - Y) % p).astype(np.uint8)
+
+
+def gemm_winograd(A: np.ndarray, B: np.ndarray, p: int, P_low: Sequence[int],
+                  levels: int) -> np.ndarray:
+    """C = A B over GF(p^k) (M x K x k and K x N x k coefficient arrays) with
+    `levels` levels of Winograd's recursion over gemm_gfpk_planes."""
+    M, K, k = A.shape
+    N = B.shape[1]
+    if levels <= 0 or M < 2 or N < 2 or K < 2:
+        return gemm_gfpk_planes(A, B, p, P_low)
+    m, n, kk = M // 2 * 2, N // 2 * 2, K // 2 * 2
+    C = np.zeros((M, N, k), dtype=np.uint8)
+    h, w, d = m // 2, n // 2, kk // 2
+    A11, A12, A21, A22 = A[:h, :d], A[:h, d:kk], A[h:m, :d], A[h:m, d:kk]
+    B11, B12, B21, B22 = B[:d, :w], B[:d, w:n], B[d:kk, :w], B[d:kk, w:n]
+    S1 = _fadd(A21, A22, p)
+    S2 = _fsub(S1, A11, p)
+    S3 = _fsub(A11, A21, p)
+    S4 = _fsub(A12, S2, p)
+    T1 = _fsub(B12, B11, p)
+    T2 = _fsub(B22, T1, p)
+    T3 = _fsub(B22, B12, p)
+    T4 = _fsub(T2, B21, p)
+    rec = lambda X, Y: gemm_winograd(X, Y, p, P_low, levels - 1)
+    P1, P2, P3 = rec(A11, B11), rec(A12, B21), rec(S4, B22)
+    P4, P5, P6, P7 = rec(A22, T4), rec(S1, T1), rec(S2, T2), rec(S3, T3)
+    U2 = _fadd(P1, P6, p)
+    U3 = _fadd(U2, P7, p)
+    U4 = _fadd(U2, P5, p)
+    C[:h, :w] = _fadd(P1, P2, p)
+    C[:h, w:n] = _fadd(U4, P3, p)
+    C[h:m, :w] = _fsub(U3, P4, p)
+    C[h:m, w:n] = _fadd(U3, P5, p)
+    if kk < K:   # rank-one term of the last k
+        C[:m, :n] = _fadd(C[:m, :n], gemm_gfpk_planes(A[:m, kk:], B[kk:, :n], p, P_low), p)
+    if m < M:    # last row
+        C[m:, :] = gemm_gfpk_planes(A[m:, :], B, p, P_low)
+    if n < N:    # last column
+        C[:m, n:] = gemm_gfpk_planes(A[:m, :], B[:, n:], p, P_low)
+    return C

@@ -557,3 +557,42 @@ def test_gemm_log_definition_on_small_cases():
                 prod = m if m in (a, b) else (a + b) % m      # g^a g^b = g^(a+b)
                 acc = gf.log_add(acc, prod, Z)
             assert C[i, j] == acc
+
+
+# ---- Winograd's product over GF(p^k) -----------------------------------------
+
+@pytest.mark.parametrize("p,P_low", [(7, (1, 0)), (3, (2, 0, 0, 2)), (5, (3, 3, 0)), (2, (1, 0, 1)),
+                                     (13, (2,))])
+def test_winograd_matches_the_definition(p, P_low):
+    k = len(P_low)
+    rng = np.random.default_rng(p * 10 + k)
+    for (M, N, K) in [(2, 2, 2), (4, 6, 8), (7, 5, 9), (16, 16, 16), (33, 18, 21), (3, 2, 1),
+                      (1, 5, 4)]:
+        A = rng.integers(0, p, size=(M, K, k), dtype=np.uint8)
+        B = rng.integers(0, p, size=(K, N, k), dtype=np.uint8)
+        want = gf.gemm_gfpk_planes(A, B, p, P_low)
+        for levels in (1, 2, 3):
+            assert np.array_equal(gf.gemm_winograd(A, B, p, P_low, levels), want), (M, N, K, levels)
+
+
+def test_winograd_one_level_by_hand_gf2():
+    # GF(2), 2 x 2 blocks of 1 x 1: the seven products and fifteen additions
+    # against the 2 x 2 product written out
+    A = np.array([[1, 1], [0, 1]], dtype=np.uint8).reshape(2, 2, 1)
+    B = np.array([[1, 0], [1, 1]], dtype=np.uint8).reshape(2, 2, 1)
+    # [[1+1, 0+1], [0+1, 0+1]] mod 2
+    want = np.array([[0, 1], [1, 1]], dtype=np.uint8).reshape(2, 2, 1)
+    assert np.array_equal(gf.gemm_winograd(A, B, 2, (1,), 1), want)
+
+
+def test_winograd_identity_and_zero():
+    p, P_low = 5, (3, 3, 0)
+    k = 3
+    rng = np.random.default_rng(4)
+    A = rng.integers(0, p, size=(12, 12, k), dtype=np.uint8)
+    I = np.zeros((12, 12, k), dtype=np.uint8)
+    for i in range(12):
+        I[i, i, 0] = 1
+    assert np.array_equal(gf.gemm_winograd(A, I, p, P_low, 2), A)
+    assert np.array_equal(gf.gemm_winograd(I, A, p, P_low, 2), A)
+    assert not gf.gemm_winograd(A, np.zeros_like(A), p, P_low, 2).any()
