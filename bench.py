@@ -192,6 +192,29 @@ def bench_gemm(w, args, torch, fqt, gf):
             results["log"] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": args.steps,
                               "tile": tile, "roofline": rl}
 
+    if args.all_paths and "packed" in results:
+        # Winograd's recursion (the setting of the paper's Fig. 3): 1 and 2
+        # levels over the packed path with its tuned tile
+        popts = {"tile": results["packed"]["tile"]} if results["packed"]["tile"] else None
+        Cw = torch.empty_like(Cref)
+        best = None
+        for levels in (1, 2):
+            fqt.gemm_winograd(f, A, B, Cw, levels=levels, path="packed", opts=popts)
+            torch.cuda.synchronize()
+            if not torch.equal(Cw, Cref):
+                raise SystemExit(f"parity failure: Winograd with {levels} levels differs")
+            ms = time_steps(lambda: fqt.gemm_winograd(f, A, B, Cw, levels=levels, path="packed",
+                                                      opts=popts),
+                            max(3, args.steps // 2), args.warmup, torch)
+            if best is None or ms < best[1]:
+                best = (levels, ms)
+        levels, ms = best
+        rl = roofline_for("packed", w.k, work, ms, results["packed"]["tile"])
+        rl["kernel"] = (f"Winograd, {levels} level(s): 7^{levels} products on tile "
+                        f"{results['packed']['tile']} + block additions (classical flop count)")
+        results["winograd"] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": args.steps,
+                               "tile": results["packed"]["tile"], "levels": levels, "roofline": rl}
+
     main_r = results[args.path]
     tr = MEASURED_TRAFFIC.get((w.name, args.path, main_r["tile"]))
     if tr:
@@ -211,7 +234,7 @@ def bench_gemm(w, args, torch, fqt, gf):
         "roofline": main_r["roofline"],
         "paths": {p: {"value": r["value"], "ms_per_step": r["ms_per_step"],
                       "roofline_frac": r["roofline"]["frac"], "unit": "field mul-adds/s",
-                      "tile": r["tile"]}
+                      "tile": r["tile"], **({"levels": r["levels"]} if "levels" in r else {})}
                   for p, r in results.items()},
         "parity": {"sampled_entries_vs_oracle": args.samples, "sampled_mismatches": bad,
                    "every_path_identical_to_plain": True},

@@ -274,6 +274,25 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path,
                                     const fqt_gemm_desc* descs,
                                     fqt_stream_t s);
 
+/* ---- Winograd's product over GF(p^k) (the paper's Fig. 3 setting) ------ */
+
+/* C = A * B over the field with `levels` levels (0..6, else
+ * FQT_ERR_INVALID_ARG) of Winograd's variant of Strassen's recursion: per
+ * level seven block products, run as fqt_gemm_gfpk_ex(path, opts) calls,
+ * and fifteen block additions coefficient-wise mod p.  Odd dimensions are
+ * peeled (last row, last column, and the last k as a rank-one product added
+ * in); blocks below 2 in any dimension go straight to the path.  Same
+ * buffers, layout and validation as fqt_gemm_gfpk_ex; the result is the same
+ * bytes.  The library keeps device temporaries per field and device, about
+ * (4hd + 4dw + 7hw) k bytes per level for blocks of h x d, d x w, h x w
+ * elements (h = M/2, d = K/2, w = N/2 at the first level): calls on one
+ * field must not overlap in time on one device.  FQT_ERR_OOM if they cannot
+ * be allocated. */
+fqt_status fqt_gemm_winograd(fqt_field f, fqt_path path, const fqt_gemm_opts* opts,
+                             uint32_t levels, int64_t M, int64_t N, int64_t K,
+                             const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb,
+                             uint8_t* C, int64_t ldc, fqt_stream_t s);
+
 /* ---- discrete-log representation (Section 7, Alg. 4) -------------------- */
 
 /* Alg. 4 takes field elements as exponents of a generator g.  A code is a

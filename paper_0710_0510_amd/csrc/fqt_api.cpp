@@ -201,6 +201,7 @@ struct fqt_field_s {
   std::vector<std::unique_ptr<BatchPlan>> plans;
   std::map<std::string, TuneEntry> tuned;
   std::map<int, Workspace> ws;  // per device: B' of the INT8 path
+  std::map<int, Workspace> wg_ws;  // per device: temporaries of Winograd's recursion
   std::map<int, uint8_t*> dev_mt;  // per device: multiplication-matrix table
   LogHost lg;
   std::map<int, DevLogBase> dev_logb;
@@ -751,6 +752,14 @@ void fqt_field_destroy(fqt_field f) {
       hipSetDevice(cur);
     }
   }
+  for (auto& kv : f->wg_ws) {
+    int cur = 0;
+    if (hipGetDevice(&cur) == hipSuccess) {
+      hipSetDevice(kv.first);
+      hipFree(kv.second.ptr);
+      hipSetDevice(cur);
+    }
+  }
   for (auto& kv : f->dev_mt) {
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess) {
@@ -1287,6 +1296,152 @@ fqt_status fqt_gemm_gfpk(fqt_field f, fqt_path path, int64_t M, int64_t N, int64
                          const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb,
                          uint8_t* C, int64_t ldc, fqt_stream_t s) {
   return fqt_gemm_gfpk_ex(f, path, nullptr, M, N, K, A, lda, B, ldb, C, ldc, s);
+}
+
+// ---- Winograd's recursion over the field ---------------------------------------
+// Seven block products and fifteen block additions per level (the schedule
+// of the paper's Fig. 3 experiments, finite-field Winograd multiplication
+// with the FQT underneath); the block products are ordinary calls of the
+// chosen path, the additions coefficient-wise mod p.  Odd dimensions are
+// peeled: the last row and column by plain calls, the last k as a rank-one
+// product added in.
+
+namespace {
+
+// Temporaries of one call: S1..S4 (h x d), T1..T4 (d x w), P1..P7 (h x w),
+// the rank-one term (m x n) when K is odd, then those of the next level.
+size_t wg_bytes(uint32_t k, uint32_t levels, int64_t M, int64_t N, int64_t K) {
+  if (!levels || M < 2 || N < 2 || K < 2) return 0;
+  const int64_t m = M & ~1LL, n = N & ~1LL, kk = K & ~1LL;
+  const int64_t h = m / 2, w = n / 2, d = kk / 2;
+  size_t here = (size_t)(4 * h * d + 4 * d * w + 7 * h * w) * k;
+  if (kk < K) here += (size_t)(m * n) * k;
+  return here + wg_bytes(k, levels - 1, h, w, d);
+}
+
+struct WgRun {
+  fqt_field f;
+  fqt_path path;
+  const fqt_gemm_opts* opts;
+  hipStream_t s;
+};
+
+fqt_status wg_add(const WgRun& r, const uint8_t* X, int64_t ldx, const uint8_t* Y, int64_t ldy,
+                  uint8_t* Z, int64_t ldz, int64_t rows, int64_t cols, bool sub) {
+  FQT_HIP(launch_mat_addsub((int)r.f->k, r.f->p, X, ldx, Y, ldy, Z, ldz, rows, cols, sub, r.s));
+  return ok();
+}
+
+fqt_status wg_rec(const WgRun& r, uint32_t levels, int64_t M, int64_t N, int64_t K,
+                  const uint8_t* A, int64_t lda, const uint8_t* B, int64_t ldb, uint8_t* C,
+                  int64_t ldc, uint8_t* ws) {
+  if (!levels || M < 2 || N < 2 || K < 2)
+    return fqt_gemm_gfpk_ex(r.f, r.path, r.opts, M, N, K, A, lda, B, ldb, C, ldc, r.s);
+  const int64_t k = r.f->k;
+  const int64_t m = M & ~1LL, n = N & ~1LL, kk = K & ~1LL;
+  const int64_t h = m / 2, w = n / 2, d = kk / 2;
+  const uint8_t *A11 = A, *A12 = A + d * k, *A21 = A + h * lda * k, *A22 = A21 + d * k;
+  const uint8_t *B11 = B, *B12 = B + w * k, *B21 = B + d * ldb * k, *B22 = B21 + w * k;
+  uint8_t *C11 = C, *C12 = C + w * k, *C21 = C + h * ldc * k, *C22 = C21 + w * k;
+  uint8_t* cur = ws;
+  auto take = [&](int64_t elems) {
+    uint8_t* q = cur;
+    cur += elems * k;
+    return q;
+  };
+  uint8_t *S1 = take(h * d), *S2 = take(h * d), *S3 = take(h * d), *S4 = take(h * d);
+  uint8_t *T1 = take(d * w), *T2 = take(d * w), *T3 = take(d * w), *T4 = take(d * w);
+  uint8_t* P[8];
+  for (int i = 1; i <= 7; ++i) P[i] = take(h * w);
+  uint8_t* R = kk < K ? take(m * n) : nullptr;
+  uint8_t* next = cur;
+  fqt_status st;
+#define FQT_WG(x)   \
+  do {              \
+    st = (x);       \
+    if (st) return st; \
+  } while (0)
+  FQT_WG(wg_add(r, A21, lda, A22, lda, S1, d, h, d, false));  // S1 = A21 + A22
+  FQT_WG(wg_add(r, S1, d, A11, lda, S2, d, h, d, true));      // S2 = S1 - A11
+  FQT_WG(wg_add(r, A11, lda, A21, lda, S3, d, h, d, true));   // S3 = A11 - A21
+  FQT_WG(wg_add(r, A12, lda, S2, d, S4, d, h, d, true));      // S4 = A12 - S2
+  FQT_WG(wg_add(r, B12, ldb, B11, ldb, T1, w, d, w, true));   // T1 = B12 - B11
+  FQT_WG(wg_add(r, B22, ldb, T1, w, T2, w, d, w, true));      // T2 = B22 - T1
+  FQT_WG(wg_add(r, B22, ldb, B12, ldb, T3, w, d, w, true));   // T3 = B22 - B12
+  FQT_WG(wg_add(r, T2, w, B21, ldb, T4, w, d, w, true));      // T4 = T2 - B21
+  auto rec = [&](const uint8_t* X, int64_t ldx, const uint8_t* Y, int64_t ldy, uint8_t* Z) {
+    return wg_rec(r, levels - 1, h, w, d, X, ldx, Y, ldy, Z, w, next);
+  };
+  FQT_WG(rec(A11, lda, B11, ldb, P[1]));
+  FQT_WG(rec(A12, lda, B21, ldb, P[2]));
+  FQT_WG(rec(S4, d, B22, ldb, P[3]));
+  FQT_WG(rec(A22, lda, T4, w, P[4]));
+  FQT_WG(rec(S1, d, T1, w, P[5]));
+  FQT_WG(rec(S2, d, T2, w, P[6]));
+  FQT_WG(rec(S3, d, T3, w, P[7]));
+  FQT_WG(wg_add(r, P[1], w, P[2], w, C11, ldc, h, w, false));  // C11 = P1 + P2
+  FQT_WG(wg_add(r, P[1], w, P[6], w, P[6], w, h, w, false));   // U2 = P1 + P6, in P6
+  FQT_WG(wg_add(r, P[6], w, P[7], w, P[7], w, h, w, false));   // U3 = U2 + P7, in P7
+  FQT_WG(wg_add(r, P[6], w, P[5], w, P[1], w, h, w, false));   // U4 = U2 + P5, in P1
+  FQT_WG(wg_add(r, P[1], w, P[3], w, C12, ldc, h, w, false));  // C12 = U4 + P3
+  FQT_WG(wg_add(r, P[7], w, P[4], w, C21, ldc, h, w, true));   // C21 = U3 - P4
+  FQT_WG(wg_add(r, P[7], w, P[5], w, C22, ldc, h, w, false));  // C22 = U3 + P5
+  if (R) {  // the last k: C[:m, :n] += A[:m, kk] B[kk, :n]
+    FQT_WG(fqt_gemm_gfpk_ex(r.f, r.path, r.opts, m, n, K - kk, A + kk * k, lda, B + kk * ldb * k,
+                            ldb, R, n, r.s));
+    FQT_WG(wg_add(r, C, ldc, R, n, C, ldc, m, n, false));
+  }
+  if (m < M)  // the last row
+    FQT_WG(fqt_gemm_gfpk_ex(r.f, r.path, r.opts, M - m, N, K, A + m * lda * k, lda, B, ldb,
+                            C + m * ldc * k, ldc, r.s));
+  if (n < N)  // the last column
+    FQT_WG(fqt_gemm_gfpk_ex(r.f, r.path, r.opts, m, N - n, K, A, lda, B + n * k, ldb, C + n * k,
+                            ldc, r.s));
+#undef FQT_WG
+  return ok();
+}
+
+fqt_status wg_workspace(fqt_field f, size_t bytes, uint8_t** out) {
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(f->mu);
+  Workspace& w = f->wg_ws[dev];
+  if (w.bytes < bytes) {
+    if (w.ptr) {
+      FQT_HIP(hipDeviceSynchronize());  // earlier calls may still use the old buffer
+      FQT_HIP(hipFree(w.ptr));
+      w.ptr = nullptr;
+      w.bytes = 0;
+    }
+    if (hipMalloc(&w.ptr, bytes) != hipSuccess)
+      return fail(FQT_ERR_OOM, "Winograd temporaries of %zu bytes", bytes);
+    w.bytes = bytes;
+  }
+  *out = w.ptr;
+  return ok();
+}
+
+}  // namespace
+
+fqt_status fqt_gemm_winograd(fqt_field f, fqt_path path, const fqt_gemm_opts* opts,
+                             uint32_t levels, int64_t M, int64_t N, int64_t K, const uint8_t* A,
+                             int64_t lda, const uint8_t* B, int64_t ldb, uint8_t* C, int64_t ldc,
+                             fqt_stream_t s) {
+  fqt_status st = check_gemm_args(f, M, N, K, A, lda, B, ldb, C, ldc);
+  if (st) return st;
+  if (levels > 6) return fail(FQT_ERR_INVALID_ARG, "levels = %u above 6", levels);
+  if (path != FQT_PATH_AUTO && path != FQT_PATH_PACKED_F64 && path != FQT_PATH_INT8 &&
+      path != FQT_PATH_PLAIN)
+    return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
+  if (M == 0 || N == 0) return ok();
+  uint8_t* ws = nullptr;
+  const size_t bytes = wg_bytes(f->k, levels, M, N, K);
+  if (bytes) {
+    st = wg_workspace(f, bytes, &ws);
+    if (st) return st;
+  }
+  const WgRun r{f, path, opts, (hipStream_t)s};
+  return wg_rec(r, levels, M, N, K, A, lda, B, ldb, C, ldc, ws);
 }
 
 static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t count,

@@ -189,6 +189,12 @@ hipError_t launch_from_log(int k, const uint16_t* codes, int64_t n, uint32_t zer
 hipError_t launch_log_add(const uint16_t* a, const uint16_t* b, int64_t n, uint32_t zero_code,
                           const uint16_t* Z, uint16_t* c, hipStream_t s);
 
+// Winograd's block additions (k_winograd.hip): Z = X +/- Y coefficient-wise
+// mod p on rows x cols elements of k bytes; ld* in elements.
+hipError_t launch_mat_addsub(int k, uint32_t p, const uint8_t* X, int64_t ldx, const uint8_t* Y,
+                             int64_t ldy, uint8_t* Z, int64_t ldz, int64_t rows, int64_t cols,
+                             bool sub, hipStream_t s);
+
 // d-split kernels (tile ids >= kFirstSplitTile, k = 3 or 4).
 hipError_t launch_gemm_split(int k, int tile, const GemmArgs& g, const PackedParams& pp,
                              hipStream_t s);

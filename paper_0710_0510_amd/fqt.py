@@ -29,6 +29,7 @@ EXPORTED = [
     "fqt_gemm_gfpk_ex", "fqt_gemm_gfpk_batched", "fqt_gemm_gfpk_batched_ex", "fqt_autotune",
     "fqt_tile_count", "fqt_last_error", "fqt_version", "fqt_polymul_dfqt", "fqt_polymul_delayed",
     "fqt_log_info", "fqt_to_log", "fqt_from_log", "fqt_log_add", "fqt_gemm_log",
+    "fqt_gemm_winograd",
 ]
 
 
@@ -86,6 +87,8 @@ def lib() -> ctypes.CDLL:
                                              ctypes.POINTER(GemmDesc), vp]),
         "fqt_autotune": (c_int, [vp, c_int, c_i64, ctypes.POINTER(GemmDesc), ctypes.c_char_p,
                                  ctypes.POINTER(c_int), ctypes.POINTER(GemmOpts), vp]),
+        "fqt_gemm_winograd": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_u32, c_i64, c_i64,
+                                      c_i64, vp, c_i64, vp, c_i64, vp, c_i64, vp]),
         "fqt_log_info": (c_int, [vp, ctypes.POINTER(c_u32), ctypes.POINTER(c_u32)]),
         "fqt_to_log": (c_int, [vp, vp, c_i64, vp, vp]),
         "fqt_from_log": (c_int, [vp, vp, c_i64, vp, vp]),
@@ -295,6 +298,26 @@ def gemm(field: Field, A, B, C=None, path: str = "auto", opts=None, stream=None)
     lda, ldb, ldc = _ld(A, field.k), _ld(B, field.k), _ld(C, field.k)
     _check(lib().fqt_gemm_gfpk_ex(field.handle, PATHS[path], _opts(opts), M, N, K, _ptr(A),
                                   lda, _ptr(B), ldb, _ptr(C), ldc, _stream(stream)))
+    return C
+
+
+def gemm_winograd(field: Field, A, B, C=None, levels: int = 1, path: str = "packed", opts=None,
+                  stream=None):
+    """C = A B over the field with `levels` levels of Winograd's recursion;
+    the block products run on `path` with `opts`."""
+    import torch
+    M, K = A.shape[0], A.shape[1]
+    N = B.shape[1]
+    if C is None:
+        C = torch.empty((M, N, field.k), dtype=torch.uint8, device=A.device)
+    for t, name in ((A, "A"), (B, "B"), (C, "C")):
+        _matrix(t, field.k, name)
+    if B.shape[0] != K or tuple(C.shape[:2]) != (M, N):
+        raise ValueError(f"shapes do not chain: A {tuple(A.shape)}, B {tuple(B.shape)}, "
+                         f"C {tuple(C.shape)}")
+    _check(lib().fqt_gemm_winograd(field.handle, PATHS[path], _opts(opts), levels, M, N, K,
+                                   _ptr(A), _ld(A, field.k), _ptr(B), _ld(B, field.k), _ptr(C),
+                                   _ld(C, field.k), _stream(stream)))
     return C
 
 

@@ -319,3 +319,18 @@ def test_log_validation_errors():
     assert gemm_log(4, 4, 4, 4, 4, 4, opts={"n_q": 100}) == "FQT_ERR_BOUNDS"
     # tiles 7 and 9 take one K-block (q = 2^10, n_q = 21 for GF(5^3))
     assert gemm_log(4, 4, 64, 64, 4, 4, opts={"tile": 7}) == "FQT_ERR_UNSUPPORTED"
+
+
+def test_winograd_validation_errors():
+    f = fqt.Field(7, 2, (1, 0))
+    L = fqt.lib()
+    name = lambda st: fqt.STATUS_NAMES[st]
+
+    def wg(levels, M, N, K, lda, ldb, ldc, path=1, C=BOGUS + (1 << 31)):
+        return name(L.fqt_gemm_winograd(f.handle, path, None, levels, M, N, K, ctypes.c_void_p(BOGUS),
+                                        lda, ctypes.c_void_p(BOGUS + (1 << 30)), ldb,
+                                        ctypes.c_void_p(C), ldc, None))
+    assert wg(7, 4, 4, 4, 4, 4, 4) == "FQT_ERR_INVALID_ARG"        # levels above 6
+    assert wg(1, 4, 4, 8, 4, 4, 4) == "FQT_ERR_INVALID_ARG"        # lda < K
+    assert wg(1, 4, 4, 4, 4, 4, 4, path=9) == "FQT_ERR_INVALID_ARG"
+    assert wg(1, 4, 4, 4, 4, 4, 4, C=BOGUS + 8) == "FQT_ERR_INVALID_ARG"  # C overlaps A
