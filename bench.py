@@ -149,23 +149,40 @@ def bench_gemm(w, args, torch, fqt, gf):
     paths = [args.path] + [p for p in ("packed", "int8", "plain") if p != args.path and args.all_paths]
     results = {}
     tuned = {}
+    def run_path(path, C, opts):
+        if path == "winograd":
+            return fqt.gemm_winograd(f, A, B, C, levels=args.levels, path="packed", opts=opts)
+        return fqt.gemm(f, A, B, C, path=path, opts=opts)
+
     for path in paths:
         opts = {"tile": args.tile} if (args.tile and path == args.path) else None
         C = torch.empty_like(Cref)
-        if opts is None and path != "plain":
+        if path == "winograd" and opts is None:
+            # tune the packed path on the block shape of the last level
+            m, n, kk = w.M >> args.levels, w.N >> args.levels, w.K >> args.levels
+            Cs = torch.empty((m, n, w.k), dtype=torch.uint8, device="cuda")
+            opts = fqt.autotune(f, fqt.make_descs(f, [A[:m, :kk]], [B[:kk, :n]], [Cs]),
+                                only="packed")[1]
+            tuned["winograd_blocks"] = opts
+        elif opts is None and path != "plain":
             # autotune this path once, outside the timed region; later calls
             # with opts=None use the tuned (q, tile)
             tuned[path] = fqt.autotune(f, fqt.make_descs(f, [A], [B], [C]), only=path)[1]
-        fqt.gemm(f, A, B, C, path=path, opts=opts)
+        run_path(path, C, opts)
         torch.cuda.synchronize()
         if not torch.equal(C, Cref):
             raise SystemExit(f"parity failure: path {path} differs from the plain path")
         steps = args.steps if path != "plain" else max(3, args.steps // 10)
-        ms = time_steps(lambda: fqt.gemm(f, A, B, C, path=path, opts=opts), steps,
+        ms = time_steps(lambda: run_path(path, C, opts), steps,
                         args.warmup if path != "plain" else 2, torch)
         tile = (opts or tuned.get(path) or {}).get("tile", 0)
+        rl = roofline_for("packed" if path == "winograd" else path, w.k, work, ms, tile)
         results[path] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": steps,
-                         "tile": tile, "roofline": roofline_for(path, w.k, work, ms, tile)}
+                         "tile": tile, "roofline": rl}
+        if path == "winograd":
+            results[path]["levels"] = args.levels
+            rl["kernel"] = (f"Winograd, {args.levels} level(s): 7^{args.levels} products on tile "
+                            f"{tile} + block additions (classical flop count)")
 
     if args.all_paths:
         # the same product on discrete-log codes (Alg. 4's representation):
@@ -192,7 +209,7 @@ def bench_gemm(w, args, torch, fqt, gf):
             results["log"] = {"value": work / (ms * 1e-3), "ms_per_step": ms, "steps": args.steps,
                               "tile": tile, "roofline": rl}
 
-    if args.all_paths and "packed" in results:
+    if args.all_paths and "packed" in results and "winograd" not in results:
         # Winograd's recursion (the setting of the paper's Fig. 3): 1 and 2
         # levels over the packed path with its tuned tile
         popts = {"tile": results["packed"]["tile"]} if results["packed"]["tile"] else None
@@ -225,7 +242,7 @@ def bench_gemm(w, args, torch, fqt, gf):
         "metric": METRIC, "value": main_r["value"], "unit": "field mul-adds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"packed": "f64", "int8": "int8", "plain": "int32"}[args.path],
+        "dtype": {"packed": "f64", "int8": "int8", "plain": "int32", "winograd": "f64"}[args.path],
         "data": "synthetic",
         "config": {"workload": w.name, "field": f"GF({w.p}^{w.k})", "P": poly_str(w.P_low),
                    "M": w.M, "N": w.N, "K": w.K, "seed": w.seed, "path": args.path,
@@ -450,7 +467,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="gemm-gf7^2-1024")
-    ap.add_argument("--path", default="packed", choices=["packed", "int8", "plain"])
+    ap.add_argument("--path", default="packed", choices=["packed", "int8", "plain", "winograd"])
+    ap.add_argument("--levels", type=int, default=2,
+                    help="levels of Winograd's recursion for --path winograd")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--all-paths", type=int, default=1, help="also time the other paths")
     ap.add_argument("--samples", type=int, default=256)
