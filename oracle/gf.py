@@ -705,3 +705,63 @@ def gemm_winograd(A: np.ndarray, B: np.ndarray, p: int, P_low: Sequence[int],
     if n < N:    # last column
         C[:m, n:] = gemm_gfpk_planes(A[:m, :], B[:, n:], p, P_low)
     return C
+
+
+# ---------------------------------------------------------------------------
+# Centred representation inside the FQT (a reading: Section 6 names the
+# centred residues (1-p)/2 .. (p-1)/2 for delayed reduction; here they are
+# packed instead of [0, p) coefficients)
+# ---------------------------------------------------------------------------
+#
+# With every coefficient s in [-h, h], h = (p-1)/2, a product digit is at most
+# k h^2 in magnitude and a block of n products at most n k h^2; while that
+# stays below q/2, adding q/2 to every digit (the constant
+# B = sum_{i<2k-1} (q/2) q^i) leaves non-negative digits below q, so the
+# sum B + r has no borrows and REDQ applies unchanged.  The residues then
+# carry the known shift of B, which L + H maps to one constant element.
+
+
+def centred(c: Sequence[int], p: int) -> List[int]:
+    h = (p - 1) // 2
+    return [x - p if x > h else x for x in c]
+
+
+def centred_nq_max(p: int, k: int, q: int) -> int:
+    """Largest n with n k h^2 <= q/2 - 1 (p odd, q even)."""
+    h = (p - 1) // 2
+    return (q // 2 - 1) // (k * h * h)
+
+
+def fgdp_centred(v1, v2, p: int, P_low: Sequence[int], q: int) -> List[int]:
+    """Alg. 4 for one dot product with centred packing: evaluate the centred
+    coefficients at q, add B, REDQ, L + H, then subtract L + H of B's own
+    residues."""
+    k = len(P_low)
+    nd = 2 * k - 1
+    B = sum((q // 2) * q ** i for i in range(nd))
+    r = B + sum(dqt(centred(a, p), q) * dqt(centred(b, p), q) for a, b in zip(v1, v2))
+    assert 0 <= r < q ** nd
+    rop = r // p
+    u = [r // q ** i - p * (rop // q ** i) for i in range(nd)]
+    beta = [(B // q ** i) % p for i in range(nd)]
+    R = field_add(table_L(u[0:k], q, p), table_H(u[k - 1:nd], q, p, P_low), p)
+    C0 = field_add(table_L(beta[0:k], q, p), table_H(beta[k - 1:nd], q, p, P_low), p)
+    return [(x - y) % p for x, y in zip(R, C0)]
+
+
+def gemm_centred_alg4(A, B, p: int, P_low: Sequence[int], q: int, n_q: int):
+    """C = A B with fgdp_centred on K-blocks of at most n_q products, block
+    results added in the field.  Small cases only (pure Python)."""
+    M, K = len(A), len(A[0]) if len(A) else 0
+    N = len(B[0]) if len(B) else 0
+    k = len(P_low)
+    C = [[[0] * k for _ in range(N)] for _ in range(M)]
+    for i in range(M):
+        for j in range(N):
+            acc = [0] * k
+            for s in range(0, K, n_q):
+                part = fgdp_centred(A[i][s:s + n_q], [B[l][j] for l in range(s, min(K, s + n_q))],
+                                    p, P_low, q)
+                acc = field_add(acc, part, p)
+            C[i][j] = acc
+    return C

@@ -596,3 +596,55 @@ def test_winograd_identity_and_zero():
     assert np.array_equal(gf.gemm_winograd(A, I, p, P_low, 2), A)
     assert np.array_equal(gf.gemm_winograd(I, A, p, P_low, 2), A)
     assert not gf.gemm_winograd(A, np.zeros_like(A), p, P_low, 2).any()
+
+
+# ---- centred packing -----------------------------------------------------------
+
+@pytest.mark.parametrize("p,P_low", [(3, (2, 0, 0, 2)), (5, (3, 3, 0)), (7, (1, 0)), (3, (1, 0)),
+                                     (13, (2,))])
+def test_centred_alg4_matches_the_definition(p, P_low):
+    k = len(P_low)
+    q, _ = gf.max_pow2_q(p, k)
+    nq = min(gf.centred_nq_max(p, k, q), 64)
+    rng = np.random.default_rng(p * k)
+    for (M, K, N) in [(3, 1, 2), (4, 9, 3), (2, 2 * nq + 3, 2)]:
+        A = rng.integers(0, p, size=(M, K, k))
+        B = rng.integers(0, p, size=(K, N, k))
+        got = gf.gemm_centred_alg4(A.tolist(), B.tolist(), p, P_low, q, nq)
+        want = gf.gemm_gfpk_planes(A.astype(np.uint8), B.astype(np.uint8), p, P_low)
+        assert np.array_equal(np.array(got, dtype=np.uint8).reshape(want.shape), want), (M, K, N)
+
+
+@pytest.mark.parametrize("p,P_low", [(3, (2, 0, 0, 2)), (5, (3, 3, 0)), (7, (1, 0))])
+def test_centred_bound_is_tight(p, P_low):
+    # the extreme digit sums: every centred coefficient h against every h
+    # (all products +h^2) and against -h (all -h^2).  At n_q = centred_nq_max
+    # both are exact; one product more pushes the positive extreme to q/2,
+    # whose shifted digit q carries into the next one and breaks the result
+    # (the negative side may reach -q/2 exactly: shifted digit 0)
+    k = len(P_low)
+    h = (p - 1) // 2
+    q, _ = gf.max_pow2_q(p, k)
+    if q > 2 ** 10:
+        q = 2 ** 10                    # a small q keeps the case short
+    nq = gf.centred_nq_max(p, k, q)
+    pos, neg = [h] * k, [p - h] * k    # centred values h and -h
+
+    def run(b, n):
+        A = [[pos] * n]
+        B = [[b] for _ in range(n)]
+        got = gf.gemm_centred_alg4(A, B, p, P_low, q, n)
+        want = gf.gemm_gfpk_planes(np.array(A, dtype=np.uint8), np.array(B, dtype=np.uint8),
+                                   p, P_low)
+        return np.array_equal(np.array(got, dtype=np.uint8).reshape(want.shape), want)
+
+    assert run(pos, nq) and run(neg, nq)
+    assert not run(pos, nq + 1)
+
+
+def test_centred_doubles_n_q():
+    # GF(3^4) at q = 2^7: 7 products per block in [0, p), 15 centred;
+    # GF(5^3) at q = 2^10: 21 and 42; GF(7^2) at q = 2^17: 1820 and 3640
+    assert gf.centred_nq_max(3, 4, 2 ** 7) == 15 and gf.max_pow2_q(3, 4)[1] == 7
+    assert gf.centred_nq_max(5, 3, 2 ** 10) == 42 and gf.max_pow2_q(5, 3)[1] == 21
+    assert gf.centred_nq_max(7, 2, 2 ** 17) == 3640 and gf.max_pow2_q(7, 2)[1] == 1820
