@@ -117,6 +117,13 @@ typedef struct {
                         radix conversion, bit fields for q = 2^b) with the
                         reduction mod p delayed to the end (Section 6).  Both
                         give identical bytes. */
+  uint32_t centered; /* packed path, LDS-staged tiles 1..6, odd p: 1 packs
+                        centred coefficients (c > (p-1)/2 taken as c - p, the
+                        residues Section 6 names for delayed reduction) with
+                        q/2 added to every digit of a block, so a block holds
+                        n_q <= (q/2 - 1) / (k ((p-1)/2)^2) products, about
+                        twice the eq. (2) bound; the same bytes come out.
+                        FQT_ERR_UNSUPPORTED for p = 2 or other tiles. */
 } fqt_gemm_opts;
 
 /* ---- field handle (Section 7: GF(p^k) = GF(p)[X]/(P)) ------------------- */

@@ -553,6 +553,7 @@ struct PackedChoice {
   bool multi;
   int mode;           // 0 single block, 1 REDQ residues, 2 digit sums
   uint32_t fold;      // boundaries between folds of the 16-bit lanes (0: never)
+  bool centered;      // centred packing, digits shifted by q/2
 };
 
 // d-split tiles: chunks of 2 coefficients packed at q = 2^17 (q^3 < 2^53).
@@ -572,6 +573,8 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   if (o && o->tile > (uint32_t)kPackedTiles)
     return fail(FQT_ERR_INVALID_ARG, "unknown tile id %u", o->tile);
   if (o && o->tile && is_split_tile((int)o->tile)) {
+    if (o->centered)
+      return fail(FQT_ERR_UNSUPPORTED, "centred packing runs on the LDS-staged tiles");
     if (k != 3 && k != 4)
       return fail(FQT_ERR_UNSUPPORTED, "d-split tiles pair coefficients of k = 3 or 4 (k = %u)", k);
     if (o->log2q && o->log2q != kSplitB)
@@ -596,8 +599,14 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
     pc->tile = o->tile;
     pc->mode = 0;
     pc->fold = 0;
+    pc->centered = false;
     return ok();
   }
+  const bool cen = o && o->centered;
+  if (cen && p == 2) return fail(FQT_ERR_UNSUPPORTED, "centred packing needs an odd p");
+  if (cen && o->tile && (int)o->tile > kStagedTiles)
+    return fail(FQT_ERR_UNSUPPORTED, "centred packing runs on the LDS-staged tiles 1..%d",
+                kStagedTiles);
   const uint32_t bmax = max_pow2_b(k);
   uint32_t b = (o && o->log2q) ? o->log2q : bmax;
   if (b > bmax || b < 1)
@@ -607,11 +616,16 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
     return fail(FQT_ERR_UNSUPPORTED, "q = 2^%u leaves no room for the residue bytes (k = %u)", b,
                 k);
   const uint64_t q = 1ull << b;
-  const uint64_t unit = (uint64_t)k * (p - 1) * (p - 1);
-  const uint64_t nq_max = unit ? (q - 1) / unit : UINT32_MAX;  // eq. (2): q > n_q k (p-1)^2
+  // eq. (2): q > n_q k (p-1)^2; centred: n_q k ((p-1)/2)^2 <= q/2 - 1
+  const uint64_t hc = (p - 1) / 2;
+  const uint64_t unit = cen ? (uint64_t)k * hc * hc : (uint64_t)k * (p - 1) * (p - 1);
+  if (cen && b < 2) return fail(FQT_ERR_BOUNDS, "centred packing needs q >= 4");
+  const uint64_t room = cen ? q / 2 - 1 : q - 1;
+  const uint64_t nq_max = unit ? room / unit : UINT32_MAX;
   uint64_t nq = (o && o->n_q) ? o->n_q : nq_max;
   if (nq > nq_max)
-    return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks q > n_q k (p-1)^2 for q = 2^%u", nq, b);
+    return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks the %s bound for q = 2^%u", nq,
+                cen ? "centred" : "eq. (2)", b);
   nq = std::min<uint64_t>(nq, 1u << 30);
   // Blocks are whole MFMA k-groups of 4 slots.  A block of n_q % 4 != 0
   // products is padded with zero slots when the slot count divides every
@@ -643,7 +657,8 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
     if (bmode == 2 && 2 * b > 24)
       return fail(FQT_ERR_UNSUPPORTED, "digit-sum boundaries need q <= 2^12 (q = 2^%u)", b);
     const uint64_t width = bmode == 1 ? 65535 : (1ull << (2 * b)) - 1;
-    const uint64_t growth = bmode == 1 ? 2 * (uint64_t)p - 1 : real * unit;
+    // centred: every block's shifted digits are below q
+    const uint64_t growth = bmode == 1 ? 2 * (uint64_t)p - 1 : cen ? q - 1 : real * unit;
     const uint64_t nblocks = ((uint64_t)K + real - 1) / real + 8;
     const uint64_t cap = (width - (p - 1)) / std::max<uint64_t>(growth, 1);
     if (cap < 2) return fail(FQT_ERR_UNSUPPORTED, "residue lanes too narrow for n_q = %" PRIu64, nq);
@@ -676,6 +691,7 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
   pc->nq_real = (uint32_t)real;
   pc->tile = tile;
   pc->multi = multi;
+  pc->centered = cen;
   pc->mode = multi ? (int)bmode : 0;
   pc->fold = fold;
   return ok();
@@ -1096,7 +1112,7 @@ fqt_status fqt_gemm_log(fqt_field f, const fqt_gemm_opts* opts, int64_t M, int64
   fqt_status st = check_gemm_args(f, M, N, K, A8, lda, B8, ldb, C8, ldc, 2);
   if (st) return st;
   if (M == 0 || N == 0) return ok();
-  fqt_gemm_opts o = opts ? *opts : fqt_gemm_opts{0, 0, 0, 0};
+  fqt_gemm_opts o = opts ? *opts : fqt_gemm_opts{0, 0, 0, 0, 0};
   if (o.tile && !is_log_tile((int)o.tile))
     return fail(FQT_ERR_UNSUPPORTED, "tile %u: the log form runs tiles 7, 9 and 11", o.tile);
   uint32_t m;
@@ -1146,6 +1162,35 @@ fqt_status fqt_gemm_log(fqt_field f, const fqt_gemm_opts* opts, int64_t M, int64
   return ok();
 }
 
+// Centred packing: every block starts from 2^52 + B, B = sum_{i<2k-1} (q/2) q^i,
+// whose residues beta_i = floor(B / q^i) mod p shift the residues of every
+// block; L + H is linear in the residues, so the result carries
+// n_blocks * (L + H)(beta), taken off at the end with c0neg.
+// Caller holds f->mu.
+void centred_params(fqt_field_s* f, uint32_t b, PackedParams* pp) {
+  const uint32_t p = f->p, k = f->k, cb = f->cb, nd = 2 * k - 1;
+  const uint64_t q = 1ull << b;
+  uint64_t B = 0;
+  for (uint32_t i = 0; i < nd; ++i) B = B * q + q / 2;  // below q^(2k-1) <= 2^52
+  std::vector<uint32_t> beta(nd);
+  for (uint32_t i = 0; i < nd; ++i) beta[i] = (uint32_t)((B >> (b * i)) % p);
+  const auto& ht = host_tables(f, q);
+  uint32_t il = 0, ih = 0;
+  for (uint32_t d = 0; d < k; ++d) {
+    il |= beta[d] << (cb * d);
+    ih |= beta[k - 1 + d] << (cb * d);
+  }
+  const uint32_t lw = ht.first[il], hw = ht.second[ih];
+  uint32_t neg = 0;
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint32_t c = (((lw >> (8 * i)) & 0xffu) + ((hw >> (8 * i)) & 0xffu)) % p;
+    neg |= ((p - c) % p) << (8 * i);
+  }
+  pp->centered = 1;
+  pp->c0neg = neg;
+  pp->cbias = 4503599627370496.0 + (double)B;
+}
+
 static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
                               hipStream_t s) {
   PackedChoice pc;
@@ -1170,6 +1215,10 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
   pp.fa = field_args(f, q);
   pp.L = dt.L;
   pp.H = dt.H;
+  if (pc.centered) {
+    std::lock_guard<std::mutex> lk(f->mu);
+    centred_params(f, pc.b, &pp);
+  }
   if (split)
     FQT_HIP(launch_gemm_split((int)f->k, (int)pc.tile, g, pp, s));
   else if (is_direct_tile((int)pc.tile))
@@ -1453,7 +1502,8 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     Nmax = std::max(Nmax, descs[i].N);
   }
   PackedChoice pc;
-  fqt_gemm_opts o = opts ? *opts : fqt_gemm_opts{0, 0, 0, 0};
+  std::memset(&pc, 0, sizeof pc);  // the plan key copies its bytes
+  fqt_gemm_opts o = opts ? *opts : fqt_gemm_opts{0, 0, 0, 0, 0};
   if (!o.tile) o.tile = 2;
   fqt_status st = resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc);
   if (st) return st;
@@ -1526,6 +1576,7 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     pp.fa = field_args(f, q);
     pp.L = dt.L;
     pp.H = dt.H;
+    if (pc.centered) centred_params(f, pc.b, &pp);  // f->mu is held
     // Capture the persistent launch once; later calls replay the graph.
     FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -1784,12 +1835,12 @@ bool read_cache(const char* path, const std::string& key, TuneEntry* e) {
   while (std::fgets(line, sizeof line, fp)) {
     char k[256];
     int pth = 0;
-    unsigned lq = 0, nq = 0, tile = 0, bnd = 0;
-    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u, \"boundary\": %u",
-                    k, &pth, &lq, &nq, &tile, &bnd) == 6 &&
+    unsigned lq = 0, nq = 0, tile = 0, bnd = 0, cen = 0;
+    if (std::sscanf(line, "{\"key\": \"%255[^\"]\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u, \"boundary\": %u, \"centered\": %u",
+                    k, &pth, &lq, &nq, &tile, &bnd, &cen) == 7 &&
         key == k) {
       e->path = (fqt_path)pth;
-      e->opts = fqt_gemm_opts{lq, nq, tile, bnd};
+      e->opts = fqt_gemm_opts{lq, nq, tile, bnd, cen};
       found = true;  // the last matching line wins
     }
   }
@@ -1832,34 +1883,38 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   // products per K-block), and every INT8 tile for single products.
   std::vector<Candidate> cands;
   const uint32_t bmax = max_pow2_b(f->k);
+  for (uint32_t cen : {0u, 1u})
   for (uint32_t b : {bmax, bmax - 1}) {
     if (only == FQT_PATH_INT8) break;
-    if (b < 1) continue;
-    const uint64_t unit_nq = (uint64_t)f->k * (f->p - 1) * (f->p - 1);
-    const uint32_t nq_top = unit_nq ? (uint32_t)std::min<uint64_t>(((1ull << b) - 1) / unit_nq, 1u << 30) : 0;
-    for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t)
+    if (b < 1 || (cen && f->p == 2)) continue;
+    const uint64_t h = (f->p - 1) / 2;
+    const uint64_t unit_nq = cen ? (uint64_t)f->k * h * h : (uint64_t)f->k * (f->p - 1) * (f->p - 1);
+    const uint64_t room = cen ? (1ull << (b - 1)) - 1 : (1ull << b) - 1;
+    const uint32_t nq_top = unit_nq ? (uint32_t)std::min<uint64_t>(room / unit_nq, 1u << 30) : 0;
+    for (uint32_t t = 1; t <= (uint32_t)(cen ? kStagedTiles : kPackedTiles); ++t)
       for (uint32_t bm : {1u, 2u})
       for (uint32_t nqc : {0u, nq_top & ~3u}) {
         if (nqc && nqc == nq_top) continue;  // same as the default
-        fqt_gemm_opts o{b, nqc, t, bm};
+        fqt_gemm_opts o{b, nqc, t, bm, cen};
         PackedChoice pc;
         if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) != FQT_OK) continue;
         if (t == 4 && f->k >= 3 && pc.mode == 1) continue;  // that variant spills registers
         if (!pc.multi && bm == 2) continue;              // one block: no boundary step
+        if (cen && !pc.multi) continue;                  // one block: nothing to gain
         cands.push_back({FQT_PATH_PACKED_F64, o});
       }
   }
   // d-split tiles bring their own q (one block, no boundary step)
   if (only != FQT_PATH_INT8)
     for (uint32_t t = (uint32_t)kFirstSplitTile; t <= (uint32_t)kPackedTiles; ++t) {
-      fqt_gemm_opts o{0, 0, t, 0};
+      fqt_gemm_opts o{0, 0, t, 0, 0};
       PackedChoice pc;
       if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) == FQT_OK)
         cands.push_back({FQT_PATH_PACKED_F64, o});
     }
   if (only != FQT_PATH_PACKED_F64)
     for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
-      cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0}});
+      cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0, 0}});
   if (cands.empty()) return fail(FQT_ERR_UNSUPPORTED, "no admissible candidate");
 
   hipStream_t st = (hipStream_t)s;
@@ -1941,9 +1996,9 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
     if (FILE* fp = std::fopen(cache_path, "a")) {
       std::fprintf(fp,
                    "{\"key\": \"%s\", \"path\": %d, \"log2q\": %u, \"n_q\": %u, \"tile\": %u, "
-                   "\"boundary\": %u, \"ms\": %.6f, \"candidates\": %zu}\n",
+                   "\"boundary\": %u, \"centered\": %u, \"ms\": %.6f, \"candidates\": %zu}\n",
                    key.c_str(), (int)w.path, w.opts.log2q, w.opts.n_q, w.opts.tile, w.opts.boundary,
-                   best_ms, cands.size());
+                   w.opts.centered, best_ms, cands.size());
       std::fclose(fp);
     }
   }

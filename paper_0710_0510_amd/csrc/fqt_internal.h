@@ -27,6 +27,9 @@ struct PackedParams {
   uint32_t qmask;      // q - 1
   uint32_t qmod;       // q mod p
   uint32_t blk_real;   // products per K-block (< 4*nq_groups: padded blocks)
+  uint32_t centered;   // centred packing (staged tiles): digits shifted by q/2
+  uint32_t c0neg;      // centred: -(L + H of the shift's residues), one word
+  double cbias;        // centred: 2^52 + sum_{i<2k-1} (q/2) q^i, every block's seed
   FieldArgs fa;
   const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)
   const uint32_t* H;

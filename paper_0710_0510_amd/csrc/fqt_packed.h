@@ -99,17 +99,50 @@ struct DqtShifts {
 // host keeps it below 2^32.  KE - 1 byte-select shifts and adds (KE = 1: one
 // extract) and one conversion; elements that straddle words need no realign.
 template <int KE, int NWD>
-__device__ __forceinline__ double packed_elem(const uint32_t (&raw)[NWD], int e,
-                                              const DqtShifts& sh) {
+__device__ __forceinline__ uint32_t dqt_u32(const uint32_t (&raw)[NWD], int e,
+                                            const DqtShifts& sh) {
   const int o = e * KE;
   if constexpr (KE == 1) {
-    return (double)((raw[o >> 2] >> (8 * (o & 3))) & 0xffu);
+    return (raw[o >> 2] >> (8 * (o & 3))) & 0xffu;
   } else {
     uint32_t v = add_byte(byte_shl(raw[(o + 1) >> 2], (o + 1) & 3, sh.s[1]), raw[o >> 2], o & 3);
 #pragma unroll
     for (int j = 2; j < KE; ++j) v += byte_shl(raw[(o + j) >> 2], (o + j) & 3, sh.s[j]);
-    return (double)v;
+    return v;
   }
+}
+
+template <int KE, int NWD>
+__device__ __forceinline__ double packed_elem(const uint32_t (&raw)[NWD], int e,
+                                              const DqtShifts& sh) {
+  return (double)dqt_u32<KE, NWD>(raw, e, sh);
+}
+
+// Centred packing: coefficients c > h = (p-1)/2 stand for c - p, so the
+// packed value is sum_j c_j q^j - p sum_j [c_j > h] q^j, a signed integer
+// below 2^31 in magnitude.  gt holds the bytes [c > h] of raw (centred_flags).
+__device__ __forceinline__ uint32_t centred_flags(uint32_t w, uint32_t hmask) {
+  return ((w + hmask) >> 7) & 0x01010101u;  // hmask = (0x7f - h) in every byte; c < 128
+}
+
+template <int KE, int NWD>
+__device__ __forceinline__ double packed_elem_centred(const uint32_t (&raw)[NWD],
+                                                      const uint32_t (&gt)[NWD], int e,
+                                                      const DqtShifts& sh, uint32_t p) {
+  const int32_t v = (int32_t)dqt_u32<KE, NWD>(raw, e, sh) - (int32_t)(p * dqt_u32<KE, NWD>(gt, e, sh));
+  return (double)v;
+}
+
+// Centred packing's final correction: n_blocks times the constant -(L + H)
+// of the shift's residues, every coefficient scaled mod p.
+template <int KE>
+__device__ __forceinline__ uint32_t centred_correction(uint32_t c0neg, uint32_t nblocks,
+                                                       const FieldArgs& fa) {
+  const uint32_t n = nblocks % fa.p;
+  uint32_t w = 0;
+#pragma unroll
+  for (int i = 0; i < KE; ++i) w |= mod_p_small(((c0neg >> (8 * i)) & 0xffu) * n, fa) << (8 * i);
+  return w;
 }
 
 template <int KE, int MODE>

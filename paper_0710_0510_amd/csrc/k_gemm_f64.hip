@@ -100,7 +100,9 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   // slots, the last slots of a block zero (blk_slots divides BK).
   const bool padded = MULTI && pp.blk_real != 4 * pp.nq_groups;
 
-  const v4d bias = {kTwo52, kTwo52, kTwo52, kTwo52};
+  // every block starts from 2^52 (centred packing: plus q/2 in every digit)
+  const double bz = pp.centered ? pp.cbias : kTwo52;
+  const v4d bias = {bz, bz, bz, bz};
   v4d acc[TM][TN];
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -202,9 +204,33 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
       load_chunk<KE>(g.B, k0 + bkr + r * BRS, n0 + 4 * bnc, g.K, g.N, g.ldb, aligned, rb[r]);
   };
 
+  const uint32_t hmask = (0x7fu - (pp.fa.p - 1) / 2) * 0x01010101u;
   auto lstore = [&](int buf) {
     double* as = As + buf * T::LDS_A;
     double* bs = Bs + buf * T::LDS_B;
+    if (pp.centered) {
+#pragma unroll
+      for (int r = 0; r < T::RA; ++r) {
+        uint32_t gt[KE];
+#pragma unroll
+        for (int w = 0; w < KE; ++w) gt[w] = centred_flags(ra[r][w], hmask);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          as[(arow + r * ARS) * T::SA + 4 * akc + e] =
+              packed_elem_centred<KE, KE>(ra[r], gt, e, sh, pp.fa.p);
+      }
+#pragma unroll
+      for (int r = 0; r < T::RB; ++r) {
+        uint32_t gt[KE];
+#pragma unroll
+        for (int w = 0; w < KE; ++w) gt[w] = centred_flags(rb[r][w], hmask);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] =
+              packed_elem_centred<KE, KE>(rb[r], gt, e, sh, pp.fa.p);
+      }
+      return;
+    }
 #pragma unroll
     for (int r = 0; r < T::RA; ++r)
 #pragma unroll
@@ -219,9 +245,10 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
             packed_elem<KE, KE>(rb[r], e, sh);
   };
 
-  uint32_t nbound = 0;
+  uint32_t nbound = 0, nblk = 1;  // blocks seeded so far (the centred correction counts them)
   auto boundary = [&]() {
     if constexpr (MULTI) {
+      ++nblk;
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -281,6 +308,7 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   }
 
   // Epilogue: final residues, L + H (Thm. 3), store k bytes per element.
+  const uint32_t corr = pp.centered ? centred_correction<KE>(pp.c0neg, nblk, pp.fa) : 0u;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -289,7 +317,8 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
       for (int v = 0; v < 4; ++v) {
         uint32_t u[T::ND];
         st[MULTI ? i : 0][MULTI ? j : 0][v].residues(acc[i][j][v], b, pp, u);
-        const uint32_t e = lh_combine<KE>(u, pp, Ls, Hs);
+        uint32_t e = lh_combine<KE>(u, pp, Ls, Hs);
+        if (pp.centered) e = add_bytes_mod_p(e, corr, pp.fa);
         const int64_t row = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
         const int64_t col = n0 + wn0 + 16 * j + (lane & 15);
         if (row < g.M && col < g.N) store_elem<KE>(g.C + (row * g.ldc + col) * KE, e);

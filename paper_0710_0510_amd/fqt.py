@@ -42,7 +42,8 @@ class FqtError(RuntimeError):
 
 class GemmOpts(ctypes.Structure):
     _fields_ = [("log2q", ctypes.c_uint32), ("n_q", ctypes.c_uint32),
-                ("tile", ctypes.c_uint32), ("boundary", ctypes.c_uint32)]
+                ("tile", ctypes.c_uint32), ("boundary", ctypes.c_uint32),
+                ("centered", ctypes.c_uint32)]
 
 
 class GemmDesc(ctypes.Structure):
@@ -258,7 +259,8 @@ def _opts(opts) -> Optional[ctypes.POINTER(GemmOpts)]:
     if isinstance(opts, GemmOpts):
         return ctypes.pointer(opts)
     return ctypes.pointer(GemmOpts(int(opts.get("log2q", 0)), int(opts.get("n_q", 0)),
-                                   int(opts.get("tile", 0)), int(opts.get("boundary", 0))))
+                                   int(opts.get("tile", 0)), int(opts.get("boundary", 0)),
+                                   int(opts.get("centered", 0))))
 
 
 def _ld(t, k: int) -> int:
@@ -350,7 +352,7 @@ def autotune(field: Field, descs, cache_path: Optional[str] = None, only: str = 
                               cache_path.encode() if cache_path else None, ctypes.byref(path),
                               ctypes.byref(best), _stream(stream)))
     return PATH_NAMES[path.value], {"log2q": best.log2q, "n_q": best.n_q, "tile": best.tile,
-                                    "boundary": best.boundary}
+                                    "boundary": best.boundary, "centered": best.centered}
 
 
 def tile_count(path: str) -> int:

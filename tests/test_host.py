@@ -334,3 +334,18 @@ def test_winograd_validation_errors():
     assert wg(1, 4, 4, 8, 4, 4, 4) == "FQT_ERR_INVALID_ARG"        # lda < K
     assert wg(1, 4, 4, 4, 4, 4, 4, path=9) == "FQT_ERR_INVALID_ARG"
     assert wg(1, 4, 4, 4, 4, 4, 4, C=BOGUS + 8) == "FQT_ERR_INVALID_ARG"  # C overlaps A
+
+
+def test_centred_validation_errors():
+    # centred packing: odd p only, staged tiles 1..6 only, n_q up to
+    # (q/2 - 1) / (k ((p-1)/2)^2): 15 for GF(3^4) at q = 2^7
+    g2 = fqt.Field(2, 3, (1, 0, 1))
+    assert _gemm_status(g2, "packed", 4, 4, 4, 4, 4, 4, opts={"centered": 1}) == "FQT_ERR_UNSUPPORTED"
+    f = fqt.Field(3, 4, (2, 0, 0, 2))
+    for tile in (7, 11, 13):
+        assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4,
+                            opts={"centered": 1, "tile": tile}) == "FQT_ERR_UNSUPPORTED"
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4,
+                        opts={"centered": 1, "n_q": 16}) == "FQT_ERR_BOUNDS"
+    # without centring the same n_q breaks eq. (2)
+    assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"n_q": 15}) == "FQT_ERR_BOUNDS"
