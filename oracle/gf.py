@@ -765,3 +765,33 @@ def gemm_centred_alg4(A, B, p: int, P_low: Sequence[int], q: int, n_q: int):
                 acc = field_add(acc, part, p)
             C[i][j] = acc
     return C
+
+
+def dfqt_polymul_centred(a: Sequence[int], b: Sequence[int], p: int, d: int, q: int,
+                         n_q: int) -> List[int]:
+    """The d-FQT product with centred chunks (the representation Section 6
+    names for delayed reduction): coefficients above (p-1)/2 packed as c - p,
+    every block of at most n_q chunk products shifted by B = sum (q/2) q^j
+    (2d+1 digits) so its digits stay in [0, q) while n_q (d+1) ((p-1)/2)^2 <=
+    q/2 - 1; the block's REDQ_{2d+1} digits then carry q/2 each, which comes
+    off mod p."""
+    if len(a) == 0 or len(b) == 0:
+        return []
+    nd = 2 * d + 1
+    B = sum((q // 2) * q ** j for j in range(nd))
+    P = [dqt(centred(ch, p), q) for ch in dfqt_chunks(a, d)]
+    Q = [dqt(centred(ch, p), q) for ch in dfqt_chunks(b, d)]
+    out = [0] * (len(a) + len(b) - 1)
+    for t in range(len(P) + len(Q) - 1):
+        terms = [P[i] * Q[t - i] for i in range(len(P)) if 0 <= t - i < len(Q)]
+        mu_t = [0] * nd
+        for s in range(0, len(terms), n_q):
+            r = B + sum(terms[s:s + n_q])
+            assert 0 <= r < q ** nd
+            _, _, mu, _ = redq_steps(r, p, q, nd - 1)
+            mu_t = [(x + y - q // 2) % p for x, y in zip(mu_t, mu)]
+        for j, m in enumerate(mu_t):
+            n = t * (d + 1) + j
+            if n < len(out):
+                out[n] = (out[n] + m) % p
+    return out

@@ -648,3 +648,33 @@ def test_centred_doubles_n_q():
     assert gf.centred_nq_max(3, 4, 2 ** 7) == 15 and gf.max_pow2_q(3, 4)[1] == 7
     assert gf.centred_nq_max(5, 3, 2 ** 10) == 42 and gf.max_pow2_q(5, 3)[1] == 21
     assert gf.centred_nq_max(7, 2, 2 ** 17) == 3640 and gf.max_pow2_q(7, 2)[1] == 1820
+
+
+@pytest.mark.parametrize("p,d", [(3, 4), (3, 3), (5, 2), (7, 1), (3, 0), (13, 1)])
+def test_dfqt_centred_matches_the_definition(p, d):
+    b = 52 // (2 * d + 1)
+    q = 2 ** b
+    h = (p - 1) // 2
+    nq = (q // 2 - 1) // ((d + 1) * h * h)
+    assert nq >= 1
+    rng = random.Random(p * 10 + d)
+    for (la, lb) in [(1, 1), (5, 3), (40, 17), (501, 501)]:
+        a = [rng.randrange(p) for _ in range(la)]
+        b_ = [rng.randrange(p) for _ in range(lb)]
+        want = gf.polymul_long(a, b_, p)
+        for n_q in sorted({1, max(1, nq // 2), nq}):
+            assert gf.dfqt_polymul_centred(a, b_, p, d, q, n_q) == want, (la, lb, n_q)
+    # the extremes: all h (every chunk product digit +h^2 per term) and h
+    # against -h, in blocks at the centred bound
+    for bv in (h, p - h):
+        a = [h] * 200
+        b_ = [bv] * 200
+        assert gf.dfqt_polymul_centred(a, b_, p, d, q, nq) == gf.polymul_long(a, b_, p)
+
+
+def test_dfqt_centred_n_q_for_the_workload():
+    # p = 3, d = 4: q = 2^5 holds one [0, p) chunk product per block (5 * 4 < 32)
+    # and three centred ones (3 * 5 * 1 <= 15)
+    q = 2 ** 5
+    assert (q - 1) // (5 * 4) == 1
+    assert (q // 2 - 1) // (5 * 1) == 3
