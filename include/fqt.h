@@ -229,10 +229,18 @@ fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q,
  *   n_q    products per block; 0 = the largest eq. (2) allows,
  *          q > n_q (d+1)(p-1)^2 (FQT_ERR_BOUNDS when q cannot hold one).
  *   boundary  as fqt_gemm_opts.boundary (0 default, 1 REDQ residues,
- *          2 digit sums, q <= 2^12); identical bytes. */
+ *          2 digit sums, q <= 2^12); identical bytes.
+ *   centered  0 or 1 (else FQT_ERR_INVALID_ARG); 1, for odd p only
+ *          (FQT_ERR_UNSUPPORTED for p = 2): coefficients above (p-1)/2
+ *          enter the chunks as c - p (the centred residues Section 6 names
+ *          for delayed reduction) and every block's digits are shifted by
+ *          q/2, so n_q may reach (q/2 - 1) / ((d+1) ((p-1)/2)^2), about twice
+ *          eq. (2)'s bound (3 instead of 1 for p = 3, d = 4); identical
+ *          bytes. */
 fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
-                            uint32_t boundary, const uint8_t* a, const uint8_t* b,
-                            int64_t count, int64_t len, uint8_t* c, fqt_stream_t s);
+                            uint32_t boundary, uint32_t centered, const uint8_t* a,
+                            const uint8_t* b, int64_t count, int64_t len, uint8_t* c,
+                            fqt_stream_t s);
 
 /* The comparator of Section 6: the classical product with delayed reduction
  * (eq. (3)): every coefficient accumulated in 32-bit integers and reduced

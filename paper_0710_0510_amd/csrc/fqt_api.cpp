@@ -955,8 +955,9 @@ fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q, const uint8_t* 
 }
 
 fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
-                            uint32_t boundary, const uint8_t* a, const uint8_t* b, int64_t count,
-                            int64_t len, uint8_t* c, fqt_stream_t s) {
+                            uint32_t boundary, uint32_t centered, const uint8_t* a,
+                            const uint8_t* b, int64_t count, int64_t len, uint8_t* c,
+                            fqt_stream_t s) {
   if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
   if (p > 127) return fail(FQT_ERR_UNSUPPORTED, "p = %u above 127", p);
   if (d > 7) return fail(FQT_ERR_UNSUPPORTED, "d = %u above 7 (chunks of at most 8 coefficients)", d);
@@ -968,6 +969,8 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
     return fail(FQT_ERR_UNSUPPORTED, "len = %lld needs %lld chunks, above %d", (long long)len,
                 (long long)nch, kDfqtMaxChunks);
   if (boundary > 2) return fail(FQT_ERR_INVALID_ARG, "unknown boundary mode %u", boundary);
+  if (centered > 1) return fail(FQT_ERR_INVALID_ARG, "centered is 0 or 1");
+  if (centered && p == 2) return fail(FQT_ERR_UNSUPPORTED, "centred chunks need an odd p");
   // eq. (2) with k = d+1 coefficients per packed number: q^(2d+1) < 2^53,
   // q > n_q (d+1)(p-1)^2; q = 2^b with (2d+1) b <= 52 so that the biased
   // accumulator holds the sum, and the residue bytes stay below bit 52
@@ -978,13 +981,18 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
   if (bq * (2 * ke - 2) + 8 > 52)
     return fail(FQT_ERR_UNSUPPORTED, "q = 2^%u leaves no room for the residue bytes", bq);
   const uint64_t q = 1ull << bq;
-  const uint64_t unit = (uint64_t)ke * (p - 1) * (p - 1);
-  const uint64_t nq_max = unit ? (q - 1) / unit : (uint64_t)1 << 30;
+  // centred chunks: n_q (d+1) ((p-1)/2)^2 <= q/2 - 1 instead of eq. (2)
+  const uint64_t hc = (p - 1) / 2;
+  const uint64_t unit = centered ? (uint64_t)ke * hc * hc : (uint64_t)ke * (p - 1) * (p - 1);
+  const uint64_t room = centered ? (bq >= 2 ? q / 2 - 1 : 0) : q - 1;
+  const uint64_t nq_max = unit ? room / unit : (uint64_t)1 << 30;
   if (nq_max < 1)
-    return fail(FQT_ERR_BOUNDS, "q = 2^%u is not above (d+1)(p-1)^2 = %" PRIu64, bq, unit);
+    return fail(FQT_ERR_BOUNDS, "q = 2^%u cannot hold one chunk product (d = %u, p = %u)", bq, d,
+                p);
   const uint64_t nq = n_q ? n_q : std::min<uint64_t>(nq_max, (uint64_t)1 << 30);
   if (nq > nq_max)
-    return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks q > n_q (d+1)(p-1)^2", nq);
+    return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks the %s bound", nq,
+                centered ? "centred" : "eq. (2)");
   const bool multi = (uint64_t)nch > nq;  // the longest S_t has nch products
   if (multi && bq != bmax)
     return fail(FQT_ERR_UNSUPPORTED, "several blocks need the largest q = 2^%u", bmax);
@@ -995,7 +1003,7 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
     if (mode == 2 && 2 * bq > 24)
       return fail(FQT_ERR_UNSUPPORTED, "digit-sum boundaries need q <= 2^12 (q = 2^%u)", bq);
     const uint64_t width = mode == 1 ? 65535 : q * q - 1;
-    const uint64_t growth = mode == 1 ? 2 * (uint64_t)p - 1 : nq * unit;
+    const uint64_t growth = mode == 1 ? 2 * (uint64_t)p - 1 : centered ? q - 1 : nq * unit;
     const uint64_t nblocks = ((uint64_t)nch + nq - 1) / nq + 1;
     const uint64_t cap = (width - (p - 1)) / std::max<uint64_t>(growth, 1);
     if (cap < 2) return fail(FQT_ERR_UNSUPPORTED, "residue lanes too narrow for n_q = %" PRIu64, nq);
@@ -1021,6 +1029,13 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
   g.pp.qmod = (uint32_t)(q % p);
   g.pp.fold_blocks = fold;
   g.pp.b = bq;
+  if (centered) {
+    uint64_t B = 0;
+    for (uint32_t j = 0; j < 2 * ke - 1; ++j) B = B * q + q / 2;  // below q^(2d+1) <= 2^52
+    g.pp.centered = 1;
+    g.pp.cbias = 4503599627370496.0 + (double)B;
+    g.pp.c0neg = (uint32_t)((q / 2) % p);
+  }
   FQT_HIP(launch_dfqt((int)ke, mode, g, (hipStream_t)s));
   return ok();
 }

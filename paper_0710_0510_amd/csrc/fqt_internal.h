@@ -29,6 +29,7 @@ struct PackedParams {
   uint32_t blk_real;   // products per K-block (< 4*nq_groups: padded blocks)
   uint32_t centered;   // centred packing (staged tiles): digits shifted by q/2
   uint32_t c0neg;      // centred: -(L + H of the shift's residues), one word
+                       // (d-FQT: (q/2) mod p, the shift of every digit of a block)
   double cbias;        // centred: 2^52 + sum_{i<2k-1} (q/2) q^i, every block's seed
   FieldArgs fa;
   const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)

@@ -27,7 +27,7 @@
 
 namespace fqt {
 
-template <int KE, int MODE>
+template <int KE, int MODE, bool CEN>
 __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
   constexpr int ND = 2 * KE - 1;
   constexpr bool MULTI = MODE != 0;
@@ -43,27 +43,38 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
   const uint8_t* pb = g.b + (live ? prod : 0) * len;
   uint8_t* pc = g.c + (live ? prod : 0) * (int64_t)(2 * len - 1);
 
-  // DQT of every chunk: sum_j c_j 2^(b j) < 2^52, exact in binary64
+  // DQT of every chunk: sum_j c_j 2^(b j) < 2^52, exact in binary64; centred
+  // chunks take c - p for c > (p-1)/2 (a signed sum, as exact)
+  const PackedParams& pp = g.pp;
   if (live) {
+    const int32_t p = (int32_t)pp.fa.p, h = (p - 1) / 2;
     for (int i = lane; i < nch; i += 64) {
+      // sums of (possibly negative) c_j 2^(b j) in two's complement mod 2^64;
+      // the true value is below 2^52 in magnitude
       uint64_t va = 0, vb = 0;
 #pragma unroll
       for (int j = 0; j < KE; ++j) {
         const int idx = i * KE + j;
         if (idx < len) {
-          va |= (uint64_t)pa[idx] << (b * j);
-          vb |= (uint64_t)pb[idx] << (b * j);
+          int32_t ca = pa[idx], cb = pb[idx];
+          if constexpr (CEN) {
+            ca -= ca > h ? p : 0;
+            cb -= cb > h ? p : 0;
+          }
+          va += (uint64_t)(int64_t)ca << (b * j);
+          vb += (uint64_t)(int64_t)cb << (b * j);
         }
       }
-      P[i] = (double)va;
-      Q[i] = (double)vb;
+      P[i] = (double)(int64_t)va;
+      Q[i] = (double)(int64_t)vb;
     }
   }
   __syncthreads();
   if (!live) return;  // no barrier below
 
-  const PackedParams& pp = g.pp;
   const int nt = 2 * nch;  // t = 0 .. 2nch-1
+  // every block starts from 2^52 (centred: plus q/2 in every digit)
+  const double bz = CEN ? pp.cbias : kTwo52;
   uint32_t carry[KE > 1 ? KE - 1 : 1];
 #pragma unroll
   for (int j = 0; j < KE - 1; ++j) carry[j] = 0;
@@ -72,7 +83,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
     double acc[4];
     BlockLanes<KE, MODE> st[MULTI ? 4 : 1];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = kTwo52;
+    for (int r = 0; r < 4; ++r) acc[r] = bz;
     if constexpr (MULTI) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) st[r].clear();
@@ -84,7 +95,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
       const int j = tb + r - ilo;
       qw[r] = (j >= 0 && j < nch) ? Q[j] : 0.0;
     }
-    uint32_t cnt = 0, nbound = 0;
+    uint32_t cnt = 0, nbound = 0, nblk = 1;  // blocks of this pass (the centred shift counts them)
     for (int i = ilo; i <= ihi; ++i) {
       const double pi = P[i];
 #pragma unroll
@@ -95,8 +106,9 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             st[r].add(acc[r], pp.fa);
-            acc[r] = kTwo52;
+            acc[r] = bz;
           }
+          ++nblk;
           if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
             nbound = 0;
 #pragma unroll
@@ -114,12 +126,18 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
 
     // Thm. 2's residues u_i, then Alg. 2's second part (the Q_d correction of
     // Section 5.1): digit i mod p is (u_i - q u_{i+1}) mod p, the top one u_2d
+    // centred: every digit carries q/2 per block, taken off mod p
+    const uint32_t shift = CEN ? (pp.fa.p - (nblk % pp.fa.p) * pp.c0neg % pp.fa.p) % pp.fa.p : 0u;
     uint32_t u[4][ND];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       st[MULTI ? r : 0].residues(acc[r], b, pp, u[r]);
 #pragma unroll
       for (int i = 0; i < ND - 1; ++i) u[r][i] = mod_p_small(u[r][i] + pp.fa.c * u[r][i + 1], pp.fa);
+      if constexpr (CEN) {
+#pragma unroll
+        for (int i = 0; i < ND; ++i) u[r][i] = mod_p_small(u[r][i] + shift, pp.fa);
+      }
     }
     // digits d+1..2d of S_{tb-1}: previous lane's last t, or the carried ones
     uint32_t prev[KE > 1 ? KE - 1 : 1];
@@ -199,15 +217,15 @@ __global__ __launch_bounds__(256) void polymul_delayed_kernel(DelayedArgs g) {
   }
 }
 
-template <int KE>
+template <int KE, bool CEN>
 static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
   const dim3 grid((unsigned)((g.count + 3) / 4));
   switch (mode) {
-    case 0: hipLaunchKernelGGL((dfqt_kernel<KE, 0>), grid, dim3(256), 0, s, g); break;
-    case 1: hipLaunchKernelGGL((dfqt_kernel<KE, 1>), grid, dim3(256), 0, s, g); break;
+    case 0: hipLaunchKernelGGL((dfqt_kernel<KE, 0, CEN>), grid, dim3(256), 0, s, g); break;
+    case 1: hipLaunchKernelGGL((dfqt_kernel<KE, 1, CEN>), grid, dim3(256), 0, s, g); break;
     case 2:
       if constexpr (digit_sums_fit<KE>()) {
-        hipLaunchKernelGGL((dfqt_kernel<KE, 2>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((dfqt_kernel<KE, 2, CEN>), grid, dim3(256), 0, s, g);
         break;
       } else {
         return hipErrorInvalidValue;
@@ -215,6 +233,11 @@ static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <int KE>
+static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
+  return g.pp.centered ? dfqt_k<KE, true>(mode, g, s) : dfqt_k<KE, false>(mode, g, s);
 }
 
 hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s) {

@@ -76,8 +76,8 @@ def lib() -> ctypes.CDLL:
         "fqt_unpack_redq": (c_int, [vp, c_u64, vp, c_sz, c_u32, c_int, vp, vp]),
         "fqt_unpack_redq_u64": (c_int, [vp, c_u64, vp, c_sz, c_u32, c_int, vp, vp]),
         "fqt_polymul_batch": (c_int, [c_u32, c_u32, c_u64, vp, vp, c_sz, vp, vp]),
-        "fqt_polymul_dfqt": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, vp, vp, c_i64, c_i64, vp,
-                                     vp]),
+        "fqt_polymul_dfqt": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, c_u32, vp, vp, c_i64,
+                                     c_i64, vp, vp]),
         "fqt_polymul_delayed": (c_int, [c_u32, vp, vp, c_i64, c_i64, vp, vp]),
         "fqt_gemm_gfpk": (c_int, [vp, c_int, c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp,
                                   c_i64, vp]),
@@ -229,15 +229,16 @@ def _poly_operands(a, b, name: str):
 
 
 def polymul_dfqt(p: int, d: int, a, b, log2q: int = 0, n_q: int = 0, boundary: int = 0,
-                 out=None, stream=None):
-    """d-FQT products of long polynomials (Section 6): out[i] = a[i] * b[i]."""
+                 out=None, stream=None, centered: int = 0):
+    """d-FQT products of long polynomials (Section 6): out[i] = a[i] * b[i];
+    centered=1 packs centred chunks (about twice the products per block)."""
     import torch
     _poly_operands(a, b, "polymul_dfqt")
     count, length = a.shape
     if out is None:
         out = torch.empty((count, max(2 * length - 1, 0)), dtype=torch.uint8, device=a.device)
-    _check(lib().fqt_polymul_dfqt(p, d, log2q, n_q, boundary, _ptr(a), _ptr(b), count, length,
-                                  _ptr(out), _stream(stream)))
+    _check(lib().fqt_polymul_dfqt(p, d, log2q, n_q, boundary, centered, _ptr(a), _ptr(b), count,
+                                  length, _ptr(out), _stream(stream)))
     return out
 
 

@@ -140,3 +140,53 @@ def test_dfqt_workload_sampled():
     rng = np.random.default_rng(11)
     picks = sorted({0, w.count - 1} | set(rng.integers(0, w.count, size=64).tolist()))
     assert np.array_equal(out_h[picks], want_rows(a_h[picks], b_h[picks], w.p))
+
+
+# ---- centred chunks ------------------------------------------------------------
+
+CPD = [(p, d) for (p, d) in PD if p % 2 == 1]
+
+
+@pytest.mark.parametrize("p,d", CPD)
+def test_dfqt_centred_matches_product_definition(p, d):
+    rng = np.random.default_rng(p * 1000 + d)
+    for length in sorted({1, 2, d + 1, 37, 256, 501, min(1024 * (d + 1), 3000)}):
+        note(f"dfqt centred p={p} d={d} len={length}")
+        a = rng.integers(0, p, size=(3, length), dtype=np.uint8)
+        b = rng.integers(0, p, size=(3, length), dtype=np.uint8)
+        out = host(fqt.polymul_dfqt(p, d, dev(a), dev(b), centered=1))
+        assert np.array_equal(out, want_rows(a, b, p)), length
+
+
+@pytest.mark.parametrize("p,d", [(3, 4), (3, 3), (5, 2), (7, 1)])
+@pytest.mark.parametrize("boundary", [1, 2])
+def test_dfqt_centred_extremes(p, d, boundary):
+    # every coefficient h against h (+h^2 per term) and against -h (-h^2): the
+    # block digits reach both ends of [-q/2, q/2) at the centred n_q
+    q = 2 ** (52 // (2 * d + 1))
+    if boundary == 2 and q > 2 ** 12:
+        pytest.skip("digit-sum boundaries need q <= 2^12")
+    h = (p - 1) // 2
+    length = 501
+    for bv in (h, p - h):
+        note(f"dfqt centred extremes p={p} d={d} boundary={boundary} b={bv}")
+        a = np.full((2, length), h, dtype=np.uint8)
+        b = np.full((2, length), bv, dtype=np.uint8)
+        out = host(fqt.polymul_dfqt(p, d, dev(a), dev(b), boundary=boundary, centered=1))
+        assert np.array_equal(out, want_rows(a, b, p)), bv
+
+
+def test_dfqt_centred_workload_sampled():
+    from paper_0710_0510_amd import workloads as W
+    w = W.WORKLOADS["dfqt-gf3-n500-d4"]
+    a_h, b_h = W.poly_long_inputs(w)
+    a, b = dev(a_h), dev(b_h)
+    note("dfqt centred workload")
+    plain = fqt.polymul_dfqt(w.p, w.d, a, b)
+    cen = fqt.polymul_dfqt(w.p, w.d, a, b, centered=1)
+    torch.cuda.synchronize()
+    assert torch.equal(plain, cen)
+    rng = np.random.default_rng(5)
+    out = host(cen)
+    for i in rng.integers(0, w.count, size=8).tolist():
+        assert out[i].tolist() == gf.polymul_long(a_h[i].tolist(), b_h[i].tolist(), w.p)

@@ -238,11 +238,19 @@ def test_autotune_rejects_plain_only():
 # ---- d-FQT long polynomials: every refusal happens before device work -------
 
 def _dfqt_status(p, d, log2q, n_q, boundary, count, length, a=BOGUS, b=BOGUS + (1 << 30),
-                 c=BOGUS + (1 << 31)):
+                 c=BOGUS + (1 << 31), centered=0):
     L = fqt.lib()
-    return fqt.STATUS_NAMES[L.fqt_polymul_dfqt(p, d, log2q, n_q, boundary, ctypes.c_void_p(a),
-                                               ctypes.c_void_p(b), count, length,
-                                               ctypes.c_void_p(c), None)]
+    return fqt.STATUS_NAMES[L.fqt_polymul_dfqt(p, d, log2q, n_q, boundary, centered,
+                                               ctypes.c_void_p(a), ctypes.c_void_p(b), count,
+                                               length, ctypes.c_void_p(c), None)]
+
+
+def test_dfqt_centred_validation_errors():
+    assert _dfqt_status(2, 1, 0, 0, 0, 1, 10, centered=1) == "FQT_ERR_UNSUPPORTED"
+    assert _dfqt_status(3, 4, 0, 0, 0, 1, 10, centered=2) == "FQT_ERR_INVALID_ARG"
+    # p = 3, d = 4, q = 2^5: centred blocks hold 3 chunk products, not 4
+    assert _dfqt_status(3, 4, 0, 4, 0, 1, 10, centered=1) == "FQT_ERR_BOUNDS"
+    assert _dfqt_status(3, 4, 0, 2, 0, 1, 10, centered=0) == "FQT_ERR_BOUNDS"
 
 
 def test_dfqt_validation_errors():
