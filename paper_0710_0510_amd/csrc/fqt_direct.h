@@ -108,7 +108,7 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
         for (int v = 0; v < 4; ++v) st[i][j][v].clear();
   }
-  uint32_t gcnt = 0, nbound = 0;
+  uint32_t gcnt = 0, nbound = 0, nadd = 0;  // nadd: blocks in the lane state since its last fold
 
   // Byte pointers of this lane's first K-step.
   const uint8_t* pa = g.A + ((wm0 + c) * g.lda + 4 * grp) * EB;
@@ -220,6 +220,7 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
           for (int v = 0; v < 4; ++v) st[i][j][v].add(acc[i][j][v], pp.fa);
           acc[i][j] = bias;
         }
+      ++nadd;
       if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
         nbound = 0;
 #pragma unroll
@@ -227,7 +228,8 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
           for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) st[i][j][v].fold(pp.fa);
+            for (int v = 0; v < 4; ++v) st[i][j][v].fold(pp.fa, nadd);
+        nadd = 0;
       }
     }
   };
@@ -357,7 +359,7 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         uint32_t u[2 * KE - 1];
-        st[MULTI ? i : 0][MULTI ? j : 0][v].residues(acc[i][j][v], b, pp, u);
+        st[MULTI ? i : 0][MULTI ? j : 0][v].residues(acc[i][j][v], b, pp, u, nadd);
         e[j] = LOG ? lh_log<KE>(u, pp, Ls, Hs, Zs) : lh_combine<KE>(u, pp, Ls, Hs);
       }
       const int64_t row = wm0 + 16 * i + grp + 4 * v;

@@ -12,9 +12,13 @@
 //           two residues per word (digit 2w low, 2w+1 high).
 //   MODE 2: digit sums.  With q = 2^b the digits of a block are bit fields of
 //           its accumulator; the bits of its even digits are added into E,
-//           those of its odd digits into O, so every field has b spare bits
-//           above it and sums below q^2 never carry (needs 2b <= 24).  At the
-//           end Horner's rule mod p gives u_i = sum_{j>=i} D_j q^(j-i) mod p.
+//           those of its odd digits form O, so every field has b spare bits
+//           above it and sums below q^2 never carry (needs 2b <= 24).  O is
+//           not kept: T, the plain sum of the accumulators' bit patterns, is
+//           (odd + even digit bits) + n * bits(2^52), so O = T - E - n bits(2^52)
+//           with n the blocks added since the last fold (one mask-and-add less
+//           per block).  At the end Horner's rule mod p gives
+//           u_i = sum_{j>=i} D_j q^(j-i) mod p.
 // Lanes and fields are folded mod p every fold_blocks boundaries, before they
 // could overflow.  In modes 1 and 2, q is the largest power of two eq. (2)
 // admits and is fixed at compile time.
@@ -151,13 +155,13 @@ struct BlockLanes {
   static constexpr int NW = KE;  // 16-bit lane words, (ND + 1) / 2
   static constexpr uint32_t BQ = MODE ? multi_block_b<KE>() : 0u;
   static constexpr uint64_t EM = MODE == 2 ? digit_mask(ND, BQ, 0) : 0;
-  static constexpr uint64_t OM = MODE == 2 ? digit_mask(ND, BQ, 1) : 0;
+  static constexpr uint64_t XB = 0x4330000000000000ull;  // bits of 2^52, one per block
 
-  uint64_t E, O;   // MODE 2
+  uint64_t E, T;   // MODE 2: even digit fields; sum of the blocks' bit patterns
   uint32_t W[NW];  // MODE 1
 
   __device__ __forceinline__ void clear() {
-    E = O = 0;
+    E = T = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) W[w] = 0;
   }
@@ -185,7 +189,7 @@ struct BlockLanes {
     if constexpr (MODE == 2) {
       const uint64_t rb = bits64(acc);
       E += rb & EM;
-      O += rb & OM;
+      T += rb;
     } else if constexpr (MODE == 1) {
       uint32_t wd[NW];
       residue_words(acc, fa, wd);
@@ -194,9 +198,10 @@ struct BlockLanes {
     }
   }
 
-  // Reduce every lane or field mod p.
-  __device__ __forceinline__ void fold(const FieldArgs& fa) {
+  // Reduce every lane or field mod p; nadd = blocks added since the last fold.
+  __device__ __forceinline__ void fold(const FieldArgs& fa, uint32_t nadd) {
     if constexpr (MODE == 2) {
+      const uint64_t O = T - E - (uint64_t)nadd * XB;
       uint64_t e = 0, o = 0;
 #pragma unroll
       for (int d = 0; d < ND; ++d) {
@@ -205,7 +210,7 @@ struct BlockLanes {
         else e |= r << (BQ * d);
       }
       E = e;
-      O = o;
+      T = e + o;  // no block bits: the count starts again
     } else if constexpr (MODE == 1) {
 #pragma unroll
       for (int w = 0; w < NW; ++w) {
@@ -216,13 +221,15 @@ struct BlockLanes {
   }
 
   // Final residues u_0..u_{2k-2} in [0, p) of all blocks, the last block
-  // still in its accumulator.  b is q's exponent for MODE 0.
+  // still in its accumulator; nadd = blocks added since the last fold.  b is
+  // q's exponent for MODE 0.
   __device__ __forceinline__ void residues(double acc, uint32_t b, const PackedParams& pp,
-                                           uint32_t (&u)[ND]) const {
+                                           uint32_t (&u)[ND], uint32_t nadd = 0) const {
     const FieldArgs& fa = pp.fa;
     if constexpr (MODE == 2) {
       const uint64_t rb = bits64(acc);
-      const uint64_t e = E + (rb & EM), o = O + (rb & OM);
+      const uint64_t e = E + (rb & EM);
+      const uint64_t o = T + rb - e - (uint64_t)(nadd + 1) * XB;
       u[ND - 1] = mod_p_small(field(((ND - 1) & 1) ? o : e, ND - 1), fa);
 #pragma unroll
       for (int d = ND - 2; d >= 0; --d)

@@ -96,6 +96,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
       qw[r] = (j >= 0 && j < nch) ? Q[j] : 0.0;
     }
     uint32_t cnt = 0, nbound = 0, nblk = 1;  // blocks of this pass (the centred shift counts them)
+    uint32_t nadd = 0;                       // blocks in the lane state since its last fold
     for (int i = ilo; i <= ihi; ++i) {
       const double pi = P[i];
 #pragma unroll
@@ -109,10 +110,12 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
             acc[r] = bz;
           }
           ++nblk;
+          ++nadd;
           if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
             nbound = 0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) st[r].fold(pp.fa);
+            for (int r = 0; r < 4; ++r) st[r].fold(pp.fa, nadd);
+            nadd = 0;
           }
         }
       }
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
     uint32_t u[4][ND];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      st[MULTI ? r : 0].residues(acc[r], b, pp, u[r]);
+      st[MULTI ? r : 0].residues(acc[r], b, pp, u[r], nadd);
 #pragma unroll
       for (int i = 0; i < ND - 1; ++i) u[r][i] = mod_p_small(u[r][i] + pp.fa.c * u[r][i + 1], pp.fa);
       if constexpr (CEN) {

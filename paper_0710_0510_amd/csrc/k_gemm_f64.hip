@@ -246,9 +246,11 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
   };
 
   uint32_t nbound = 0, nblk = 1;  // blocks seeded so far (the centred correction counts them)
+  uint32_t nadd = 0;              // blocks in the lane state since its last fold
   auto boundary = [&]() {
     if constexpr (MULTI) {
       ++nblk;
+      ++nadd;
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -265,7 +267,8 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
           for (int j = 0; j < TN; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) st[i][j][v].fold(pp.fa);
+            for (int v = 0; v < 4; ++v) st[i][j][v].fold(pp.fa, nadd);
+        nadd = 0;
       }
     }
   };
@@ -316,7 +319,7 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         uint32_t u[T::ND];
-        st[MULTI ? i : 0][MULTI ? j : 0][v].residues(acc[i][j][v], b, pp, u);
+        st[MULTI ? i : 0][MULTI ? j : 0][v].residues(acc[i][j][v], b, pp, u, nadd);
         uint32_t e = lh_combine<KE>(u, pp, Ls, Hs);
         if (pp.centered) e = add_bytes_mod_p(e, corr, pp.fa);
         const int64_t row = m0 + wm0 + 16 * i + (lane >> 4) + 4 * v;
