@@ -100,7 +100,8 @@ typedef struct {
                       into MFMA registers (all but 11 need K <= n_q and
                       return FQT_ERR_UNSUPPORTED otherwise; these ids never
                       pad a K-block: n_q is rounded down to a multiple of
-                      4).  Ids 13 and 14 (k = 3 or 4 only, else
+                      4; id 12 also needs each operand's extent, rows x ld
+                      x k bytes, below 2^31, else FQT_ERR_UNSUPPORTED).  Ids 13 and 14 (k = 3 or 4 only, else
                       FQT_ERR_UNSUPPORTED) split every element into two
                       chunks of 2 coefficients (Section 6's chunking with
                       d = 1) packed at q = 2^17 and contract three

@@ -1206,11 +1206,21 @@ void centred_params(fqt_field_s* f, uint32_t b, PackedParams* pp) {
   pp->cbias = 4503599627370496.0 + (double)B;
 }
 
+// Buffered direct tiles address A and B through 32-bit offsets.
+static bool extents_fit_32(const GemmArgs& g, uint32_t k) {
+  const uint64_t lim = 0x7fffffffull;
+  const uint64_t ea = g.M && g.K ? ((uint64_t)(g.M - 1) * g.lda + g.K) * k : 0;
+  const uint64_t eb = g.K && g.N ? ((uint64_t)(g.K - 1) * g.ldb + g.N) * k : 0;
+  return ea < lim && eb < lim;
+}
+
 static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
                               hipStream_t s) {
   PackedChoice pc;
   fqt_status st = resolve_packed(f, opts, g.K, g.M, g.N, &pc);
   if (st) return st;
+  if (direct_tile_buffered((int)pc.tile) && !extents_fit_32(g, f->k))
+    return fail(FQT_ERR_UNSUPPORTED, "tile %u addresses operands below 2^31 bytes only", pc.tile);
   const uint64_t q = 1ull << pc.b;
   const bool split = is_split_tile((int)pc.tile);
   DevTables dt;
@@ -1522,6 +1532,14 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
   if (!o.tile) o.tile = 2;
   fqt_status st = resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc);
   if (st) return st;
+  if (direct_tile_buffered((int)pc.tile))
+    for (int64_t d = 0; d < count; ++d) {
+      const fqt_gemm_desc& e = descs[d];
+      const GemmArgs ga{e.A, e.B, e.C, e.M, e.N, e.K, e.lda, e.ldb, e.ldc};
+      if (!extents_fit_32(ga, f->k))
+        return fail(FQT_ERR_UNSUPPORTED, "tile %u addresses operands below 2^31 bytes only "
+                    "(descriptor %lld)", pc.tile, (long long)d);
+    }
   const uint64_t q = 1ull << pc.b;
   const bool split = is_split_tile((int)pc.tile);
   DevTables dt;

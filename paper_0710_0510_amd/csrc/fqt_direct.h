@@ -66,7 +66,40 @@ struct DStage {
   uint32_t b[4][TN * EB / 4];  // B rows 16s+4g+gk, columns wn0+TN*c .. +TN-1
 };
 
-template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD, bool LOG = false>
+// Operand words through a buffer resource: voff is the lane's byte offset,
+// soff a wave-uniform one (the K-step advance), both below 2^31.
+template <int NW>
+__device__ __forceinline__ void buf_load(__amdgpu_buffer_rsrc_t r, int32_t voff, int32_t soff,
+                                         uint32_t (&out)[NW]) {
+  if constexpr (NW == 1) {
+    out[0] = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  } else if constexpr (NW == 2) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    out[0] = v[0];
+    out[1] = v[1];
+  } else if constexpr (NW == 3) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b96(r, voff, soff, 0);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+  } else {
+    static_assert(NW == 4, "1 to 4 words");
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    out[0] = v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    out[3] = v[3];
+  }
+}
+
+// gfx9 buffer resource word 3 (raw, untyped 32-bit data)
+constexpr int kBufferWord3 = 0x00020000;
+
+// BUF: interior K-steps load through buffer resources with the K-step in
+// the scalar offset, so no per-load address arithmetic; needs both operand
+// extents below 2^31 bytes (checked on the host).
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD, bool LOG = false,
+          bool BUF = false>
 __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int tile_n,
                                             const PackedParams& pp, double* __restrict__ red,
                                             const uint32_t* __restrict__ Ls,
@@ -79,7 +112,9 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
   constexpr bool MULTI = MODE != 0;
   static_assert(!(MULTI && SK > 1), "split-K waves combine single-block accumulators");
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  // BUF: the wave index as a scalar, so the K range and the scalar offsets
+  // derived from it are wave-uniform for the compiler too
+  const int wave = BUF ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : threadIdx.x >> 6;
   const int sw = wave % T::SP, kw = wave / T::SP;
   const int c = lane & 15, grp = lane >> 4;
   const int64_t wm0 = (int64_t)tile_m * T::BM + (sw / T::WGN) * T::WM;
@@ -117,7 +152,26 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
   const int64_t b_gstep = g.ldb * EB;       // next B row
   const int64_t b_sstep = 16 * g.ldb * EB;  // next K-step
 
+  int32_t voa[TM], vob[4];
+  if constexpr (BUF) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i) voa[i] = (int32_t)((pa - g.A) + i * a_istep);
+#pragma unroll
+    for (int gk = 0; gk < 4; ++gk) vob[gk] = (int32_t)((pb - g.B) + gk * b_gstep);
+  }
   auto load_fast = [&](St& x, int64_t s) {
+    if constexpr (BUF) {
+      const auto rsa = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.A), (short)0,
+                                                         0x7fffffff, kBufferWord3);
+      const auto rsb = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.B), (short)0,
+                                                         0x7fffffff, kBufferWord3);
+      const int32_t sa = (int32_t)(s * 16 * EB), sb = (int32_t)(s * b_sstep);
+#pragma unroll
+      for (int i = 0; i < TM; ++i) buf_load<EB>(rsa, voa[i], sa, x.a[i]);
+#pragma unroll
+      for (int gk = 0; gk < 4; ++gk) buf_load<T::BW>(rsb, vob[gk], sb, x.b[gk]);
+      return;
+    }
     const uint8_t* a0 = pa + s * 16 * EB;
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
@@ -388,7 +442,8 @@ __device__ __forceinline__ void direct_tile(const GemmArgs& g, int tile_m, int t
   }
 }
 
-template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD, bool LOG = false>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD, bool LOG = false,
+          bool BUF = false>
 __global__ __launch_bounds__(64 * NWV) void gemm_direct_kernel(GemmArgs g, PackedParams pp,
                                                           int tiles_n, int ntiles) {
   using T = DT<LOG ? 2 : KE, TM, TN, SK, NWV>;
@@ -402,11 +457,12 @@ __global__ __launch_bounds__(64 * NWV) void gemm_direct_kernel(GemmArgs g, Packe
   if constexpr (LOG) log_lds_tables(pp, tabs, &pks, &Zs);
   __syncthreads();
   const int tile = xcd_tile((int)blockIdx.x, ntiles / tiles_n, tiles_n);
-  direct_tile<KE, TM, TN, SK, NWV, MODE, PD, LOG>(g, tile / tiles_n, tile % tiles_n, pp, red, Ls,
-                                                  Hs, pks, Zs);
+  direct_tile<KE, TM, TN, SK, NWV, MODE, PD, LOG, BUF>(g, tile / tiles_n, tile % tiles_n, pp, red,
+                                                       Ls, Hs, pks, Zs);
 }
 
-template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD, bool LOG = false>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, int PD, bool LOG = false,
+          bool BUF = false>
 __global__ __launch_bounds__(64 * NWV) void gemm_direct_batched_kernel(
     const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items, int32_t n_items,
     uint32_t* counter, PackedParams pp) {
@@ -429,7 +485,8 @@ __global__ __launch_bounds__(64 * NWV) void gemm_direct_batched_kernel(
     if (it >= n_items) break;
     const TileItem ti = items[it];
     const GemmArgs g = descs[ti.gemm];
-    direct_tile<KE, TM, TN, SK, NWV, MODE, PD, LOG>(g, ti.tm, ti.tn, pp, red, Ls, Hs, pks, Zs);
+    direct_tile<KE, TM, TN, SK, NWV, MODE, PD, LOG, BUF>(g, ti.tm, ti.tn, pp, red, Ls, Hs, pks,
+                                                         Zs);
   }
   // The last workgroup to leave resets the queue for the next launch (every
   // workgroup has made its final counter[0] increment before counter[1]).

@@ -8,7 +8,7 @@ namespace fqt {
 
 // ---- dispatch ----------------------------------------------------------------
 
-template <int KE, int TM, int TN, int SK, int NWV, int MODE>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, bool BUF>
 static hipError_t direct_one(const GemmArgs& g, const PackedParams& pp, hipStream_t s) {
   using T = DT<KE, TM, TN, SK, NWV>;
   const int tiles_m = (int)((g.M + T::BM - 1) / T::BM);
@@ -16,29 +16,30 @@ static hipError_t direct_one(const GemmArgs& g, const PackedParams& pp, hipStrea
   const int ntiles = tiles_m * tiles_n;
   if (ntiles == 0) return hipSuccess;
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_direct_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages>), dim3(ntiles),
-                     dim3(64 * NWV), dyn, s, g, pp, tiles_n, ntiles);
+  hipLaunchKernelGGL((gemm_direct_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages, false, BUF>),
+                     dim3(ntiles), dim3(64 * NWV), dyn, s, g, pp, tiles_n, ntiles);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, int SK, int NWV, int MODE>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, bool BUF>
 static hipError_t direct_batched(const GemmArgs* descs, const TileItem* items, int32_t n_items,
                                  uint32_t* counter, int grid, const PackedParams& pp,
                                  hipStream_t s) {
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL((gemm_direct_batched_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages>),
-                     dim3(grid), dim3(64 * NWV), dyn, s, descs, items, n_items, counter, pp);
+  hipLaunchKernelGGL(
+      (gemm_direct_batched_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages, false, BUF>), dim3(grid),
+      dim3(64 * NWV), dyn, s, descs, items, n_items, counter, pp);
   return hipGetLastError();
 }
 
-template <int KE, int TM, int TN, int SK, int NWV, int MODE>
+template <int KE, int TM, int TN, int SK, int NWV, int MODE, bool BUF>
 static int direct_occupancy(uint32_t tbl_log2) {
   int blocks = 0;
   const size_t dyn = 2u * (1u << tbl_log2) * sizeof(uint32_t);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
           &blocks,
-          (const void*)gemm_direct_batched_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages>, 64 * NWV,
-          dyn) != hipSuccess)
+          (const void*)gemm_direct_batched_kernel<KE, TM, TN, SK, NWV, MODE, kDirectStages, false, BUF>,
+          64 * NWV, dyn) != hipSuccess)
     blocks = 1;
   return blocks > 0 ? blocks : 1;
 }
@@ -48,7 +49,7 @@ static int direct_occupancy(uint32_t tbl_log2) {
 #define FQT_DIRECT_CASE(ID, TM, TN, SK, NWV, MULTI_OK)                       \
   case ID:                                                                    \
     if constexpr ((MODE == 0 || MULTI_OK) && (MODE != 2 || digit_sums_fit<KE>())) \
-      return FN<KE, TM, TN, SK, NWV, MODE>(ARGS);                             \
+      return FN<KE, TM, TN, SK, NWV, MODE, direct_tile_buffered(ID)>(ARGS);   \
     else                                                                      \
       return FAIL;
 
