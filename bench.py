@@ -36,6 +36,9 @@ MEASURED_TRAFFIC = {
     ("gemm-gf7^2-1024", "packed", 7): {
         "bytes": 15_269_888,  # FETCH 6432 KiB x 2.000 + WRITE 2048 KiB x 1.000
         "source": "profiles/gemm_direct_gf7-2_1024.md"},
+    ("gemm-gf7^2-1024", "packed", 12): {
+        "bytes": 14_993_408,  # FETCH 6297 KiB x 2.000 + WRITE 2048 KiB x 1.000
+        "source": "profiles/gemm_direct_gf7-2_1024.md"},
     ("dfqt-gf3-n500-d4", "dfqt", 4, 1): {
         "bytes": 34_088_960,  # FETCH 8581.0 KiB x 2.000 + WRITE 16128 KiB x 1.000
         "source": "profiles/dfqt_gf3_n500_d4.md"},
@@ -53,6 +56,30 @@ def poly_str(P_low):
         if c:
             terms.append(("" if c == 1 and i else str(c)) + (f"X^{i}" if i > 1 else ("X" if i == 1 else "")))
     return "+".join(terms)
+
+
+# Default step counts are sized from the step's own duration: the GPU clock
+# settles over some milliseconds of sustained load, so a short timed region of
+# a ~40 us kernel reads a few per cent slow.
+TIMED_MS, WARMUP_MS = 40.0, 20.0
+
+
+def size_counts(fn, args, torch):
+    """Fill in --steps / --warmup when not given: at least 50 timed steps
+    covering TIMED_MS and at least 10 warmup steps covering WARMUP_MS."""
+    if args.steps is not None and args.warmup is not None:
+        return
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    ms = max((time.perf_counter() - t0) * 1e3 / 3, 1e-3)
+    if args.steps is None:
+        args.steps = int(min(5000, max(50, -(-TIMED_MS // ms))))
+    if args.warmup is None:
+        args.warmup = int(min(5000, max(10, -(-WARMUP_MS // ms))))
 
 
 def time_steps(fn, steps, warmup, torch):
@@ -175,6 +202,7 @@ def bench_gemm(w, args, torch, fqt, gf):
         torch.cuda.synchronize()
         if not torch.equal(C, Cref):
             raise SystemExit(f"parity failure: path {path} differs from the plain path")
+        size_counts(lambda: run_path(path, C, opts), args, torch)
         steps = args.steps if path != "plain" else max(3, args.steps // 10)
         ms = time_steps(lambda: run_path(path, C, opts), steps,
                         args.warmup if path != "plain" else 2, torch)
@@ -324,6 +352,7 @@ def bench_batched(w, args, torch, fqt, gf):
     torch.cuda.synchronize()
     if not torch.equal(dC, dR):
         raise SystemExit("parity failure: batched packed path differs from the plain path")
+    size_counts(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=opts), args, torch)
     ms = time_steps(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=opts),
                     args.steps, args.warmup, torch)
     dI = torch.zeros_like(dC)
@@ -368,6 +397,7 @@ def bench_polymul(w, args, torch, fqt, gf):
     want = gf.polymul_batch(a_h, b_h, w.p)
     if not np.array_equal(c.cpu().numpy(), want):
         raise SystemExit("parity failure: polymul differs from the oracle")
+    size_counts(lambda: fqt.polymul_batch(w.p, w.k, w.q, a, b, out=c), args, torch)
     ms = time_steps(lambda: fqt.polymul_batch(w.p, w.k, w.q, a, b, out=c), args.steps,
                     args.warmup, torch)
     work = w.n * w.k * w.k
@@ -411,6 +441,8 @@ def bench_dfqt(w, args, torch, fqt, gf):
             if not torch.equal(out, ref):
                 raise SystemExit(f"parity failure: d-FQT with d = {d}, centered = {cen} differs "
                                  "from the comparator")
+            size_counts(lambda: fqt.polymul_dfqt(w.p, d, a, b, out=out, centered=cen), args,
+                        torch)
             ms = time_steps(lambda: fqt.polymul_dfqt(w.p, d, a, b, out=out, centered=cen),
                             args.steps, args.warmup, torch)
             nch = -(-w.length // (d + 1))
@@ -477,8 +509,10 @@ def bench_dfqt(w, args, torch, fqt, gf):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: >= 50, covering %g ms)" % TIMED_MS)
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warmup steps (default: >= 10, covering %g ms)" % WARMUP_MS)
     ap.add_argument("--workload", default="gemm-gf7^2-1024")
     ap.add_argument("--path", default="packed", choices=["packed", "int8", "plain", "winograd"])
     ap.add_argument("--levels", type=int, default=2,
