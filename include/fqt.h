@@ -101,7 +101,8 @@ typedef struct {
                       return FQT_ERR_UNSUPPORTED otherwise; these ids never
                       pad a K-block: n_q is rounded down to a multiple of
                       4; id 12 also needs each operand's extent, rows x ld
-                      x k bytes, below 2^31, else FQT_ERR_UNSUPPORTED).  Ids 13 and 14 (k = 3 or 4 only, else
+                      x k bytes, below 2^31, else FQT_ERR_UNSUPPORTED).
+                      Ids 13 and 14 (k = 3 or 4 only, else
                       FQT_ERR_UNSUPPORTED) split every element into two
                       chunks of 2 coefficients (Section 6's chunking with
                       d = 1) packed at q = 2^17 and contract three
@@ -110,7 +111,14 @@ typedef struct {
                       for k = 4 and 4 for k = 3 (4095 for GF(3^4)); longer
                       K runs in blocks of a multiple of 16 products.  They
                       accept log2q 0 or 17 only (FQT_ERR_INVALID_ARG) and
-                      ignore boundary. */
+                      ignore boundary.
+                      INT8 path: ids 1..3 expand B into B' (k x k
+                      multiplication matrices) in a device workspace, then
+                      run the INT8 GEMM; ids 4..6 build B' K-tile by K-tile
+                      in LDS inside the GEMM (no workspace) and return
+                      FQT_ERR_UNSUPPORTED when their operand tiles and the
+                      2^(k ceil(log2 p)) x k^2-byte table exceed the 160 KiB
+                      LDS of a CU.  All INT8 ids give identical bytes. */
   uint32_t boundary; /* packed path, K > n_q: step at each K-block boundary.
                         0 = default (2 when q <= 2^12, else 1); 1 = REDQ
                         residues of the block (Alg. 2,

@@ -1282,13 +1282,58 @@ static uint32_t row_align(const void* base, int64_t row_bytes) {
   return 1;
 }
 
-// K-tiles (128 bytes of K) between reductions mod p, 0 when the whole sum fits:
-// (p-1) + n (128 (p-1)^2) < 2^31 keeps every INT32 partial sum exact.
-static uint32_t i8_red_tiles(int64_t KK, int64_t p) {
-  const int64_t per_tile = 128 * (p - 1) * (p - 1);
-  const int64_t nkt = (KK + 127) / 128;
+// K-tiles (bkk bytes of K) between reductions mod p, 0 when the whole sum
+// fits: (p-1) + n (bkk (p-1)^2) < 2^31 keeps every INT32 partial sum exact.
+static uint32_t i8_red_tiles(int64_t KK, int64_t p, int64_t bkk = 128) {
+  const int64_t per_tile = bkk * (p - 1) * (p - 1);
+  const int64_t nkt = (KK + bkk - 1) / bkk;
   if (per_tile == 0 || nkt * per_tile < (1ll << 31)) return 0;
   return (uint32_t)(((1ll << 31) - 1 - (p - 1)) / per_tile);
+}
+
+// Fused INT8 tiles hold the multiplication-matrix table in LDS beside their
+// operand tiles: admissible when both fit one CU's LDS.
+static bool i8f_fits(const fqt_field_s* f, uint32_t tile) {
+  const size_t table = ((size_t)1 << f->tbl_log2) * mt_stride(f->k);
+  const size_t st = i8f_static_lds((int)tile, (int)f->k);
+  return st > 0 && st + table <= kLdsBytes;
+}
+
+static I8Args i8_args(const fqt_field_s* f, const uint8_t* A, int64_t lda, uint8_t* C,
+                      int64_t ldc, int64_t M, int64_t N, int64_t K, int64_t bkk) {
+  const int64_t k = f->k, p = f->p;
+  I8Args a{};
+  a.A = A;
+  a.lda = lda * k;
+  a.C = C;
+  a.ldc = ldc * k;
+  a.M = M;
+  a.NN = N * k;
+  a.KK = K * k;
+  a.p = (uint32_t)p;
+  a.red_tiles = i8_red_tiles(K * k, p, bkk);
+  a.a_vec = row_align(A, a.lda);
+  a.inv_p = 1.0 / (double)p;
+  return a;
+}
+
+// Fused INT8 tiles: one kernel, B'^T built per K-tile in LDS.
+static fqt_status gemm_int8_fused(fqt_field f, uint32_t tile, const GemmArgs& g, hipStream_t s) {
+  const int k = (int)f->k;
+  if (!i8f_fits(f, tile))
+    return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u: operand tiles and the %u-bit table exceed "
+                "the LDS", tile, f->tbl_log2);
+  uint8_t* mt = nullptr;
+  fqt_status st = device_mt(f, &mt);
+  if (st) return st;
+  I8Batch b{};
+  b.a = i8_args(f, g.A, g.lda, g.C, g.ldc, g.M, g.N, g.K, i8f_k_bytes(k));
+  b.B = g.B;
+  b.ldb = g.ldb;
+  b.K = g.K;
+  b.N = g.N;
+  FQT_HIP(launch_gemm_i8f((int)tile, k, b, mt, f->cb, f->tbl_log2, s));
+  return ok();
 }
 
 // INT8 path: exact while n_d (p-1)^2 < 2^31 per accumulation run (eq. (3)).
@@ -1297,6 +1342,7 @@ static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmAr
   const int64_t k = f->k, p = f->p;
   uint32_t tile = (opts && opts->tile) ? opts->tile : 0;
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
+  if (tile >= (uint32_t)kFirstFusedI8Tile) return gemm_int8_fused(f, tile, g, s);
   // B'^T rows are padded to whole 128-byte K-tiles of the INT8 GEMM
   const int64_t NN = g.N * k, KK = g.K * k, KKpad = (KK + 127) / 128 * 128;
   if (!tile) tile = (g.M >= 1024 && NN >= 1024) ? 2 : 1;
@@ -1652,10 +1698,68 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
   uint8_t* mt = nullptr;  // before taking the field lock (device_mt takes it)
   fqt_status mst = device_mt(f, &mt);
   if (mst) return mst;
+  const bool fused = tile >= (uint32_t)kFirstFusedI8Tile;
+  if (fused && !i8f_fits(f, tile))
+    return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u: operand tiles and the %u-bit table exceed "
+                "the LDS", tile, f->tbl_log2);
   std::lock_guard<std::mutex> lk(f->mu);
   BatchPlan* plan = nullptr;
   for (auto& pp : f->plans)
     if (pp->key == key) plan = pp.get();
+  if (!plan && fused) {
+    // one persistent kernel over every product's tiles, no B' workspace
+    const int bm = i8f_tile_m((int)tile), bne = i8f_tile_n((int)tile, (int)k);
+    std::vector<I8Batch> gs(count);
+    std::vector<TileItem> items;
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      I8Batch& b = gs[i];
+      b.a = i8_args(f, d.A, d.lda, d.C, d.ldc, d.M, d.N, d.K, i8f_k_bytes((int)k));
+      b.B = d.B;
+      b.ldb = d.ldb;
+      b.K = d.K;
+      b.N = d.N;
+      const int tm = (int)((d.M + bm - 1) / bm), tn = (int)((d.N + bne - 1) / bne);
+      for (int a = 0; a < tm; ++a)
+        for (int c = 0; c < tn; ++c) items.push_back(TileItem{(int32_t)i, a, c, 0});
+    }
+    std::stable_sort(items.begin(), items.end(), [&](const TileItem& x, const TileItem& y) {
+      return descs[x.gemm].K > descs[y.gemm].K;
+    });
+    auto pl = std::make_unique<BatchPlan>();
+    pl->key = key;
+    pl->device = dev;
+    pl->n_items = (int32_t)items.size();
+    FQT_HIP(hipMalloc(&pl->d_i8, sizeof(I8Batch) * count));
+    FQT_HIP(hipMalloc(&pl->d_items, sizeof(TileItem) * std::max<size_t>(items.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_counter, 2 * sizeof(uint32_t)));
+    FQT_HIP(hipMemcpy(pl->d_i8, gs.data(), sizeof(I8Batch) * count, hipMemcpyHostToDevice));
+    if (!items.empty())
+      FQT_HIP(hipMemcpy(pl->d_items, items.data(), sizeof(TileItem) * items.size(),
+                        hipMemcpyHostToDevice));
+    FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
+    hipDeviceProp_t prop;
+    FQT_HIP(hipGetDeviceProperties(&prop, dev));
+    pl->grid = std::max(
+        1, std::min<int>(prop.multiProcessorCount *
+                             i8f_batched_occupancy((int)tile, (int)k, f->tbl_log2),
+                         std::max<int32_t>(pl->n_items, 1)));
+    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    if (pl->n_items > 0)
+      le = launch_gemm_i8f_batched((int)tile, (int)k, pl->d_i8, pl->d_items, pl->n_items,
+                                   pl->d_counter, pl->grid, mt, f->cb, f->tbl_log2,
+                                   pl->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (le != hipSuccess) return hip_fail(le, "fused INT8 batched launch (capture)");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    pl->graph = graph;
+    FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
+    plan = pl.get();
+    f->plans.push_back(std::move(pl));
+  }
   if (!plan) {
     const int bm = tile == 2 ? 128 : 64, bn = tile == 1 ? 64 : 128;
     std::vector<I8Batch> gs(count);
@@ -1742,6 +1846,7 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
     plan = pl.get();
     f->plans.push_back(std::move(pl));
   }
+  if (fused && plan->n_items == 0) return ok();  // nothing captured
   FQT_HIP(hipGraphLaunch(plan->exec, s));
   return ok();
 }
@@ -1947,7 +2052,8 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
     }
   if (only != FQT_PATH_PACKED_F64)
     for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
-      cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0, 0}});
+      if (t < (uint32_t)kFirstFusedI8Tile || i8f_fits(f, t))
+        cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0, 0}});
   if (cands.empty()) return fail(FQT_ERR_UNSUPPORTED, "no admissible candidate");
 
   hipStream_t st = (hipStream_t)s;

@@ -210,8 +210,11 @@ hipError_t launch_gemm_split_batched(int k, int tile, const GemmArgs* descs,
                                      int grid, const PackedParams& pp, hipStream_t s);
 int split_batched_occupancy(int k, int tile, uint32_t tbl_log2);
 
-// INT8 path: B -> B'^T expansion, then the INT8 MFMA GEMM (tile ids 1..3).
-constexpr int kInt8Tiles = 3;
+// INT8 path, tile ids 1..3: B -> B'^T expansion in HBM, then the INT8 MFMA
+// GEMM; ids 4..6: one kernel that expands each K-tile of B in LDS.
+constexpr int kInt8Tiles = 6;
+constexpr int kFirstFusedI8Tile = 4;
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 CU
 hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
                            const uint8_t* mt, uint32_t cb, uint32_t tbl_log2, uint8_t* Bt,
                            int64_t ldbt, int64_t Kpad, hipStream_t s);
@@ -222,6 +225,20 @@ hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* i
 hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* items,
                                   int32_t n_items, uint32_t* counter, int grid, hipStream_t s);
 int i8_batched_occupancy(int tile);
+// Fused tiles (ids 4..6): bytes of K per K-tile, elements of N per output
+// tile, rows of M per output tile, and static LDS bytes (the dynamic part is
+// the multiplication-matrix table, 2^tbl_log2 entries of mt_stride(k)).
+int i8f_k_bytes(int k);
+int i8f_tile_n(int tile, int k);
+int i8f_tile_m(int tile);
+size_t i8f_static_lds(int tile, int k);
+hipError_t launch_gemm_i8f(int tile, int k, const I8Batch& g, const uint8_t* mt, uint32_t cb,
+                           uint32_t tbl_log2, hipStream_t s);
+hipError_t launch_gemm_i8f_batched(int tile, int k, const I8Batch* gs, const TileItem* items,
+                                   int32_t n_items, uint32_t* counter, int grid,
+                                   const uint8_t* mt, uint32_t cb, uint32_t tbl_log2,
+                                   hipStream_t s);
+int i8f_batched_occupancy(int tile, int k, uint32_t tbl_log2);
 
 // d-FQT (ke = d + 1 in 1..8, mode 0/1/2 as in fqt_packed.h) and its comparator.
 hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s);

@@ -312,7 +312,7 @@ def test_gemm_batched_replay():
         torch.cuda.synchronize()
         for c, w in zip(Cs, wants):
             assert np.array_equal(host(c), w)
-    for tile in (1, 2, 3):
+    for tile in (1, 2, 3, 4, 5, 6):
         for rep in range(2):
             note(f"batched int8 tile {tile} replay {rep}")
             for c in Cs:
@@ -332,7 +332,7 @@ def test_gemm_batched_replay():
 # ---- INT8 coefficient-wise path -------------------------------------------------
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
 def test_gemm_int8_shapes(p, k, P, tile):
     for (M, N, K) in SHAPES + [(130, 200, 257)]:
         note(f"gemm int8 GF({p}^{k}) tile={tile} {M}x{N}x{K}")
@@ -342,33 +342,53 @@ def test_gemm_int8_shapes(p, k, P, tile):
 
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-def test_gemm_int8_adversarial(p, k, P):
-    note(f"gemm int8 adversarial GF({p}^{k})")
-    C, want = _gemm_case(p, k, P, 40, 50, 3001, seed=0, adversarial=True, path="int8")
+@pytest.mark.parametrize("tile", [None, 4])
+def test_gemm_int8_adversarial(p, k, P, tile):
+    note(f"gemm int8 adversarial GF({p}^{k}) tile={tile}")
+    C, want = _gemm_case(p, k, P, 40, 50, 3001, seed=0, adversarial=True, path="int8",
+                         opts={"tile": tile} if tile else None)
     assert np.array_equal(C, want)
 
 
-def test_gemm_int8_delayed_reduction_gf61_2():
+@pytest.mark.parametrize("tile", [None, 4])
+def test_gemm_int8_delayed_reduction_gf61_2(tile):
     # K k (p-1)^2 far above 2^31: the INT32 accumulators are reduced mod p
     # every few thousand K-tiles (eq. (3) with n_d (p-1)^2 < 2^31).
     p, P = 61, (59, 0)   # X^2 - 2, irreducible since 2 is a non-residue mod 61
     assert gf.is_irreducible(P, p)
-    note("gemm int8 delayed reduction GF(61^2) K=300000")
+    note(f"gemm int8 delayed reduction GF(61^2) K=300000 tile={tile}")
     for adversarial in (True, False):
         C, want = _gemm_case(p, 2, P, 16, 24, 300000, seed=5, adversarial=adversarial,
-                             path="int8")
+                             path="int8", opts={"tile": tile} if tile else None)
         assert np.array_equal(C, want)
 
 
-def test_gemm_int8_strided_unaligned():
+@pytest.mark.parametrize("tile", [None, 4, 5, 6])
+def test_gemm_int8_strided_unaligned(tile):
     p, k, P = 5, 3, (3, 3, 0)
     f = fqt.Field(p, k, P)
     rng = np.random.default_rng(19)
     Abig = rng.integers(0, p, size=(70, 93, k), dtype=np.uint8)
     Bbig = rng.integers(0, p, size=(93, 75, k), dtype=np.uint8)
-    note("gemm int8 strided/unaligned")
-    C = host(fqt.gemm(f, dev(Abig)[:50, :61], dev(Bbig)[:61, :40], path="int8"))
+    note(f"gemm int8 strided/unaligned tile={tile}")
+    C = host(fqt.gemm(f, dev(Abig)[:50, :61], dev(Bbig)[:61, :40], path="int8",
+                      opts={"tile": tile} if tile else None))
     assert np.array_equal(C, gf.gemm_gfpk_planes(Abig[:50, :61], Bbig[:61, :40], p, P))
+
+
+def test_gemm_int8_fused_table_too_large():
+    # GF(13^3): 12-bit table index, 4096 entries of 16 bytes beside the
+    # 128 x 128 operand tiles of id 5 exceed the LDS; id 4 fits
+    p, k, P = 13, 3, (1, 0, 4)
+    assert gf.is_irreducible(P, p)
+    f = fqt.Field(p, k, P)
+    rng = np.random.default_rng(23)
+    A = rng.integers(0, p, size=(70, 90, k), dtype=np.uint8)
+    B = rng.integers(0, p, size=(90, 50, k), dtype=np.uint8)
+    with pytest.raises(fqt.FqtError):
+        fqt.gemm(f, dev(A), dev(B), path="int8", opts={"tile": 5})
+    C = host(fqt.gemm(f, dev(A), dev(B), path="int8", opts={"tile": 4}))
+    assert np.array_equal(C, gf.gemm_gfpk_planes(A, B, p, P))
 
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
