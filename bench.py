@@ -112,6 +112,50 @@ def cpu_baseline_gemm(w, A, B, gf, target_s=15.0):
                       f"numpy int64 plane products, {dt:.1f} s"}
 
 
+def _sized_run(fn, units_total, first, target_s):
+    """Time fn(n) on a bounded prefix: a first run on `first` units sizes a
+    second one to about target_s seconds (never more than units_total)."""
+    n = min(first, units_total)
+    t0 = time.time()
+    fn(n)
+    dt = time.time() - t0
+    n = int(max(n, min(units_total, n * target_s / max(dt, 1e-3))))
+    t0 = time.time()
+    out = fn(n)
+    return n, time.time() - t0, out
+
+
+def cpu_plain_gemm(w, A, B, Rh, target_s):
+    """The multi-core C schoolbook comparator (oracle/plain_gf.c) on a row
+    prefix of the same product; its rows are checked against the GPU's."""
+    from oracle import plain_c
+    rows, dt, C = _sized_run(lambda r: plain_c.gemm(A[:r], B, w.p, w.P_low), A.shape[0], 16,
+                             target_s)
+    return {"value": rows * B.shape[1] * A.shape[1] / dt, "unit": "field mul-adds/s",
+            "cores": plain_c.threads_used(), "kind": "plain schoolbook, C + OpenMP",
+            "sample": f"first {rows} rows of A times all of B, {dt:.1f} s",
+            "identical_to_gpu_rows": bool(np.array_equal(C, Rh[:rows]))}
+
+
+def cpu_batched(w, As, Bs, mnk, gf, target_s):
+    """The oracle and the C comparator on a prefix of the batch's products."""
+    from oracle import plain_c
+    cum = np.cumsum(mnk[:, 0] * mnk[:, 1] * mnk[:, 2])
+    out = {}
+    n, dt, _ = _sized_run(lambda c: [gf.gemm_gfpk_planes(a, b, w.p, w.P_low)
+                                     for a, b in zip(As[:c], Bs[:c])], len(As), 8, target_s)
+    out["cpu_baseline"] = {"value": float(cum[n - 1]) / dt, "unit": "field mul-adds/s",
+                           "cores": 1, "kind": "oracle",
+                           "sample": f"first {n} of the {len(As)} products, numpy int64 plane "
+                                     f"products, {dt:.1f} s"}
+    n, dt, _ = _sized_run(lambda c: plain_c.gemm_batched(As[:c], Bs[:c], w.p, w.P_low),
+                          len(As), 16, min(target_s, 8.0))
+    out["cpu_plain"] = {"value": float(cum[n - 1]) / dt, "unit": "field mul-adds/s",
+                        "cores": plain_c.threads_used(), "kind": "plain schoolbook, C + OpenMP",
+                        "sample": f"first {n} of the {len(As)} products, {dt:.1f} s"}
+    return out
+
+
 # Kernel that carries a packed step, by tile id (1..6 LDS-staged, 7..12 direct).
 def packed_kernel_name(tile):
     if tile and tile >= 13:
@@ -291,6 +335,7 @@ def bench_gemm(w, args, torch, fqt, gf):
         out["speedup_vs_plain"] = results["plain"]["ms_per_step"] / main_r["ms_per_step"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_gemm(w, A_h, B_h, gf, target_s=args.cpu_seconds)
+        out["cpu_plain"] = cpu_plain_gemm(w, A_h, B_h, Rh, target_s=min(args.cpu_seconds, 8.0))
     return out
 
 
@@ -385,6 +430,8 @@ def bench_batched(w, args, torch, fqt, gf):
                    "identical_to_plain_path": True},
     }
     out["roofline"]["kernel"] = "persistent batched " + out["roofline"]["kernel"]
+    if not args.no_cpu:
+        out.update(cpu_batched(w, As, Bs, mnk, gf, args.cpu_seconds))
     return out
 
 
@@ -403,6 +450,22 @@ def bench_polymul(w, args, torch, fqt, gf):
     work = w.n * w.k * w.k
     nbytes = w.n * (2 * w.k + 2 * w.k - 1)
     ach = nbytes / (ms * 1e-3)
+    cpu = {}
+    if not args.no_cpu:
+        from oracle import plain_c
+        t0 = time.time()
+        gf.polymul_batch(a_h, b_h, w.p)
+        dt = max(time.time() - t0, 1e-6)
+        cpu["cpu_baseline"] = {"value": work / dt, "unit": "GF(p) mul-adds/s", "cores": 1,
+                               "kind": "oracle", "sample": f"all {w.n} products, numpy int64, "
+                                                           f"{dt:.3f} s"}
+        t0 = time.time()
+        cp = plain_c.polymul_batch(a_h, b_h, w.p)
+        dt = max(time.time() - t0, 1e-6)
+        cpu["cpu_plain"] = {"value": work / dt, "unit": "GF(p) mul-adds/s",
+                            "cores": plain_c.threads_used(), "kind": "plain schoolbook, C + OpenMP",
+                            "sample": f"all {w.n} products, {dt:.3f} s",
+                            "identical_to_gpu": bool(np.array_equal(cp, c.cpu().numpy()))}
     return {
         "metric": METRIC, "value": work / (ms * 1e-3), "unit": "GF(p) mul-adds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
@@ -413,6 +476,7 @@ def bench_polymul(w, args, torch, fqt, gf):
                      "frac": ach / PEAK_HBM, "traffic": None, "kernel": "polymul_kernel",
                      "algorithmic": f"{2 * w.k} B in + {2 * w.k - 1} B out per product"},
         "parity": {"full_output_vs_oracle": True},
+        **cpu,
     }
 
 
