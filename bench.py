@@ -112,14 +112,19 @@ def cpu_baseline_gemm(w, A, B, gf, target_s=15.0):
                       f"numpy int64 plane products, {dt:.1f} s"}
 
 
-def _sized_run(fn, units_total, first, target_s):
+def _sized_run(fn, units_total, first, target_s, cum=None):
     """Time fn(n) on a bounded prefix: a first run on `first` units sizes a
-    second one to about target_s seconds (never more than units_total)."""
+    second one to about target_s seconds (never more than units_total).
+    cum[i], when given, is the work of the first i + 1 units."""
     n = min(first, units_total)
     t0 = time.time()
     fn(n)
-    dt = time.time() - t0
-    n = int(max(n, min(units_total, n * target_s / max(dt, 1e-3))))
+    dt = max(time.time() - t0, 1e-3)
+    if cum is None:
+        n = int(max(n, min(units_total, n * target_s / dt)))
+    else:
+        want = cum[n - 1] * target_s / dt
+        n = int(max(n, min(units_total, np.searchsorted(cum, want) + 1)))
     t0 = time.time()
     out = fn(n)
     return n, time.time() - t0, out
@@ -143,13 +148,14 @@ def cpu_batched(w, As, Bs, mnk, gf, target_s):
     cum = np.cumsum(mnk[:, 0] * mnk[:, 1] * mnk[:, 2])
     out = {}
     n, dt, _ = _sized_run(lambda c: [gf.gemm_gfpk_planes(a, b, w.p, w.P_low)
-                                     for a, b in zip(As[:c], Bs[:c])], len(As), 8, target_s)
+                                     for a, b in zip(As[:c], Bs[:c])], len(As), 8, target_s,
+                          cum)
     out["cpu_baseline"] = {"value": float(cum[n - 1]) / dt, "unit": "field mul-adds/s",
                            "cores": 1, "kind": "oracle",
                            "sample": f"first {n} of the {len(As)} products, numpy int64 plane "
                                      f"products, {dt:.1f} s"}
     n, dt, _ = _sized_run(lambda c: plain_c.gemm_batched(As[:c], Bs[:c], w.p, w.P_low),
-                          len(As), 16, min(target_s, 8.0))
+                          len(As), 64, min(target_s, 8.0), cum)
     out["cpu_plain"] = {"value": float(cum[n - 1]) / dt, "unit": "field mul-adds/s",
                         "cores": plain_c.threads_used(), "kind": "plain schoolbook, C + OpenMP",
                         "sample": f"first {n} of the {len(As)} products, {dt:.1f} s"}
