@@ -181,7 +181,8 @@ def roofline_for(path, k, work, ms, tile=0):
         ach = ops / (ms * 1e-3)
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_INT8 / 1e12,
                 "unit": "TOP/s", "frac": ach / PEAK_INT8, "traffic": None,
-                "kernel": "gemm_i8_kernel (+ expand_b_kernel in the step)",
+                "kernel": ("gemm_i8f_kernel (B' built in LDS)" if tile >= 4 else
+                           "gemm_i8_kernel (+ expand_b_kernel in the step)"),
                 "algorithmic": "2 k^2 int8 ops per field mul-add"}
     if path == "plain":
         ops = 2.0 * k * k * work
