@@ -1342,7 +1342,7 @@ static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmAr
   const int64_t k = f->k, p = f->p;
   uint32_t tile = (opts && opts->tile) ? opts->tile : 0;
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
-  if (tile >= (uint32_t)kFirstFusedI8Tile) return gemm_int8_fused(f, tile, g, s);
+  if (i8_fused_tile(tile)) return gemm_int8_fused(f, tile, g, s);
   // B'^T rows are padded to whole 128-byte K-tiles of the INT8 GEMM
   const int64_t NN = g.N * k, KK = g.K * k, KKpad = (KK + 127) / 128 * 128;
   if (!tile) tile = (g.M >= 1024 && NN >= 1024) ? 2 : 1;
@@ -1698,7 +1698,7 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
   uint8_t* mt = nullptr;  // before taking the field lock (device_mt takes it)
   fqt_status mst = device_mt(f, &mt);
   if (mst) return mst;
-  const bool fused = tile >= (uint32_t)kFirstFusedI8Tile;
+  const bool fused = i8_fused_tile(tile);
   if (fused && !i8f_fits(f, tile))
     return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u: operand tiles and the %u-bit table exceed "
                 "the LDS", tile, f->tbl_log2);
@@ -1761,7 +1761,7 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
     f->plans.push_back(std::move(pl));
   }
   if (!plan) {
-    const int bm = tile == 2 ? 128 : 64, bn = tile == 1 ? 64 : 128;
+    const int bm = i8_tile_m((int)tile), bn = i8_tile_n((int)tile);
     std::vector<I8Batch> gs(count);
     std::vector<ExpandItem> exps;
     std::vector<TileItem> items;
@@ -2052,7 +2052,7 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
     }
   if (only != FQT_PATH_PACKED_F64)
     for (uint32_t t = 1; t <= (uint32_t)kInt8Tiles; ++t)
-      if (t < (uint32_t)kFirstFusedI8Tile || i8f_fits(f, t))
+      if (!i8_fused_tile(t) || i8f_fits(f, t))
         cands.push_back({FQT_PATH_INT8, fqt_gemm_opts{0, 0, t, 0, 0}});
   if (cands.empty()) return fail(FQT_ERR_UNSUPPORTED, "no admissible candidate");
 

@@ -312,7 +312,7 @@ def test_gemm_batched_replay():
         torch.cuda.synchronize()
         for c, w in zip(Cs, wants):
             assert np.array_equal(host(c), w)
-    for tile in (1, 2, 3, 4, 5, 6):
+    for tile in (1, 2, 3, 4, 5, 6, 7, 8):
         for rep in range(2):
             note(f"batched int8 tile {tile} replay {rep}")
             for c in Cs:
@@ -332,7 +332,7 @@ def test_gemm_batched_replay():
 # ---- INT8 coefficient-wise path -------------------------------------------------
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_gemm_int8_shapes(p, k, P, tile):
     for (M, N, K) in SHAPES + [(130, 200, 257)]:
         note(f"gemm int8 GF({p}^{k}) tile={tile} {M}x{N}x{K}")
@@ -342,7 +342,7 @@ def test_gemm_int8_shapes(p, k, P, tile):
 
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-@pytest.mark.parametrize("tile", [None, 4])
+@pytest.mark.parametrize("tile", [None, 4, 7])
 def test_gemm_int8_adversarial(p, k, P, tile):
     note(f"gemm int8 adversarial GF({p}^{k}) tile={tile}")
     C, want = _gemm_case(p, k, P, 40, 50, 3001, seed=0, adversarial=True, path="int8",
@@ -350,7 +350,7 @@ def test_gemm_int8_adversarial(p, k, P, tile):
     assert np.array_equal(C, want)
 
 
-@pytest.mark.parametrize("tile", [None, 4])
+@pytest.mark.parametrize("tile", [None, 4, 8])
 def test_gemm_int8_delayed_reduction_gf61_2(tile):
     # K k (p-1)^2 far above 2^31: the INT32 accumulators are reduced mod p
     # every few thousand K-tiles (eq. (3) with n_d (p-1)^2 < 2^31).
@@ -363,7 +363,7 @@ def test_gemm_int8_delayed_reduction_gf61_2(tile):
         assert np.array_equal(C, want)
 
 
-@pytest.mark.parametrize("tile", [None, 4, 5, 6])
+@pytest.mark.parametrize("tile", [None, 4, 5, 6, 7, 8])
 def test_gemm_int8_strided_unaligned(tile):
     p, k, P = 5, 3, (3, 3, 0)
     f = fqt.Field(p, k, P)
