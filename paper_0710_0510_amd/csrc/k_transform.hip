@@ -215,42 +215,97 @@ hipError_t launch_unpack_u64(int k, uint32_t nd, int mode, uint64_t q, int pow2,
 
 // ---- Alg. 1 on a batch of polynomial pairs -----------------------------------
 
-__global__ __launch_bounds__(kTB) void polymul_kernel(const uint8_t* __restrict__ a,
-                                                      const uint8_t* __restrict__ bb, size_t n,
-                                                      int k, RedqArgs ra,
-                                                      uint8_t* __restrict__ c) {
-  __shared__ uint8_t sa[kTB * 8];
-  __shared__ uint8_t sb[kTB * 8];
-  __shared__ uint8_t sc[kTB * 15];
-  const size_t base = (size_t)blockIdx.x * kTB;
-  stage_in(sa, a, base * k, (size_t)kTB * k, n * k);
-  stage_in(sb, bb, base * k, (size_t)kTB * k, n * k);
+// 16-byte staging for the batched products: whole uint4 transfers where the
+// global range is 16-byte aligned, the dword/byte copies above otherwise.
+__device__ __forceinline__ void stage_in16(uint8_t* lds, const uint8_t* g, size_t off,
+                                           size_t len, size_t total) {
+  if ((((uintptr_t)(g + off)) & 15) != 0 || (len & 15) != 0) {
+    stage_in(lds, g, off, len, total);
+    return;
+  }
+  const size_t nc = len >> 4;
+  for (size_t i = threadIdx.x; i < nc; i += blockDim.x) {
+    uint4 v;
+    if (off + 16 * i + 15 < total) {
+      v = reinterpret_cast<const uint4*>(g + off)[i];
+    } else {
+      uint32_t w[4] = {0, 0, 0, 0};
+      for (int j = 0; j < 16; ++j)
+        if (off + 16 * i + j < total) w[j >> 2] |= (uint32_t)g[off + 16 * i + j] << (8 * (j & 3));
+      v = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    reinterpret_cast<uint4*>(lds)[i] = v;
+  }
+}
+
+__device__ __forceinline__ void stage_out16(uint8_t* g, const uint8_t* lds, size_t off,
+                                            size_t len, size_t total) {
+  if ((((uintptr_t)(g + off)) & 15) != 0 || (len & 15) != 0) {
+    stage_out(g, lds, off, len, total);
+    return;
+  }
+  const size_t lim = off + len < total ? len : (off < total ? total - off : 0);
+  const size_t nc = lim >> 4;
+  for (size_t i = threadIdx.x; i < nc; i += blockDim.x)
+    reinterpret_cast<uint4*>(g + off)[i] = reinterpret_cast<const uint4*>(lds)[i];
+  for (size_t i = 16 * nc + threadIdx.x; i < lim; i += blockDim.x) g[off + i] = lds[i];
+}
+
+// K coefficients per operand known at compile time; every workgroup takes
+// kPM = 4 kTB pairs (each thread four), so the HBM transfers are 16-byte
+// runs and the digit loops unroll.
+constexpr int kPM = 4 * kTB;
+
+template <int K>
+__global__ __launch_bounds__(kTB) void polymul_k_kernel(const uint8_t* __restrict__ a,
+                                                        const uint8_t* __restrict__ bb,
+                                                        size_t n, RedqArgs ra,
+                                                        uint8_t* __restrict__ c) {
+  constexpr int ND = 2 * K - 1;
+  __shared__ __align__(16) uint8_t sa[kPM * K];
+  __shared__ __align__(16) uint8_t sb[kPM * K];
+  __shared__ __align__(16) uint8_t sc[kPM * ND];
+  const size_t base = (size_t)blockIdx.x * kPM;
+  stage_in16(sa, a, base * K, (size_t)kPM * K, n * K);
+  stage_in16(sb, bb, base * K, (size_t)kPM * K, n * K);
   __syncthreads();
-  const int nd = 2 * k - 1;
-  const size_t i = base + threadIdx.x;
-  if (i < n) {
-    const double qd = (double)ra.q;
-    const double va = dqt_eval(sa + threadIdx.x * k, k, ra.pow2, ra.b, qd);
-    const double vb = dqt_eval(sb + threadIdx.x * k, k, ra.pow2, ra.b, qd);
-    const double r = va * vb;  // Alg. 1 step 2: exact, r < q^(2k-1) < 2^53
-    uint32_t u[16];
-    redq_residues<false>((uint64_t)r, nd, ra, u);
-    uint8_t* dst = sc + threadIdx.x * nd;
-    for (int d = 0; d < nd - 1; ++d) dst[d] = (uint8_t)modp(u[d] + ra.c * u[d + 1], ra);
-    dst[nd - 1] = (uint8_t)u[nd - 1];
+  const double qd = (double)ra.q;
+#pragma unroll
+  for (int j = 0; j < kPM / kTB; ++j) {
+    const int t = threadIdx.x + j * kTB;
+    if (base + t < n) {
+      const double va = dqt_eval(sa + t * K, K, ra.pow2, ra.b, qd);
+      const double vb = dqt_eval(sb + t * K, K, ra.pow2, ra.b, qd);
+      const double r = va * vb;  // Alg. 1 step 2: exact, r < q^(2k-1) < 2^53
+      uint32_t u[ND];
+      redq_residues<false>((uint64_t)r, ND, ra, u);
+      uint8_t* dst = sc + t * ND;
+#pragma unroll
+      for (int d = 0; d < ND - 1; ++d) dst[d] = (uint8_t)modp(u[d] + ra.c * u[d + 1], ra);
+      dst[ND - 1] = (uint8_t)u[ND - 1];
+    }
   }
   __syncthreads();
-  stage_out(c, sc, base * nd, (size_t)kTB * nd, n * nd);
+  stage_out16(c, sc, base * ND, (size_t)kPM * ND, n * ND);
 }
 
 hipError_t launch_polymul(int k, uint64_t q, int pow2, uint32_t b, const FieldArgs& fa,
                           const uint8_t* a, const uint8_t* bb, size_t n, uint8_t* c,
                           hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const size_t grid = (n + kTB - 1) / kTB;
-  hipLaunchKernelGGL(polymul_kernel, dim3((unsigned)grid), dim3(kTB), 0, s, a, bb, n, k,
-                     make_redq(q, pow2, b, fa), c);
-  return hipGetLastError();
+  const RedqArgs ra = make_redq(q, pow2, b, fa);
+  const size_t gk = (n + kPM - 1) / kPM;
+  switch (k) {
+#define FQT_PM_CASE(K)                                                                   \
+  case K:                                                                                \
+    hipLaunchKernelGGL(polymul_k_kernel<K>, dim3((unsigned)gk), dim3(kTB), 0, s, a, bb, n, \
+                       ra, c);                                                           \
+    return hipGetLastError();
+    FQT_PM_CASE(1) FQT_PM_CASE(2) FQT_PM_CASE(3) FQT_PM_CASE(4)
+    FQT_PM_CASE(5) FQT_PM_CASE(6) FQT_PM_CASE(7) FQT_PM_CASE(8)
+#undef FQT_PM_CASE
+    default: return hipErrorInvalidValue;  // k is checked on the host (1..8)
+  }
 }
 
 }  // namespace fqt

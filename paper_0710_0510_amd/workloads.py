@@ -56,6 +56,9 @@ class Workload:
 
 WORKLOADS = {
     "polymul-gf5-k3": Workload("polymul-gf5-k3", "polymul", 5, 3, (), seed=1, n=65536, q=64),
+    # the same products scaled to 2^24 pairs: large enough to stream at HBM rate
+    "polymul-gf5-k3-2^24": Workload("polymul-gf5-k3-2^24", "polymul", 5, 3, (), seed=1,
+                                    n=1 << 24, q=64),
     "gemm-gf7^2-1024": Workload("gemm-gf7^2-1024", "gemm", 7, 2, GF7_2.P_low, seed=2,
                                 M=1024, N=1024, K=1024),
     "batched-gf3^4-4096": Workload("batched-gf3^4-4096", "batched", 3, 4, GF3_4.P_low,

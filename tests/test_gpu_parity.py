@@ -54,11 +54,12 @@ def test_polymul_cfg1_exhaustive():
     assert np.array_equal(out, gf.polymul_batch(a, b, p))
 
 
-def test_polymul_cfg1_workload():
+@pytest.mark.parametrize("name", ["polymul-gf5-k3", "polymul-gf5-k3-2^24"])
+def test_polymul_cfg1_workload(name):
     from paper_0710_0510_amd import workloads as W
-    w = W.WORKLOADS["polymul-gf5-k3"]
+    w = W.WORKLOADS[name]
     a, b = W.polymul_inputs(w)
-    note("polymul workload 65536")
+    note(f"polymul workload {name}")
     out = host(fqt.polymul_batch(w.p, w.k, w.q, dev(a), dev(b)))
     assert np.array_equal(out, gf.polymul_batch(a, b, w.p))
 
@@ -85,6 +86,23 @@ def test_polymul_params(p, k, q, n):
     b[0] = p - 1
     out = host(fqt.polymul_batch(p, k, q, dev(a), dev(b)))
     assert np.array_equal(out, gf.polymul_batch(a, b, p))
+
+
+@pytest.mark.parametrize("p,k,q,n", [(3, 3, 256, 2049), (3, 4, 64, 1024), (2, 8, 9, 1025),
+                                     (5, 1, 2 ** 20, 5000)])
+def test_polymul_unaligned_views(p, k, q, n):
+    # operands and output start one row into their buffers (k and 2k - 1
+    # bytes: not 16-byte aligned), and the batch ends inside a workgroup
+    assert gf.eq2_holds(p, k, q, 1)
+    note(f"polymul unaligned views k={k} n={n}")
+    rng = np.random.default_rng(k * 7 + n)
+    a = rng.integers(0, p, size=(n + 1, k), dtype=np.uint8)
+    b = rng.integers(0, p, size=(n + 1, k), dtype=np.uint8)
+    cbig = torch.full((n + 1, 2 * k - 1), 255, dtype=torch.uint8, device="cuda")
+    fqt.polymul_batch(p, k, q, dev(a)[1:], dev(b)[1:], out=cbig[1:])
+    got = host(cbig)
+    assert np.array_equal(got[1:], gf.polymul_batch(a[1:], b[1:], p))
+    assert (got[0] == 255).all()  # nothing written before the output view
 
 
 def test_polymul_empty():
