@@ -39,6 +39,9 @@ MEASURED_TRAFFIC = {
     ("gemm-gf7^2-1024", "packed", 12): {
         "bytes": 14_993_408,  # FETCH 6297 KiB x 2.000 + WRITE 2048 KiB x 1.000
         "source": "profiles/gemm_direct_gf7-2_1024.md"},
+    ("polymul-gf5-k3-2^24", "polymul"): {
+        "bytes": 184_764_621,  # FETCH 49257.1 KiB x 2.000 + WRITE 81920 KiB x 1.000
+        "source": "profiles/polymul_gf5_k3_2-24.md"},
     ("dfqt-gf3-n500-d4", "dfqt", 4, 1): {
         "bytes": 34_088_960,  # FETCH 8581.0 KiB x 2.000 + WRITE 16128 KiB x 1.000
         "source": "profiles/dfqt_gf3_n500_d4.md"},
@@ -480,7 +483,9 @@ def bench_polymul(w, args, torch, fqt, gf):
         "config": {"workload": w.name, "p": w.p, "k": w.k, "q": w.q, "n": w.n, "seed": w.seed},
         "products_per_s": w.n / (ms * 1e-3),
         "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                     "frac": ach / PEAK_HBM, "traffic": None, "kernel": "polymul_kernel",
+                     "frac": ach / PEAK_HBM,
+                     "traffic": (MEASURED_TRAFFIC.get((w.name, "polymul")) or {}).get("bytes"),
+                     "kernel": f"polymul_k_kernel<{w.k}>",
                      "algorithmic": f"{2 * w.k} B in + {2 * w.k - 1} B out per product"},
         "parity": {"full_output_vs_oracle": True},
         **cpu,
