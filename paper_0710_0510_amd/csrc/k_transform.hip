@@ -59,6 +59,42 @@ __device__ __forceinline__ void stage_out(uint8_t* g, const uint8_t* lds, size_t
   }
 }
 
+// 16-byte staging (batched products, REDQ unpack): whole uint4 transfers where the
+// global range is 16-byte aligned, the dword/byte copies above otherwise.
+__device__ __forceinline__ void stage_in16(uint8_t* lds, const uint8_t* g, size_t off,
+                                           size_t len, size_t total) {
+  if ((((uintptr_t)(g + off)) & 15) != 0 || (len & 15) != 0) {
+    stage_in(lds, g, off, len, total);
+    return;
+  }
+  const size_t nc = len >> 4;
+  for (size_t i = threadIdx.x; i < nc; i += blockDim.x) {
+    uint4 v;
+    if (off + 16 * i + 15 < total) {
+      v = reinterpret_cast<const uint4*>(g + off)[i];
+    } else {
+      uint32_t w[4] = {0, 0, 0, 0};
+      for (int j = 0; j < 16; ++j)
+        if (off + 16 * i + j < total) w[j >> 2] |= (uint32_t)g[off + 16 * i + j] << (8 * (j & 3));
+      v = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    reinterpret_cast<uint4*>(lds)[i] = v;
+  }
+}
+
+__device__ __forceinline__ void stage_out16(uint8_t* g, const uint8_t* lds, size_t off,
+                                            size_t len, size_t total) {
+  if ((((uintptr_t)(g + off)) & 15) != 0 || (len & 15) != 0) {
+    stage_out(g, lds, off, len, total);
+    return;
+  }
+  const size_t lim = off + len < total ? len : (off < total ? total - off : 0);
+  const size_t nc = lim >> 4;
+  for (size_t i = threadIdx.x; i < nc; i += blockDim.x)
+    reinterpret_cast<uint4*>(g + off)[i] = reinterpret_cast<const uint4*>(lds)[i];
+  for (size_t i = 16 * nc + threadIdx.x; i < lim; i += blockDim.x) g[off + i] = lds[i];
+}
+
 // Exact floor(x / d) for x < 2^53, d >= 2: binary64 estimate, then one
 // correction from the exact remainder (the estimate is off by at most 1).
 __device__ __forceinline__ uint64_t floor_div53(uint64_t x, uint64_t d, double inv_d) {
@@ -147,18 +183,22 @@ __global__ __launch_bounds__(kTB) void unpack_kernel(const void* __restrict__ in
                                                      FieldArgs fa, const uint32_t* __restrict__ L,
                                                      const uint32_t* __restrict__ H,
                                                      uint8_t* __restrict__ out) {
-  __shared__ uint8_t buf[kTB * 16];
-  const size_t base = (size_t)blockIdx.x * kTB;
-  const size_t i = base + threadIdx.x;
+  // four values per thread, 4 kTB per workgroup; outputs staged in LDS and
+  // written as 16-byte runs
+  __shared__ __align__(16) uint8_t buf[4 * kTB * 16];
+  const size_t base = (size_t)blockIdx.x * (4 * kTB);
   const int ob = mode == 0 ? nd : k;  // output bytes per value
-  if (i < n) {
+  for (int j = 0; j < 4; ++j) {
+    const int t = threadIdx.x + j * kTB;
+    const size_t i = base + t;
+    if (i >= n) break;
     uint64_t r;
     if (WIDE) r = reinterpret_cast<const uint64_t*>(in)[i];
     else r = (uint64_t)reinterpret_cast<const double*>(in)[i];
     uint32_t u[16];
     const int nr = mode == 0 ? nd : 2 * k - 1;
     redq_residues<WIDE>(r, nr, ra, u);
-    uint8_t* dst = buf + threadIdx.x * ob;
+    uint8_t* dst = buf + t * ob;
     if (mode == 0) {
       // Q_d: mu_{nd-1} = u_{nd-1}; mu_i = u_i - q u_{i+1} = u_i + c u_{i+1} mod p.
       for (int d = 0; d < nd - 1; ++d) dst[d] = (uint8_t)modp(u[d] + ra.c * u[d + 1], ra);
@@ -175,7 +215,7 @@ __global__ __launch_bounds__(kTB) void unpack_kernel(const void* __restrict__ in
     }
   }
   __syncthreads();
-  stage_out(out, buf, base * ob, (size_t)kTB * ob, n * ob);
+  stage_out16(out, buf, base * ob, (size_t)(4 * kTB) * ob, n * ob);
 }
 
 static RedqArgs make_redq(uint64_t q, int pow2, uint32_t b, const FieldArgs& fa) {
@@ -195,7 +235,7 @@ hipError_t launch_unpack_f64(int k, uint32_t nd, int mode, uint64_t q, int pow2,
                              const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
                              const double* in, size_t n, uint8_t* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const size_t grid = (n + kTB - 1) / kTB;
+  const size_t grid = (n + 4 * kTB - 1) / (4 * kTB);
   hipLaunchKernelGGL(unpack_kernel<false>, dim3((unsigned)grid), dim3(kTB), 0, s,
                      (const void*)in, n, k, (int)nd, mode, make_redq(q, pow2, b, fa), fa, L, H,
                      out);
@@ -206,7 +246,7 @@ hipError_t launch_unpack_u64(int k, uint32_t nd, int mode, uint64_t q, int pow2,
                              const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
                              const uint64_t* in, size_t n, uint8_t* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const size_t grid = (n + kTB - 1) / kTB;
+  const size_t grid = (n + 4 * kTB - 1) / (4 * kTB);
   hipLaunchKernelGGL(unpack_kernel<true>, dim3((unsigned)grid), dim3(kTB), 0, s,
                      (const void*)in, n, k, (int)nd, mode, make_redq(q, pow2, b, fa), fa, L, H,
                      out);
@@ -214,42 +254,6 @@ hipError_t launch_unpack_u64(int k, uint32_t nd, int mode, uint64_t q, int pow2,
 }
 
 // ---- Alg. 1 on a batch of polynomial pairs -----------------------------------
-
-// 16-byte staging for the batched products: whole uint4 transfers where the
-// global range is 16-byte aligned, the dword/byte copies above otherwise.
-__device__ __forceinline__ void stage_in16(uint8_t* lds, const uint8_t* g, size_t off,
-                                           size_t len, size_t total) {
-  if ((((uintptr_t)(g + off)) & 15) != 0 || (len & 15) != 0) {
-    stage_in(lds, g, off, len, total);
-    return;
-  }
-  const size_t nc = len >> 4;
-  for (size_t i = threadIdx.x; i < nc; i += blockDim.x) {
-    uint4 v;
-    if (off + 16 * i + 15 < total) {
-      v = reinterpret_cast<const uint4*>(g + off)[i];
-    } else {
-      uint32_t w[4] = {0, 0, 0, 0};
-      for (int j = 0; j < 16; ++j)
-        if (off + 16 * i + j < total) w[j >> 2] |= (uint32_t)g[off + 16 * i + j] << (8 * (j & 3));
-      v = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-    reinterpret_cast<uint4*>(lds)[i] = v;
-  }
-}
-
-__device__ __forceinline__ void stage_out16(uint8_t* g, const uint8_t* lds, size_t off,
-                                            size_t len, size_t total) {
-  if ((((uintptr_t)(g + off)) & 15) != 0 || (len & 15) != 0) {
-    stage_out(g, lds, off, len, total);
-    return;
-  }
-  const size_t lim = off + len < total ? len : (off < total ? total - off : 0);
-  const size_t nc = lim >> 4;
-  for (size_t i = threadIdx.x; i < nc; i += blockDim.x)
-    reinterpret_cast<uint4*>(g + off)[i] = reinterpret_cast<const uint4*>(lds)[i];
-  for (size_t i = 16 * nc + threadIdx.x; i < lim; i += blockDim.x) g[off + i] = lds[i];
-}
 
 // K coefficients per operand known at compile time; every workgroup takes
 // kPM = 4 kTB pairs (each thread four), so the HBM transfers are 16-byte

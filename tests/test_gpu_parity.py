@@ -151,6 +151,11 @@ def test_unpack_poly_and_field(p, k, P, qkind):
     field = host(fqt.unpack_redq(f, q, packed, nd, fqt.UNPACK_FIELD))
     want_field = np.array([gf.poly_rem(row.tolist(), P, p) for row in want_poly], dtype=np.uint8)
     assert np.array_equal(field, want_field)
+    # an output view one row into its buffer (not 16-byte aligned)
+    big = torch.full((2501, nd), 255, dtype=torch.uint8, device="cuda")
+    fqt.unpack_redq(f, q, packed, nd, fqt.UNPACK_POLY, out=big[1:])
+    got = host(big)
+    assert np.array_equal(got[1:], want_poly) and (got[0] == 255).all()
     # the uint64 variant agrees on the same values
     packed64 = dev(np.array(vals, dtype=np.int64))
     assert np.array_equal(host(fqt.unpack_redq(f, q, packed64, nd, fqt.UNPACK_POLY)), want_poly)
