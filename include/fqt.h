@@ -112,11 +112,12 @@ typedef struct {
                       K runs in blocks of a multiple of 16 products.  They
                       accept log2q 0 or 17 only (FQT_ERR_INVALID_ARG) and
                       ignore boundary.
-                      INT8 path: ids 1..3, 7 and 8 expand B into B' (k x k
+                      INT8 path: ids 1..3 and 7..10 expand B into B' (k x k
                       multiplication matrices) in a device workspace, then
                       run the INT8 GEMM (C' tiles 64 x 64, 128 x 128,
-                      64 x 128, 256 x 256, 128 x 256 bytes; 7 and 8 with
-                      8 waves); ids 4..6 build B' K-tile by K-tile
+                      64 x 128, 256 x 256, 128 x 256, 64 x 64, 64 x 128
+                      bytes; 7 and 8 with 8 waves, 9 and 10 with K-tiles of
+                      256 bytes); ids 4..6 build B' K-tile by K-tile
                       in LDS inside the GEMM (no workspace) and return
                       FQT_ERR_UNSUPPORTED when their operand tiles and the
                       2^(k ceil(log2 p)) x k^2-byte table exceed the 160 KiB

@@ -1366,7 +1366,7 @@ static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmAr
   a.KK = KK;
   a.KKpad = KKpad;
   a.p = (uint32_t)p;
-  a.red_tiles = i8_red_tiles(KK, p);
+  a.red_tiles = i8_red_tiles(KK, p, i8_tile_k((int)tile));
   a.a_vec = row_align(g.A, a.lda);
   a.inv_p = 1.0 / (double)p;
   FQT_HIP(launch_gemm_i8((int)tile, a, s));
@@ -1793,7 +1793,7 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
       b.a.KK = d.K * k;
       b.a.KKpad = KKpad;
       b.a.p = (uint32_t)p;
-      b.a.red_tiles = i8_red_tiles(d.K * k, p);
+      b.a.red_tiles = i8_red_tiles(d.K * k, p, i8_tile_k((int)tile));
       b.a.a_vec = row_align(d.A, d.lda * k);
       b.a.inv_p = 1.0 / (double)p;
       b.B = d.B;

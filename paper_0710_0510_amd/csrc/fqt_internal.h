@@ -210,9 +210,9 @@ hipError_t launch_gemm_split_batched(int k, int tile, const GemmArgs* descs,
                                      int grid, const PackedParams& pp, hipStream_t s);
 int split_batched_occupancy(int k, int tile, uint32_t tbl_log2);
 
-// INT8 path, tile ids 1..3, 7, 8: B -> B'^T expansion in HBM, then the INT8
+// INT8 path, tile ids 1..3, 7..10: B -> B'^T expansion in HBM, then the INT8
 // MFMA GEMM; ids 4..6: one kernel that expands each K-tile of B in LDS.
-constexpr int kInt8Tiles = 8;
+constexpr int kInt8Tiles = 10;
 constexpr bool i8_fused_tile(uint32_t tile) { return tile >= 4 && tile <= 6; }
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 CU
 hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
@@ -227,6 +227,7 @@ hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* i
 int i8_batched_occupancy(int tile);
 int i8_tile_m(int tile);  // output tile of the two-kernel ids: rows of C'
 int i8_tile_n(int tile);  // ... and columns of C' (bytes)
+int i8_tile_k(int tile);  // ... and bytes of K per K-tile (128 or 256)
 // Fused tiles (ids 4..6): bytes of K per K-tile, elements of N per output
 // tile, rows of M per output tile, and static LDS bytes (the dynamic part is
 // the multiplication-matrix table, 2^tbl_log2 entries of mt_stride(k)).

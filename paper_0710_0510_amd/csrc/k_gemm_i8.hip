@@ -20,7 +20,7 @@
 // 16x16x64 i8: lane l supplies row l%16, bytes k = 16(l/16)..16(l/16)+15 of a
 // 64-deep step (A and B use the same k order, so any order shared by both is
 // correct); result element v of lane l sits at row 4(l/16)+v, column l%16.
-// Tile ids 1..3, 7 and 8 run expand_b_kernel and gemm_i8_kernel; ids 4..6 run
+// Tile ids 1..3 and 7..10 run expand_b_kernel and gemm_i8_kernel; ids 4..6 run
 // gemm_i8f_kernel, which builds B'^T tile by tile in LDS instead.
 
 #include "fqt_internal.h"
@@ -191,11 +191,11 @@ hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int6
 // Workgroup = 2 x WGN waves (wave tile 16TM x 16TN): 4 waves, or 8 for the
 // 128 x 256 and 256 x 256 tiles that halve the L2 traffic per output of
 // large products.
-template <int TM, int TN, int WGN = 2>
+template <int TM, int TN, int WGN = 2, int BK = 128>
 struct I8T {
   static constexpr int NT = 128 * WGN;     // threads
   static constexpr int BM = 32 * TM, BN = 16 * TN * WGN;
-  static constexpr int BKK = 128;          // bytes of K per tile
+  static constexpr int BKK = BK;           // bytes of K per tile (128 or 256)
   static constexpr int S = BKK + 16;       // LDS row stride (bytes): conflict-free b128 reads
   static constexpr int CA = BM * BKK / 16;  // 16-byte chunks of A per tile
   static constexpr int CB = BN * BKK / 16;
@@ -236,17 +236,17 @@ __device__ __forceinline__ uint4 load16(const uint8_t* base, int64_t ld, int64_t
   return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-template <int TM, int TN, int WGN>
+template <int TM, int TN, int WGN, int BK>
 __device__ __forceinline__ void i8_tile(
     const I8Args& a, int64_t m0, int64_t n0,
-    uint8_t (*As)[I8T<TM, TN, WGN>::BM * I8T<TM, TN, WGN>::S],
-    uint8_t (*Bs)[I8T<TM, TN, WGN>::BN * I8T<TM, TN, WGN>::S]) {
-  using T = I8T<TM, TN, WGN>;
+    uint8_t (*As)[I8T<TM, TN, WGN, BK>::BM * I8T<TM, TN, WGN, BK>::S],
+    uint8_t (*Bs)[I8T<TM, TN, WGN, BK>::BN * I8T<TM, TN, WGN, BK>::S]) {
+  using T = I8T<TM, TN, WGN, BK>;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * 16 * TM, wn0 = (wave % WGN) * 16 * TN;
-  // chunk r: row crow + r NT/8, bytes ccol..ccol+15
-  constexpr int RSTEP = T::NT / 8;
-  const int crow = tid >> 3, ccol = (tid & 7) * 16;
+  // chunk r: row crow + r NT/CPR, bytes ccol..ccol+15 (CPR chunks per row)
+  constexpr int CPR = T::BKK / 16, RSTEP = T::NT / CPR;
+  const int crow = tid / CPR, ccol = (tid % CPR) * 16;
 
   v4i acc[TM][TN];
 #pragma unroll
@@ -326,25 +326,25 @@ __device__ __forceinline__ void i8_tile(
       }
 }
 
-template <int TM, int TN, int WGN>
+template <int TM, int TN, int WGN, int BK>
 __global__ __launch_bounds__(128 * WGN) void gemm_i8_kernel(I8Args a, int tiles_n,
                                                                        int ntiles) {
-  using T = I8T<TM, TN, WGN>;
+  using T = I8T<TM, TN, WGN, BK>;
   __shared__ __attribute__((aligned(16))) uint8_t As[2][T::BM * T::S];
   __shared__ __attribute__((aligned(16))) uint8_t Bs[2][T::BN * T::S];
   int tile = blockIdx.x;
   if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-  i8_tile<TM, TN, WGN>(a, (int64_t)(tile / tiles_n) * T::BM, (int64_t)(tile % tiles_n) * T::BN,
+  i8_tile<TM, TN, WGN, BK>(a, (int64_t)(tile / tiles_n) * T::BM, (int64_t)(tile % tiles_n) * T::BN,
                        As, Bs);
 }
 
 // Persistent INT8 kernel over the tiles of a whole batch (atomic queue, the
 // last workgroup out resets it for the next launch).
-template <int TM, int TN, int WGN>
+template <int TM, int TN, int WGN, int BK>
 __global__ __launch_bounds__(128 * WGN) void gemm_i8_batched_kernel(
     const I8Batch* __restrict__ gs, const TileItem* __restrict__ items, int32_t n_items,
     uint32_t* counter) {
-  using T = I8T<TM, TN, WGN>;
+  using T = I8T<TM, TN, WGN, BK>;
   __shared__ __attribute__((aligned(16))) uint8_t As[2][T::BM * T::S];
   __shared__ __attribute__((aligned(16))) uint8_t Bs[2][T::BN * T::S];
   __shared__ int32_t cur;
@@ -356,7 +356,7 @@ __global__ __launch_bounds__(128 * WGN) void gemm_i8_batched_kernel(
     if (it >= n_items) break;
     const TileItem ti = items[it];
     const I8Args a = gs[ti.gemm].a;
-    i8_tile<TM, TN, WGN>(a, (int64_t)ti.tm * T::BM, (int64_t)ti.tn * T::BN, As, Bs);
+    i8_tile<TM, TN, WGN, BK>(a, (int64_t)ti.tm * T::BM, (int64_t)ti.tn * T::BN, As, Bs);
   }
   if (threadIdx.x == 0) {
     __threadfence();
@@ -368,43 +368,45 @@ __global__ __launch_bounds__(128 * WGN) void gemm_i8_batched_kernel(
   }
 }
 
-template <int TM, int TN, int WGN>
+template <int TM, int TN, int WGN, int BK>
 static hipError_t launch_i8(const I8Args& a, hipStream_t s) {
-  using T = I8T<TM, TN, WGN>;
+  using T = I8T<TM, TN, WGN, BK>;
   const int tiles_m = (int)((a.M + T::BM - 1) / T::BM);
   const int tiles_n = (int)((a.NN + T::BN - 1) / T::BN);
   const int ntiles = tiles_m * tiles_n;
   if (ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL((gemm_i8_kernel<TM, TN, WGN>), dim3(ntiles), dim3(T::NT), 0, s, a, tiles_n,
+  hipLaunchKernelGGL((gemm_i8_kernel<TM, TN, WGN, BK>), dim3(ntiles), dim3(T::NT), 0, s, a, tiles_n,
                      ntiles);
   return hipGetLastError();
 }
 
-template <int TM, int TN, int WGN>
+template <int TM, int TN, int WGN, int BK>
 static hipError_t launch_i8_batched(const I8Batch* gs, const TileItem* items, int32_t n,
                                     uint32_t* counter, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((gemm_i8_batched_kernel<TM, TN, WGN>), dim3(grid),
-                     dim3(I8T<TM, TN, WGN>::NT), 0, s, gs, items, n, counter);
+  hipLaunchKernelGGL((gemm_i8_batched_kernel<TM, TN, WGN, BK>), dim3(grid),
+                     dim3(I8T<TM, TN, WGN, BK>::NT), 0, s, gs, items, n, counter);
   return hipGetLastError();
 }
 
-template <int TM, int TN, int WGN>
+template <int TM, int TN, int WGN, int BK>
 static int occ_i8() {
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, (const void*)gemm_i8_batched_kernel<TM, TN, WGN>, I8T<TM, TN, WGN>::NT,
+          &blocks, (const void*)gemm_i8_batched_kernel<TM, TN, WGN, BK>, I8T<TM, TN, WGN, BK>::NT,
           0) != hipSuccess)
     blocks = 1;
   return blocks > 0 ? blocks : 1;
 }
 
-// INT8 tile ids of the two-kernel path: X(id, TM, TN, WGN)
-#define FQT_I8_TILES(X) X(1, 2, 2, 2) X(2, 4, 4, 2) X(3, 2, 4, 2) X(7, 8, 4, 4) X(8, 4, 4, 4)
+// INT8 tile ids of the two-kernel path: X(id, TM, TN, WGN, BK)
+#define FQT_I8_TILES(X)                                                                  \
+  X(1, 2, 2, 2, 128) X(2, 4, 4, 2, 128) X(3, 2, 4, 2, 128) X(7, 8, 4, 4, 128)            \
+  X(8, 4, 4, 4, 128) X(9, 2, 2, 2, 256) X(10, 2, 4, 2, 256)
 
 int i8_batched_occupancy(int tile) {
   switch (tile) {
-#define FQT_I8_OCC(ID, TM, TN, WGN) \
-  case ID: return occ_i8<TM, TN, WGN>();
+#define FQT_I8_OCC(ID, TM, TN, WGN, BK) \
+  case ID: return occ_i8<TM, TN, WGN, BK>();
     FQT_I8_TILES(FQT_I8_OCC)
 #undef FQT_I8_OCC
     default: return 1;
@@ -413,18 +415,28 @@ int i8_batched_occupancy(int tile) {
 
 int i8_tile_m(int tile) {
   switch (tile) {
-#define FQT_I8_BM(ID, TM, TN, WGN) \
-  case ID: return I8T<TM, TN, WGN>::BM;
+#define FQT_I8_BM(ID, TM, TN, WGN, BK) \
+  case ID: return I8T<TM, TN, WGN, BK>::BM;
     FQT_I8_TILES(FQT_I8_BM)
 #undef FQT_I8_BM
     default: return 0;
   }
 }
 
+int i8_tile_k(int tile) {
+  switch (tile) {
+#define FQT_I8_BK(ID, TM, TN, WGN, BK) \
+  case ID: return BK;
+    FQT_I8_TILES(FQT_I8_BK)
+#undef FQT_I8_BK
+    default: return 128;
+  }
+}
+
 int i8_tile_n(int tile) {
   switch (tile) {
-#define FQT_I8_BN(ID, TM, TN, WGN) \
-  case ID: return I8T<TM, TN, WGN>::BN;
+#define FQT_I8_BN(ID, TM, TN, WGN, BK) \
+  case ID: return I8T<TM, TN, WGN, BK>::BN;
     FQT_I8_TILES(FQT_I8_BN)
 #undef FQT_I8_BN
     default: return 0;
@@ -434,8 +446,8 @@ int i8_tile_n(int tile) {
 hipError_t launch_gemm_i8_batched(int tile, const I8Batch* gs, const TileItem* items,
                                   int32_t n_items, uint32_t* counter, int grid, hipStream_t s) {
   switch (tile) {
-#define FQT_I8_BATCHED(ID, TM, TN, WGN) \
-  case ID: return launch_i8_batched<TM, TN, WGN>(gs, items, n_items, counter, grid, s);
+#define FQT_I8_BATCHED(ID, TM, TN, WGN, BK) \
+  case ID: return launch_i8_batched<TM, TN, WGN, BK>(gs, items, n_items, counter, grid, s);
     FQT_I8_TILES(FQT_I8_BATCHED)
 #undef FQT_I8_BATCHED
     default: return hipErrorInvalidValue;
@@ -462,8 +474,8 @@ hipError_t launch_expand_b_batched(int k, const I8Batch* gs, const ExpandItem* i
 
 hipError_t launch_gemm_i8(int tile, const I8Args& a, hipStream_t s) {
   switch (tile) {
-#define FQT_I8_ONE(ID, TM, TN, WGN) \
-  case ID: return launch_i8<TM, TN, WGN>(a, s);
+#define FQT_I8_ONE(ID, TM, TN, WGN, BK) \
+  case ID: return launch_i8<TM, TN, WGN, BK>(a, s);
     FQT_I8_TILES(FQT_I8_ONE)
 #undef FQT_I8_ONE
     default: return hipErrorInvalidValue;

@@ -335,7 +335,7 @@ def test_gemm_batched_replay():
         torch.cuda.synchronize()
         for c, w in zip(Cs, wants):
             assert np.array_equal(host(c), w)
-    for tile in (1, 2, 3, 4, 5, 6, 7, 8):
+    for tile in range(1, 11):
         for rep in range(2):
             note(f"batched int8 tile {tile} replay {rep}")
             for c in Cs:
@@ -355,7 +355,7 @@ def test_gemm_batched_replay():
 # ---- INT8 coefficient-wise path -------------------------------------------------
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-@pytest.mark.parametrize("tile", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("tile", list(range(1, 11)))
 def test_gemm_int8_shapes(p, k, P, tile):
     for (M, N, K) in SHAPES + [(130, 200, 257)]:
         note(f"gemm int8 GF({p}^{k}) tile={tile} {M}x{N}x{K}")
@@ -365,7 +365,7 @@ def test_gemm_int8_shapes(p, k, P, tile):
 
 
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
-@pytest.mark.parametrize("tile", [None, 4, 7])
+@pytest.mark.parametrize("tile", [None, 4, 7, 9])
 def test_gemm_int8_adversarial(p, k, P, tile):
     note(f"gemm int8 adversarial GF({p}^{k}) tile={tile}")
     C, want = _gemm_case(p, k, P, 40, 50, 3001, seed=0, adversarial=True, path="int8",
@@ -373,7 +373,7 @@ def test_gemm_int8_adversarial(p, k, P, tile):
     assert np.array_equal(C, want)
 
 
-@pytest.mark.parametrize("tile", [None, 4, 8])
+@pytest.mark.parametrize("tile", [None, 4, 8, 10])
 def test_gemm_int8_delayed_reduction_gf61_2(tile):
     # K k (p-1)^2 far above 2^31: the INT32 accumulators are reduced mod p
     # every few thousand K-tiles (eq. (3) with n_d (p-1)^2 < 2^31).
@@ -386,7 +386,7 @@ def test_gemm_int8_delayed_reduction_gf61_2(tile):
         assert np.array_equal(C, want)
 
 
-@pytest.mark.parametrize("tile", [None, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("tile", [None, 4, 5, 6, 7, 8, 9, 10])
 def test_gemm_int8_strided_unaligned(tile):
     p, k, P = 5, 3, (3, 3, 0)
     f = fqt.Field(p, k, P)
