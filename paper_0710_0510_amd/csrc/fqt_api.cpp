@@ -1800,11 +1800,11 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
       b.ldb = d.ldb;
       b.K = d.K;
       b.N = d.N;
-      // 32 x 64-element expansion blocks covering the padded row
+      // kExpandL x kExpandN-element expansion blocks covering the padded row
       const int64_t lcols = (KKpad + k - 1) / k;
       if (d.K && d.N)
-        for (int32_t lb = 0; lb < (int32_t)((lcols + 31) / 32); ++lb)
-          for (int32_t nb = 0; nb < (int32_t)((d.N + 63) / 64); ++nb)
+        for (int32_t lb = 0; lb < (int32_t)((lcols + kExpandL - 1) / kExpandL); ++lb)
+          for (int32_t nb = 0; nb < (int32_t)((d.N + kExpandN - 1) / kExpandN); ++nb)
             exps.push_back(ExpandItem{(int32_t)i, lb, nb, 0});
       const int tm = (int)((d.M + bm - 1) / bm), tn = (int)((d.N * k + bn - 1) / bn);
       for (int a = 0; a < tm; ++a)

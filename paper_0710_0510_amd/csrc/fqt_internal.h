@@ -213,6 +213,8 @@ int split_batched_occupancy(int k, int tile, uint32_t tbl_log2);
 // INT8 path, tile ids 1..3, 7..10: B -> B'^T expansion in HBM, then the INT8
 // MFMA GEMM; ids 4..6: one kernel that expands each K-tile of B in LDS.
 constexpr int kInt8Tiles = 10;
+// Block of the B -> B'^T expansion: kExpandL elements of K x kExpandN of N.
+constexpr int kExpandL = 128, kExpandN = 16;
 constexpr bool i8_fused_tile(uint32_t tile) { return tile >= 4 && tile <= 6; }
 constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one gfx950 CU
 hipError_t launch_expand_b(int k, const uint8_t* B, int64_t ldb, int64_t K, int64_t N,
