@@ -51,6 +51,16 @@ MEASURED_TRAFFIC = {
 }
 
 
+def hbm_rate(alg_bytes, ms, traffic=None):
+    """Achieved HBM rates of one step: algorithmic bytes (inputs read once,
+    outputs written once) and, where counters were taken, measured bytes."""
+    out = {"algorithmic_bytes": int(alg_bytes),
+           "algorithmic_GBps": alg_bytes / (ms * 1e-3) / 1e9,
+           "measured_bytes": traffic,
+           "measured_GBps": traffic / (ms * 1e-3) / 1e9 if traffic else None}
+    return out
+
+
 def poly_str(P_low):
     k = len(P_low)
     terms = [f"X^{k}"]
@@ -343,6 +353,8 @@ def bench_gemm(w, args, torch, fqt, gf):
     }
     if "plain" in results and args.path != "plain":
         out["speedup_vs_plain"] = results["plain"]["ms_per_step"] / main_r["ms_per_step"]
+    out["hbm"] = hbm_rate((w.M * w.K + w.K * w.N + w.M * w.N) * w.k, main_r["ms_per_step"],
+                          main_r["roofline"].get("traffic"))
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_gemm(w, A_h, B_h, gf, target_s=args.cpu_seconds)
         out["cpu_plain"] = cpu_plain_gemm(w, A_h, B_h, Rh, target_s=min(args.cpu_seconds, 8.0))
@@ -440,6 +452,8 @@ def bench_batched(w, args, torch, fqt, gf):
                    "identical_to_plain_path": True},
     }
     out["roofline"]["kernel"] = "persistent batched " + out["roofline"]["kernel"]
+    out["hbm"] = hbm_rate(int(((mnk[:, 0] * mnk[:, 2] + mnk[:, 2] * mnk[:, 1]
+                                + mnk[:, 0] * mnk[:, 1]) * k).sum()), ms)
     if not args.no_cpu:
         out.update(cpu_batched(w, As, Bs, mnk, gf, args.cpu_seconds))
     return out
@@ -564,6 +578,8 @@ def bench_dfqt(w, args, torch, fqt, gf):
         out["roofline"]["traffic"] = tr["bytes"]
         out["roofline"]["traffic_source"] = tr["source"]
         out["roofline"]["algorithmic_bytes"] = w.count * (2 * w.length + 2 * w.length - 1)
+    out["hbm"] = hbm_rate(w.count * (2 * w.length + 2 * w.length - 1), main_v["ms_per_step"],
+                          out["roofline"].get("traffic"))
     if not args.no_cpu:
         n = 4
         t0 = time.time()
