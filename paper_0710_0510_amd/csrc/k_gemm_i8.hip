@@ -15,8 +15,9 @@
 //
 // expand_b_kernel writes B' transposed (Nk rows of Kk bytes, zero padded to a
 // multiple of 128 columns) so that both MFMA operands are 16 contiguous bytes
-// per lane.  gemm_i8_kernel: workgroup = 2 x 2 waves, wave tile 16TM x 16TN,
-// K-tiles of 128 bytes double-buffered in LDS; operand layout of
+// per lane.  gemm_i8_kernel: workgroup = 2 x WGN waves (WGN = 2 or 4), wave
+// tile 16TM x 16TN, K-tiles of 128 or 256 bytes double-buffered in LDS;
+// operand layout of
 // 16x16x64 i8: lane l supplies row l%16, bytes k = 16(l/16)..16(l/16)+15 of a
 // 64-deep step (A and B use the same k order, so any order shared by both is
 // correct); result element v of lane l sits at row 4(l/16)+v, column l%16.
