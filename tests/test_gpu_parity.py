@@ -75,7 +75,7 @@ def test_polymul_example1_general_q():
 @pytest.mark.parametrize("p,k,q,n", [(3, 2, 100, 1000), (7, 2, 2 ** 17, 257), (5, 3, 1552, 255),
                                      (3, 4, 190, 999), (2, 7, 8, 4097), (11, 1, 2 ** 40, 33),
                                      (13, 3, 1000, 700), (127, 2, 2 ** 15, 300),
-                                     (127, 2, 32259, 300)])
+                                     (127, 2, 32259, 300), (2, 5, 8, 3000), (3, 6, 25, 2100)])
 def test_polymul_params(p, k, q, n):
     note(f"polymul p={p} k={k} q={q} n={n}")
     assert gf.eq2_holds(p, k, q, 1)
