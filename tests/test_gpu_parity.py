@@ -364,6 +364,16 @@ def test_gemm_int8_shapes(p, k, P, tile):
         assert np.array_equal(C, want), (M, N, K)
 
 
+@pytest.mark.parametrize("tile", list(range(1, 11)))
+def test_gemm_int8_prime_field(tile):
+    # k = 1: GF(13), B' is B itself (1 x 1 multiplication matrices)
+    p, k, P = 13, 1, (11,)
+    for (M, N, K) in [(17, 33, 45), (100, 70, 300), (129, 257, 130)]:
+        note(f"gemm int8 GF(13) tile={tile} {M}x{N}x{K}")
+        C, want = _gemm_case(p, k, P, M, N, K, seed=M + K, path="int8", opts={"tile": tile})
+        assert np.array_equal(C, want), (M, N, K)
+
+
 @pytest.mark.parametrize("p,k,P", CONFIG_FIELDS)
 @pytest.mark.parametrize("tile", [None, 4, 7, 9])
 def test_gemm_int8_adversarial(p, k, P, tile):
