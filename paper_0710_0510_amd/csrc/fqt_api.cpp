@@ -1345,7 +1345,10 @@ static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmAr
   if (i8_fused_tile(tile)) return gemm_int8_fused(f, tile, g, s);
   // B'^T rows are padded to whole 128-byte K-tiles of the INT8 GEMM
   const int64_t NN = g.N * k, KK = g.K * k, KKpad = (KK + 127) / 128 * 128;
-  if (!tile) tile = (g.M >= 1024 && NN >= 1024) ? 2 : 1;
+  // untuned default, from measurements on MI355X: the 256 x 256 8-wave tile
+  // for large products, 64 x 64 with 256-byte K-tiles from about 2^20
+  // outputs, 64 x 64 below
+  if (!tile) tile = (g.M >= 2048 && NN >= 2048) ? 7 : (g.M * NN >= (1 << 20) ? 9 : 1);
   uint8_t* ws = nullptr;
   fqt_status st = workspace(f, (size_t)std::max<int64_t>(NN * KKpad, 1), &ws);
   if (st) return st;
@@ -1686,7 +1689,7 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
 static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t count,
                                const fqt_gemm_desc* descs, hipStream_t s) {
   const int64_t k = f->k, p = f->p;
-  uint32_t tile = (opts && opts->tile) ? opts->tile : 1;
+  uint32_t tile = (opts && opts->tile) ? opts->tile : 2;  // measured best on uneven batches
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
