@@ -163,6 +163,27 @@ def test_direct_tiles_refuse_several_blocks():
                         opts={"tile": 7}) == "FQT_ERR_UNSUPPORTED"
 
 
+def test_buffered_tile_refuses_extents_beyond_32_bits():
+    # tile 12 addresses A and B through 32-bit byte offsets: an operand that
+    # spans 2^31 bytes or more is refused before any device work
+    f = fqt.Field(7, 2, (1, 0))
+    big_ld = 1 << 21                           # (1023 * 2^21 + 1024) * 2 bytes > 2^31
+    assert _gemm_status(f, "packed", 1024, 4, 1024, big_ld, 4, 4, A=BOGUS, B=BOGUS + (1 << 33),
+                        C=BOGUS + (1 << 34), opts={"tile": 12}) == "FQT_ERR_UNSUPPORTED"
+    assert _gemm_status(f, "packed", 4, 1024, 1024, 1024, big_ld, 1024, A=BOGUS,
+                        B=BOGUS + (1 << 33), C=BOGUS + (1 << 40),
+                        opts={"tile": 12}) == "FQT_ERR_UNSUPPORTED"
+
+
+def test_int8_tile_ids_and_lds_refusal():
+    f = fqt.Field(7, 2, (1, 0))
+    assert _gemm_status(f, "int8", 4, 4, 4, 4, 4, 4, opts={"tile": 11}) == "FQT_ERR_INVALID_ARG"
+    # GF(13^3): a 12-bit table index, 4096 entries of 16 bytes; with the
+    # 128 x 128 operand tiles of id 5 that exceeds one CU's LDS
+    g = fqt.Field(13, 3, (1, 0, 4))
+    assert _gemm_status(g, "int8", 4, 4, 4, 4, 4, 4, opts={"tile": 5}) == "FQT_ERR_UNSUPPORTED"
+
+
 def test_split_tiles_validation():
     # d-split tiles: k = 3 or 4 only, q = 2^17 only, n_q <= (2^17 - 1) / (w (p-1)^2)
     # (w = 8 for k = 4: 4095 for p = 3), blocks of at least 16 products
