@@ -1689,7 +1689,7 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
 static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t count,
                                const fqt_gemm_desc* descs, hipStream_t s) {
   const int64_t k = f->k, p = f->p;
-  uint32_t tile = (opts && opts->tile) ? opts->tile : 2;  // measured best on uneven batches
+  uint32_t tile = (opts && opts->tile) ? opts->tile : 8;  // measured best on uneven batches
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
