@@ -120,8 +120,9 @@ typedef struct {
                       256 bytes); ids 4..6 build B' K-tile by K-tile
                       in LDS inside the GEMM (no workspace) and return
                       FQT_ERR_UNSUPPORTED when their operand tiles and the
-                      2^(k ceil(log2 p)) x k^2-byte table exceed the 160 KiB
-                      LDS of a CU.  All INT8 ids give identical bytes. */
+                      table (2^(k ceil(log2 p)) entries of k^2 bytes padded
+                      to 4 or 16) exceed the 160 KiB LDS of a CU.  All INT8
+                      ids give identical bytes. */
   uint32_t boundary; /* packed path, K > n_q: step at each K-block boundary.
                         0 = default (2 when q <= 2^12, else 1); 1 = REDQ
                         residues of the block (Alg. 2,
