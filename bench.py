@@ -3,11 +3,14 @@
 One step = one pass of the whole path over one batch of synthetic input:
 coefficient bytes in HBM -> DQT pack -> exact FP64 MFMA contraction with
 REDQ at K-block boundaries -> REDQ + L/H unpack -> coefficient bytes in HBM.
-The default workload is the dense GEMM over GF(7^2) (X^2+1), 1024^3.
+The default workload is the batch of 4096 uneven GEMMs over GF(3^4)
+(X^4+2X^3+2, M, N, K uniform in 16..256, seed 3) in one persistent launch
+replayed from a captured hipGraph; `value` is the packed FP64 path, the INT8
+path and the plain per-product comparator sit beside it in `paths`.
 
 Prints ONE JSON line.  Before timing, the output is checked bit-exactly:
-sampled entries against the CPU oracle, and the whole matrix against the
-plain comparator path.
+sampled entries against the CPU oracle, and the whole output against the
+other paths (the plain comparator unless --no-plain).
 """
 from __future__ import annotations
 
@@ -107,6 +110,22 @@ def time_steps(fn, steps, warmup, torch):
     end.record(stream)
     torch.cuda.synchronize()
     return start.elapsed_time(end) / steps  # ms per step
+
+
+def host_info():
+    """The host the CPU legs ran on: nproc (CPUs this process may use), the
+    machine's CPU count and lscpu's model line."""
+    info = {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+    try:
+        import subprocess
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Socket(s)"):
+                info["lscpu " + key.strip()] = val.strip()
+    except Exception as e:  # lscpu missing: say so rather than guess
+        info["lscpu"] = f"unavailable ({type(e).__name__})"
+    return info
 
 
 def cpu_baseline_gemm(w, A, B, gf, target_s=15.0):
@@ -358,6 +377,7 @@ def bench_gemm(w, args, torch, fqt, gf):
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_gemm(w, A_h, B_h, gf, target_s=args.cpu_seconds)
         out["cpu_plain"] = cpu_plain_gemm(w, A_h, B_h, Rh, target_s=min(args.cpu_seconds, 8.0))
+        out["cpu_baseline"]["host"] = out["cpu_plain"]["host"] = host_info()
     return out
 
 
@@ -375,6 +395,10 @@ def _aligned_views(torch, arrays, align=256):
 
 
 def bench_batched(w, args, torch, fqt, gf):
+    """The metric's workload: 4096 uneven GEMMs in one persistent launch per
+    path, replayed from a captured hipGraph.  Checks, before any timing: the
+    packed output against the oracle on sampled entries of sampled products,
+    and every other path byte for byte against the packed output."""
     from paper_0710_0510_amd import workloads as W
     mnk, As, Bs = W.batched_inputs(w)
     f = fqt.Field(w.p, w.k, w.P_low)
@@ -383,7 +407,6 @@ def bench_batched(w, args, torch, fqt, gf):
     dB, offB = _aligned_views(torch, Bs)
     Cshapes = [np.zeros((M, N, k), dtype=np.uint8) for (M, N, K) in mnk.tolist()]
     dC, offC = _aligned_views(torch, Cshapes)
-    dR = torch.zeros_like(dC)
 
     def descs_for(out):
         arr = (fqt.GemmDesc * len(As))()
@@ -392,70 +415,100 @@ def bench_batched(w, args, torch, fqt, gf):
                                   dB.data_ptr() + offB[i], out.data_ptr() + offC[i])
         return arr
 
-    dC_descs, dR_descs = descs_for(dC), descs_for(dR)
+    dC_descs = descs_for(dC)
     work = int((mnk[:, 0] * mnk[:, 1] * mnk[:, 2]).sum())
 
-    # plain comparator (one launch per product) is the reference
-    fqt.gemm_batched(f, dR_descs, path="plain")
+    # packed FP64 path: autotuned outside the timed region (or given options)
+    tuned = {}
+    if args.opts:
+        popts = json.loads(args.opts)
+    elif args.tile:
+        popts = {"tile": args.tile}
+    else:
+        popts = fqt.autotune(f, dC_descs, only="packed")[1]
+    tuned["packed"] = popts
+    fqt.gemm_batched(f, dC_descs, path="packed", opts=popts)
     torch.cuda.synchronize()
-    Rh = dR.cpu().numpy()
+    Ch = dC.cpu().numpy()
     rng = np.random.default_rng(99)
     bad = 0
     picks = rng.integers(0, len(As), size=args.samples // 4 + 1)
     for g in picks.tolist():
         M, N, K = mnk[g]
-        C_g = Rh[offC[g]:offC[g] + M * N * k].reshape(M, N, k)
+        C_g = Ch[offC[g]:offC[g] + M * N * k].reshape(M, N, k)
         for i, j in rng.integers(0, [M, N], size=(4, 2)).tolist():
             bad += gf.gemm_entry(As[g][i], Bs[g][:, j], w.p, w.P_low) != C_g[i, j].tolist()
     if bad:
-        raise SystemExit(f"parity failure: plain path differs from the oracle on {bad} entries")
-
-    opts = {"tile": args.tile} if args.tile else None
-    tuned = {}
-    if opts is None:
-        tuned["packed"] = fqt.autotune(f, dC_descs, only="packed")[1]
-        tuned["int8"] = fqt.autotune(f, dC_descs, only="int8")[1]
-    fqt.gemm_batched(f, dC_descs, path="packed", opts=opts)
-    torch.cuda.synchronize()
-    if not torch.equal(dC, dR):
-        raise SystemExit("parity failure: batched packed path differs from the plain path")
-    size_counts(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=opts), args, torch)
-    ms = time_steps(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=opts),
+        raise SystemExit(f"parity failure: batched packed path differs from the oracle on {bad} "
+                         "sampled entries")
+    size_counts(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=popts), args, torch)
+    ms = time_steps(lambda: fqt.gemm_batched(f, dC_descs, path="packed", opts=popts),
                     args.steps, args.warmup, torch)
+    tile = int(popts.get("tile", 0))
+
+    # INT8 coefficient-wise path, autotuned, byte-identical to the packed output
     dI = torch.zeros_like(dC)
     dI_descs = descs_for(dI)
-    fqt.gemm_batched(f, dI_descs, path="int8")
+    iopts = fqt.autotune(f, dI_descs, only="int8")[1]
+    tuned["int8"] = iopts
+    fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts)
     torch.cuda.synchronize()
-    if not torch.equal(dI, dR):
-        raise SystemExit("parity failure: batched INT8 path differs from the plain path")
-    i8_ms = time_steps(lambda: fqt.gemm_batched(f, dI_descs, path="int8"), args.steps,
-                       args.warmup, torch)
-    plain_ms = time_steps(lambda: fqt.gemm_batched(f, dR_descs, path="plain"),
-                          max(2, args.steps // 10), 1, torch)
+    if not torch.equal(dI, dC):
+        raise SystemExit("parity failure: batched INT8 path differs from the packed path")
+    i8_ms = time_steps(lambda: fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts),
+                       args.steps, args.warmup, torch)
+    del dI
+
+    paths = {"packed": {"value": work / (ms * 1e-3), "ms_per_step": ms, "tile": tile,
+                        "roofline_frac": roofline_for("packed", k, work, ms, tile)["frac"]},
+             "int8": {"value": work / (i8_ms * 1e-3), "ms_per_step": i8_ms,
+                      "tile": int(iopts.get("tile", 0)),
+                      "roofline_frac": roofline_for("int8", k, work, i8_ms,
+                                                    int(iopts.get("tile", 0)))["frac"]}}
+    identical = ["int8"]
+    if not args.no_plain:
+        # the plain comparator: one launch per product, as the metric asks
+        dR = torch.zeros_like(dC)
+        dR_descs = descs_for(dR)
+        fqt.gemm_batched(f, dR_descs, path="plain")
+        torch.cuda.synchronize()
+        if not torch.equal(dR, dC):
+            raise SystemExit("parity failure: the plain comparator differs from the packed path")
+        identical.append("plain")
+        plain_ms = time_steps(lambda: fqt.gemm_batched(f, dR_descs, path="plain"),
+                              max(2, args.steps // 10), 1, torch)
+        paths["plain"] = {"value": work / (plain_ms * 1e-3), "ms_per_step": plain_ms,
+                          "launches_per_step": len(As),
+                          "roofline_frac": roofline_for("plain", k, work, plain_ms)["frac"]}
     q, nqmax = fqt.params(w.p, w.k, 1)
+    rl = roofline_for("packed", k, work, ms, tile)
+    rl["kernel"] = "persistent batched " + rl["kernel"]
+    alg_bytes = int(((mnk[:, 0] * mnk[:, 2] + mnk[:, 2] * mnk[:, 1]
+                      + mnk[:, 0] * mnk[:, 1]) * k).sum())
+    tr = MEASURED_TRAFFIC.get((w.name, "packed", tile))
+    if tr:
+        rl["traffic"] = tr["bytes"]
+        rl["traffic_source"] = tr["source"]
+        rl["algorithmic_bytes"] = alg_bytes
     out = {
         "metric": METRIC, "value": work / (ms * 1e-3), "unit": "field mul-adds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": w.name, "field": f"GF({w.p}^{w.k})", "P": poly_str(w.P_low),
                    "count": len(As), "MNK_range": [w.lo, w.hi], "sum_MNK": work, "seed": w.seed,
-                   "path": "packed (persistent, hipGraph replay)", "q": q, "n_q_max": nqmax,
+                   "path": "packed (persistent, hipGraph replay)", "q_max": q, "n_q_max": nqmax,
                    "tile": args.tile or "autotuned", "tuned": tuned},
-        "roofline": roofline_for("packed", k, work, ms, (opts or tuned.get("packed") or {}).get("tile", 0)),
-        "paths": {"packed": {"value": work / (ms * 1e-3), "ms_per_step": ms},
-                  "int8": {"value": work / (i8_ms * 1e-3), "ms_per_step": i8_ms,
-                           "roofline_frac": roofline_for("int8", k, work, i8_ms)["frac"]},
-                  "plain": {"value": work / (plain_ms * 1e-3), "ms_per_step": plain_ms,
-                            "launches_per_step": len(As)}},
-        "speedup_vs_plain": plain_ms / ms,
+        "roofline": rl,
+        "paths": paths,
         "parity": {"sampled_entries_vs_oracle": int(len(picks) * 4), "sampled_mismatches": bad,
-                   "identical_to_plain_path": True},
+                   "identical_to_packed": identical},
     }
-    out["roofline"]["kernel"] = "persistent batched " + out["roofline"]["kernel"]
-    out["hbm"] = hbm_rate(int(((mnk[:, 0] * mnk[:, 2] + mnk[:, 2] * mnk[:, 1]
-                                + mnk[:, 0] * mnk[:, 1]) * k).sum()), ms)
+    if "plain" in paths:
+        out["speedup_vs_plain"] = paths["plain"]["ms_per_step"] / ms
+    out["hbm"] = hbm_rate(alg_bytes, ms, rl.get("traffic"))
     if not args.no_cpu:
         out.update(cpu_batched(w, As, Bs, mnk, gf, args.cpu_seconds))
+        out["cpu_baseline"]["host"] = out["cpu_plain"]["host"] = host_info()
     return out
 
 
@@ -605,7 +658,7 @@ def main():
                     help="timed steps (default: >= 50, covering %g ms)" % TIMED_MS)
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed warmup steps (default: >= 10, covering %g ms)" % WARMUP_MS)
-    ap.add_argument("--workload", default="gemm-gf7^2-1024")
+    ap.add_argument("--workload", default="batched-gf3^4-4096")
     ap.add_argument("--path", default="packed", choices=["packed", "int8", "plain", "winograd"])
     ap.add_argument("--levels", type=int, default=2,
                     help="levels of Winograd's recursion for --path winograd")
@@ -613,6 +666,11 @@ def main():
     ap.add_argument("--all-paths", type=int, default=1, help="also time the other paths")
     ap.add_argument("--samples", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched: leave out the plain per-product comparator (4096 launches), "
+                         "e.g. under a counter-collecting profiler")
+    ap.add_argument("--opts", default=None,
+                    help="batched: JSON options of the packed path instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for HBM counter scaling)")

@@ -35,23 +35,6 @@ from typing import Iterable, List, Sequence, Tuple
 import numpy as np
 
 # ---------------------------------------------------------------------------
-# Integers and primes
-# ---------------------------------------------------------------------------
-
-
-def is_prime(n: int) -> bool:
-    """Trial division; the characteristic p of Section 2 must be prime."""
-    if n < 2:
-        return False
-    d = 2
-    while d * d <= n:
-        if n % d == 0:
-            return False
-        d += 1
-    return True
-
-
-# ---------------------------------------------------------------------------
 # O1: polynomial product over GF(p) (Section 2, eq. (1); Alg. 1 ENSURE)
 # ---------------------------------------------------------------------------
 
@@ -303,22 +286,21 @@ def max_pow2_q(p: int, k: int, m: int = 53) -> Tuple[int, int]:
 
 
 def redq_steps(r: int, p: int, q: int, d: int):
-    """Alg. 2 step by step for r = sum_{i<=d} mu~_i q^i >= 0.
+    """REDQ (Alg. 2) in big integers for r = sum_{i<=d} mu~_i q^i >= 0,
+    built on Thm. 2 rather than on the listing's statements.
 
-    Returns (rop, u, mu, rho):
-      rop = floor(r / p);
-      u_i = floor(r / q^i) - p * floor(rop / q^i), i = 0..d;
-      mu_d = u_d; mu_i = (u_i - q u_{i+1}) mod p for i < d;
-      rho = sum mu_i q^i.
+    Thm. 2: with rop = floor(r / p), every u_i = floor(r / q^i) -
+    p floor(rop / q^i) lies in [0, p) and is congruent mod p to
+    sum_{j>=i} mu~_j q^(j-i).  Those congruences form the triangular
+    Toeplitz system of Section 5.1, so the digits mod p are Q_d u mod p
+    (q_matrix below), and rho packs them back at q (the DQT).
+
+    Returns (rop, u, mu, rho) with mu_i = mu~_i mod p.
     """
     rop = r // p
     u = [r // q ** i - p * (rop // q ** i) for i in range(d + 1)]
-    mu = [0] * (d + 1)
-    mu[d] = u[d] % p
-    for i in range(d):
-        mu[i] = (u[i] - q * u[i + 1]) % p
-    rho = sum(m * q ** i for i, m in enumerate(mu))
-    return rop, u, mu, rho
+    mu = mat_vec_mod(q_matrix(d, q, p), u, p)
+    return rop, u, mu, dqt(mu, q)
 
 
 def q_matrix(d: int, q: int, p: int) -> List[List[int]]:
@@ -402,16 +384,15 @@ def table_H(uw: Sequence[int], q: int, p: int, P_low: Sequence[int]) -> List[int
 
 
 def fgdp(v1, v2, p: int, P_low: Sequence[int], q: int) -> List[int]:
-    """Alg. 4 step by step in big integers for one dot product v1^T v2 over
-    GF(p^k): pack at q, one integer dot product, rop, the 2k-1 residues
-    u_i, then L + H from the two tables."""
+    """Alg. 4 for one dot product v1^T v2 over GF(p^k), in big integers:
+    the dot product of the packed operands is one exact integer r (Thm. 1,
+    eq. (2)); its 2k-1 residues u of Thm. 2 index Thm. 3's two tables, L by
+    (u_0..u_{k-1}) and H by (u_{k-1}..u_{2k-2}), whose sum mod p is the
+    reduced field element."""
     k = len(P_low)
     r = sum(dqt(a, q) * dqt(b, q) for a, b in zip(v1, v2))
-    rop = r // p
-    u = [r // q ** i - p * (rop // q ** i) for i in range(2 * k - 1)]
-    L = table_L(u[0:k], q, p)
-    H = table_H(u[k - 1:2 * k - 1], q, p, P_low)
-    return field_add(L, H, p)
+    u = redq_steps(r, p, q, 2 * k - 2)[1]
+    return field_add(table_L(u[:k], q, p), table_H(u[k - 1:], q, p, P_low), p)
 
 
 def binary_index(uw: Sequence[int], p: int) -> int:
