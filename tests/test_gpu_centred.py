@@ -43,6 +43,13 @@ def host(t):
     return t.cpu().numpy()
 
 
+def refused(status, fn):
+    """The host refuses the call with `status` before any launch."""
+    with pytest.raises(fqt.FqtError) as ei:
+        fn()
+    assert ei.value.name == status, str(ei.value)
+
+
 def centred_nq(p, k, b=0):
     q = 2 ** b if b else fqt.params(p, k, 1)[0]
     return gf.centred_nq_max(p, k, q)
@@ -76,13 +83,17 @@ def test_centred_shapes(p, k, P, tile):
 @pytest.mark.parametrize("nq", [0, 4, 8])
 def test_centred_blocks(p, k, P, boundary, nq):
     q = fqt.params(p, k, 1)[0]
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
+    block = nq or centred_nq(p, k)  # products per K-block (a multiple of 4 here)
     for (M, N, K) in [(40, 50, 97), (64, 128, 256), (33, 129, 1001)]:
         note(f"centred blocks GF({p}^{k}) boundary={boundary} n_q={nq} {M}x{N}x{K}")
-        C, want = run(p, k, P, M, N, K, seed=K + nq,
-                      opts={"tile": 2, "centered": 1, "boundary": boundary, "n_q": nq})
-        assert np.array_equal(C, want), (M, N, K)
+        case = lambda: run(p, k, P, M, N, K, seed=K + nq,
+                           opts={"tile": 2, "centered": 1, "boundary": boundary, "n_q": nq})
+        if boundary == 2 and q > 2 ** 12 and K > block:
+            # several blocks with digit-sum fields of 2b > 24 bits
+            refused("FQT_ERR_UNSUPPORTED", case)
+        else:
+            C, want = case()
+            assert np.array_equal(C, want), (M, N, K)
 
 
 @pytest.mark.parametrize("p,k,P", FIELDS[:4])
@@ -91,18 +102,21 @@ def test_centred_adversarial(p, k, P, boundary):
     # the extreme digit sums: every coefficient h against h (+h^2 per term)
     # and h against -h (-h^2), one block at the centred bound and many blocks
     q = fqt.params(p, k, 1)[0]
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
     h = (p - 1) // 2
-    nq = min(centred_nq(p, k), 3000)
+    block = centred_nq(p, k)
+    nq = min(block, 3000)
     for K in (nq, 3 * nq + 5):
         for bval in (h, p - h):
             note(f"centred adversarial GF({p}^{k}) boundary={boundary} K={K} b={bval}")
             A = np.full((48, K, k), h, dtype=np.uint8)
             B = np.full((K, 96, k), bval, dtype=np.uint8)
-            C, want = run(p, k, P, 48, 96, K, 0, {"tile": 2, "centered": 1, "boundary": boundary},
-                          A, B)
-            assert np.array_equal(C, want), (K, bval)
+            case = lambda: run(p, k, P, 48, 96, K, 0,
+                               {"tile": 2, "centered": 1, "boundary": boundary}, A, B)
+            if boundary == 2 and q > 2 ** 12 and K > block:
+                refused("FQT_ERR_UNSUPPORTED", case)
+            else:
+                C, want = case()
+                assert np.array_equal(C, want), (K, bval)
 
 
 @pytest.mark.parametrize("p,k,P", FIELDS[:2])

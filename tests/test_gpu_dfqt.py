@@ -38,6 +38,13 @@ def host(t):
     return t.cpu().numpy()
 
 
+def refused(status, fn):
+    """The host refuses the call with `status` before any launch."""
+    with pytest.raises(fqt.FqtError) as ei:
+        fn()
+    assert ei.value.name == status, str(ei.value)
+
+
 def want_rows(a, b, p):
     return np.array([gf.polymul_long(x.tolist(), y.tolist(), p) for x, y in zip(a, b)],
                     dtype=np.uint8).reshape(a.shape[0], 2 * a.shape[1] - 1)
@@ -66,13 +73,14 @@ def test_dfqt_matches_product_definition(p, d):
 @pytest.mark.parametrize("boundary", [1, 2])
 def test_dfqt_block_modes(p, d, nq, boundary):
     q, nqmax = gf.max_pow2_q(p, d + 1)
-    if nq > nqmax:
-        pytest.skip("n_q above the bound")
+    zeros = dev(np.zeros((1, 1000), np.uint8))
+    if nq > nqmax:  # eq. (2) fails for this n_q with k = d + 1 at the largest q
+        refused("FQT_ERR_BOUNDS", lambda: fqt.polymul_dfqt(p, d, zeros, zeros, n_q=nq,
+                                                             boundary=boundary))
+        return
     if boundary == 2 and q > 2 ** 12:
-        with pytest.raises(fqt.FqtError) as ei:
-            fqt.polymul_dfqt(p, d, dev(np.zeros((1, 1000), np.uint8)),
-                             dev(np.zeros((1, 1000), np.uint8)), n_q=nq, boundary=2)
-        assert ei.value.name == "FQT_ERR_UNSUPPORTED"
+        refused("FQT_ERR_UNSUPPORTED", lambda: fqt.polymul_dfqt(p, d, zeros, zeros, n_q=nq,
+                                                                  boundary=2))
         return
     rng = np.random.default_rng(nq * 10 + d)
     for length in (255, 1000, 1024 * (d + 1)):
@@ -164,16 +172,19 @@ def test_dfqt_centred_extremes(p, d, boundary):
     # every coefficient h against h (+h^2 per term) and against -h (-h^2): the
     # block digits reach both ends of [-q/2, q/2) at the centred n_q
     q = 2 ** (52 // (2 * d + 1))
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
     h = (p - 1) // 2
     length = 501
+    chunks = -(-length // (d + 1))
+    several = chunks > gf.centred_nq_max(p, d + 1, q)  # blocks per longest S_t above one
     for bv in (h, p - h):
         note(f"dfqt centred extremes p={p} d={d} boundary={boundary} b={bv}")
         a = np.full((2, length), h, dtype=np.uint8)
         b = np.full((2, length), bv, dtype=np.uint8)
-        out = host(fqt.polymul_dfqt(p, d, dev(a), dev(b), boundary=boundary, centered=1))
-        assert np.array_equal(out, want_rows(a, b, p)), bv
+        case = lambda: fqt.polymul_dfqt(p, d, dev(a), dev(b), boundary=boundary, centered=1)
+        if boundary == 2 and q > 2 ** 12 and several:
+            refused("FQT_ERR_UNSUPPORTED", case)
+        else:
+            assert np.array_equal(host(case()), want_rows(a, b, p)), bv
 
 
 def test_dfqt_centred_workload_sampled():

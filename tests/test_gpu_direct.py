@@ -54,6 +54,13 @@ def nq_direct(p, k):
     return fqt.params(p, k, 1)[1] // 4 * 4
 
 
+def refused(status, fn):
+    """The host refuses the call with `status` before any launch."""
+    with pytest.raises(fqt.FqtError) as ei:
+        fn()
+    assert ei.value.name == status, str(ei.value)
+
+
 def run(p, k, P, M, N, K, tile, seed, adversarial=False, opts=None):
     f = fqt.Field(p, k, P)
     rng = np.random.default_rng(seed)
@@ -114,14 +121,17 @@ def test_direct_adversarial_single_block(p, k, P, tile):
 @pytest.mark.parametrize("boundary", [1, 2])
 def test_direct_multiblock(p, k, P, nq, boundary):
     q, nqmax = fqt.params(p, k, 1)
-    if nq > nqmax:
-        pytest.skip("n_q above the bound")
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
     for (M, N, K) in [(40, 50, 97), (64, 128, 256), (33, 129, 1001)]:
         note(f"direct multiblock GF({p}^{k}) n_q={nq} boundary={boundary} {M}x{N}x{K}")
-        C, want = run(p, k, P, M, N, K, 11, seed=nq + K, opts={"n_q": nq, "boundary": boundary})
-        assert np.array_equal(C, want), (M, N, K)
+        case = lambda: run(p, k, P, M, N, K, 11, seed=nq + K,
+                           opts={"n_q": nq, "boundary": boundary})
+        if nq > nqmax:  # eq. (2) fails for this n_q at the largest q
+            refused("FQT_ERR_BOUNDS", case)
+        elif boundary == 2 and q > 2 ** 12:  # every K here exceeds n_q: several blocks
+            refused("FQT_ERR_UNSUPPORTED", case)
+        else:
+            C, want = case()
+            assert np.array_equal(C, want), (M, N, K)
 
 
 @pytest.mark.parametrize("p,k,P", [(3, 4, (2, 0, 0, 2)), (5, 3, (3, 3, 0))])

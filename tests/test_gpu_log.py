@@ -102,6 +102,13 @@ def test_gemm_log_refuses_fields_without_a_k_group():
     assert ei.value.name == "FQT_ERR_UNSUPPORTED"
 
 
+def refused(status, fn):
+    """The host refuses the call with `status` before any launch."""
+    with pytest.raises(fqt.FqtError) as ei:
+        fn()
+    assert ei.value.name == status, str(ei.value)
+
+
 def run(p, k, P, M, N, K, seed, opts=None, adversarial=False, lda_pad=0):
     f = fqt.Field(p, k, P)
     m = p ** k - 1
@@ -144,14 +151,18 @@ def test_gemm_log_shapes(p, k, P, tile):
 @pytest.mark.parametrize("boundary", [1, 2])
 def test_gemm_log_blocks(p, k, P, boundary):
     q, nq = fqt.params(p, k, 1)
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
     for (M, N, K, nqc) in [(40, 50, 97, 4), (64, 128, 256, 8), (33, 129, 1001, 0)]:
-        if nqc > nq:
-            continue
         note(f"gemm_log blocks GF({p}^{k}) boundary={boundary} n_q={nqc} {M}x{N}x{K}")
-        C, want = run(p, k, P, M, N, K, seed=K, opts={"tile": 11, "n_q": nqc, "boundary": boundary})
-        assert np.array_equal(C, want), (M, N, K)
+        case = lambda: run(p, k, P, M, N, K, seed=K,
+                           opts={"tile": 11, "n_q": nqc, "boundary": boundary})
+        block = (nqc or nq) // 4 * 4  # the direct tiles round n_q down to whole MFMA groups
+        if nqc > nq:  # eq. (2) fails for this n_q at the largest q
+            refused("FQT_ERR_BOUNDS", case)
+        elif boundary == 2 and q > 2 ** 12 and K > block:  # digit-sum fields above 24 bits
+            refused("FQT_ERR_UNSUPPORTED", case)
+        else:
+            C, want = case()
+            assert np.array_equal(C, want), (M, N, K)
 
 
 @pytest.mark.parametrize("p,k,P", FIELDS[:4])

@@ -42,6 +42,13 @@ def host(t):
     return t.cpu().numpy()
 
 
+def refused(status, fn):
+    """The host refuses the call with `status` before any launch."""
+    with pytest.raises(fqt.FqtError) as ei:
+        fn()
+    assert ei.value.name == status, str(ei.value)
+
+
 # ---- Alg. 1: batched polynomial products -------------------------------------
 
 def test_polymul_cfg1_exhaustive():
@@ -216,15 +223,17 @@ def test_gemm_packed_shapes(p, k, P, tile):
 @pytest.mark.parametrize("boundary", [1, 2])
 def test_gemm_packed_multiblock(p, k, P, nq, boundary):
     q, nqmax = fqt.params(p, k, 1)
-    if nq > nqmax:
-        pytest.skip("n_q above the bound")
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
     for (M, N, K) in [(40, 50, 97), (64, 64, 256)]:
         note(f"gemm packed multiblock GF({p}^{k}) n_q={nq} boundary={boundary} {M}x{N}x{K}")
-        C, want = _gemm_case(p, k, P, M, N, K, seed=nq,
-                             opts={"n_q": nq, "tile": 2, "boundary": boundary})
-        assert np.array_equal(C, want), (M, N, K)
+        case = lambda: _gemm_case(p, k, P, M, N, K, seed=nq,
+                                  opts={"n_q": nq, "tile": 2, "boundary": boundary})
+        if nq > nqmax:  # eq. (2) fails for this n_q at the largest q
+            refused("FQT_ERR_BOUNDS", case)
+        elif boundary == 2 and q > 2 ** 12:  # digit-sum fields of 2b bits exceed 24
+            refused("FQT_ERR_UNSUPPORTED", case)
+        else:
+            C, want = case()
+            assert np.array_equal(C, want), (M, N, K)
 
 
 @pytest.mark.parametrize("tile", [1, 4])
@@ -494,16 +503,18 @@ def test_autotune_batched():
 def test_gemm_packed_padded_blocks(p, k, P, nq, boundary):
     # n_q not a multiple of 4: blocks of n_q products padded to 8 or 16 MFMA slots
     q, nqmax = fqt.params(p, k, 1)
-    if nq > nqmax:
-        pytest.skip("n_q above the bound")
-    if boundary == 2 and q > 2 ** 12:
-        pytest.skip("digit-sum boundaries need q <= 2^12")
     for tile in (1, 3):
         for (M, N, K) in [(40, 50, 97), (64, 64, 256), (17, 9, 7 * nq + 3)]:
             note(f"gemm padded GF({p}^{k}) n_q={nq} boundary={boundary} tile={tile} {M}x{N}x{K}")
-            C, want = _gemm_case(p, k, P, M, N, K, seed=nq + K,
-                                 opts={"n_q": nq, "tile": tile, "boundary": boundary})
-            assert np.array_equal(C, want), (M, N, K)
+            case = lambda: _gemm_case(p, k, P, M, N, K, seed=nq + K,
+                                      opts={"n_q": nq, "tile": tile, "boundary": boundary})
+            if nq > nqmax:
+                refused("FQT_ERR_BOUNDS", case)
+            elif boundary == 2 and q > 2 ** 12:  # every K here exceeds n_q: several blocks
+                refused("FQT_ERR_UNSUPPORTED", case)
+            else:
+                C, want = case()
+                assert np.array_equal(C, want), (M, N, K)
 
 
 @pytest.mark.parametrize("boundary", [1, 2])
