@@ -192,6 +192,20 @@ def gemm_gfpk_planes(A: np.ndarray, B: np.ndarray, p: int,
     return (out % p).astype(np.uint8)
 
 
+def freivalds(A: np.ndarray, B: np.ndarray, C: np.ndarray, p: int, P_low: Sequence[int],
+              rng: np.random.Generator, vectors: int = 20) -> bool:
+    """Freivalds' test of Alg. 4's ENSURE (C = AB over GF(p^k)) on every
+    entry at once: C x = A (B x) for x uniform in GF(p^k)^(N x vectors), the
+    three products by gemm_gfpk_planes.  A true product always passes.  If
+    C != AB, a nonzero row d of C - AB gives d x uniform over the field for
+    each column of x, so a wrong C survives one column with probability at
+    most 1/p^k."""
+    x = rng.integers(0, p, size=(B.shape[1], vectors, len(P_low)), dtype=np.uint8)
+    left = gemm_gfpk_planes(C, x, p, P_low)
+    right = gemm_gfpk_planes(A, gemm_gfpk_planes(B, x, p, P_low), p, P_low)
+    return bool(np.array_equal(left, right))
+
+
 def gemm_entry(A_row: np.ndarray, B_col: np.ndarray, p: int,
                P_low: Sequence[int]) -> List[int]:
     """One entry C[i][j] = sum_l A[i][l] B[l][j] over GF(p^k), big ints.

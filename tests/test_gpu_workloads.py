@@ -1,8 +1,11 @@
 """The benchmark's full-size workloads, run the way the benchmark times them
 (each path autotuned, then called with the tuned q / n_q / tile), checked
-against the oracle on sampled outputs: whole columns of C through the
-oracle's plane products, and single entries through its one-entry dot
-product.  Batched: whole sampled products plus single entries of others.
+against the oracle on every output byte by Freivalds' test (C x = A (B x)
+for 20 random vectors x over the field: a wrong C survives one vector with
+probability at most 1/p^k), plus exact samples: whole columns of C through
+the oracle's plane products and single entries through its one-entry dot
+product.  Batched: Freivalds on every product, whole sampled products and
+single entries of others.
 """
 import sys
 
@@ -48,6 +51,8 @@ def test_workload_gemm_sampled(name, path):
     fqt.gemm(f, A, B, C, path=path)
     Ch = C.cpu().numpy()
     rng = np.random.default_rng(2024)
+    note(f"workload {name} path={path}: Freivalds, 20 vectors")
+    assert gf.freivalds(A_h, B_h, Ch, w.p, w.P_low, rng)
     cols = sorted({0, w.N - 1} | set(rng.integers(0, w.N, size=2).tolist()))
     note(f"workload {name} path={path}: oracle columns {cols}")
     assert np.array_equal(Ch[:, cols], gf.gemm_gfpk_planes(A_h, B_h[:, cols], w.p, w.P_low))
@@ -94,6 +99,12 @@ def test_workload_batched_sampled(path):
         dC.fill_(255)
         fqt.gemm_batched(f, descs, path=path)
         Ch = dC.cpu().numpy()
+        if rep == 0:
+            note(f"workload batched path={path}: Freivalds on all {len(As)} products")
+            for g in range(len(As)):
+                M, N, K = mnk[g].tolist()
+                got = Ch[offC[g]:offC[g] + M * N * k].reshape(M, N, k)
+                assert gf.freivalds(As[g], Bs[g], got, w.p, w.P_low, rng), g
         for g in whole:
             M, N, K = mnk[g].tolist()
             got = Ch[offC[g]:offC[g] + M * N * k].reshape(M, N, k)

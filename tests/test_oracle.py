@@ -281,6 +281,30 @@ def test_gemm_identity_and_associativity(p, P_low):
     assert np.array_equal(left, right)
 
 
+@pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
+def test_freivalds_accepts_the_product_and_catches_every_single_wrong_byte(p, P_low):
+    # the check the full-size GPU outputs go through: the true product
+    # passes, and C with any one coefficient changed (every position of a
+    # small C, every nonzero offset) fails with 20 vectors
+    k = len(P_low)
+    rng = np.random.default_rng(31 + p)
+    A = rng.integers(0, p, size=(4, 6, k), dtype=np.uint8)
+    B = rng.integers(0, p, size=(6, 3, k), dtype=np.uint8)
+    C = gf.gemm_gfpk_planes(A, B, p, P_low)
+    assert gf.freivalds(A, B, C, p, P_low, rng)
+    for i, j, s in itertools.product(range(4), range(3), range(k)):
+        for off in range(1, p):
+            bad = C.copy()
+            bad[i, j, s] = (int(bad[i, j, s]) + off) % p
+            assert not gf.freivalds(A, B, bad, p, P_low, rng), (i, j, s, off)
+    # a transposed-operand mistake (C = B^T A^T read as AB) is caught too
+    A2 = rng.integers(0, p, size=(5, 5, k), dtype=np.uint8)
+    B2 = rng.integers(0, p, size=(5, 5, k), dtype=np.uint8)
+    wrong = gf.gemm_gfpk_planes(B2, A2, p, P_low)
+    if not np.array_equal(wrong, gf.gemm_gfpk_planes(A2, B2, p, P_low)):
+        assert not gf.freivalds(A2, B2, wrong, p, P_low, rng)
+
+
 # --- Thm. 3: the L/H tables and Alg. 4 -------------------------------------
 
 @pytest.mark.parametrize("p,P_low", CONFIG_FIELDS)
