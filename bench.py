@@ -196,6 +196,9 @@ def cpu_batched(w, As, Bs, mnk, gf, target_s):
 
 # Kernel that carries a packed step, by tile id (1..6 LDS-staged, 7..12 direct).
 def packed_kernel_name(tile):
+    if tile == 15:
+        return ("gemm_wave_batched_kernel, tile 15 (wave-persistent 32 x 32 tiles: DQT by byte "
+                "dot products into MFMA registers + FP64 MFMA + digit-sum block steps + L/H)")
     if tile and tile >= 13:
         return (f"gemm_split_kernel, tile {tile} (2-coefficient chunks at q = 2^17, three "
                 "FP64 MFMA chunk-pair sums + REDQ_3 + L/H)")
@@ -223,7 +226,7 @@ def roofline_for(path, k, work, ms, tile=0):
                 "unit": "TOP/s", "frac": ach / PEAK_I32_VALU, "traffic": None,
                 "kernel": "gemm_plain_kernel",
                 "algorithmic": "2 k^2 integer ops per field mul-add (reductions not counted)"}
-    if tile and tile >= 13:
+    if tile and 13 <= tile <= 14:
         # d-split: three chunk-pair products per field mul-add
         ach = 6.0 * work / (ms * 1e-3)
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_FP64 / 1e12,

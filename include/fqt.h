@@ -112,6 +112,16 @@ typedef struct {
                       K runs in blocks of a multiple of 16 products.  They
                       accept log2q 0 or 17 only (FQT_ERR_INVALID_ARG) and
                       ignore boundary.
+                      Id 15 (k = 4 only, else FQT_ERR_UNSUPPORTED) is made
+                      for batches of small products: every wave computes a
+                      32 x 32 output tile alone, K-blocks of 4, 8, 12 or 16
+                      products (the largest multiple of 4 up to n_q and
+                      16), q = 2^7 (log2q 0 or 7), digit-sum block steps
+                      (boundary 0 or 2), centred packing for p = 3, 5, 7;
+                      other settings, operands not 4-byte aligned, or an
+                      operand extent ((rows - 1) ld + cols) k of 2^30 bytes
+                      or more give FQT_ERR_UNSUPPORTED.  A single product
+                      runs as a batch of one.
                       INT8 path: ids 1..3 and 7..10 expand B into B' (k x k
                       multiplication matrices) in a device workspace, then
                       run the INT8 GEMM (C' tiles 64 x 64, 128 x 128,
@@ -130,7 +140,7 @@ typedef struct {
                         radix conversion, bit fields for q = 2^b) with the
                         reduction mod p delayed to the end (Section 6).  Both
                         give identical bytes. */
-  uint32_t centered; /* packed path, LDS-staged tiles 1..6, odd p: 1 packs
+  uint32_t centered; /* packed path, LDS-staged tiles 1..6 and 15, odd p: 1 packs
                         centred coefficients (c > (p-1)/2 taken as c - p, the
                         residues Section 6 names for delayed reduction) with
                         q/2 added to every digit of a block, so a block holds

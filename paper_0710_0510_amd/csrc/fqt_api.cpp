@@ -19,6 +19,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <queue>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -151,6 +152,7 @@ struct BatchPlan {
   hipGraphExec_t exec = nullptr;
   hipStream_t cap_stream = nullptr;
   int device = -1;
+  int32_t* d_wbeg = nullptr;  // tile kWaveTile: first item of every wave
   // INT8 plans only
   I8Batch* d_i8 = nullptr;
   ExpandItem* d_exp = nullptr;
@@ -602,6 +604,48 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
     pc->centered = false;
     return ok();
   }
+  if (o && o->tile == (uint32_t)kWaveTile) {
+    // wave-persistent tile: k = 4, q = 2^7, digit-sum block steps, blocks of
+    // 4 nqg products with nqg = 1..kWaveMaxNqg fixed at compile time
+    if (k != 4)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d runs fields of k = 4 (k = %u)", kWaveTile, k);
+    const uint32_t b = max_pow2_b(k);
+    if (o->log2q && o->log2q != b)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d packs at q = 2^%u", kWaveTile, b);
+    const bool cenw = o->centered != 0;
+    if (cenw && (p == 2 || p > 8))
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d centres coefficients for odd p <= 7 (p = %u)",
+                  kWaveTile, p);
+    const uint32_t bmode = o->boundary ? o->boundary : 2u;
+    if (bmode != 2)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d takes digit-sum block steps only", kWaveTile);
+    const uint64_t q = 1ull << b, hc = (p - 1) / 2;
+    const uint64_t unit = cenw ? (uint64_t)k * hc * hc : (uint64_t)k * (p - 1) * (p - 1);
+    const uint64_t room = cenw ? q / 2 - 1 : q - 1;
+    const uint64_t nq_max = room / unit;
+    const uint64_t nq = o->n_q ? o->n_q : nq_max;
+    if (nq > nq_max)
+      return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks the %s bound for q = 2^%u", nq,
+                  cenw ? "centred" : "eq. (2)", b);
+    const uint64_t nqg = std::min<uint64_t>(nq / 4, (uint64_t)kWaveMaxNqg);
+    if (nqg == 0)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d needs blocks of at least 4 products (n_q = %"
+                  PRIu64 ")", kWaveTile, nq);
+    // digit sums in fields of 2b bits: every absorbed block adds at most q - 1
+    // to a field (its digits; centred: shifted digits), a fold leaves < p;
+    // blocks: ceil(K / (4 nqg)) and one of the bias alone
+    const uint64_t width = (1ull << (2 * b)) - 1, growth = q - 1;
+    const uint64_t cap = (width - (p - 1)) / growth;
+    const uint64_t nblocks = ((uint64_t)K + 4 * nqg - 1) / (4 * nqg) + 1;
+    pc->b = b;
+    pc->nq = pc->nq_real = (uint32_t)(4 * nqg);
+    pc->tile = (uint32_t)kWaveTile;
+    pc->multi = (uint64_t)K > 4 * nqg;
+    pc->mode = 2;
+    pc->fold = nblocks + 1 > cap ? (uint32_t)(cap - 1) : 0u;
+    pc->centered = cenw;
+    return ok();
+  }
   const bool cen = o && o->centered;
   if (cen && p == 2) return fail(FQT_ERR_UNSUPPORTED, "centred packing needs an odd p");
   if (cen && o->tile && (int)o->tile > kStagedTiles)
@@ -811,6 +855,7 @@ void fqt_field_destroy(fqt_field f) {
     hipFree(pl->d_descs);
     hipFree(pl->d_items);
     hipFree(pl->d_counter);
+    hipFree(pl->d_wbeg);
     hipFree(pl->d_i8);
     hipFree(pl->d_exp);
     hipFree(pl->d_ws);
@@ -1206,6 +1251,28 @@ void centred_params(fqt_field_s* f, uint32_t b, PackedParams* pp) {
   pp->cbias = 4503599627370496.0 + (double)B;
 }
 
+// DQT route of the LDS-staged loaders (PackedParams::dqt_flags, fqt_packed.h
+// dqt_chunk): two byte dot products per element where k = 4 and q <= 2^7;
+// for centred packing with p <= 8, a byte permutation to the offset form
+// (c + h) mod p = c' + h and the constant -h (1 + q + ... + q^(k-1)).
+void dqt_params(const fqt_field_s* f, uint32_t b, bool centered, PackedParams* pp) {
+  pp->dqt_flags = 0;
+  pp->lut_lo = pp->lut_hi = 0;
+  pp->dqt_off = 0;
+  if (f->k == 4 && b <= 7) pp->dqt_flags |= kDqtDot4;
+  if (centered && f->p <= 8) {
+    const uint32_t p = f->p, h = (p - 1) / 2;
+    uint32_t lut[2] = {0, 0};
+    for (uint32_t c = 0; c < 8; ++c) lut[c / 4] |= ((c + h) % p) << (8 * (c % 4));
+    uint64_t S = 0, qj = 1;
+    for (uint32_t j = 0; j < f->k; ++j, qj <<= b) S += qj;
+    pp->lut_lo = lut[0];
+    pp->lut_hi = lut[1];
+    pp->dqt_off = -(int32_t)(h * S);  // h S < 2^31 under eq. (2)
+    pp->dqt_flags |= kDqtLut;
+  }
+}
+
 // Buffered direct tiles address A and B through 32-bit offsets.
 static bool extents_fit_32(const GemmArgs& g, uint32_t k) {
   const uint64_t lim = 0x7fffffffull;
@@ -1214,11 +1281,18 @@ static bool extents_fit_32(const GemmArgs& g, uint32_t k) {
   return ea < lim && eb < lim;
 }
 
+static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t count,
+                               const fqt_gemm_desc* descs, hipStream_t s);
+
 static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
                               hipStream_t s) {
   PackedChoice pc;
   fqt_status st = resolve_packed(f, opts, g.K, g.M, g.N, &pc);
   if (st) return st;
+  if (pc.tile == (uint32_t)kWaveTile) {  // a batch of one
+    const fqt_gemm_desc d{g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.A, g.B, g.C};
+    return batched_wave(f, pc, 1, &d, s);
+  }
   if (direct_tile_buffered((int)pc.tile) && !extents_fit_32(g, f->k))
     return fail(FQT_ERR_UNSUPPORTED, "tile %u addresses operands below 2^31 bytes only", pc.tile);
   const uint64_t q = 1ull << pc.b;
@@ -1244,6 +1318,7 @@ static fqt_status gemm_packed(fqt_field f, const fqt_gemm_opts* opts, const Gemm
     std::lock_guard<std::mutex> lk(f->mu);
     centred_params(f, pc.b, &pp);
   }
+  dqt_params(f, pc.b, pc.centered, &pp);
   if (split)
     FQT_HIP(launch_gemm_split((int)f->k, (int)pc.tile, g, pp, s));
   else if (is_direct_tile((int)pc.tile))
@@ -1567,6 +1642,168 @@ fqt_status fqt_gemm_winograd(fqt_field f, fqt_path path, const fqt_gemm_opts* op
   return wg_rec(r, levels, M, N, K, A, lda, B, ldb, C, ldc, ws);
 }
 
+// Tile kWaveTile: wave tiles of 32 x 32 outputs, products dealt to 8 queues
+// (one per XCD) longest first, the items of a queue in the order of their
+// products; tables for q = 0 mod p (the epilogue reduces digit sums).
+static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t count,
+                               const fqt_gemm_desc* descs, hipStream_t s) {
+  const uint32_t k = f->k, p = f->p;
+  for (int64_t d = 0; d < count; ++d) {
+    const fqt_gemm_desc& e = descs[d];
+    const uint64_t lim = 1ull << 30;  // buffer offsets stay below 2^31 with a far offset
+    const uint64_t ea = e.M && e.K ? ((uint64_t)(e.M - 1) * e.lda + e.K) * k : 0;
+    const uint64_t eb = e.K && e.N ? ((uint64_t)(e.K - 1) * e.ldb + e.N) * k : 0;
+    if (ea >= lim || eb >= lim)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d addresses operands below 2^30 bytes only "
+                  "(descriptor %lld)", kWaveTile, (long long)d);
+    if ((((uintptr_t)e.A) | ((uintptr_t)e.B)) & 3)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d reads operands as words: A and B must be "
+                  "4-byte aligned (descriptor %lld)", kWaveTile, (long long)d);
+  }
+  DevTables dt;
+  fqt_status st = device_tables(f, p, &dt);  // q = 0 mod p: Q_d is the identity
+  if (st) return st;
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  PackedChoice key_pc = pc;
+  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + sizeof(PackedChoice) + sizeof(int));
+  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
+  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, &key_pc, sizeof key_pc);
+  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count + sizeof key_pc, &dev, sizeof dev);
+
+  std::lock_guard<std::mutex> lk(f->mu);
+  BatchPlan* plan = nullptr;
+  for (auto& pl : f->plans)
+    if (pl->key == key) plan = pl.get();
+  if (!plan) {
+    const int nqg = (int)(pc.nq / 4);
+    const int64_t kb = 4 * nqg;
+    hipDeviceProp_t prop;
+    FQT_HIP(hipGetDeviceProperties(&prop, dev));
+    int grid = prop.multiProcessorCount * wave_batched_occupancy(nqg, f->tbl_log2);
+    grid = std::max(8, grid / 8 * 8);  // whole rounds over the 8 XCDs
+    const int nwaves = grid * 4;
+    // cost of a 32 x 32 tile: its K-blocks plus about one block's worth of epilogue
+    auto tile_cost = [&](int64_t i) { return (descs[i].K + kb - 1) / kb + 1; };
+    // products to XCDs: longest processing time first onto the lightest
+    std::vector<int64_t> order(count);
+    for (int64_t i = 0; i < count; ++i) order[i] = i;
+    auto prod_cost = [&](int64_t i) {
+      return ((descs[i].M + 31) / 32) * ((descs[i].N + 31) / 32) * tile_cost(i);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return prod_cost(a) > prod_cost(b); });
+    std::vector<std::vector<int64_t>> xcd(8);
+    int64_t xload[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i : order) {
+      int x = 0;
+      for (int y = 1; y < 8; ++y)
+        if (xload[y] < xload[x]) x = y;
+      xcd[x].push_back(i);
+      xload[x] += prod_cost(i);
+    }
+    // tiles of an XCD's products to its waves (wave w sits on XCD (w / 4) % 8),
+    // longest first onto the lightest (a heap of wave loads)
+    std::vector<std::vector<TileItem>> wl(nwaves);
+    for (int x = 0; x < 8; ++x) {
+      std::vector<int> ws;
+      for (int w = 0; w < nwaves; ++w)
+        if ((w / 4) % 8 == x) ws.push_back(w);
+      using Slot = std::pair<int64_t, int>;  // (load, wave)
+      std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+      for (int w : ws) heap.push({0, w});
+      for (int64_t i : xcd[x]) {  // products already longest first
+        const fqt_gemm_desc& d = descs[i];
+        for (int a = 0; a < (int)((d.M + 31) / 32); ++a)
+          for (int b = 0; b < (int)((d.N + 31) / 32); ++b) {
+            Slot sl = heap.top();
+            heap.pop();
+            wl[sl.second].push_back(TileItem{(int32_t)i, a, b, 0});
+            heap.push({sl.first + tile_cost(i), sl.second});
+          }
+      }
+    }
+    std::vector<GemmArgs> args(count);
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      args[i] = GemmArgs{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
+    }
+    std::vector<TileItem> items;
+    std::vector<int32_t> wbeg(nwaves + 1);
+    for (int w = 0; w < nwaves; ++w) {
+      wbeg[w] = (int32_t)items.size();
+      items.insert(items.end(), wl[w].begin(), wl[w].end());
+    }
+    wbeg[nwaves] = (int32_t)items.size();
+    auto pl = std::make_unique<BatchPlan>();
+    pl->key = key;
+    pl->n_items = (int32_t)items.size();
+    pl->device = dev;
+    pl->grid = grid;
+    FQT_HIP(hipMalloc(&pl->d_descs, sizeof(GemmArgs) * std::max<int64_t>(count, 1)));
+    FQT_HIP(hipMalloc(&pl->d_items, sizeof(TileItem) * std::max<size_t>(items.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_wbeg, sizeof(int32_t) * wbeg.size()));
+    FQT_HIP(hipMemcpy(pl->d_descs, args.data(), sizeof(GemmArgs) * count, hipMemcpyHostToDevice));
+    if (!items.empty())
+      FQT_HIP(hipMemcpy(pl->d_items, items.data(), sizeof(TileItem) * items.size(),
+                        hipMemcpyHostToDevice));
+    FQT_HIP(hipMemcpy(pl->d_wbeg, wbeg.data(), sizeof(int32_t) * wbeg.size(),
+                      hipMemcpyHostToDevice));
+    const uint64_t q = 1ull << pc.b;
+    PackedParams pp{};
+    pp.b = pc.b;
+    pp.nq_groups = (uint32_t)nqg;
+    pp.tbl_log2 = f->tbl_log2;
+    pp.aligned = 1;
+    pp.fold_blocks = pc.fold;
+    pp.qmask = (uint32_t)(q - 1);
+    pp.qmod = 0;
+    pp.blk_real = pc.nq_real;
+    pp.fa = field_args(f, q);
+    pp.L = dt.L;
+    pp.H = dt.H;
+    if (pc.centered) {
+      centred_params(f, pc.b, &pp);  // the bias 2^52 + sum (q/2) q^i; f->mu is held
+      // every digit of every block carries q/2: take off n_blocks (q/2) (L + H)(1..1)
+      // with the q = 0 tables
+      const auto& ht = host_tables(f, p);
+      const uint32_t beta = (uint32_t)((q / 2) % p);
+      uint32_t il = 0;
+      for (uint32_t dd = 0; dd < k; ++dd) il |= beta << (f->cb * dd);
+      const uint32_t lw = ht.first[il], hw = ht.second[il];
+      uint32_t neg = 0;
+      for (uint32_t i = 0; i < k; ++i) {
+        const uint32_t cc = (((lw >> (8 * i)) & 0xffu) + ((hw >> (8 * i)) & 0xffu)) % p;
+        neg |= ((p - cc) % p) << (8 * i);
+      }
+      pp.c0neg = neg;
+    }
+    dqt_params(f, pc.b, pc.centered, &pp);
+    if (!(pp.dqt_flags & kDqtLut)) {  // the kernel always permutes: identity bytes
+      pp.lut_lo = 0x03020100u;
+      pp.lut_hi = 0x07060504u;
+      pp.dqt_off = 0;
+    }
+    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    if (pl->n_items > 0)
+      le = launch_gemm_wave_batched(nqg, pl->d_descs, pl->d_items, pl->d_wbeg, pl->grid, pp,
+                                    pl->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (le != hipSuccess) return hip_fail(le, "wave batched launch (capture)");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    pl->graph = graph;
+    FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
+    plan = pl.get();
+    f->plans.push_back(std::move(pl));
+  }
+  if (plan->n_items == 0) return ok();
+  FQT_HIP(hipGraphLaunch(plan->exec, s));
+  return ok();
+}
+
 static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t count,
                                  const fqt_gemm_desc* descs, hipStream_t s) {
   int64_t Kmax = 0, Mmax = 0, Nmax = 0;
@@ -1581,6 +1818,7 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
   if (!o.tile) o.tile = 2;
   fqt_status st = resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc);
   if (st) return st;
+  if (pc.tile == (uint32_t)kWaveTile) return batched_wave(f, pc, count, descs, s);
   if (direct_tile_buffered((int)pc.tile))
     for (int64_t d = 0; d < count; ++d) {
       const fqt_gemm_desc& e = descs[d];
@@ -1659,6 +1897,7 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     pp.L = dt.L;
     pp.H = dt.H;
     if (pc.centered) centred_params(f, pc.b, &pp);  // f->mu is held
+    dqt_params(f, pc.b, pc.centered, &pp);
     // Capture the persistent launch once; later calls replay the graph.
     FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
     FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -2032,10 +2271,12 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
     const uint64_t unit_nq = cen ? (uint64_t)f->k * h * h : (uint64_t)f->k * (f->p - 1) * (f->p - 1);
     const uint64_t room = cen ? (1ull << (b - 1)) - 1 : (1ull << b) - 1;
     const uint32_t nq_top = unit_nq ? (uint32_t)std::min<uint64_t>(room / unit_nq, 1u << 30) : 0;
-    for (uint32_t t = 1; t <= (uint32_t)(cen ? kStagedTiles : kPackedTiles); ++t)
+    for (uint32_t t = 1; t <= (uint32_t)kPackedTiles; ++t)
       for (uint32_t bm : {1u, 2u})
       for (uint32_t nqc : {0u, nq_top & ~3u}) {
         if (nqc && nqc == nq_top) continue;  // same as the default
+        if (is_split_tile((int)t)) continue;  // below, with their own q
+        if (cen && t > (uint32_t)kStagedTiles && t != (uint32_t)kWaveTile) continue;
         fqt_gemm_opts o{b, nqc, t, bm, cen};
         PackedChoice pc;
         if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) != FQT_OK) continue;
@@ -2047,7 +2288,7 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   }
   // d-split tiles bring their own q (one block, no boundary step)
   if (only != FQT_PATH_INT8)
-    for (uint32_t t = (uint32_t)kFirstSplitTile; t <= (uint32_t)kPackedTiles; ++t) {
+    for (uint32_t t = (uint32_t)kFirstSplitTile; t <= (uint32_t)kLastSplitTile; ++t) {
       fqt_gemm_opts o{0, 0, t, 0, 0};
       PackedChoice pc;
       if (resolve_packed(f, &o, Kmax, Mmax, Nmax, &pc) == FQT_OK)

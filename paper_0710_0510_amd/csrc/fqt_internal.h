@@ -17,6 +17,9 @@ struct GemmArgs {
   int64_t M, N, K, lda, ldb, ldc;
 };
 
+// PackedParams::dqt_flags
+constexpr uint32_t kDqtLut = 1u, kDqtDot4 = 2u;
+
 // Parameters of the packed-FP64 path (Alg. 4 with K-blocks, eq. (2)).
 struct PackedParams {
   uint32_t b;          // q = 2^b
@@ -31,6 +34,11 @@ struct PackedParams {
   uint32_t c0neg;      // centred: -(L + H of the shift's residues), one word
                        // (d-FQT: (q/2) mod p, the shift of every digit of a block)
   double cbias;        // centred: 2^52 + sum_{i<2k-1} (q/2) q^i, every block's seed
+  // DQT of the LDS-staged loaders (fqt_packed.h dqt_chunk):
+  uint32_t dqt_flags;  // kDqtLut: centred bytes through the perm table below (p <= 8);
+                       // kDqtDot4: k = 4 and q <= 2^7, two byte dot products per element
+  uint32_t lut_lo, lut_hi;  // byte c -> (c + h) mod p for c = 0..7, h = (p-1)/2
+  int32_t dqt_off;     // -h (1 + q + ... + q^(k-1)): offset form back to centred values
   FieldArgs fa;
   const uint32_t* L;   // device tables of Thm. 3 (binary index, Section 5.3)
   const uint32_t* H;
@@ -126,21 +134,24 @@ constexpr int kStagedTiles = 6;
 constexpr bool direct_tile_buffered(int id) { return id == 12; }
 // d-split kernels (k_gemm_split.hip), k = 3 or 4, wave tile 16 x 64:
 // id kFirstSplitTile = 2 x 2 waves, kFirstSplitTile + 1 = 4 x 1 waves.
-constexpr int kFirstSplitTile = 13;
-constexpr int kPackedTiles = 14;
+constexpr int kFirstSplitTile = 13, kLastSplitTile = 14;
+// Wave-persistent tile for batches over GF(p^4) (k_gemm_wave.hip): every wave
+// computes 32 x 32 outputs alone, K-blocks fixed at compile time.
+constexpr int kWaveTile = 15;
+constexpr int kPackedTiles = 15;
 #ifndef FQT_DIRECT_STAGES
 #define FQT_DIRECT_STAGES 2
 #endif
 constexpr int kDirectStages = FQT_DIRECT_STAGES;  // K-steps in flight per wave
 inline bool is_direct_tile(int id) { return id > kStagedTiles && id < kFirstSplitTile; }
-inline bool is_split_tile(int id) { return id >= kFirstSplitTile; }
+inline bool is_split_tile(int id) { return id >= kFirstSplitTile && id <= kLastSplitTile; }
 inline bool direct_tile_multi_ok(int id) { return id == 11; }
 // Workgroup tile (rows x columns of C) of every tile id.
 inline void packed_tile_shape(int id, int* bm, int* bn) {
-  //                                     1   2    3    4   5   6   7   8    9   10   11  12  13  14
-  static const int m[kPackedTiles] = {32, 64, 64, 128, 64, 32, 64, 64, 128, 64, 32, 64, 32, 64};
+  //                                     1   2    3    4   5   6   7   8    9   10   11  12  13  14  15
+  static const int m[kPackedTiles] = {32, 64, 64, 128, 64, 32, 64, 64, 128, 64, 32, 64, 32, 64, 32};
   static const int n[kPackedTiles] = {32, 64, 128, 128, 32, 64, 64, 64, 128, 128, 128, 64, 128,
-                                      64};
+                                      64, 32};
   *bm = m[id - 1];
   *bn = n[id - 1];
 }
@@ -202,7 +213,16 @@ hipError_t launch_mat_addsub(int k, uint32_t p, const uint8_t* X, int64_t ldx, c
                              int64_t ldy, uint8_t* Z, int64_t ldz, int64_t rows, int64_t cols,
                              bool sub, hipStream_t s);
 
-// d-split kernels (tile ids >= kFirstSplitTile, k = 3 or 4).
+// Wave-persistent batched kernel (tile kWaveTile, k = 4, q = 2^7): blocks of
+// 4 nqg products (nqg 1..4), items = 32 x 32 wave tiles; wave w of the grid
+// (workgroup w / 4) computes items[wave_begin[w] .. wave_begin[w + 1]).
+hipError_t launch_gemm_wave_batched(int nqg, const GemmArgs* descs, const TileItem* items,
+                                    const int32_t* wave_begin, int grid, const PackedParams& pp,
+                                    hipStream_t s);
+int wave_batched_occupancy(int nqg, uint32_t tbl_log2);
+constexpr int kWaveMaxNqg = 4;
+
+// d-split kernels (tile ids kFirstSplitTile..kLastSplitTile, k = 3 or 4).
 hipError_t launch_gemm_split(int k, int tile, const GemmArgs& g, const PackedParams& pp,
                              hipStream_t s);
 hipError_t launch_gemm_split_batched(int k, int tile, const GemmArgs* descs,

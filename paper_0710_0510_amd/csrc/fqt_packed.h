@@ -137,6 +137,58 @@ __device__ __forceinline__ double packed_elem_centred(const uint32_t (&raw)[NWD]
   return (double)v;
 }
 
+// DQT of a chunk of 4 consecutive elements (KE raw words) into 4 binary64
+// values, the form the LDS-staged loaders store.  Every VALU instruction here
+// costs issue cycles of the SIMD that runs the FP64 MFMAs (they do not
+// overlap on gfx950), so the conversion takes the shortest route the field
+// admits:
+//  * centred, p <= 8 (kDqtLut): one byte permutation per word maps every
+//    coefficient c to its offset form (c + h) mod p = c' + h, c' in [-h, h];
+//    the packed offset form minus h (1 + q + ... + q^(k-1)) is sum c'_j q^j.
+//  * k = 4, q <= 2^7 (kDqtDot4): an element is one word; two byte dot
+//    products give c0 + q c1 and c2 + q c3, one shift-add joins them (the
+//    offset above rides in the first dot product's addend).
+//  * otherwise the byte-select shifts of dqt_u32, or the flag arithmetic of
+//    packed_elem_centred for centred fields with p > 8.
+template <int KE>
+__device__ __forceinline__ void dqt_chunk(uint32_t (&raw)[KE], const DqtShifts& sh,
+                                          const PackedParams& pp, double (&out)[4]) {
+  if (pp.centered && !(pp.dqt_flags & kDqtLut)) {
+    const uint32_t hmask = (0x7fu - (pp.fa.p - 1) / 2) * 0x01010101u;
+    uint32_t gt[KE];
+#pragma unroll
+    for (int w = 0; w < KE; ++w) gt[w] = centred_flags(raw[w], hmask);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = packed_elem_centred<KE, KE>(raw, gt, e, sh, pp.fa.p);
+    return;
+  }
+  if (pp.dqt_flags & kDqtLut) {
+#pragma unroll
+    for (int w = 0; w < KE; ++w) raw[w] = perm_b32(pp.lut_hi, pp.lut_lo, raw[w]);
+  }
+  if constexpr (KE == 4) {
+    if (pp.dqt_flags & kDqtDot4) {
+      const uint32_t q = 1u << sh.s[1];
+      const uint32_t wlo = 1u | (q << 8), whi = (1u << 16) | (q << 24);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t lo = __builtin_amdgcn_udot4(raw[e], wlo, (uint32_t)pp.dqt_off, false);
+        const uint32_t hi = __builtin_amdgcn_udot4(raw[e], whi, 0u, false);
+        out[e] = (double)(int32_t)(lo + (hi << sh.s[2]));
+      }
+      return;
+    }
+  }
+  if (pp.dqt_flags & kDqtLut) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      out[e] = (double)(int32_t)(dqt_u32<KE, KE>(raw, e, sh) + (uint32_t)pp.dqt_off);
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) out[e] = packed_elem<KE, KE>(raw, e, sh);
+}
+
 // Centred packing's final correction: n_blocks times the constant -(L + H)
 // of the shift's residues, every coefficient scaled mod p.
 template <int KE>

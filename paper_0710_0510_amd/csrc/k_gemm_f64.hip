@@ -204,45 +204,23 @@ __device__ __forceinline__ void packed_tile(const GemmArgs& g, int tile_m, int t
       load_chunk<KE>(g.B, k0 + bkr + r * BRS, n0 + 4 * bnc, g.K, g.N, g.ldb, aligned, rb[r]);
   };
 
-  const uint32_t hmask = (0x7fu - (pp.fa.p - 1) / 2) * 0x01010101u;
   auto lstore = [&](int buf) {
     double* as = As + buf * T::LDS_A;
     double* bs = Bs + buf * T::LDS_B;
-    if (pp.centered) {
 #pragma unroll
-      for (int r = 0; r < T::RA; ++r) {
-        uint32_t gt[KE];
+    for (int r = 0; r < T::RA; ++r) {
+      double v[4];
+      dqt_chunk<KE>(ra[r], sh, pp, v);
 #pragma unroll
-        for (int w = 0; w < KE; ++w) gt[w] = centred_flags(ra[r][w], hmask);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          as[(arow + r * ARS) * T::SA + 4 * akc + e] =
-              packed_elem_centred<KE, KE>(ra[r], gt, e, sh, pp.fa.p);
-      }
-#pragma unroll
-      for (int r = 0; r < T::RB; ++r) {
-        uint32_t gt[KE];
-#pragma unroll
-        for (int w = 0; w < KE; ++w) gt[w] = centred_flags(rb[r][w], hmask);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] =
-              packed_elem_centred<KE, KE>(rb[r], gt, e, sh, pp.fa.p);
-      }
-      return;
+      for (int e = 0; e < 4; ++e) as[(arow + r * ARS) * T::SA + 4 * akc + e] = v[e];
     }
 #pragma unroll
-    for (int r = 0; r < T::RA; ++r)
+    for (int r = 0; r < T::RB; ++r) {
+      double v[4];
+      dqt_chunk<KE>(rb[r], sh, pp, v);
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        as[(arow + r * ARS) * T::SA + 4 * akc + e] =
-            packed_elem<KE, KE>(ra[r], e, sh);
-#pragma unroll
-    for (int r = 0; r < T::RB; ++r)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] =
-            packed_elem<KE, KE>(rb[r], e, sh);
+      for (int e = 0; e < 4; ++e) bs[(bkr + r * BRS) * T::SB + 4 * bnc + e] = v[e];
+    }
   };
 
   uint32_t nbound = 0, nblk = 1;  // blocks seeded so far (the centred correction counts them)

@@ -8,6 +8,7 @@ import time
 import types
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -57,6 +58,10 @@ def test_hbm_rate_and_sized_run():
 
 def test_roofline_names_the_kernel_of_the_tuned_tile():
     assert "gemm_direct_kernel" in bench.roofline_for("packed", 2, 1e9, 1.0, 12)["kernel"]
+    wave = bench.roofline_for("packed", 4, 1e9, 1.0, 15)
+    assert "gemm_wave_batched_kernel" in wave["kernel"]
+    assert wave["achieved"] == pytest.approx(2.0 * 1e9 / 1e-3 / 1e12)  # 2 flop per mul-add
+    assert "gemm_split_kernel" in bench.roofline_for("packed", 4, 1e9, 1.0, 14)["kernel"]
     assert "gemm_i8f_kernel" in bench.roofline_for("int8", 2, 1e9, 1.0, 5)["kernel"]
     rl = bench.roofline_for("packed", 2, 1024 ** 3, 0.03876, 12)
     assert abs(rl["frac"] - 2 * 1024 ** 3 / 0.03876e-3 / 78.6e12) < 1e-12

@@ -245,7 +245,7 @@ def test_autotune_argument_errors():
 
 
 def test_tile_counts():
-    assert fqt.tile_count("packed") == 14
+    assert fqt.tile_count("packed") == 15
     assert fqt.tile_count("int8") == 10
 
 
