@@ -449,27 +449,28 @@ def bench_batched(w, args, torch, fqt, gf):
                     args.steps, args.warmup, torch)
     tile = int(popts.get("tile", 0))
 
-    # INT8 coefficient-wise path, autotuned, byte-identical to the packed output
-    dI = torch.zeros_like(dC)
-    dI_descs = descs_for(dI)
-    iopts = fqt.autotune(f, dI_descs, only="int8")[1]
-    tuned["int8"] = iopts
-    fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts)
-    torch.cuda.synchronize()
-    if not torch.equal(dI, dC):
-        raise SystemExit("parity failure: batched INT8 path differs from the packed path")
-    i8_ms = time_steps(lambda: fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts),
-                       args.steps, args.warmup, torch)
-    del dI
-
     paths = {"packed": {"value": work / (ms * 1e-3), "ms_per_step": ms, "tile": tile,
-                        "roofline_frac": roofline_for("packed", k, work, ms, tile)["frac"]},
-             "int8": {"value": work / (i8_ms * 1e-3), "ms_per_step": i8_ms,
-                      "tile": int(iopts.get("tile", 0)),
-                      "roofline_frac": roofline_for("int8", k, work, i8_ms,
-                                                    int(iopts.get("tile", 0)))["frac"]}}
-    identical = ["int8"]
-    if not args.no_plain:
+                        "roofline_frac": roofline_for("packed", k, work, ms, tile)["frac"]}}
+    identical = []
+    if "int8" in args.paths:
+        # INT8 coefficient-wise path, autotuned, byte-identical to the packed output
+        dI = torch.zeros_like(dC)
+        dI_descs = descs_for(dI)
+        iopts = fqt.autotune(f, dI_descs, only="int8")[1]
+        tuned["int8"] = iopts
+        fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts)
+        torch.cuda.synchronize()
+        if not torch.equal(dI, dC):
+            raise SystemExit("parity failure: batched INT8 path differs from the packed path")
+        i8_ms = time_steps(lambda: fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts),
+                           args.steps, args.warmup, torch)
+        del dI
+        paths["int8"] = {"value": work / (i8_ms * 1e-3), "ms_per_step": i8_ms,
+                         "tile": int(iopts.get("tile", 0)),
+                         "roofline_frac": roofline_for("int8", k, work, i8_ms,
+                                                       int(iopts.get("tile", 0)))["frac"]}
+        identical.append("int8")
+    if "plain" in args.paths and not args.no_plain:
         # the plain comparator: one launch per product, as the metric asks
         dR = torch.zeros_like(dC)
         dR_descs = descs_for(dR)
@@ -672,6 +673,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true",
                     help="batched: leave out the plain per-product comparator (4096 launches), "
                          "e.g. under a counter-collecting profiler")
+    ap.add_argument("--paths", default="packed,int8,plain",
+                    help="batched: the paths to run beside the packed one (comma list of "
+                         "int8, plain)")
     ap.add_argument("--opts", default=None,
                     help="batched: JSON options of the packed path instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

@@ -21,7 +21,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["fqt_api.cpp", "k_transform.hip", "k_gemm_f64.hip", "k_gemm_direct.hip", "k_gemm_i8.hip",
            "k_plain.hip", "k_dfqt.hip", "k_gemm_split.hip",
-           "k_gemm_log.hip", "k_winograd.hip", "k_gemm_wave.hip"]
+           "k_gemm_log.hip", "k_winograd.hip", "k_gemm_wave.hip",
+           "k_gemm_i8cs.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -1412,11 +1412,18 @@ static fqt_status gemm_int8_fused(fqt_field f, uint32_t tile, const GemmArgs& g,
 }
 
 // INT8 path: exact while n_d (p-1)^2 < 2^31 per accumulation run (eq. (3)).
+static fqt_status batched_i8cs(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
+                               hipStream_t s);
+
 static fqt_status gemm_int8(fqt_field f, const fqt_gemm_opts* opts, const GemmArgs& g,
                             hipStream_t s) {
   const int64_t k = f->k, p = f->p;
   uint32_t tile = (opts && opts->tile) ? opts->tile : 0;
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
+  if (tile == kInt8StripTile) {  // a batch of one
+    const fqt_gemm_desc d{g.M, g.N, g.K, g.lda, g.ldb, g.ldc, g.A, g.B, g.C};
+    return batched_i8cs(f, 1, &d, s);
+  }
   if (i8_fused_tile(tile)) return gemm_int8_fused(f, tile, g, s);
   // B'^T rows are padded to whole 128-byte K-tiles of the INT8 GEMM
   const int64_t NN = g.N * k, KK = g.K * k, KKpad = (KK + 127) / 128 * 128;
@@ -1925,11 +1932,138 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
   return ok();
 }
 
+// INT8 tile 11: strips of 16 output elements dealt to workgroups (products
+// to XCDs longest first, then strips to the XCD's workgroups the same way).
+static fqt_status batched_i8cs(fqt_field f, int64_t count, const fqt_gemm_desc* descs,
+                               hipStream_t s) {
+  const uint32_t k = f->k, p = f->p;
+  if (k != 4)
+    return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u runs fields of k = 4 (k = %u)",
+                kInt8StripTile, k);
+  int64_t Kmax = 0;
+  for (int64_t d = 0; d < count; ++d) {
+    const fqt_gemm_desc& e = descs[d];
+    const uint64_t lim = 1ull << 30;
+    const uint64_t ea = e.M && e.K ? ((uint64_t)(e.M - 1) * e.lda + e.K) * k : 0;
+    const uint64_t eb = e.K && e.N ? ((uint64_t)(e.K - 1) * e.ldb + e.N) * k : 0;
+    if (ea >= lim || eb >= lim || (uint64_t)e.lda * k * 256 >= lim ||
+        (uint64_t)e.ldb * k * 256 >= lim)
+      return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u addresses operands below 2^30 bytes and "
+                  "rows below 2^22 bytes only (descriptor %lld)", kInt8StripTile, (long long)d);
+    if ((((uintptr_t)e.A) | ((uintptr_t)e.B)) & 3)
+      return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u reads operands as words: A and B must be "
+                  "4-byte aligned (descriptor %lld)", kInt8StripTile, (long long)d);
+    Kmax = std::max(Kmax, e.K);
+  }
+  uint8_t* mt = nullptr;  // before taking the field lock (device_mt takes it)
+  fqt_status mst = device_mt(f, &mt);
+  if (mst) return mst;
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + 2 * sizeof(int));
+  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
+  const int tag[2] = {-(int)kInt8StripTile, dev};
+  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, tag, sizeof tag);
+  std::lock_guard<std::mutex> lk(f->mu);
+  BatchPlan* plan = nullptr;
+  for (auto& pp : f->plans)
+    if (pp->key == key) plan = pp.get();
+  if (!plan) {
+    hipDeviceProp_t prop;
+    FQT_HIP(hipGetDeviceProperties(&prop, dev));
+    int grid = prop.multiProcessorCount * i8cs_occupancy(f->tbl_log2);
+    grid = std::max(8, grid / 8 * 8);
+    // cost of a strip: chunks of 32 rows per wave (4 waves) times K-tiles of 64
+    auto strip_cost = [&](int64_t i) {
+      const fqt_gemm_desc& d = descs[i];
+      return ((d.M + 127) / 128) * ((d.K + 63) / 64 + 1);
+    };
+    auto prod_cost = [&](int64_t i) { return ((descs[i].N + 15) / 16) * strip_cost(i); };
+    std::vector<int64_t> order(count);
+    for (int64_t i = 0; i < count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return prod_cost(a) > prod_cost(b); });
+    std::vector<std::vector<int64_t>> xcd(8);
+    int64_t xload[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t i : order) {
+      int x = 0;
+      for (int y = 1; y < 8; ++y)
+        if (xload[y] < xload[x]) x = y;
+      xcd[x].push_back(i);
+      xload[x] += prod_cost(i);
+    }
+    std::vector<std::vector<int32_t>> wl(grid);  // (product, strip) pairs per workgroup
+    for (int x = 0; x < 8; ++x) {
+      using Slot = std::pair<int64_t, int>;
+      std::priority_queue<Slot, std::vector<Slot>, std::greater<Slot>> heap;
+      for (int w = x; w < grid; w += 8) heap.push({0, w});
+      for (int64_t i : xcd[x])
+        for (int nc = 0; nc < (int)((descs[i].N + 15) / 16); ++nc) {
+          Slot sl = heap.top();
+          heap.pop();
+          wl[sl.second].insert(wl[sl.second].end(), {(int32_t)i, nc, 0, 0});
+          heap.push({sl.first + strip_cost(i), sl.second});
+        }
+    }
+    std::vector<int32_t> items, wbeg(grid + 1);
+    for (int w = 0; w < grid; ++w) {
+      wbeg[w] = (int32_t)(items.size() / 4);
+      items.insert(items.end(), wl[w].begin(), wl[w].end());
+    }
+    wbeg[grid] = (int32_t)(items.size() / 4);
+    std::vector<GemmArgs> args(count);
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      args[i] = GemmArgs{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
+    }
+    auto pl = std::make_unique<BatchPlan>();
+    pl->key = key;
+    pl->device = dev;
+    pl->n_items = (int32_t)(items.size() / 4);
+    pl->grid = grid;
+    FQT_HIP(hipMalloc(&pl->d_descs, sizeof(GemmArgs) * std::max<int64_t>(count, 1)));
+    FQT_HIP(hipMalloc(&pl->d_items, sizeof(int32_t) * std::max<size_t>(items.size(), 4)));
+    FQT_HIP(hipMalloc(&pl->d_wbeg, sizeof(int32_t) * wbeg.size()));
+    FQT_HIP(hipMemcpy(pl->d_descs, args.data(), sizeof(GemmArgs) * count, hipMemcpyHostToDevice));
+    if (!items.empty())
+      FQT_HIP(hipMemcpy(pl->d_items, items.data(), sizeof(int32_t) * items.size(),
+                        hipMemcpyHostToDevice));
+    FQT_HIP(hipMemcpy(pl->d_wbeg, wbeg.data(), sizeof(int32_t) * wbeg.size(),
+                      hipMemcpyHostToDevice));
+    // INT32 sums grow by at most 64 k (p-1)^2 per K-tile of 64 elements
+    const uint64_t per_tile = 64ull * k * (p - 1) * (p - 1);
+    const uint64_t cap = per_tile ? (0x7fffffffull - (p - 1)) / per_tile : 0;
+    const uint64_t ktiles = ((uint64_t)Kmax + 63) / 64;
+    const uint32_t red = (per_tile && ktiles > cap) ? (uint32_t)std::max<uint64_t>(cap - 1, 1) : 0;
+    const uint64_t top = red ? (uint64_t)red * per_tile + p : (uint64_t)ktiles * per_tile;
+    const uint32_t small = top < (1ull << 25) ? 1u : 0u;
+    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    if (pl->n_items > 0)
+      le = launch_gemm_i8cs_batched(pl->d_descs, reinterpret_cast<const int32_t*>(pl->d_items),
+                                    pl->d_wbeg, pl->grid, mt, f->tbl_log2, p, f->cb, red, small,
+                                    pl->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (le != hipSuccess) return hip_fail(le, "INT8 strip batched launch (capture)");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    pl->graph = graph;
+    FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
+    plan = pl.get();
+    f->plans.push_back(std::move(pl));
+  }
+  if (plan->n_items == 0) return ok();
+  FQT_HIP(hipGraphLaunch(plan->exec, s));
+  return ok();
+}
+
 static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t count,
                                const fqt_gemm_desc* descs, hipStream_t s) {
   const int64_t k = f->k, p = f->p;
   uint32_t tile = (opts && opts->tile) ? opts->tile : 8;  // measured best on uneven batches
   if (tile > (uint32_t)kInt8Tiles) return fail(FQT_ERR_INVALID_ARG, "unknown INT8 tile id %u", tile);
+  if (tile == kInt8StripTile) return batched_i8cs(f, count, descs, s);
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
   std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + 2 * sizeof(int));
@@ -2319,21 +2453,31 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   size_t best_i = 0;
   std::vector<double> times(cands.size(), 0.0);
   fqt_status status = FQT_OK;
+  bool have_ref = false;
+  size_t ref_i = 0;
   for (size_t i = 0; i < cands.size() && status == FQT_OK; ++i) {
     status = run(cands[i]);  // warm-up: builds plans and graphs
+    if (status == FQT_ERR_UNSUPPORTED) {  // refused on the host for this problem: skip it
+      status = FQT_OK;
+      times[i] = -1.0;
+      continue;
+    }
     if (status) break;
-    status = i == 0 ? snapshot(f, count, descs, st, &ref, &ref_n)
-                    : snapshot(f, count, descs, st, &cur, &cur_n);
+    status = !have_ref ? snapshot(f, count, descs, st, &ref, &ref_n)
+                       : snapshot(f, count, descs, st, &cur, &cur_n);
     if (status) break;
-    if (i > 0 && std::memcmp(cur.p, ref.p, ref_n) != 0) {
+    if (!have_ref) {
+      have_ref = true;
+      ref_i = i;
+    } else if (std::memcmp(cur.p, ref.p, ref_n) != 0) {
       size_t at = 0;
       while (at < ref_n && cur.p[at] == ref.p[at]) ++at;
       size_t nbad = 0;
       for (size_t j = 0; j < ref_n; ++j) nbad += cur.p[j] != ref.p[j];
       status = fail(FQT_ERR_DEVICE, "autotune candidate %zu (path %d, q = 2^%u, tile %u, boundary "
-                    "%u) is not byte-identical to candidate 0: %zu of %zu bytes differ, first at "
-                    "byte %zu (%u vs %u)", i, (int)cands[i].path, cands[i].opts.log2q,
-                    cands[i].opts.tile, cands[i].opts.boundary, nbad, ref_n, at,
+                    "%u) is not byte-identical to candidate %zu: %zu of %zu bytes differ, first "
+                    "at byte %zu (%u vs %u)", i, (int)cands[i].path, cands[i].opts.log2q,
+                    cands[i].opts.tile, cands[i].opts.boundary, ref_i, nbad, ref_n, at,
                     (unsigned)cur.p[at], (unsigned)ref.p[at]);
       break;
     }
@@ -2369,6 +2513,9 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   hipEventDestroy(e1);
   if (status) return status;
 
+  if (status == FQT_OK && !have_ref)
+    status = fail(FQT_ERR_UNSUPPORTED, "every candidate was refused for this problem");
+  if (status) return status;
   const Candidate& w = cands[best_i];
   {
     std::lock_guard<std::mutex> lk(f->mu);

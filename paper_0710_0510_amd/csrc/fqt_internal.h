@@ -232,7 +232,17 @@ int split_batched_occupancy(int k, int tile, uint32_t tbl_log2);
 
 // INT8 path, tile ids 1..3, 7..10: B -> B'^T expansion in HBM, then the INT8
 // MFMA GEMM; ids 4..6: one kernel that expands each K-tile of B in LDS.
-constexpr int kInt8Tiles = 10;
+constexpr int kInt8Tiles = 11;
+// INT8 id 11 (k_gemm_i8cs.hip, k = 4): one workgroup per strip of 16 output
+// elements of a product, B' of each K-tile built in LDS once for all rows;
+// items = (product, strip) int32 pairs padded to 4 words, workgroup w takes
+// items[wg_begin[w] .. wg_begin[w + 1]).
+constexpr uint32_t kInt8StripTile = 11;
+hipError_t launch_gemm_i8cs_batched(const GemmArgs* descs, const int32_t* items_raw,
+                                    const int32_t* wg_begin, int grid, const uint8_t* mt,
+                                    uint32_t tbl_log2, uint32_t p, uint32_t cb,
+                                    uint32_t red_tiles, uint32_t small, hipStream_t s);
+int i8cs_occupancy(uint32_t tbl_log2);
 // Block of the B -> B'^T expansion: kExpandL elements of K x kExpandN of N.
 constexpr int kExpandL = 128, kExpandN = 16;
 constexpr bool i8_fused_tile(uint32_t tile) { return tile >= 4 && tile <= 6; }

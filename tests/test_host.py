@@ -177,7 +177,9 @@ def test_buffered_tile_refuses_extents_beyond_32_bits():
 
 def test_int8_tile_ids_and_lds_refusal():
     f = fqt.Field(7, 2, (1, 0))
-    assert _gemm_status(f, "int8", 4, 4, 4, 4, 4, 4, opts={"tile": 11}) == "FQT_ERR_INVALID_ARG"
+    assert _gemm_status(f, "int8", 4, 4, 4, 4, 4, 4, opts={"tile": 12}) == "FQT_ERR_INVALID_ARG"
+    # id 11 (strips of 16 outputs, B' built in LDS) runs k = 4 fields only
+    assert _gemm_status(f, "int8", 4, 4, 4, 4, 4, 4, opts={"tile": 11}) == "FQT_ERR_UNSUPPORTED"
     # GF(13^3): a 12-bit table index, 4096 entries of 16 bytes; with the
     # 128 x 128 operand tiles of id 5 that exceeds one CU's LDS
     g = fqt.Field(13, 3, (1, 0, 4))
@@ -246,7 +248,7 @@ def test_autotune_argument_errors():
 
 def test_tile_counts():
     assert fqt.tile_count("packed") == 15
-    assert fqt.tile_count("int8") == 10
+    assert fqt.tile_count("int8") == 11
 
 
 def test_autotune_rejects_plain_only():
