@@ -655,6 +655,143 @@ def bench_dfqt(w, args, torch, fqt, gf):
     return out
 
 
+def bench_dfqt_batched(w, args, torch, fqt, gf):
+    """d-FQT over a batch of uneven pairs (Section 6) in one persistent
+    launch replayed from a captured graph; work = sum of la lb GF(p)
+    mul-adds (the classical count).  Beside it, the same pairs padded to the
+    longest length through the equal-length d-FQT and through the classical
+    product with delayed reduction (eq. (3)), the comparator."""
+    from paper_0710_0510_amd import workloads as W
+    lens, a_h, b_h = W.poly_uneven_inputs(w)
+    la, lb = lens[:, 0], lens[:, 1]
+    lc = la + lb - 1
+    oa = np.concatenate(([0], np.cumsum(la)))
+    ob = np.concatenate(([0], np.cumsum(lb)))
+    oc = np.concatenate(([0], np.cumsum(lc)))
+    a, b = torch.from_numpy(a_h).cuda(), torch.from_numpy(b_h).cuda()
+    c = torch.empty(int(lc.sum()), dtype=torch.uint8, device="cuda")
+    descs = fqt.poly_descs_flat(a, b, c, lens)
+    work = int((la * lb).sum())
+    hi = int(lens.max())
+    # the padded comparator's operands, built on the host by index arrays
+    rows_a, rows_b = np.repeat(np.arange(w.count), la), np.repeat(np.arange(w.count), lb)
+    A = np.zeros((w.count, hi), np.uint8)
+    B = np.zeros((w.count, hi), np.uint8)
+    A[rows_a, np.arange(len(a_h)) - np.repeat(oa[:-1], la)] = a_h
+    B[rows_b, np.arange(len(b_h)) - np.repeat(ob[:-1], lb)] = b_h
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    ref = fqt.polymul_delayed(w.p, Ad, Bd)
+    # positions of every batch output inside the padded rows
+    gather = torch.from_numpy(np.repeat(np.arange(w.count) * (2 * hi - 1) - oc[:-1], lc)
+                              + np.arange(int(lc.sum()))).cuda()
+    ref_flat = ref.view(-1)[gather]
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(77)
+    picks = rng.integers(0, w.count, size=max(4, args.samples // 16)).tolist()
+    ref_h = ref_flat.cpu().numpy()
+    bad = sum(gf.polymul_long(a_h[oa[i]:oa[i + 1]].tolist(), b_h[ob[i]:ob[i + 1]].tolist(), w.p)
+              != ref_h[oc[i]:oc[i + 1]].tolist() for i in picks)
+    if bad:
+        raise SystemExit(f"parity failure: the delayed comparator differs from the oracle on {bad}")
+
+    def chunk_products(d):
+        ke = d + 1
+        return int((((la + ke - 1) // ke) * ((lb + ke - 1) // ke)).sum())
+
+    variants = {}
+    for d in range(8):
+        for cen in ((0, 1) if w.p % 2 else (0,)):
+            fn = lambda: fqt.polymul_dfqt_batched(w.p, d, descs, centered=cen)
+            c.fill_(0xEE)
+            try:
+                fn()
+            except fqt.FqtError as e:  # eq. (2) admits no q for this chunk length
+                if e.name in ("FQT_ERR_BOUNDS", "FQT_ERR_UNSUPPORTED"):
+                    continue
+                raise
+            torch.cuda.synchronize()
+            if not torch.equal(c, ref_flat):
+                raise SystemExit(f"parity failure: batched d-FQT with d = {d}, centered = {cen} "
+                                 "differs from the comparator")
+            size_counts(fn, args, torch)
+            ms = time_steps(fn, args.steps, args.warmup, torch)
+            fl = 2.0 * chunk_products(d) / (ms * 1e-3)
+            variants[(d, cen)] = {"value": work / (ms * 1e-3), "ms_per_step": ms,
+                                  "fp64_tflops": fl / 1e12, "centered": cen}
+    tuned = fqt.autotune_polymul(w.p, descs)
+    # the padded equal-length d-FQT and the comparator, at the workload's d
+    cen_w = min((key for key in variants if key[0] == w.d),
+                key=lambda key: variants[key]["ms_per_step"])[1]
+    pad_out = fqt.polymul_dfqt(w.p, w.d, Ad, Bd, centered=cen_w)
+    torch.cuda.synchronize()
+    if not torch.equal(pad_out, ref):
+        raise SystemExit("parity failure: padded d-FQT differs from the comparator")
+    pms = time_steps(lambda: fqt.polymul_dfqt(w.p, w.d, Ad, Bd, out=pad_out, centered=cen_w),
+                     args.steps, args.warmup, torch)
+    dms = time_steps(lambda: fqt.polymul_delayed(w.p, Ad, Bd, out=ref), args.steps, args.warmup,
+                     torch)
+    main_key = (tuned["d"], tuned["centered"])
+    if main_key not in variants:  # the autotuner's d is outside the timed set
+        fn = lambda: fqt.polymul_dfqt_batched(w.p, main_key[0], descs, centered=main_key[1])
+        c.fill_(0xEE)
+        fn()
+        torch.cuda.synchronize()
+        if not torch.equal(c, ref_flat):
+            raise SystemExit(f"parity failure: batched d-FQT {main_key} differs")
+        ms = time_steps(fn, args.steps, args.warmup, torch)
+        variants[main_key] = {"value": work / (ms * 1e-3), "ms_per_step": ms,
+                              "fp64_tflops": 2.0 * chunk_products(main_key[0]) / (ms * 1e-3)
+                              / 1e12, "centered": main_key[1]}
+    main_v = variants[main_key]
+    out = {
+        "metric": METRIC, "value": main_v["value"], "unit": "GF(p) mul-adds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_v["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "p": w.p, "count": w.count, "lengths": f"{w.lo}..{w.hi}",
+                   "seed": w.seed, "d": main_key[0], "centered": main_key[1],
+                   "autotuned": True},
+        "products_per_s": w.count / (main_v["ms_per_step"] * 1e-3),
+        "roofline": {"bound": "alu", "achieved": main_v["fp64_tflops"], "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": main_v["fp64_tflops"] * 1e12 / PEAK_FP64,
+                     "traffic": None, "kernel": "dfqt_batched_kernel (queue of uneven pairs: "
+                     "DQT + FP64 FMA convolution + block digits + overlap-add)",
+                     "algorithmic": "2 flop per product of packed chunks, "
+                                    "ceil(la/(d+1)) ceil(lb/(d+1)) per pair"},
+        "paths": {**{f"dfqt_batched_d{d}" + ("_centred" if cen else ""):
+                     {"value": v["value"], "ms_per_step": v["ms_per_step"]}
+                     for (d, cen), v in variants.items()},
+                  f"dfqt_padded_d{w.d}": {"value": work / (pms * 1e-3), "ms_per_step": pms,
+                                         "padded_to": hi},
+                  "delayed_padded": {"value": work / (dms * 1e-3), "ms_per_step": dms,
+                                     "padded_to": hi}},
+        "comparator": {"kind": "classical, delayed reduction (eq. (3)), pairs padded to "
+                               f"{hi} coefficients", "value": work / (dms * 1e-3),
+                       "ms_per_step": dms},
+        "speedup_vs_delayed": dms / main_v["ms_per_step"],
+        "speedup_vs_padded_dfqt": pms / main_v["ms_per_step"],
+        "parity": {"sampled_products_vs_oracle": len(picks), "sampled_mismatches": bad,
+                   "every_variant_identical_to_comparator": True},
+    }
+    out["hbm"] = hbm_rate(int(la.sum() + lb.sum() + lc.sum()), main_v["ms_per_step"], None)
+    if not args.no_cpu:
+        n = 16
+        t0 = time.time()
+        for i in range(n):
+            gf.polymul_long(a_h[oa[i]:oa[i + 1]].tolist(), b_h[ob[i]:ob[i + 1]].tolist(), w.p)
+        dt = max(time.time() - t0, 1e-6)
+        n = int(max(16, min(w.count, n * args.cpu_seconds / dt)))
+        t0 = time.time()
+        for i in range(n):
+            gf.polymul_long(a_h[oa[i]:oa[i + 1]].tolist(), b_h[ob[i]:ob[i + 1]].tolist(), w.p)
+        dt = time.time() - t0
+        out["cpu_baseline"] = {"value": int((la[:n] * lb[:n]).sum()) / dt,
+                               "unit": "GF(p) mul-adds/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first {n} of the {w.count} pairs, numpy int64 "
+                                         f"convolution, {dt:.1f} s", "host": host_info()}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -709,6 +846,8 @@ def main():
         out = bench_gemm(w, args, torch, fqt, gf)
     elif w.kind == "dfqt":
         out = bench_dfqt(w, args, torch, fqt, gf)
+    elif w.kind == "dfqt_batched":
+        out = bench_dfqt_batched(w, args, torch, fqt, gf)
     elif w.kind == "batched":
         out = bench_batched(w, args, torch, fqt, gf)
     else:

@@ -35,6 +35,18 @@
  *   - Launches are asynchronous on the caller's stream (NULL = default
  *     stream).  A device failure shows up as FQT_ERR_DEVICE from the call that
  *     observed it.
+ *   - Ordering: the library keeps device state per field and device (tables,
+ *     INT8 and Winograd workspaces, batch plans with their queue counters)
+ *     and, for the polynomial batches, per process and device.  Calls that
+ *     share such state must be ordered on the device: issue them on one
+ *     stream, or make a second stream wait for the first.  Calls on one
+ *     field that overlap in time on two streams may race and write wrong
+ *     bytes; different fields never share state.
+ *   - Batch plans: a batched call builds a plan the first time it sees a
+ *     descriptor list and replays it later.  At most 32 plans are kept per
+ *     field (and 32 polynomial-batch plans per process); building one more
+ *     destroys the least recently used after waiting for the device to go
+ *     idle.  fqt_field_destroy waits likewise and releases everything.
  *   - fqt_last_error() returns a thread-local, human-readable message for the
  *     last failing call of the calling thread.
  *   - Nothing throws across this ABI.
@@ -265,6 +277,43 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
                             const uint8_t* b, int64_t count, int64_t len, uint8_t* c,
                             fqt_stream_t s);
 
+/* One pair of an uneven polynomial batch (device pointers): c = a * b in
+ * GF(p)[X], a of la coefficients, b of lb, c of la + lb - 1 (nothing is
+ * written when la or lb is 0). */
+typedef struct {
+  int64_t la, lb;
+  const uint8_t* a;
+  const uint8_t* b;
+  uint8_t* c;
+} fqt_poly_desc;
+
+/* The d-FQT of Section 6 (as fqt_polymul_dfqt, same p, d, log2q, n_q,
+ * boundary and centered, with the same errors) on a batch of pairs of
+ * uneven lengths, in ONE persistent launch: every wave takes pairs from a
+ * queue ordered longest first and multiplies each one alone.  n_q and the
+ * block steps are chosen for the batch's longest chunk-pair sum.
+ *   descs  host array of count descriptors; every byte of a, b in [0, p);
+ *          la, lb >= 0 (FQT_ERR_INVALID_ARG if negative), at most
+ *          1024 (d+1) each (FQT_ERR_UNSUPPORTED beyond); c must not overlap
+ *          its own a or b (FQT_ERR_INVALID_ARG).
+ * The first call with a given descriptor list builds a plan (queue order,
+ * device descriptors) and captures the launch in a hipGraph; later calls
+ * with the same list replay it, on whatever stream s is given.  Replays of
+ * one plan must not overlap on two streams (they share the plan's queue
+ * counter). */
+fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                                    uint32_t boundary, uint32_t centered, int64_t count,
+                                    const fqt_poly_desc* descs, fqt_stream_t s);
+
+/* Time the d-FQT of an uneven batch for every chunk length d + 1 = 1..8 and,
+ * for odd p, both chunk representations (default q and n_q); every
+ * candidate's output must be byte-identical to the first admissible one's
+ * (else FQT_ERR_DEVICE).  Writes the fastest (d, centered).  cache_path
+ * (NULL: none) is a JSON-lines file read first and appended to. */
+fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* descs,
+                                const char* cache_path, uint32_t* d, uint32_t* centered,
+                                fqt_stream_t s);
+
 /* The comparator of Section 6: the classical product with delayed reduction
  * (eq. (3)): every coefficient accumulated in 32-bit integers and reduced
  * mod p once (or every n_d products if len (p-1)^2 could overflow).
@@ -301,8 +350,10 @@ fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path,
  *   descs  host array of count descriptors (device data pointers).
  * The first call with a given descriptor list builds a plan (tiles sorted by
  * cost, uploaded to the device) and captures it in a hipGraph; later calls
- * with an identical list and stream replay the graph.  FQT_PATH_PLAIN runs
- * one launch per product (the comparator). */
+ * with an identical list replay the graph on whatever stream s is given
+ * (replays of one plan must not overlap on two streams: they share its queue
+ * counter and, on FQT_PATH_INT8, the field's B' workspace).  FQT_PATH_PLAIN
+ * runs one launch per product (the comparator). */
 fqt_status fqt_gemm_gfpk_batched(fqt_field f, fqt_path path, int64_t count,
                                  const fqt_gemm_desc* descs, fqt_stream_t s);
 

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cinttypes>
 #include <cmath>
 #include <cstdarg>
@@ -25,6 +26,7 @@
 #include <vector>
 
 #include "fqt_internal.h"
+#include "plan_cache.h"
 
 using namespace fqt;
 
@@ -141,8 +143,15 @@ struct DevTables {
   uint32_t* H = nullptr;
 };
 
+// Calls on one device copy their work into a plan once per descriptor list:
+// device copies of the descriptors, the schedule, the captured graph.  The
+// plan owns them; its destructor waits for the device (a replay may still be
+// in flight) and releases them.
 struct BatchPlan {
-  std::vector<uint8_t> key;
+  BatchPlan() = default;
+  BatchPlan(const BatchPlan&) = delete;
+  BatchPlan& operator=(const BatchPlan&) = delete;
+  ~BatchPlan();
   GemmArgs* d_descs = nullptr;
   TileItem* d_items = nullptr;
   uint32_t* d_counter = nullptr;
@@ -150,14 +159,40 @@ struct BatchPlan {
   int grid = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipStream_t cap_stream = nullptr;
   int device = -1;
   int32_t* d_wbeg = nullptr;  // tile kWaveTile: first item of every wave
   // INT8 plans only
   I8Batch* d_i8 = nullptr;
   ExpandItem* d_exp = nullptr;
-  uint8_t* d_ws = nullptr;
+  bool shares_ws = false;  // its graph reads the field's batch workspace of B'
 };
+
+// Runs `fn` with `device` current, then restores the caller's device.
+template <class Fn>
+void on_device(int device, Fn fn) {
+  int cur = -1;
+  const bool sw = device >= 0 && hipGetDevice(&cur) == hipSuccess && cur != device;
+  if (sw) hipSetDevice(device);
+  fn();
+  if (sw) hipSetDevice(cur);
+}
+
+BatchPlan::~BatchPlan() {
+  on_device(device, [&] {
+    if (exec) hipDeviceSynchronize();
+    if (exec) hipGraphExecDestroy(exec);
+    if (graph) hipGraphDestroy(graph);
+    hipFree(d_descs);
+    hipFree(d_items);
+    hipFree(d_counter);
+    hipFree(d_wbeg);
+    hipFree(d_i8);
+    hipFree(d_exp);
+  });
+}
+
+// Plans kept per field; the least recently used beyond this are destroyed.
+constexpr size_t kMaxPlans = 32;
 
 struct Workspace {
   uint8_t* ptr = nullptr;
@@ -200,7 +235,9 @@ struct fqt_field_s {
   std::mutex mu;
   std::map<uint32_t, std::pair<std::vector<uint32_t>, std::vector<uint32_t>>> host_tables;
   std::map<std::pair<int, uint32_t>, DevTables> dev_tables;
-  std::vector<std::unique_ptr<BatchPlan>> plans;
+  fqt_detail::PlanCache<BatchPlan> plans{kMaxPlans};
+  std::map<int, hipStream_t> cap_stream;  // per device: where plans are captured
+  std::map<int, Workspace> bws;  // per device: B' of batched INT8 plans, shared by all
   std::map<std::string, TuneEntry> tuned;
   std::map<int, Workspace> ws;  // per device: B' of the INT8 path
   std::map<int, Workspace> wg_ws;  // per device: temporaries of Winograd's recursion
@@ -211,6 +248,20 @@ struct fqt_field_s {
 };
 
 namespace {
+
+// The stream the plans of `f` on device `dev` are captured on: one per field
+// and device, created on first use (f->mu is held).
+hipError_t capture_stream(fqt_field f, int dev, hipStream_t* out) {
+  auto it = f->cap_stream.find(dev);
+  if (it == f->cap_stream.end()) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    it = f->cap_stream.emplace(dev, st).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
 
 FieldArgs field_args(const fqt_field_s* f, uint64_t q) {
   FieldArgs fa{};
@@ -558,6 +609,12 @@ struct PackedChoice {
   bool centered;      // centred packing, digits shifted by q/2
 };
 
+// The fields of a choice as words (no padding bytes), for plan keys.
+std::array<uint32_t, 8> choice_words(const PackedChoice& c) {
+  return {c.b, c.nq, c.nq_real, c.tile, (uint32_t)c.multi, (uint32_t)c.mode, c.fold,
+          (uint32_t)c.centered};
+}
+
 // d-split tiles: chunks of 2 coefficients packed at q = 2^17 (q^3 < 2^53).
 // The largest digits are those of S_K = sum (a_lo + a_hi)(b_lo + b_hi), up
 // to w (p-1)^2 per k with w = 8 for k = 4 and 4 for k = 3: one block takes
@@ -795,6 +852,9 @@ fqt_status fqt_field_create(uint32_t p, uint32_t k, const uint32_t* P_low, fqt_f
 
 void fqt_field_destroy(fqt_field f) {
   if (!f) return;
+  f->plans.clear();  // waits for replays in flight
+  for (auto& kv : f->cap_stream) on_device(kv.first, [&] { hipStreamDestroy(kv.second); });
+  for (auto& kv : f->bws) on_device(kv.first, [&] { hipFree(kv.second.ptr); });
   for (auto& kv : f->dev_tables) {
     int cur = 0;
     if (hipGetDevice(&cur) == hipSuccess) {
@@ -847,18 +907,6 @@ void fqt_field_destroy(fqt_field f) {
       hipFree(kv.second.H);
       hipSetDevice(cur);
     }
-  }
-  for (auto& pl : f->plans) {
-    if (pl->exec) hipGraphExecDestroy(pl->exec);
-    if (pl->graph) hipGraphDestroy(pl->graph);
-    if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
-    hipFree(pl->d_descs);
-    hipFree(pl->d_items);
-    hipFree(pl->d_counter);
-    hipFree(pl->d_wbeg);
-    hipFree(pl->d_i8);
-    hipFree(pl->d_exp);
-    hipFree(pl->d_ws);
   }
   delete f;
 }
@@ -999,23 +1047,27 @@ fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q, const uint8_t* 
   return ok();
 }
 
-fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
-                            uint32_t boundary, uint32_t centered, const uint8_t* a,
-                            const uint8_t* b, int64_t count, int64_t len, uint8_t* c,
-                            fqt_stream_t s) {
+}  // extern "C"
+
+namespace {
+
+// Resolved parameters of the d-FQT (Section 6) for products whose longest
+// chunk-pair sum has nprod products.
+struct DfqtChoice {
+  uint32_t ke, bq, fold;
+  uint64_t q, nq;
+  int mode;
+};
+
+fqt_status resolve_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q, uint32_t boundary,
+                        uint32_t centered, int64_t nprod, DfqtChoice* out) {
   if (!is_prime_u32(p)) return fail(FQT_ERR_NOT_PRIME, "p = %u is not prime", p);
   if (p > 127) return fail(FQT_ERR_UNSUPPORTED, "p = %u above 127", p);
   if (d > 7) return fail(FQT_ERR_UNSUPPORTED, "d = %u above 7 (chunks of at most 8 coefficients)", d);
-  if (count < 0 || len < 1) return fail(FQT_ERR_INVALID_ARG, "count < 0 or len < 1");
-  if (count && (!a || !b || !c)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
-  const uint32_t ke = d + 1;
-  const int64_t nch = (len + ke - 1) / ke;
-  if (nch > kDfqtMaxChunks)
-    return fail(FQT_ERR_UNSUPPORTED, "len = %lld needs %lld chunks, above %d", (long long)len,
-                (long long)nch, kDfqtMaxChunks);
   if (boundary > 2) return fail(FQT_ERR_INVALID_ARG, "unknown boundary mode %u", boundary);
   if (centered > 1) return fail(FQT_ERR_INVALID_ARG, "centered is 0 or 1");
   if (centered && p == 2) return fail(FQT_ERR_UNSUPPORTED, "centred chunks need an odd p");
+  const uint32_t ke = d + 1;
   // eq. (2) with k = d+1 coefficients per packed number: q^(2d+1) < 2^53,
   // q > n_q (d+1)(p-1)^2; q = 2^b with (2d+1) b <= 52 so that the biased
   // accumulator holds the sum, and the residue bytes stay below bit 52
@@ -1038,7 +1090,7 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
   if (nq > nq_max)
     return fail(FQT_ERR_BOUNDS, "n_q = %" PRIu64 " breaks the %s bound", nq,
                 centered ? "centred" : "eq. (2)");
-  const bool multi = (uint64_t)nch > nq;  // the longest S_t has nch products
+  const bool multi = (uint64_t)nprod > nq;  // the longest S_t has nprod products
   if (multi && bq != bmax)
     return fail(FQT_ERR_UNSUPPORTED, "several blocks need the largest q = 2^%u", bmax);
   int mode = 0;
@@ -1049,18 +1101,86 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
       return fail(FQT_ERR_UNSUPPORTED, "digit-sum boundaries need q <= 2^12 (q = 2^%u)", bq);
     const uint64_t width = mode == 1 ? 65535 : q * q - 1;
     const uint64_t growth = mode == 1 ? 2 * (uint64_t)p - 1 : centered ? q - 1 : nq * unit;
-    const uint64_t nblocks = ((uint64_t)nch + nq - 1) / nq + 1;
+    const uint64_t nblocks = ((uint64_t)nprod + nq - 1) / nq + 1;
     const uint64_t cap = (width - (p - 1)) / std::max<uint64_t>(growth, 1);
     if (cap < 2) return fail(FQT_ERR_UNSUPPORTED, "residue lanes too narrow for n_q = %" PRIu64, nq);
     if (nblocks + 1 > cap) fold = (uint32_t)(cap - 1);
   }
+  *out = DfqtChoice{ke, bq, fold, q, nq, mode};
+  return ok();
+}
+
+PackedParams dfqt_params(uint32_t p, uint32_t centered, const DfqtChoice& c) {
+  fqt_field_s tmp;
+  tmp.p = p;
+  tmp.k = c.ke;
+  tmp.cb = std::max(1u, ceil_log2(p));
+  PackedParams pp{};
+  pp.fa = field_args(&tmp, c.q);
+  pp.qmod = (uint32_t)(c.q % p);
+  pp.fold_blocks = c.fold;
+  pp.b = c.bq;
+  if (centered) {
+    uint64_t B = 0;
+    for (uint32_t j = 0; j < 2 * c.ke - 1; ++j) B = B * c.q + c.q / 2;  // below q^(2d+1) <= 2^52
+    pp.centered = 1;
+    pp.cbias = 4503599627370496.0 + (double)B;
+    pp.c0neg = (uint32_t)((c.q / 2) % p);
+  }
+  return pp;
+}
+
+// Plans of uneven polynomial batches (no field handle: one process-wide
+// cache, bounded like a field's, and one capture stream per device).
+struct PolyPlan {
+  PolyPlan() = default;
+  PolyPlan(const PolyPlan&) = delete;
+  PolyPlan& operator=(const PolyPlan&) = delete;
+  ~PolyPlan() {
+    on_device(device, [&] {
+      if (exec) hipDeviceSynchronize();
+      if (exec) hipGraphExecDestroy(exec);
+      if (graph) hipGraphDestroy(graph);
+      hipFree(d_descs);
+      hipFree(d_order);
+      hipFree(d_counter);
+    });
+  }
+  PolyDesc* d_descs = nullptr;
+  int32_t* d_order = nullptr;
+  uint32_t* d_counter = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int device = -1;
+  int32_t live = 0;  // pairs with output
+};
+std::mutex g_poly_mu;
+fqt_detail::PlanCache<PolyPlan> g_poly_plans{kMaxPlans};
+std::map<int, hipStream_t> g_poly_cap;  // per device; lives until the process ends
+
+}  // namespace
+
+extern "C" {
+
+fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                            uint32_t boundary, uint32_t centered, const uint8_t* a,
+                            const uint8_t* b, int64_t count, int64_t len, uint8_t* c,
+                            fqt_stream_t s) {
+  if (count < 0 || len < 1) return fail(FQT_ERR_INVALID_ARG, "count < 0 or len < 1");
+  if (count && (!a || !b || !c)) return fail(FQT_ERR_INVALID_ARG, "null buffer");
+  if (d <= 7) {
+    const int64_t nch = (len + d) / (d + 1);
+    if (nch > kDfqtMaxChunks)
+      return fail(FQT_ERR_UNSUPPORTED, "len = %lld needs %lld chunks, above %d", (long long)len,
+                  (long long)nch, kDfqtMaxChunks);
+  }
+  DfqtChoice ch;
+  fqt_status st = resolve_dfqt(p, d, log2q, n_q, boundary, centered, (len + d) / (d + 1), &ch);
+  if (st) return st;
+  const int64_t nch = (len + ch.ke - 1) / ch.ke;
   const size_t nc = (size_t)count * (size_t)(2 * len - 1), ni = (size_t)count * (size_t)len;
   if (overlap(c, nc, a, ni) || overlap(c, nc, b, ni))
     return fail(FQT_ERR_INVALID_ARG, "output overlaps an input");
-  fqt_field_s tmp;
-  tmp.p = p;
-  tmp.k = ke;
-  tmp.cb = std::max(1u, ceil_log2(p));
   DfqtArgs g{};
   g.a = a;
   g.b = b;
@@ -1068,20 +1188,106 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
   g.count = count;
   g.len = (int32_t)len;
   g.nch = (int32_t)nch;
-  g.nq = (uint32_t)nq;
-  g.lg2q = bq;
-  g.pp.fa = field_args(&tmp, q);
-  g.pp.qmod = (uint32_t)(q % p);
-  g.pp.fold_blocks = fold;
-  g.pp.b = bq;
-  if (centered) {
-    uint64_t B = 0;
-    for (uint32_t j = 0; j < 2 * ke - 1; ++j) B = B * q + q / 2;  // below q^(2d+1) <= 2^52
-    g.pp.centered = 1;
-    g.pp.cbias = 4503599627370496.0 + (double)B;
-    g.pp.c0neg = (uint32_t)((q / 2) % p);
+  g.nq = (uint32_t)ch.nq;
+  g.lg2q = ch.bq;
+  g.pp = dfqt_params(p, centered, ch);
+  FQT_HIP(launch_dfqt((int)ch.ke, ch.mode, g, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                                    uint32_t boundary, uint32_t centered, int64_t count,
+                                    const fqt_poly_desc* descs, fqt_stream_t s) {
+  if (count < 0 || (count && !descs)) return fail(FQT_ERR_INVALID_ARG, "bad descriptor array");
+  if (count > INT32_MAX) return fail(FQT_ERR_UNSUPPORTED, "more than 2^31 - 1 pairs");
+  if (d > 7) return fail(FQT_ERR_UNSUPPORTED, "d = %u above 7 (chunks of at most 8 coefficients)", d);
+  const int64_t ke = d + 1;
+  int64_t nprod = 1, live = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const fqt_poly_desc& e = descs[i];
+    if (e.la < 0 || e.lb < 0)
+      return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: negative length", (long long)i);
+    if (e.la == 0 || e.lb == 0) continue;
+    ++live;
+    if (!e.a || !e.b || !e.c)
+      return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: null buffer", (long long)i);
+    const int64_t nca = (e.la + ke - 1) / ke, ncb = (e.lb + ke - 1) / ke;
+    if (nca > kDfqtMaxChunks || ncb > kDfqtMaxChunks)
+      return fail(FQT_ERR_UNSUPPORTED, "descriptor %lld: %lld x %lld coefficients need more "
+                  "than %d chunks", (long long)i, (long long)e.la, (long long)e.lb,
+                  kDfqtMaxChunks);
+    const size_t nc = (size_t)(e.la + e.lb - 1);
+    if (overlap(e.c, nc, e.a, (size_t)e.la) || overlap(e.c, nc, e.b, (size_t)e.lb))
+      return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: output overlaps an input", (long long)i);
+    nprod = std::max(nprod, std::min(nca, ncb));
   }
-  FQT_HIP(launch_dfqt((int)ke, mode, g, (hipStream_t)s));
+  DfqtChoice ch;
+  fqt_status st = resolve_dfqt(p, d, log2q, n_q, boundary, centered, nprod, &ch);
+  if (st) return st;
+  if (live == 0) return ok();  // nothing to write: an empty product has no coefficient
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  // plan key: descriptors, resolved parameters, p, centring, device
+  const uint32_t tag[8] = {p, ch.ke, ch.bq, (uint32_t)ch.nq, (uint32_t)ch.mode, ch.fold,
+                           centered, (uint32_t)dev};
+  const fqt_detail::PlanKey key{descs, sizeof(fqt_poly_desc) * count, fqt_detail::key_tail(tag)};
+  std::lock_guard<std::mutex> lk(g_poly_mu);
+  PolyPlan* plan = g_poly_plans.find(key);
+  if (!plan) {
+    // longest first: a pair costs about nca ncb chunk products
+    std::vector<int32_t> order;
+    for (int64_t i = 0; i < count; ++i)
+      if (descs[i].la > 0 && descs[i].lb > 0) order.push_back((int32_t)i);
+    auto cost = [&](int32_t i) {
+      return ((descs[i].la + ke - 1) / ke) * ((descs[i].lb + ke - 1) / ke);
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+    auto pl = std::make_unique<PolyPlan>();
+    pl->device = dev;
+    pl->live = (int32_t)order.size();
+    FQT_HIP(hipMalloc(&pl->d_descs, sizeof(PolyDesc) * count));
+    FQT_HIP(hipMalloc(&pl->d_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_counter, 2 * sizeof(uint32_t)));
+    static_assert(sizeof(PolyDesc) == sizeof(fqt_poly_desc), "descriptor layouts agree");
+    FQT_HIP(hipMemcpy(pl->d_descs, descs, sizeof(PolyDesc) * count, hipMemcpyHostToDevice));
+    if (!order.empty())
+      FQT_HIP(hipMemcpy(pl->d_order, order.data(), sizeof(int32_t) * order.size(),
+                        hipMemcpyHostToDevice));
+    FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
+    hipDeviceProp_t prop;
+    FQT_HIP(hipGetDeviceProperties(&prop, dev));
+    // four waves per workgroup, each with 16 KiB of LDS per operand: two
+    // workgroups per CU; never more waves than pairs
+    const int grid = std::max(1, std::min(prop.multiProcessorCount * 2, (pl->live + 3) / 4));
+    DfqtBatchArgs g{};
+    g.descs = pl->d_descs;
+    g.order = pl->d_order;
+    g.count = pl->live;
+    g.total_waves = (uint32_t)grid * 4u;
+    g.counter = pl->d_counter;
+    g.nq = (uint32_t)ch.nq;
+    g.lg2q = ch.bq;
+    g.pp = dfqt_params(p, centered, ch);
+    if (!g_poly_cap.count(dev)) {
+      hipStream_t ns = nullptr;
+      FQT_HIP(hipStreamCreateWithFlags(&ns, hipStreamNonBlocking));
+      g_poly_cap[dev] = ns;
+    }
+    hipStream_t cs = g_poly_cap[dev];
+    FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    if (pl->live > 0) le = launch_dfqt_batched((int)ch.ke, ch.mode, g, grid, cs);
+    hipGraph_t graph = nullptr;
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    pl->graph = graph;
+    if (le != hipSuccess) return hip_fail(le, "d-FQT batched launch (capture)");
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
+    plan = g_poly_plans.insert(key, std::move(pl));
+  }
+  if (plan->live == 0) return ok();
+  FQT_HIP(hipGraphLaunch(plan->exec, (hipStream_t)s));
   return ok();
 }
 
@@ -1466,12 +1672,22 @@ fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opt
   if (st) return st;
   GemmArgs g{A, B, C, M, N, K, lda, ldb, ldc};
   if (M == 0 || N == 0) return ok();
+  // Tuned options stand for a shape class (power-of-two buckets of M, N, K)
+  // and were checked admissible at the K they were tuned on; a larger K of
+  // the same class may need more K-blocks than they allow.  Such a refusal
+  // falls back to the path's defaults.
+  fqt_gemm_opts tuned{};
+  bool from_tuned = false;
   if (path == FQT_PATH_AUTO) {
     std::lock_guard<std::mutex> lk(f->mu);
     auto it = f->tuned.find(shape_key(f, 1, M, N, K));
     if (it != f->tuned.end()) {
       path = it->second.path;
-      if (!opts) opts = &it->second.opts;
+      if (!opts) {
+        tuned = it->second.opts;
+        opts = &tuned;
+        from_tuned = true;
+      }
     } else {
       path = FQT_PATH_PACKED_F64;
     }
@@ -1480,21 +1696,30 @@ fqt_status fqt_gemm_gfpk_ex(fqt_field f, fqt_path path, const fqt_gemm_opts* opt
     std::lock_guard<std::mutex> lk(f->mu);
     auto it = f->tuned.find(shape_key(f, 1, M, N, K) +
                             (path == FQT_PATH_INT8 ? "_int8" : "_packed"));
-    if (it != f->tuned.end()) opts = &it->second.opts;
-  }
-  switch (path) {
-    case FQT_PATH_PACKED_F64:
-      return gemm_packed(f, opts, g, (hipStream_t)s);
-    case FQT_PATH_PLAIN: {
-      const FieldArgs fa = field_args(f, 2);
-      FQT_HIP(launch_gemm_plain((int)f->k, g, fa, f->P_low, (hipStream_t)s));
-      return ok();
+    if (it != f->tuned.end()) {
+      tuned = it->second.opts;
+      opts = &tuned;
+      from_tuned = true;
     }
-    case FQT_PATH_INT8:
-      return gemm_int8(f, opts, g, (hipStream_t)s);
-    default:
-      return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
   }
+  auto run = [&](const fqt_gemm_opts* o) -> fqt_status {
+    switch (path) {
+      case FQT_PATH_PACKED_F64:
+        return gemm_packed(f, o, g, (hipStream_t)s);
+      case FQT_PATH_PLAIN: {
+        const FieldArgs fa = field_args(f, 2);
+        FQT_HIP(launch_gemm_plain((int)f->k, g, fa, f->P_low, (hipStream_t)s));
+        return ok();
+      }
+      case FQT_PATH_INT8:
+        return gemm_int8(f, o, g, (hipStream_t)s);
+      default:
+        return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
+    }
+  };
+  st = run(opts);
+  if (from_tuned && (st == FQT_ERR_UNSUPPORTED || st == FQT_ERR_BOUNDS)) st = run(nullptr);
+  return st;
 }
 
 fqt_status fqt_gemm_gfpk(fqt_field f, fqt_path path, int64_t M, int64_t N, int64_t K,
@@ -1672,16 +1897,11 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
   if (st) return st;
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
-  PackedChoice key_pc = pc;
-  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + sizeof(PackedChoice) + sizeof(int));
-  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
-  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, &key_pc, sizeof key_pc);
-  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count + sizeof key_pc, &dev, sizeof dev);
+  const fqt_detail::PlanKey key{descs, sizeof(fqt_gemm_desc) * count,
+                                fqt_detail::key_tail(choice_words(pc), dev)};
 
   std::lock_guard<std::mutex> lk(f->mu);
-  BatchPlan* plan = nullptr;
-  for (auto& pl : f->plans)
-    if (pl->key == key) plan = pl.get();
+  BatchPlan* plan = f->plans.find(key);
   if (!plan) {
     const int nqg = (int)(pc.nq / 4);
     const int64_t kb = 4 * nqg;
@@ -1743,7 +1963,6 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
     }
     wbeg[nwaves] = (int32_t)items.size();
     auto pl = std::make_unique<BatchPlan>();
-    pl->key = key;
     pl->n_items = (int32_t)items.size();
     pl->device = dev;
     pl->grid = grid;
@@ -1791,20 +2010,20 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
       pp.lut_hi = 0x07060504u;
       pp.dqt_off = 0;
     }
-    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t cs = nullptr;
+    FQT_HIP(capture_stream(f, dev, &cs));
+    FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     if (pl->n_items > 0)
       le = launch_gemm_wave_batched(nqg, pl->d_descs, pl->d_items, pl->d_wbeg, pl->grid, pp,
-                                    pl->cap_stream);
+                                    cs);
     hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    pl->graph = graph;
     if (le != hipSuccess) return hip_fail(le, "wave batched launch (capture)");
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    pl->graph = graph;
     FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
-    plan = pl.get();
-    f->plans.push_back(std::move(pl));
+    plan = f->plans.insert(key, std::move(pl));
   }
   if (plan->n_items == 0) return ok();
   FQT_HIP(hipGraphLaunch(plan->exec, s));
@@ -1843,15 +2062,11 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
   FQT_HIP(hipGetDevice(&dev));
 
   // Plan key: the descriptor bytes, the resolved parameters and the device.
-  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + sizeof(PackedChoice) + sizeof(int));
-  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
-  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, &pc, sizeof pc);
-  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count + sizeof pc, &dev, sizeof dev);
+  const fqt_detail::PlanKey key{descs, sizeof(fqt_gemm_desc) * count,
+                                fqt_detail::key_tail(choice_words(pc), dev)};
 
   std::lock_guard<std::mutex> lk(f->mu);
-  BatchPlan* plan = nullptr;
-  for (auto& p : f->plans)
-    if (p->key == key) plan = p.get();
+  BatchPlan* plan = f->plans.find(key);
   if (!plan) {
     int bm, bn;
     packed_tile_shape((int)pc.tile, &bm, &bn);
@@ -1872,7 +2087,6 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
       return descs[x.gemm].K > descs[y.gemm].K;
     });
     auto pl = std::make_unique<BatchPlan>();
-    pl->key = key;
     pl->n_items = (int32_t)items.size();
     pl->device = dev;
     FQT_HIP(hipMalloc(&pl->d_descs, sizeof(GemmArgs) * std::max<int64_t>(count, 1)));
@@ -1906,26 +2120,26 @@ static fqt_status batched_packed(fqt_field f, const fqt_gemm_opts* opts, int64_t
     if (pc.centered) centred_params(f, pc.b, &pp);  // f->mu is held
     dqt_params(f, pc.b, pc.centered, &pp);
     // Capture the persistent launch once; later calls replay the graph.
-    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t cs = nullptr;
+    FQT_HIP(capture_stream(f, dev, &cs));
+    FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le =
         split    ? launch_gemm_split_batched((int)f->k, (int)pc.tile, pl->d_descs, pl->d_items,
                                              pl->n_items, pl->d_counter, pl->grid, pp,
-                                             pl->cap_stream)
+                                             cs)
         : direct ? launch_gemm_direct_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
                                               pl->d_items, pl->n_items, pl->d_counter, pl->grid,
-                                              pp, pl->cap_stream)
+                                              pp, cs)
                  : launch_gemm_packed_batched((int)f->k, (int)pc.tile, pc.mode, pl->d_descs,
                                               pl->d_items, pl->n_items, pl->d_counter, pl->grid,
-                                              pp, pl->cap_stream);
+                                              pp, cs);
     hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    pl->graph = graph;
     if (le != hipSuccess) return hip_fail(le, "batched launch (capture)");
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    pl->graph = graph;
     FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
-    plan = pl.get();
-    f->plans.push_back(std::move(pl));
+    plan = f->plans.insert(key, std::move(pl));
   }
   if (plan->n_items == 0) return ok();
   FQT_HIP(hipGraphLaunch(plan->exec, s));
@@ -1960,14 +2174,10 @@ static fqt_status batched_i8cs(fqt_field f, int64_t count, const fqt_gemm_desc* 
   if (mst) return mst;
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
-  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + 2 * sizeof(int));
-  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
   const int tag[2] = {-(int)kInt8StripTile, dev};
-  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, tag, sizeof tag);
+  const fqt_detail::PlanKey key{descs, sizeof(fqt_gemm_desc) * count, fqt_detail::key_tail(tag)};
   std::lock_guard<std::mutex> lk(f->mu);
-  BatchPlan* plan = nullptr;
-  for (auto& pp : f->plans)
-    if (pp->key == key) plan = pp.get();
+  BatchPlan* plan = f->plans.find(key);
   if (!plan) {
     hipDeviceProp_t prop;
     FQT_HIP(hipGetDeviceProperties(&prop, dev));
@@ -2017,7 +2227,6 @@ static fqt_status batched_i8cs(fqt_field f, int64_t count, const fqt_gemm_desc* 
       args[i] = GemmArgs{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
     }
     auto pl = std::make_unique<BatchPlan>();
-    pl->key = key;
     pl->device = dev;
     pl->n_items = (int32_t)(items.size() / 4);
     pl->grid = grid;
@@ -2037,21 +2246,21 @@ static fqt_status batched_i8cs(fqt_field f, int64_t count, const fqt_gemm_desc* 
     const uint32_t red = (per_tile && ktiles > cap) ? (uint32_t)std::max<uint64_t>(cap - 1, 1) : 0;
     const uint64_t top = red ? (uint64_t)red * per_tile + p : (uint64_t)ktiles * per_tile;
     const uint32_t small = top < (1ull << 25) ? 1u : 0u;
-    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t cs = nullptr;
+    FQT_HIP(capture_stream(f, dev, &cs));
+    FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     if (pl->n_items > 0)
       le = launch_gemm_i8cs_batched(pl->d_descs, reinterpret_cast<const int32_t*>(pl->d_items),
                                     pl->d_wbeg, pl->grid, mt, f->tbl_log2, p, f->cb, red, small,
-                                    pl->cap_stream);
+                                    cs);
     hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    pl->graph = graph;
     if (le != hipSuccess) return hip_fail(le, "INT8 strip batched launch (capture)");
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    pl->graph = graph;
     FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
-    plan = pl.get();
-    f->plans.push_back(std::move(pl));
+    plan = f->plans.insert(key, std::move(pl));
   }
   if (plan->n_items == 0) return ok();
   FQT_HIP(hipGraphLaunch(plan->exec, s));
@@ -2066,10 +2275,8 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
   if (tile == kInt8StripTile) return batched_i8cs(f, count, descs, s);
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
-  std::vector<uint8_t> key(sizeof(fqt_gemm_desc) * count + 2 * sizeof(int));
-  std::memcpy(key.data(), descs, sizeof(fqt_gemm_desc) * count);
   const int tag[2] = {-(int)tile, dev};  // negative: INT8 plans never match packed ones
-  std::memcpy(key.data() + sizeof(fqt_gemm_desc) * count, tag, sizeof tag);
+  const fqt_detail::PlanKey key{descs, sizeof(fqt_gemm_desc) * count, fqt_detail::key_tail(tag)};
 
   uint8_t* mt = nullptr;  // before taking the field lock (device_mt takes it)
   fqt_status mst = device_mt(f, &mt);
@@ -2079,9 +2286,7 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
     return fail(FQT_ERR_UNSUPPORTED, "INT8 tile %u: operand tiles and the %u-bit table exceed "
                 "the LDS", tile, f->tbl_log2);
   std::lock_guard<std::mutex> lk(f->mu);
-  BatchPlan* plan = nullptr;
-  for (auto& pp : f->plans)
-    if (pp->key == key) plan = pp.get();
+  BatchPlan* plan = f->plans.find(key);
   if (!plan && fused) {
     // one persistent kernel over every product's tiles, no B' workspace
     const int bm = i8f_tile_m((int)tile), bne = i8f_tile_n((int)tile, (int)k);
@@ -2103,7 +2308,6 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
       return descs[x.gemm].K > descs[y.gemm].K;
     });
     auto pl = std::make_unique<BatchPlan>();
-    pl->key = key;
     pl->device = dev;
     pl->n_items = (int32_t)items.size();
     FQT_HIP(hipMalloc(&pl->d_i8, sizeof(I8Batch) * count));
@@ -2120,21 +2324,21 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
         1, std::min<int>(prop.multiProcessorCount *
                              i8f_batched_occupancy((int)tile, (int)k, f->tbl_log2),
                          std::max<int32_t>(pl->n_items, 1)));
-    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t cs = nullptr;
+    FQT_HIP(capture_stream(f, dev, &cs));
+    FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     if (pl->n_items > 0)
       le = launch_gemm_i8f_batched((int)tile, (int)k, pl->d_i8, pl->d_items, pl->n_items,
                                    pl->d_counter, pl->grid, mt, f->cb, f->tbl_log2,
-                                   pl->cap_stream);
+                                   cs);
     hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    pl->graph = graph;
     if (le != hipSuccess) return hip_fail(le, "fused INT8 batched launch (capture)");
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    pl->graph = graph;
     FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
-    plan = pl.get();
-    f->plans.push_back(std::move(pl));
+    plan = f->plans.insert(key, std::move(pl));
   }
   if (!plan) {
     const int bm = i8_tile_m((int)tile), bn = i8_tile_n((int)tile);
@@ -2149,18 +2353,33 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
       ws_off[i] = ws_total;
       ws_total += ((size_t)(d.N * k) * (size_t)KKpad + 255) / 256 * 256;
     }
+    // B' of every product, in one buffer per device that all such plans share
+    // (a plan's graph expands its own B' first); growing it destroys the
+    // plans captured with the old buffer, which are rebuilt on their next call
+    Workspace& bw = f->bws[dev];
+    if (bw.bytes < ws_total) {
+      f->plans.erase_if([&](const BatchPlan& q) { return q.shares_ws && q.device == dev; });
+      if (bw.ptr) {
+        FQT_HIP(hipDeviceSynchronize());
+        FQT_HIP(hipFree(bw.ptr));
+        bw.ptr = nullptr;
+        bw.bytes = 0;
+      }
+      const size_t want = std::max<size_t>(ws_total, 256);
+      if (hipMalloc(&bw.ptr, want) != hipSuccess)
+        return fail(FQT_ERR_OOM, "INT8 batch workspace of %zu bytes", want);
+      bw.bytes = want;
+    }
     auto pl = std::make_unique<BatchPlan>();
-    pl->key = key;
     pl->device = dev;
-    if (hipMalloc(&pl->d_ws, std::max<size_t>(ws_total, 256)) != hipSuccess)
-      return fail(FQT_ERR_OOM, "INT8 batch workspace of %zu bytes", ws_total);
+    pl->shares_ws = true;
     for (int64_t i = 0; i < count; ++i) {
       const fqt_gemm_desc& d = descs[i];
       const int64_t KKpad = (d.K * k + 127) / 128 * 128;
       I8Batch& b = gs[i];
       b.a.A = d.A;
       b.a.lda = d.lda * k;
-      b.a.Bt = pl->d_ws + ws_off[i];
+      b.a.Bt = bw.ptr + ws_off[i];
       b.a.ldbt = KKpad;
       b.a.C = d.C;
       b.a.ldc = d.ldc * k;
@@ -2206,21 +2425,21 @@ static fqt_status batched_int8(fqt_field f, const fqt_gemm_opts* opts, int64_t c
     FQT_HIP(hipGetDeviceProperties(&prop, dev));
     pl->grid = std::max(1, std::min<int>(prop.multiProcessorCount * i8_batched_occupancy((int)tile),
                                          std::max<int32_t>(pl->n_items, 1)));
-    FQT_HIP(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
-    FQT_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipStream_t cs = nullptr;
+    FQT_HIP(capture_stream(f, dev, &cs));
+    FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = launch_expand_b_batched((int)k, pl->d_i8, pl->d_exp, (int32_t)exps.size(),
-                                            mt, f->cb, f->tbl_log2, pl->cap_stream);
+                                            mt, f->cb, f->tbl_log2, cs);
     if (le == hipSuccess && pl->n_items > 0)
       le = launch_gemm_i8_batched((int)tile, pl->d_i8, pl->d_items, pl->n_items, pl->d_counter,
-                                  pl->grid, pl->cap_stream);
+                                  pl->grid, cs);
     hipGraph_t graph = nullptr;
-    hipError_t ce = hipStreamEndCapture(pl->cap_stream, &graph);
+    hipError_t ce = hipStreamEndCapture(cs, &graph);
+    pl->graph = graph;
     if (le != hipSuccess) return hip_fail(le, "INT8 batched launch (capture)");
     if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-    pl->graph = graph;
     FQT_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0));
-    plan = pl.get();
-    f->plans.push_back(std::move(pl));
+    plan = f->plans.insert(key, std::move(pl));
   }
   if (fused && plan->n_items == 0) return ok();  // nothing captured
   FQT_HIP(hipGraphLaunch(plan->exec, s));
@@ -2237,6 +2456,8 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_o
     if (st) return fail(st, "descriptor %lld: %s", (long long)i, g_last_error.c_str());
   }
   if (count == 0) return ok();
+  fqt_gemm_opts tuned{};
+  bool from_tuned = false;
   if (path == FQT_PATH_AUTO) {
     int64_t Mmax = 0, Nmax = 0, Kmax = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -2249,7 +2470,11 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_o
     path = FQT_PATH_PACKED_F64;
     if (it != f->tuned.end()) {
       path = it->second.path;
-      if (!opts) opts = &it->second.opts;
+      if (!opts) {
+        tuned = it->second.opts;
+        opts = &tuned;
+        from_tuned = true;
+      }
     }
   }
   if (!opts && (path == FQT_PATH_PACKED_F64 || path == FQT_PATH_INT8)) {
@@ -2262,25 +2487,36 @@ fqt_status fqt_gemm_gfpk_batched_ex(fqt_field f, fqt_path path, const fqt_gemm_o
     std::lock_guard<std::mutex> lk(f->mu);
     auto it = f->tuned.find(shape_key(f, count, Mmax, Nmax, Kmax) +
                             (path == FQT_PATH_INT8 ? "_int8" : "_packed"));
-    if (it != f->tuned.end()) opts = &it->second.opts;
-  }
-  switch (path) {
-    case FQT_PATH_PACKED_F64:
-      return batched_packed(f, opts, count, descs, (hipStream_t)s);
-    case FQT_PATH_PLAIN: {
-      const FieldArgs fa = field_args(f, 2);
-      for (int64_t i = 0; i < count; ++i) {
-        const fqt_gemm_desc& d = descs[i];
-        GemmArgs g{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
-        FQT_HIP(launch_gemm_plain((int)f->k, g, fa, f->P_low, (hipStream_t)s));
-      }
-      return ok();
+    if (it != f->tuned.end()) {
+      tuned = it->second.opts;
+      opts = &tuned;
+      from_tuned = true;
     }
-    case FQT_PATH_INT8:
-      return batched_int8(f, opts, count, descs, (hipStream_t)s);
-    default:
-      return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
   }
+  auto run = [&](const fqt_gemm_opts* o) -> fqt_status {
+    switch (path) {
+      case FQT_PATH_PACKED_F64:
+        return batched_packed(f, o, count, descs, (hipStream_t)s);
+      case FQT_PATH_PLAIN: {
+        const FieldArgs fa = field_args(f, 2);
+        for (int64_t i = 0; i < count; ++i) {
+          const fqt_gemm_desc& d = descs[i];
+          GemmArgs g{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
+          FQT_HIP(launch_gemm_plain((int)f->k, g, fa, f->P_low, (hipStream_t)s));
+        }
+        return ok();
+      }
+      case FQT_PATH_INT8:
+        return batched_int8(f, o, count, descs, (hipStream_t)s);
+      default:
+        return fail(FQT_ERR_INVALID_ARG, "unknown path %d", (int)path);
+    }
+  };
+  // tuned options of the shape class may be refused at this batch's K (see
+  // fqt_gemm_gfpk_ex): then the path's defaults
+  fqt_status rst = run(opts);
+  if (from_tuned && (rst == FQT_ERR_UNSUPPORTED || rst == FQT_ERR_BOUNDS)) rst = run(nullptr);
+  return rst;
 }
 
 fqt_status fqt_gemm_gfpk_batched(fqt_field f, fqt_path path, int64_t count,
@@ -2534,6 +2770,134 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
   }
   if (best_path) *best_path = w.path;
   if (best) *best = w.opts;
+  return ok();
+}
+
+// Autotuner of uneven polynomial batches: every chunk length d+1 (1..8) in
+// both chunk representations (odd p), default q and n_q; a candidate counts
+// only if every output byte equals the first admissible candidate's.
+fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* descs,
+                                const char* cache_path, uint32_t* best_d,
+                                uint32_t* best_centered, fqt_stream_t s) {
+  if (count < 1 || !descs) return fail(FQT_ERR_INVALID_ARG, "empty batch");
+  int64_t lmax = 0, total = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    if (descs[i].la < 0 || descs[i].lb < 0)
+      return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: negative length", (long long)i);
+    lmax = std::max(lmax, std::max(descs[i].la, descs[i].lb));
+    if (descs[i].la && descs[i].lb) total += descs[i].la + descs[i].lb - 1;
+  }
+  int64_t bucket = 1;
+  while (bucket < lmax) bucket <<= 1;
+  char keybuf[96];
+  std::snprintf(keybuf, sizeof keybuf, "poly_p%u_c%lld_L%lld", p, (long long)count,
+                (long long)bucket);
+  if (cache_path) {
+    if (FILE* fp = std::fopen(cache_path, "r")) {
+      char line[256];
+      bool found = false;
+      unsigned d = 0, cen = 0;
+      while (std::fgets(line, sizeof line, fp)) {
+        char k[96];
+        unsigned dd = 0, cc = 0;
+        if (std::sscanf(line, "{\"key\": \"%95[^\"]\", \"d\": %u, \"centered\": %u", k, &dd,
+                        &cc) == 3 &&
+            std::strcmp(k, keybuf) == 0) {
+          d = dd;
+          cen = cc;
+          found = true;
+        }
+      }
+      std::fclose(fp);
+      if (found) {
+        if (best_d) *best_d = d;
+        if (best_centered) *best_centered = cen;
+        return ok();
+      }
+    }
+  }
+  hipStream_t st = (hipStream_t)s;
+  PinnedBuf ref, cur;
+  {
+    fqt_status rs = ref.resize((size_t)total);
+    if (!rs) rs = cur.resize((size_t)total);
+    if (rs) return rs;
+  }
+  // outputs in address order, adjacent ones merged into one copy each (a
+  // batch in flat buffers is one copy)
+  std::vector<std::pair<uint8_t*, size_t>> runs;
+  for (int64_t i = 0; i < count; ++i)
+    if (descs[i].la && descs[i].lb)
+      runs.push_back({descs[i].c, (size_t)(descs[i].la + descs[i].lb - 1)});
+  std::sort(runs.begin(), runs.end());
+  {
+    size_t w = 0;
+    for (size_t i = 0; i < runs.size(); ++i) {
+      if (w && runs[w - 1].first + runs[w - 1].second == runs[i].first)
+        runs[w - 1].second += runs[i].second;
+      else
+        runs[w++] = runs[i];
+    }
+    runs.resize(w);
+  }
+  auto snap = [&](PinnedBuf& b) -> fqt_status {
+    size_t off = 0;
+    for (const auto& r : runs) {
+      FQT_HIP(hipMemcpyAsync(b.p + off, r.first, r.second, hipMemcpyDeviceToHost, st));
+      off += r.second;
+    }
+    FQT_HIP(hipStreamSynchronize(st));
+    return ok();
+  };
+  hipEvent_t e0, e1;
+  FQT_HIP(hipEventCreate(&e0));
+  FQT_HIP(hipEventCreate(&e1));
+  bool have_ref = false;
+  double best_ms = 1e30;
+  uint32_t bd = 0, bc = 0;
+  fqt_status status = FQT_OK;
+  for (uint32_t cen = 0; cen <= (p % 2 ? 1u : 0u) && status == FQT_OK; ++cen)
+    for (uint32_t d = 0; d <= 7 && status == FQT_OK; ++d) {
+      auto run = [&]() { return fqt_polymul_dfqt_batched(p, d, 0, 0, 0, cen, count, descs, s); };
+      status = run();  // builds the plan and its graph
+      if (status == FQT_ERR_UNSUPPORTED || status == FQT_ERR_BOUNDS) {
+        status = FQT_OK;
+        continue;
+      }
+      if (status) break;
+      status = snap(have_ref ? cur : ref);
+      if (status) break;
+      if (have_ref && std::memcmp(cur.p, ref.p, (size_t)total) != 0) {
+        status = fail(FQT_ERR_DEVICE, "polynomial autotune candidate d = %u, centered = %u is not "
+                      "byte-identical to the first", d, cen);
+        break;
+      }
+      have_ref = true;
+      const int reps = 5;
+      hipEventRecord(e0, st);
+      for (int r = 0; r < reps && status == FQT_OK; ++r) status = run();
+      hipEventRecord(e1, st);
+      hipEventSynchronize(e1);
+      float ms = 0;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (status == FQT_OK && ms / reps < best_ms) {
+        best_ms = ms / reps;
+        bd = d;
+        bc = cen;
+      }
+    }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (status) return status;
+  if (!have_ref) return fail(FQT_ERR_UNSUPPORTED, "every candidate was refused for this batch");
+  if (cache_path)
+    if (FILE* fp = std::fopen(cache_path, "a")) {
+      std::fprintf(fp, "{\"key\": \"%s\", \"d\": %u, \"centered\": %u, \"ms\": %.6f}\n", keybuf,
+                   bd, bc, best_ms);
+      std::fclose(fp);
+    }
+  if (best_d) *best_d = bd;
+  if (best_centered) *best_centered = bc;
   return ok();
 }
 

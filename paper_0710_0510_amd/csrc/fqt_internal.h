@@ -61,6 +61,28 @@ struct DfqtArgs {
   PackedParams pp;       // fa, qmod and fold_blocks are used
 };
 
+// One pair of an uneven polynomial batch: c (la + lb - 1 coefficients) =
+// a (la) * b (lb); the layout of the public fqt_poly_desc.
+struct PolyDesc {
+  int64_t la, lb;
+  const uint8_t* a;
+  const uint8_t* b;
+  uint8_t* c;
+};
+
+// d-FQT over an uneven batch: pairs taken from one queue in the order
+// order[0 .. count) (longest first), counter[0] the queue, counter[1] the
+// waves done (both zero before a launch; the last wave leaves them zero).
+struct DfqtBatchArgs {
+  const PolyDesc* descs;
+  const int32_t* order;
+  int32_t count;
+  uint32_t total_waves;
+  uint32_t* counter;
+  uint32_t nq, lg2q;  // products per block; q = 2^lg2q
+  PackedParams pp;    // fa, qmod, fold_blocks, centring as DfqtArgs
+};
+
 // Classical product with delayed reduction (eq. (3)), the comparator.
 struct DelayedArgs {
   const uint8_t* a;
@@ -278,6 +300,8 @@ int i8f_batched_occupancy(int tile, int k, uint32_t tbl_log2);
 // d-FQT (ke = d + 1 in 1..8, mode 0/1/2 as in fqt_packed.h) and its comparator.
 hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s);
 hipError_t launch_polymul_delayed(const DelayedArgs& g, hipStream_t s);
+hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int grid,
+                               hipStream_t s);
 constexpr int kDfqtMaxChunks = 1024;  // chunks of one operand (in LDS)
 constexpr int kDelayedMaxLen = 8192;  // coefficients of one operand (in LDS)
 

@@ -22,57 +22,51 @@
 // overlapping digits of the one before).  The digits that overlap into t come
 // from t-1: the same lane for r > 0, the previous lane (a shuffle) for r = 0,
 // lane 63 of the previous pass for the first lane.
+// Pairs of uneven lengths (la, lb) run the same convolution over nca and
+// ncb chunks, every wave taking pairs from one queue (dfqt_batched_kernel).
 
 #include "fqt_packed.h"
 
 namespace fqt {
 
+// DQT of the chunks of one operand of len coefficients into X[0 .. nch):
+// sum_j c_j 2^(b j) < 2^52, exact in binary64; centred chunks take c - p for
+// c > (p-1)/2 (a signed sum, as exact).  The lanes of one wave split the
+// chunks.
+template <int KE, bool CEN>
+__device__ __forceinline__ void dfqt_pack(const uint8_t* __restrict__ x, int len, int nch,
+                                          uint32_t b, const PackedParams& pp,
+                                          double* __restrict__ X, int lane) {
+  const int32_t p = (int32_t)pp.fa.p, h = (p - 1) / 2;
+  for (int i = lane; i < nch; i += 64) {
+    // sums of (possibly negative) c_j 2^(b j) in two's complement mod 2^64;
+    // the true value is below 2^52 in magnitude
+    uint64_t v = 0;
+#pragma unroll
+    for (int j = 0; j < KE; ++j) {
+      const int idx = i * KE + j;
+      if (idx < len) {
+        int32_t cx = x[idx];
+        if constexpr (CEN) cx -= cx > h ? p : 0;
+        v += (uint64_t)(int64_t)cx << (b * j);
+      }
+    }
+    X[i] = (double)(int64_t)v;
+  }
+}
+
+// The product of one pair by one wave from its packed chunks P (nca) and Q
+// (ncb) in LDS: S_t = sum_i P_i Q_{t-i} for t = 0 .. nca + ncb - 2, blocks of
+// nq products, digits mod p, overlap-add into the nc = la + lb - 1 output
+// coefficients.
 template <int KE, int MODE, bool CEN>
-__global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
+__device__ __forceinline__ void dfqt_convolve(const double* __restrict__ P, int nca,
+                                              const double* __restrict__ Q, int ncb, int nc,
+                                              uint8_t* __restrict__ pc, uint32_t nq, uint32_t b,
+                                              const PackedParams& pp, int lane) {
   constexpr int ND = 2 * KE - 1;
   constexpr bool MULTI = MODE != 0;
-  __shared__ double sh[4][2][kDfqtMaxChunks];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t prod = (int64_t)blockIdx.x * 4 + w;
-  const bool live = prod < g.count;  // idle waves still reach every barrier
-  double* P = sh[w][0];
-  double* Q = sh[w][1];
-  const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
-  const int len = g.len, nch = g.nch;
-  const uint8_t* pa = g.a + (live ? prod : 0) * len;
-  const uint8_t* pb = g.b + (live ? prod : 0) * len;
-  uint8_t* pc = g.c + (live ? prod : 0) * (int64_t)(2 * len - 1);
-
-  // DQT of every chunk: sum_j c_j 2^(b j) < 2^52, exact in binary64; centred
-  // chunks take c - p for c > (p-1)/2 (a signed sum, as exact)
-  const PackedParams& pp = g.pp;
-  if (live) {
-    const int32_t p = (int32_t)pp.fa.p, h = (p - 1) / 2;
-    for (int i = lane; i < nch; i += 64) {
-      // sums of (possibly negative) c_j 2^(b j) in two's complement mod 2^64;
-      // the true value is below 2^52 in magnitude
-      uint64_t va = 0, vb = 0;
-#pragma unroll
-      for (int j = 0; j < KE; ++j) {
-        const int idx = i * KE + j;
-        if (idx < len) {
-          int32_t ca = pa[idx], cb = pb[idx];
-          if constexpr (CEN) {
-            ca -= ca > h ? p : 0;
-            cb -= cb > h ? p : 0;
-          }
-          va += (uint64_t)(int64_t)ca << (b * j);
-          vb += (uint64_t)(int64_t)cb << (b * j);
-        }
-      }
-      P[i] = (double)(int64_t)va;
-      Q[i] = (double)(int64_t)vb;
-    }
-  }
-  __syncthreads();
-  if (!live) return;  // no barrier below
-
-  const int nt = 2 * nch;  // t = 0 .. 2nch-1
+  const int nt = nca + ncb;  // t = 0 .. nca + ncb - 1
   // every block starts from 2^52 (centred: plus q/2 in every digit)
   const double bz = CEN ? pp.cbias : kTwo52;
   uint32_t carry[KE > 1 ? KE - 1 : 1];
@@ -88,12 +82,12 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) st[r].clear();
     }
-    const int ilo = max(0, t0 - (nch - 1)), ihi = min(nch - 1, t0 + 255);
+    const int ilo = max(0, t0 - (ncb - 1)), ihi = min(nca - 1, t0 + 255);
     double qw[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = tb + r - ilo;
-      qw[r] = (j >= 0 && j < nch) ? Q[j] : 0.0;
+      qw[r] = (j >= 0 && j < ncb) ? Q[j] : 0.0;
     }
     uint32_t cnt = 0, nbound = 0, nblk = 1;  // blocks of this pass (the centred shift counts them)
     uint32_t nadd = 0;                       // blocks in the lane state since its last fold
@@ -102,7 +96,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[r] = __builtin_fma(pi, qw[r], acc[r]);
       if constexpr (MULTI) {
-        if (++cnt == g.nq) {
+        if (++cnt == nq) {
           cnt = 0;
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -124,7 +118,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
       qw[2] = qw[1];
       qw[1] = qw[0];
       const int j = tb - i - 1;
-      qw[0] = (j >= 0 && j < nch) ? Q[j] : 0.0;
+      qw[0] = (j >= 0 && j < ncb) ? Q[j] : 0.0;
     }
 
     // Thm. 2's residues u_i, then Alg. 2's second part (the Q_d correction of
@@ -157,11 +151,75 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
 #pragma unroll
       for (int j = 0; j < KE; ++j) {
         const int n = t * KE + j;
-        if (n >= 2 * len - 1) break;
+        if (n >= nc) break;
         uint32_t v = u[r][j];
         if (j < KE - 1) v += r ? u[r - 1][KE + j] : prev[j];
         pc[n] = (uint8_t)(v >= pp.fa.p ? v - pp.fa.p : v);
       }
+    }
+  }
+}
+
+// One wave per product, four per workgroup, every pair of len coefficients.
+template <int KE, int MODE, bool CEN>
+__global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
+  __shared__ double sh[4][2][kDfqtMaxChunks];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t prod = (int64_t)blockIdx.x * 4 + w;
+  const bool live = prod < g.count;  // idle waves still reach every barrier
+  double* P = sh[w][0];
+  double* Q = sh[w][1];
+  const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
+  const int len = g.len, nch = g.nch;
+  const uint8_t* pa = g.a + (live ? prod : 0) * len;
+  const uint8_t* pb = g.b + (live ? prod : 0) * len;
+  uint8_t* pc = g.c + (live ? prod : 0) * (int64_t)(2 * len - 1);
+  if (live) {
+    dfqt_pack<KE, CEN>(pa, len, nch, b, g.pp, P, lane);
+    dfqt_pack<KE, CEN>(pb, len, nch, b, g.pp, Q, lane);
+  }
+  __syncthreads();
+  if (!live) return;  // no barrier below
+  dfqt_convolve<KE, MODE, CEN>(P, nch, Q, nch, 2 * len - 1, pc, g.nq, b, g.pp, lane);
+}
+
+// Uneven batch: every wave takes products from one queue (the host orders
+// them longest first) and computes each one alone in its own LDS region:
+// pack both operands, a wave-wide fence, the convolution.  The last wave out
+// resets the queue for the next launch.
+template <int KE, int MODE, bool CEN>
+__global__ __launch_bounds__(256) void dfqt_batched_kernel(DfqtBatchArgs g) {
+  __shared__ double sh[4][2][kDfqtMaxChunks];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* P = sh[w][0];
+  double* Q = sh[w][1];
+  const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
+  for (;;) {
+    int32_t it = 0;
+    if (lane == 0) it = (int32_t)atomicAdd(&g.counter[0], 1u);
+    it = __builtin_amdgcn_readfirstlane(it);
+    if (it >= g.count) break;
+    const PolyDesc d = g.descs[g.order[it]];
+    const int la = __builtin_amdgcn_readfirstlane((int)d.la);
+    const int lb = __builtin_amdgcn_readfirstlane((int)d.lb);
+    if (la == 0 || lb == 0) continue;  // empty product: no output
+    const int nca = (la + KE - 1) / KE, ncb = (lb + KE - 1) / KE;
+    // the previous product's reads of P and Q are done before they are rewritten
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    dfqt_pack<KE, CEN>(d.a, la, nca, b, g.pp, P, lane);
+    dfqt_pack<KE, CEN>(d.b, lb, ncb, b, g.pp, Q, lane);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    dfqt_convolve<KE, MODE, CEN>(P, nca, Q, ncb, la + lb - 1, d.c, g.nq, b, g.pp, lane);
+  }
+  if (lane == 0) {
+    __threadfence();
+    if (atomicAdd(&g.counter[1], 1u) == g.total_waves - 1) {
+      atomicExch(&g.counter[0], 0u);
+      atomicExch(&g.counter[1], 0u);
     }
   }
 }
@@ -243,6 +301,29 @@ static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
   return g.pp.centered ? dfqt_k<KE, true>(mode, g, s) : dfqt_k<KE, false>(mode, g, s);
 }
 
+template <int KE, bool CEN>
+static hipError_t dfqt_bk(int mode, const DfqtBatchArgs& g, int grid, hipStream_t s) {
+  switch (mode) {
+    case 0: hipLaunchKernelGGL((dfqt_batched_kernel<KE, 0, CEN>), grid, dim3(256), 0, s, g); break;
+    case 1: hipLaunchKernelGGL((dfqt_batched_kernel<KE, 1, CEN>), grid, dim3(256), 0, s, g); break;
+    case 2:
+      if constexpr (digit_sums_fit<KE>()) {
+        hipLaunchKernelGGL((dfqt_batched_kernel<KE, 2, CEN>), grid, dim3(256), 0, s, g);
+        break;
+      } else {
+        return hipErrorInvalidValue;
+      }
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int KE>
+static hipError_t dfqt_bk(int mode, const DfqtBatchArgs& g, int grid, hipStream_t s) {
+  return g.pp.centered ? dfqt_bk<KE, true>(mode, g, grid, s)
+                       : dfqt_bk<KE, false>(mode, g, grid, s);
+}
+
 hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s) {
   if (g.count == 0) return hipSuccess;
   switch (ke) {
@@ -254,6 +335,21 @@ hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s) {
     case 6: return dfqt_k<6>(mode, g, s);
     case 7: return dfqt_k<7>(mode, g, s);
     case 8: return dfqt_k<8>(mode, g, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int grid,
+                               hipStream_t s) {
+  switch (ke) {
+    case 1: return dfqt_bk<1>(mode, g, grid, s);
+    case 2: return dfqt_bk<2>(mode, g, grid, s);
+    case 3: return dfqt_bk<3>(mode, g, grid, s);
+    case 4: return dfqt_bk<4>(mode, g, grid, s);
+    case 5: return dfqt_bk<5>(mode, g, grid, s);
+    case 6: return dfqt_bk<6>(mode, g, grid, s);
+    case 7: return dfqt_bk<7>(mode, g, grid, s);
+    case 8: return dfqt_bk<8>(mode, g, grid, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -11,6 +11,8 @@ import ctypes
 import os
 from typing import Optional, Sequence, Tuple
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfqt.so")
 
@@ -29,7 +31,7 @@ EXPORTED = [
     "fqt_gemm_gfpk_ex", "fqt_gemm_gfpk_batched", "fqt_gemm_gfpk_batched_ex", "fqt_autotune",
     "fqt_tile_count", "fqt_last_error", "fqt_version", "fqt_polymul_dfqt", "fqt_polymul_delayed",
     "fqt_log_info", "fqt_to_log", "fqt_from_log", "fqt_log_add", "fqt_gemm_log",
-    "fqt_gemm_winograd",
+    "fqt_gemm_winograd", "fqt_polymul_dfqt_batched", "fqt_autotune_polymul",
 ]
 
 
@@ -44,6 +46,12 @@ class GemmOpts(ctypes.Structure):
     _fields_ = [("log2q", ctypes.c_uint32), ("n_q", ctypes.c_uint32),
                 ("tile", ctypes.c_uint32), ("boundary", ctypes.c_uint32),
                 ("centered", ctypes.c_uint32)]
+
+
+class PolyDesc(ctypes.Structure):
+    """fqt_poly_desc: c (la + lb - 1 coefficients) = a (la) * b (lb)."""
+    _fields_ = [("la", ctypes.c_int64), ("lb", ctypes.c_int64), ("a", ctypes.c_void_p),
+                ("b", ctypes.c_void_p), ("c", ctypes.c_void_p)]
 
 
 class GemmDesc(ctypes.Structure):
@@ -79,6 +87,11 @@ def lib() -> ctypes.CDLL:
         "fqt_polymul_dfqt": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, c_u32, vp, vp, c_i64,
                                      c_i64, vp, vp]),
         "fqt_polymul_delayed": (c_int, [c_u32, vp, vp, c_i64, c_i64, vp, vp]),
+        "fqt_polymul_dfqt_batched": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, c_u32, c_i64,
+                                             ctypes.POINTER(PolyDesc), vp]),
+        "fqt_autotune_polymul": (c_int, [c_u32, c_i64, ctypes.POINTER(PolyDesc),
+                                         ctypes.c_char_p, ctypes.POINTER(c_u32),
+                                         ctypes.POINTER(c_u32), vp]),
         "fqt_gemm_gfpk": (c_int, [vp, c_int, c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp,
                                   c_i64, vp]),
         "fqt_gemm_gfpk_ex": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_i64, c_i64, c_i64,
@@ -240,6 +253,64 @@ def polymul_dfqt(p: int, d: int, a, b, log2q: int = 0, n_q: int = 0, boundary: i
     _check(lib().fqt_polymul_dfqt(p, d, log2q, n_q, boundary, centered, _ptr(a), _ptr(b), count,
                                   length, _ptr(out), _stream(stream)))
     return out
+
+
+def make_poly_descs(As, Bs, Cs):
+    """Descriptors of an uneven polynomial batch: A[i], B[i] 1-D uint8 device
+    tensors (any lengths), C[i] of len(A[i]) + len(B[i]) - 1 bytes (or 0)."""
+    arr = (PolyDesc * len(As))()
+    for i, (a, b, c) in enumerate(zip(As, Bs, Cs)):
+        for t, name in ((a, "A"), (b, "B"), (c, "C")):
+            if t.dim() != 1 or not t.is_cuda or not t.is_contiguous() or t.element_size() != 1:
+                raise ValueError(f"{name}[{i}]: expected a contiguous 1-D uint8 device tensor")
+        la, lb = a.shape[0], b.shape[0]
+        want = la + lb - 1 if la and lb else 0
+        if c.shape[0] != want:
+            raise ValueError(f"pair {i}: C holds {c.shape[0]} coefficients, not {want}")
+        arr[i] = PolyDesc(la, lb, a.data_ptr(), b.data_ptr(), c.data_ptr())
+    return arr
+
+
+def poly_descs_flat(a, b, c, lens):
+    """Descriptors of an uneven batch held in three flat device buffers:
+    pair i reads la_i bytes of ``a`` and lb_i of ``b`` at the running sums of
+    the earlier lengths and writes la_i + lb_i - 1 bytes of ``c`` (none when a
+    length is 0) at the running sum of the earlier output lengths.
+    ``lens`` is a host count x 2 integer array of (la, lb)."""
+    lens = np.asarray(lens, dtype=np.int64).reshape(-1, 2)
+    la, lb = lens[:, 0], lens[:, 1]
+    lc = np.where((la > 0) & (lb > 0), la + lb - 1, 0)
+    for t, need, name in ((a, la.sum(), "a"), (b, lb.sum(), "b"), (c, lc.sum(), "c")):
+        if t.dim() != 1 or not t.is_cuda or not t.is_contiguous() or t.element_size() != 1:
+            raise ValueError(f"{name}: expected a contiguous 1-D uint8 device tensor")
+        if t.shape[0] < need:
+            raise ValueError(f"{name}: {t.shape[0]} bytes, the lengths need {need}")
+    off = lambda v: np.concatenate(([0], np.cumsum(v)[:-1])).astype(np.uint64)
+    rec = np.zeros(len(lens), dtype=[("la", "<i8"), ("lb", "<i8"), ("a", "<u8"), ("b", "<u8"),
+                                     ("c", "<u8")])
+    rec["la"], rec["lb"] = la, lb
+    rec["a"] = np.uint64(a.data_ptr()) + off(la)
+    rec["b"] = np.uint64(b.data_ptr()) + off(lb)
+    rec["c"] = np.uint64(c.data_ptr()) + off(lc)
+    assert rec.dtype.itemsize == ctypes.sizeof(PolyDesc)
+    return (PolyDesc * len(lens)).from_buffer_copy(rec.tobytes())
+
+
+def polymul_dfqt_batched(p: int, d: int, descs, log2q: int = 0, n_q: int = 0,
+                         boundary: int = 0, centered: int = 0, stream=None):
+    """d-FQT (Section 6) over an uneven batch described by ``make_poly_descs``,
+    in one persistent launch replayed from a captured graph."""
+    _check(lib().fqt_polymul_dfqt_batched(p, d, log2q, n_q, boundary, centered, len(descs),
+                                          descs, _stream(stream)))
+
+
+def autotune_polymul(p: int, descs, cache_path: Optional[str] = None, stream=None):
+    """The fastest (d, centered) for an uneven batch; returns a dict."""
+    d, cen = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    _check(lib().fqt_autotune_polymul(p, len(descs), descs,
+                                      cache_path.encode() if cache_path else None,
+                                      ctypes.byref(d), ctypes.byref(cen), _stream(stream)))
+    return {"d": d.value, "centered": cen.value}
 
 
 def polymul_delayed(p: int, a, b, out=None, stream=None):

@@ -37,7 +37,7 @@ GF3_2 = Field(3, 2, (1, 0))          # X^2 + 1
 @dataclass(frozen=True)
 class Workload:
     name: str
-    kind: str                 # "polymul" | "gemm" | "batched" | "dfqt"
+    kind: str                 # "polymul" | "gemm" | "batched" | "dfqt" | "dfqt_batched"
     p: int
     k: int
     P_low: Tuple[int, ...] = ()
@@ -52,6 +52,7 @@ class Workload:
     hi: int = 0
     length: int = 0           # dfqt: coefficients per operand (degree N = length - 1)
     d: int = 0                # dfqt: chunks of d + 1 coefficients
+                              # dfqt_batched: lengths uniform in [lo, hi], count pairs
 
 
 WORKLOADS = {
@@ -71,6 +72,10 @@ WORKLOADS = {
     # a batch of independent pairs
     "dfqt-gf3-n500-d4": Workload("dfqt-gf3-n500-d4", "dfqt", 3, 1, (), seed=6, count=16384,
                                  length=501, d=4),
+    # uneven pairs over GF(3): both operand lengths drawn independently,
+    # uniform in 1..1024 coefficients, one persistent launch for the batch
+    "dfqt-uneven-gf3-1024": Workload("dfqt-uneven-gf3-1024", "dfqt_batched", 3, 1, (), seed=8,
+                                     count=16384, lo=1, hi=1024, d=4),
 }
 
 
@@ -93,6 +98,25 @@ def poly_long_inputs(w: Workload, count: int = 0):
     a = rng.integers(0, w.p, size=(count, w.length), dtype=np.uint8)
     b = rng.integers(0, w.p, size=(count, w.length), dtype=np.uint8)
     return a, b
+
+
+def poly_uneven_lengths(seed: int, count: int, lo: int, hi: int) -> np.ndarray:
+    """count x 2 int64 array of operand lengths (la, lb), each uniform in
+    [lo, hi], drawn before any coefficient."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(lo, hi + 1, size=(count, 2)).astype(np.int64)
+
+
+def poly_uneven_inputs(w: Workload, count: int = 0):
+    """Lengths first (as poly_uneven_lengths), then every first operand as
+    one flat array (pair i at offset sum of the earlier la), then every
+    second operand likewise; coefficients i.i.d. uniform in [0, p)."""
+    count = count or w.count
+    rng = np.random.default_rng(w.seed)
+    lens = rng.integers(w.lo, w.hi + 1, size=(count, 2)).astype(np.int64)
+    a = rng.integers(0, w.p, size=int(lens[:, 0].sum()), dtype=np.uint8)
+    b = rng.integers(0, w.p, size=int(lens[:, 1].sum()), dtype=np.uint8)
+    return lens, a, b
 
 
 def gemm_inputs(w: Workload, M: int = 0, N: int = 0, K: int = 0):

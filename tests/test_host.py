@@ -258,6 +258,48 @@ def test_autotune_rejects_plain_only():
     assert fqt.STATUS_NAMES[fqt.lib().fqt_autotune(f.handle, 3, 1, d, None, None, None, None)] == "FQT_ERR_INVALID_ARG"
 
 
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"),
+                    reason="the fallback launches on BOGUS pointers once a GPU is present")
+def test_tuned_options_refused_at_larger_k_fall_back_to_defaults(tmp_path):
+    # GF(7^2): direct tile 12 holds no block state, so it is admissible at
+    # K = 1500 (one K-block of n_q = 1820 at q = 2^17) but not at K = 2000,
+    # which falls in the same power-of-two shape class (K bucket 2048).  A
+    # tuned entry for the class must not make the AUTO call at K = 2000 fail:
+    # the refusal (host side) falls back to the packed defaults, which pass
+    # every host check and reach the device (FQT_ERR_DEVICE without a GPU).
+    f = fqt.Field(7, 2, (1, 0))
+    L = fqt.lib()
+    cache = tmp_path / "tune.jsonl"
+    for count in (1, 2):
+        key = f"p7_k2_c{count}_1024_1024_2048"
+        with open(cache, "a") as fp:
+            fp.write('{"key": "%s", "path": 1, "log2q": 17, "n_q": 0, "tile": 12, '
+                     '"boundary": 0, "centered": 0, "ms": 1.0}\n' % key)
+        d = (fqt.GemmDesc * count)()
+        for i in range(count):
+            d[i] = fqt.GemmDesc(1024, 1024, 1500, 1500, 1024, 1024, BOGUS + i * (1 << 24),
+                                BOGUS + (1 << 30) + i * (1 << 24),
+                                BOGUS + (1 << 31) + i * (1 << 24))
+        bp = ctypes.c_int(0)
+        best = fqt.GemmOpts()
+        st = L.fqt_autotune(f.handle, 0, count, d, str(cache).encode(), ctypes.byref(bp),
+                            ctypes.byref(best), None)
+        assert fqt.STATUS_NAMES[st] == "FQT_OK", fqt.last_error()   # from the cache alone
+        assert best.tile == 12 and bp.value == 1
+        # the tuned options themselves are refused at K = 2000
+        assert _gemm_status(f, "packed", 1024, 1024, 2000, 2000, 1024, 1024,
+                            opts={"log2q": 17, "tile": 12}) == "FQT_ERR_UNSUPPORTED"
+        for i in range(count):
+            d[i].K = 2000
+            d[i].lda = 2000
+        if count == 1:
+            st = _gemm_status(f, "auto", 1024, 1024, 2000, 2000, 1024, 1024)
+        else:
+            st = fqt.STATUS_NAMES[L.fqt_gemm_gfpk_batched_ex(f.handle, 0, None, count, d, None)]
+        assert st == "FQT_ERR_DEVICE", (count, st, fqt.last_error())
+
+
 # ---- d-FQT long polynomials: every refusal happens before device work -------
 
 def _dfqt_status(p, d, log2q, n_q, boundary, count, length, a=BOGUS, b=BOGUS + (1 << 30),
@@ -380,3 +422,38 @@ def test_centred_validation_errors():
                         opts={"centered": 1, "n_q": 16}) == "FQT_ERR_BOUNDS"
     # without centring the same n_q breaks eq. (2)
     assert _gemm_status(f, "packed", 4, 4, 4, 4, 4, 4, opts={"n_q": 15}) == "FQT_ERR_BOUNDS"
+
+
+# ---- d-FQT over uneven batches: every refusal happens before device work ----
+
+def _dfqt_batch_status(p, d, pairs, log2q=0, n_q=0, boundary=0, centered=0):
+    L = fqt.lib()
+    arr = (fqt.PolyDesc * len(pairs))()
+    for i, (la, lb, a, b, c) in enumerate(pairs):
+        arr[i] = fqt.PolyDesc(la, lb, a, b, c)
+    return fqt.STATUS_NAMES[L.fqt_polymul_dfqt_batched(p, d, log2q, n_q, boundary, centered,
+                                                       len(pairs), arr, None)]
+
+
+def test_dfqt_batched_validation_errors():
+    ok_pair = (10, 20, BOGUS, BOGUS + (1 << 20), BOGUS + (1 << 30))
+    assert _dfqt_batch_status(4, 1, [ok_pair]) == "FQT_ERR_NOT_PRIME"
+    assert _dfqt_batch_status(131, 1, [ok_pair]) == "FQT_ERR_UNSUPPORTED"
+    assert _dfqt_batch_status(3, 8, [ok_pair]) == "FQT_ERR_UNSUPPORTED"
+    assert _dfqt_batch_status(2, 1, [ok_pair], centered=1) == "FQT_ERR_UNSUPPORTED"
+    assert _dfqt_batch_status(3, 1, [ok_pair], centered=2) == "FQT_ERR_INVALID_ARG"
+    assert _dfqt_batch_status(3, 1, [ok_pair], boundary=3) == "FQT_ERR_INVALID_ARG"
+    # negative length; a null operand of a non-empty pair
+    assert _dfqt_batch_status(3, 1, [(-1, 5, BOGUS, BOGUS, BOGUS)]) == "FQT_ERR_INVALID_ARG"
+    assert _dfqt_batch_status(3, 1, [(3, 5, 0, BOGUS, BOGUS + (1 << 30))]) == "FQT_ERR_INVALID_ARG"
+    # more chunks than one wave's LDS holds: 1024 (d + 1) coefficients at most
+    assert _dfqt_batch_status(3, 1, [(2049, 5, BOGUS, BOGUS + (1 << 20),
+                                      BOGUS + (1 << 30))]) == "FQT_ERR_UNSUPPORTED"
+    # the output overlaps its own operand
+    assert _dfqt_batch_status(3, 1, [(10, 10, BOGUS, BOGUS + (1 << 20),
+                                      BOGUS + 5)]) == "FQT_ERR_INVALID_ARG"
+    # eq. (2): p = 3, d = 4 at q = 2^5 holds one chunk product per block, not 2
+    assert _dfqt_batch_status(3, 4, [ok_pair], n_q=2) == "FQT_ERR_BOUNDS"
+    # empty pairs only: nothing to do, nothing refused
+    assert _dfqt_batch_status(3, 1, [(0, 7, 0, 0, 0)]) == "FQT_OK"
+    assert _dfqt_batch_status(3, 1, []) == "FQT_OK"
