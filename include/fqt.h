@@ -305,6 +305,22 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
                                     uint32_t boundary, uint32_t centered, int64_t count,
                                     const fqt_poly_desc* descs, fqt_stream_t s);
 
+/* fqt_polymul_dfqt_batched for callers that cannot allocate device memory
+ * (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, checks, errors and output bytes, but no
+ * plan and no graph; it calls no hipMalloc, hipFree or other allocating
+ * routine.  Each call copies the descriptors, in queue order, into a static
+ * device array of this library (about 640 KiB, one per GPU, held until the
+ * process ends) on stream s, clears the queue counters there with a kernel
+ * and launches the batch.  At most 16384 pairs with output per call
+ * (FQT_ERR_UNSUPPORTED beyond).  Every call on one GPU uses that GPU's one
+ * array: calls that overlap in time on one GPU (two streams, two threads)
+ * race and may write wrong bytes; calls ordered on one stream do not. */
+fqt_status fqt_polymul_dfqt_batched_noalloc(uint32_t p, uint32_t d, uint32_t log2q,
+                                            uint32_t n_q, uint32_t boundary, uint32_t centered,
+                                            int64_t count, const fqt_poly_desc* descs,
+                                            fqt_stream_t s);
+
 /* Time the d-FQT of an uneven batch for every chunk length d + 1 = 1..8 and,
  * for odd p, both chunk representations (default q and n_q); every
  * candidate's output must be byte-identical to the first admissible one's

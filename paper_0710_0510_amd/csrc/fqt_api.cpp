@@ -1195,20 +1195,27 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
   return ok();
 }
 
-fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
-                                    uint32_t boundary, uint32_t centered, int64_t count,
-                                    const fqt_poly_desc* descs, fqt_stream_t s) {
+}  // extern "C"
+
+namespace {
+
+// Checks of an uneven batch (every one on the host, before any device work)
+// and the resolved d-FQT parameters; *live counts the pairs with output.
+fqt_status poly_batch_check(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                                   uint32_t boundary, uint32_t centered, int64_t count,
+                                   const fqt_poly_desc* descs, DfqtChoice* ch, int64_t* live) {
   if (count < 0 || (count && !descs)) return fail(FQT_ERR_INVALID_ARG, "bad descriptor array");
   if (count > INT32_MAX) return fail(FQT_ERR_UNSUPPORTED, "more than 2^31 - 1 pairs");
   if (d > 7) return fail(FQT_ERR_UNSUPPORTED, "d = %u above 7 (chunks of at most 8 coefficients)", d);
   const int64_t ke = d + 1;
-  int64_t nprod = 1, live = 0;
+  int64_t nprod = 1;
+  *live = 0;
   for (int64_t i = 0; i < count; ++i) {
     const fqt_poly_desc& e = descs[i];
     if (e.la < 0 || e.lb < 0)
       return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: negative length", (long long)i);
     if (e.la == 0 || e.lb == 0) continue;
-    ++live;
+    ++*live;
     if (!e.a || !e.b || !e.c)
       return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: null buffer", (long long)i);
     const int64_t nca = (e.la + ke - 1) / ke, ncb = (e.lb + ke - 1) / ke;
@@ -1221,10 +1228,45 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
       return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: output overlaps an input", (long long)i);
     nprod = std::max(nprod, std::min(nca, ncb));
   }
+  return resolve_dfqt(p, d, log2q, n_q, boundary, centered, nprod, ch);
+}
+
+// Pairs with output, longest first (a pair costs about nca ncb chunk products).
+std::vector<int32_t> poly_queue_order(int64_t count, const fqt_poly_desc* descs,
+                                             int64_t ke) {
+  std::vector<int32_t> order;
+  for (int64_t i = 0; i < count; ++i)
+    if (descs[i].la > 0 && descs[i].lb > 0) order.push_back((int32_t)i);
+  auto cost = [&](int32_t i) {
+    return ((descs[i].la + ke - 1) / ke) * ((descs[i].lb + ke - 1) / ke);
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+  return order;
+}
+
+// Four waves per workgroup, each with 16 KiB of LDS per operand: two
+// workgroups per CU; never more waves than pairs.
+fqt_status poly_grid(int dev, int64_t live, int* grid) {
+  int cus = 0;
+  FQT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  *grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 2, (live + 3) / 4));
+  return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
+                                    uint32_t boundary, uint32_t centered, int64_t count,
+                                    const fqt_poly_desc* descs, fqt_stream_t s) {
   DfqtChoice ch;
-  fqt_status st = resolve_dfqt(p, d, log2q, n_q, boundary, centered, nprod, &ch);
+  int64_t live = 0;
+  fqt_status st = poly_batch_check(p, d, log2q, n_q, boundary, centered, count, descs, &ch, &live);
   if (st) return st;
   if (live == 0) return ok();  // nothing to write: an empty product has no coefficient
+  const int64_t ke = d + 1;
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
   // plan key: descriptors, resolved parameters, p, centring, device
@@ -1234,15 +1276,7 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
   std::lock_guard<std::mutex> lk(g_poly_mu);
   PolyPlan* plan = g_poly_plans.find(key);
   if (!plan) {
-    // longest first: a pair costs about nca ncb chunk products
-    std::vector<int32_t> order;
-    for (int64_t i = 0; i < count; ++i)
-      if (descs[i].la > 0 && descs[i].lb > 0) order.push_back((int32_t)i);
-    auto cost = [&](int32_t i) {
-      return ((descs[i].la + ke - 1) / ke) * ((descs[i].lb + ke - 1) / ke);
-    };
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t x, int32_t y) { return cost(x) > cost(y); });
+    const std::vector<int32_t> order = poly_queue_order(count, descs, ke);
     auto pl = std::make_unique<PolyPlan>();
     pl->device = dev;
     pl->live = (int32_t)order.size();
@@ -1255,11 +1289,9 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
       FQT_HIP(hipMemcpy(pl->d_order, order.data(), sizeof(int32_t) * order.size(),
                         hipMemcpyHostToDevice));
     FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
-    hipDeviceProp_t prop;
-    FQT_HIP(hipGetDeviceProperties(&prop, dev));
-    // four waves per workgroup, each with 16 KiB of LDS per operand: two
-    // workgroups per CU; never more waves than pairs
-    const int grid = std::max(1, std::min(prop.multiProcessorCount * 2, (pl->live + 3) / 4));
+    int grid = 1;
+    st = poly_grid(dev, pl->live, &grid);
+    if (st) return st;
     DfqtBatchArgs g{};
     g.descs = pl->d_descs;
     g.order = pl->d_order;
@@ -1288,6 +1320,41 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
   }
   if (plan->live == 0) return ok();
   FQT_HIP(hipGraphLaunch(plan->exec, (hipStream_t)s));
+  return ok();
+}
+
+fqt_status fqt_polymul_dfqt_batched_noalloc(uint32_t p, uint32_t d, uint32_t log2q,
+                                            uint32_t n_q, uint32_t boundary, uint32_t centered,
+                                            int64_t count, const fqt_poly_desc* descs,
+                                            fqt_stream_t s) {
+  DfqtChoice ch;
+  int64_t live = 0;
+  fqt_status st = poly_batch_check(p, d, log2q, n_q, boundary, centered, count, descs, &ch, &live);
+  if (st) return st;
+  if (live > (int64_t)kDfqtNoAllocMaxPairs)
+    return fail(FQT_ERR_UNSUPPORTED, "%lld pairs with output: the allocation-free batch takes "
+                "at most %zu", (long long)live, kDfqtNoAllocMaxPairs);
+  if (live == 0) return ok();
+  int dev = 0;
+  FQT_HIP(hipGetDevice(&dev));
+  // the descriptors in queue order, staged in a per-thread host array that
+  // keeps its capacity across calls
+  thread_local std::vector<PolyDesc> queued;
+  const std::vector<int32_t> order = poly_queue_order(count, descs, (int64_t)d + 1);
+  queued.resize(order.size());
+  for (size_t i = 0; i < order.size(); ++i)
+    std::memcpy(&queued[i], &descs[order[i]], sizeof(PolyDesc));
+  int grid = 1;
+  st = poly_grid(dev, live, &grid);
+  if (st) return st;
+  DfqtBatchArgs g{};
+  g.count = (int32_t)live;
+  g.total_waves = (uint32_t)grid * 4u;
+  g.nq = (uint32_t)ch.nq;
+  g.lg2q = ch.bq;
+  g.pp = dfqt_params(p, centered, ch);
+  FQT_HIP(launch_dfqt_batched_noalloc((int)ch.ke, ch.mode, g, queued.data(), grid,
+                                      (hipStream_t)s));
   return ok();
 }
 

@@ -303,6 +303,21 @@ hipError_t launch_polymul_delayed(const DelayedArgs& g, hipStream_t s);
 hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int grid,
                                hipStream_t s);
 constexpr int kDfqtMaxChunks = 1024;  // chunks of one operand (in LDS)
+
+// The d-FQT batch variant that allocates nothing keeps its queue counters and
+// descriptors in one static device array of this many bytes per GPU: the
+// counters in the first 256 bytes, then at most kDfqtNoAllocMaxPairs
+// descriptors.
+constexpr size_t kDfqtNoAllocMaxPairs = 16384;
+constexpr size_t kDfqtNoAllocDescOffset = 256;
+constexpr size_t kDfqtNoAllocScratch =
+    kDfqtNoAllocDescOffset + kDfqtNoAllocMaxPairs * sizeof(PolyDesc);
+// Copies `host_descs` (g.count descriptors, already in queue order) into the
+// current GPU's scratch array on stream s, clears the queue counters there
+// with a kernel and launches the batch on them; g.descs, g.order and
+// g.counter are ignored.
+hipError_t launch_dfqt_batched_noalloc(int ke, int mode, DfqtBatchArgs g,
+                                       const PolyDesc* host_descs, int grid, hipStream_t s);
 constexpr int kDelayedMaxLen = 8192;  // coefficients of one operand (in LDS)
 
 // Plain comparator: schoolbook with % p and division by P per product.

@@ -27,6 +27,9 @@
 
 #include "fqt_packed.h"
 
+#include <map>
+#include <mutex>
+
 namespace fqt {
 
 // DQT of the chunks of one operand of len coefficients into X[0 .. nch):
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(256) void dfqt_batched_kernel(DfqtBatchArgs g) {
     if (lane == 0) it = (int32_t)atomicAdd(&g.counter[0], 1u);
     it = __builtin_amdgcn_readfirstlane(it);
     if (it >= g.count) break;
-    const PolyDesc d = g.descs[g.order[it]];
+    const PolyDesc d = g.descs[g.order ? g.order[it] : it];
     const int la = __builtin_amdgcn_readfirstlane((int)d.la);
     const int lb = __builtin_amdgcn_readfirstlane((int)d.lb);
     if (la == 0 || lb == 0) continue;  // empty product: no output
@@ -352,6 +355,58 @@ hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int gri
     case 8: return dfqt_bk<8>(mode, g, grid, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---- the batch without allocation ---------------------------------------------
+// One scratch array per GPU (zero at load, kept until the process ends): the
+// two queue counters, then the descriptors in queue order.  Calls that
+// overlap on one GPU share it and race.
+static __device__ __align__(256) uint8_t scratch[kDfqtNoAllocScratch];
+
+__global__ void dfqt_clear_queue(uint32_t* counter) {
+  if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
+}
+
+// The device address of the current GPU's copy of `scratch`, looked up once
+// per device with that device current (the array's name in host code is a
+// host-side stand-in, never passed to a kernel).
+static hipError_t noalloc_scratch(uint8_t** out) {
+  static std::mutex mu;
+  static std::map<int, uint8_t*> ptrs;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = ptrs.find(dev);
+  if (it == ptrs.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    it = ptrs.emplace(dev, static_cast<uint8_t*>(p)).first;
+  }
+  *out = it->second;
+  return hipSuccess;
+}
+
+hipError_t launch_dfqt_batched_noalloc(int ke, int mode, DfqtBatchArgs g,
+                                       const PolyDesc* host_descs, int grid, hipStream_t s) {
+  if (g.count < 0 || (size_t)g.count > kDfqtNoAllocMaxPairs) return hipErrorInvalidValue;
+  uint8_t* base = nullptr;
+  hipError_t e = noalloc_scratch(&base);
+  if (e != hipSuccess) return e;
+  uint32_t* counter = reinterpret_cast<uint32_t*>(base);
+  PolyDesc* descs = reinterpret_cast<PolyDesc*>(base + kDfqtNoAllocDescOffset);
+  if (g.count == 0) return hipSuccess;
+  e = hipMemcpyAsync(descs, host_descs, sizeof(PolyDesc) * (size_t)g.count,
+                     hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(dfqt_clear_queue, dim3(1), dim3(64), 0, s, counter);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  g.descs = descs;
+  g.order = nullptr;  // the descriptors are in queue order
+  g.counter = counter;
+  return launch_dfqt_batched(ke, mode, g, grid, s);
 }
 
 hipError_t launch_polymul_delayed(const DelayedArgs& g, hipStream_t s) {

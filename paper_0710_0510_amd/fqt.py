@@ -32,6 +32,7 @@ EXPORTED = [
     "fqt_tile_count", "fqt_last_error", "fqt_version", "fqt_polymul_dfqt", "fqt_polymul_delayed",
     "fqt_log_info", "fqt_to_log", "fqt_from_log", "fqt_log_add", "fqt_gemm_log",
     "fqt_gemm_winograd", "fqt_polymul_dfqt_batched", "fqt_autotune_polymul",
+    "fqt_polymul_dfqt_batched_noalloc",
 ]
 
 
@@ -89,6 +90,8 @@ def lib() -> ctypes.CDLL:
         "fqt_polymul_delayed": (c_int, [c_u32, vp, vp, c_i64, c_i64, vp, vp]),
         "fqt_polymul_dfqt_batched": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, c_u32, c_i64,
                                              ctypes.POINTER(PolyDesc), vp]),
+        "fqt_polymul_dfqt_batched_noalloc": (c_int, [c_u32, c_u32, c_u32, c_u32, c_u32, c_u32,
+                                                     c_i64, ctypes.POINTER(PolyDesc), vp]),
         "fqt_autotune_polymul": (c_int, [c_u32, c_i64, ctypes.POINTER(PolyDesc),
                                          ctypes.c_char_p, ctypes.POINTER(c_u32),
                                          ctypes.POINTER(c_u32), vp]),
@@ -302,6 +305,14 @@ def polymul_dfqt_batched(p: int, d: int, descs, log2q: int = 0, n_q: int = 0,
     in one persistent launch replayed from a captured graph."""
     _check(lib().fqt_polymul_dfqt_batched(p, d, log2q, n_q, boundary, centered, len(descs),
                                           descs, _stream(stream)))
+
+
+def polymul_dfqt_batched_noalloc(p: int, d: int, descs, log2q: int = 0, n_q: int = 0,
+                                 boundary: int = 0, centered: int = 0, stream=None):
+    """As ``polymul_dfqt_batched`` without any device allocation: the
+    descriptors go to the library's static per-GPU array, no plan, no graph."""
+    _check(lib().fqt_polymul_dfqt_batched_noalloc(p, d, log2q, n_q, boundary, centered,
+                                                  len(descs), descs, _stream(stream)))
 
 
 def autotune_polymul(p: int, descs, cache_path: Optional[str] = None, stream=None):

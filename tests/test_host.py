@@ -457,3 +457,29 @@ def test_dfqt_batched_validation_errors():
     # empty pairs only: nothing to do, nothing refused
     assert _dfqt_batch_status(3, 1, [(0, 7, 0, 0, 0)]) == "FQT_OK"
     assert _dfqt_batch_status(3, 1, []) == "FQT_OK"
+
+
+def test_dfqt_batched_noalloc_validation_errors():
+    # the same host checks as the planned batch, and its own maximum of
+    # 16384 pairs with output, all before any device work
+    L = fqt.lib()
+
+    def status(p, d, pairs, centered=0):
+        arr = (fqt.PolyDesc * len(pairs))()
+        for i, (la, lb, a, b, c) in enumerate(pairs):
+            arr[i] = fqt.PolyDesc(la, lb, a, b, c)
+        return fqt.STATUS_NAMES[L.fqt_polymul_dfqt_batched_noalloc(p, d, 0, 0, 0, centered,
+                                                                  len(pairs), arr, None)]
+
+    ok_pair = (10, 20, BOGUS, BOGUS + (1 << 20), BOGUS + (1 << 30))
+    assert status(4, 1, [ok_pair]) == "FQT_ERR_NOT_PRIME"
+    assert status(3, 8, [ok_pair]) == "FQT_ERR_UNSUPPORTED"
+    assert status(2, 1, [ok_pair], centered=1) == "FQT_ERR_UNSUPPORTED"
+    assert status(3, 1, [(-1, 5, BOGUS, BOGUS, BOGUS)]) == "FQT_ERR_INVALID_ARG"
+    assert status(3, 1, [(2049, 5, BOGUS, BOGUS + (1 << 20), BOGUS + (1 << 30))]) == \
+        "FQT_ERR_UNSUPPORTED"
+    many = [(1, 1, BOGUS + 4 * i, BOGUS + (1 << 20) + 4 * i, BOGUS + (1 << 30) + 4 * i)
+            for i in range(16385)]
+    assert status(3, 4, many) == "FQT_ERR_UNSUPPORTED"
+    assert "16384" in fqt.last_error()
+    assert status(3, 4, [(0, 5, 0, 0, 0)]) == "FQT_OK"
