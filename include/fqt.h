@@ -80,13 +80,17 @@ typedef enum {
   FQT_PATH_PACKED_F64 = 1, /* q-adic packed FP64 MFMA + REDQ (the FQT) */
   FQT_PATH_INT8 = 2,       /* coefficient-wise INT8 MFMA, INT32 accumulation,
                               delayed reduction (Section 6, eq. (3)) */
-  FQT_PATH_PLAIN = 3       /* comparator: schoolbook product with % p and
+  FQT_PATH_PLAIN = 3,      /* comparator: schoolbook product with % p and
                               division by P for every product, no packing */
+  FQT_PATH_INT_RANGE_ = 0x7fffffff /* not a path: gives the type the range of
+                              int, so any int a caller passes is a value of it
+                              (and refused as FQT_ERR_INVALID_ARG) */
 } fqt_path;
 
 typedef enum {
   FQT_UNPACK_POLY = 0,  /* ndigits coefficients mod p (Alg. 2 + Q_d) */
-  FQT_UNPACK_FIELD = 1  /* k coefficients mod p and mod P (Alg. 4 L + H) */
+  FQT_UNPACK_FIELD = 1, /* k coefficients mod p and mod P (Alg. 4 L + H) */
+  FQT_UNPACK_INT_RANGE_ = 0x7fffffff /* not a mode: int range, as fqt_path */
 } fqt_unpack_mode;
 
 typedef struct fqt_field_s* fqt_field; /* opaque, immutable after creation */
