@@ -689,10 +689,11 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
       return fail(FQT_ERR_UNSUPPORTED, "tile %d needs blocks of at least 4 products (n_q = %"
                   PRIu64 ")", kWaveTile, nq);
     // digit sums in fields of 2b bits: every absorbed block adds at most q - 1
-    // to a field (its digits; centred: shifted digits), a fold leaves < p;
+    // to a field (its digits; centred: shifted digits), a fold leaves < p,
+    // and the epilogue adds an offset below p (the centred shift's removal);
     // blocks: ceil(K / (4 nqg)) and one of the bias alone
     const uint64_t width = (1ull << (2 * b)) - 1, growth = q - 1;
-    const uint64_t cap = (width - (p - 1)) / growth;
+    const uint64_t cap = (width - 2 * (p - 1)) / growth;
     const uint64_t nblocks = ((uint64_t)K + 4 * nqg - 1) / (4 * nqg) + 1;
     pc->b = b;
     pc->nq = pc->nq_real = (uint32_t)(4 * nqg);
@@ -2070,6 +2071,7 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
         neg |= ((p - cc) % p) << (8 * i);
       }
       pp.c0neg = neg;
+      pp.dshift = beta;
     }
     dqt_params(f, pc.b, pc.centered, &pp);
     if (!(pp.dqt_flags & kDqtLut)) {  // the kernel always permutes: identity bytes

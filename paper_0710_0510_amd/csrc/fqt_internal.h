@@ -33,6 +33,7 @@ struct PackedParams {
   uint32_t centered;   // centred packing (staged tiles): digits shifted by q/2
   uint32_t c0neg;      // centred: -(L + H of the shift's residues), one word
                        // (d-FQT: (q/2) mod p, the shift of every digit of a block)
+  uint32_t dshift;     // centred, wave tile: (q/2) mod p, taken off every digit sum
   double cbias;        // centred: 2^52 + sum_{i<2k-1} (q/2) q^i, every block's seed
   // DQT of the LDS-staged loaders (fqt_packed.h dqt_chunk):
   uint32_t dqt_flags;  // kDqtLut: centred bytes through the perm table below (p <= 8);

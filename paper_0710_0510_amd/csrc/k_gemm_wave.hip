@@ -30,8 +30,8 @@
 // coefficients of sum_l A_l B_l in GF(p)[X] (Alg. 2's mu, every block's
 // digits read as bit fields since q = 2^7); Thm. 3's tables built for
 // q = 0 mod p (Q_d the identity) reduce them modulo P.  Centred packing
-// shifts every digit of every block by q/2: n_blocks * (q/2) * (L + H)(1..1)
-// comes off at the end.
+// shifts every digit of every block by q/2: n_blocks * (q/2) mod p comes off
+// every digit sum before its reduction.
 //
 // Work order, fixed on the host: products are dealt to the 8 XCDs (workgroup
 // i runs on XCD i % 8 and each XCD has its own L2), longest first onto the
@@ -72,19 +72,25 @@ __device__ __forceinline__ double wave_dqt(uint32_t w, const PackedParams& pp) {
   return (double)(int32_t)(lo + (hi << 14));
 }
 
-// Field element of the digit sums held in (E, T): nadd blocks added since
-// the last fold, q = 2^7, tables for q = 0 mod p.
+// Field element of the digit sums held in (E, T), q = 2^7, tables for
+// q = 0 mod p.  kE and kO are the tile's constants for the even and the odd
+// fields: in every field the non-negative offset that takes the centred
+// shift off modulo p, and in kO also minus the 2^52 bits of the blocks added
+// since the last fold (each field stays below 2^14: the host keeps room for
+// the offset when it sets the folds).
 __device__ __forceinline__ uint32_t digit_sums_elem(const BlockLanes<kWaveKE, 2>& st,
-                                                    uint32_t nadd, const PackedParams& pp,
+                                                    uint64_t kE, uint64_t kO,
+                                                    const PackedParams& pp,
                                                     const uint32_t* __restrict__ Ls,
                                                     const uint32_t* __restrict__ Hs) {
   using BL = BlockLanes<kWaveKE, 2>;
   constexpr int ND = 2 * kWaveKE - 1;
-  const uint64_t O = st.T - st.E - (uint64_t)nadd * BL::XB;
+  const uint64_t E = st.E + kE;
+  const uint64_t O = st.T - st.E + kO;
   uint32_t il = 0, ih = 0;
 #pragma unroll
   for (int d = 0; d < ND; ++d) {
-    const uint32_t mu = mod_p_24(BL::field((d & 1) ? O : st.E, d), pp.fa);
+    const uint32_t mu = mod_p_24(BL::field((d & 1) ? O : E, d), pp.fa);
     if (d < kWaveKE) il |= mu << (pp.fa.cb * d);
     if (d >= kWaveKE - 1) ih |= mu << (pp.fa.cb * (d - kWaveKE + 1));
   }
@@ -133,7 +139,9 @@ __device__ __forceinline__ void load_block(const WCtx<NQG>& x, int64_t s, WStage
   constexpr int KE = kWaveKE, KB = 4 * NQG;
   const int grp = (threadIdx.x & 63) >> 4;
   const int32_t sa = (int32_t)(s * KB * KE), sb = (int32_t)(s * x.bstep);
-  const int32_t krem = (int32_t)min<int64_t>(x.K - s * KB, KB);  // may be <= 0
+  // k left in this block, in 32 bits (K < 2^30); may be <= 0
+  int32_t krem = (int32_t)x.K - (int32_t)s * KB;
+  krem = krem < KB ? krem : KB;
 #pragma unroll
   for (int i = 0; i < 2; ++i) buf_load<NQG>(x.rsa, x.voa[i], sa, st.a[i]);
 #pragma unroll
@@ -270,9 +278,19 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
         }
         continue;
       }
-      // last block of the item: mu_j = D_j mod p, L + H at q = 0 mod p, the
-      // centred shift off, k bytes per element
-      const uint32_t corr = pp.centered ? centred_correction<KE>(pp.c0neg, nblk, pp.fa) : 0u;
+      // last block of the item: mu_j = D_j mod p with the centred shift
+      // nblk (q/2) taken off every digit sum, L + H at q = 0 mod p, k bytes
+      // per element
+      uint64_t kE = 0, kO = (uint64_t)0 - (uint64_t)nadd * BlockLanes<KE, 2>::XB;
+      if (pp.centered) {
+        const uint32_t p = pp.fa.p;
+        const uint32_t cc = (p - (nblk % p) * pp.dshift % p) % p;
+#pragma unroll
+        for (int d = 0; d < 2 * KE - 1; ++d) {
+          if (d & 1) kO += (uint64_t)cc << (7 * d);
+          else kE += (uint64_t)cc << (7 * d);
+        }
+      }
       const int64_t m0 = (int64_t)ctm * 32, n0 = (int64_t)ctn * 32;
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -281,8 +299,7 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
           const int64_t row = m0 + 16 * i + grp + 4 * v;
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
-            uint32_t e = digit_sums_elem(st[i][j][v], nadd, pp, Ls, Hs);
-            if (pp.centered) e = add_bytes_mod_p(e, corr, pp.fa);
+            const uint32_t e = digit_sums_elem(st[i][j][v], kE, kO, pp, Ls, Hs);
             const int64_t col = n0 + 2 * c + j;
             if (row < cg.M && col < cg.N) store_elem<KE>(cg.C + (row * cg.ldc + col) * KE, e);
           }
@@ -301,8 +318,10 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
 }
 
 // Items of wave w: items[wave_begin[w] .. wave_begin[w + 1]), in order.
+// Three waves per SIMD; with NQG = 4 (p = 2) two, whose registers hold the
+// larger stages without spilling.
 template <int NQG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void gemm_wave_batched_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQG == 4 ? 2 : 3))) void gemm_wave_batched_kernel(
     const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items,
     const int32_t* __restrict__ wave_begin, PackedParams pp) {
   extern __shared__ uint32_t tabs[];
