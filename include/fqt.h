@@ -293,18 +293,17 @@ typedef struct {
 
 /* The d-FQT of Section 6 (as fqt_polymul_dfqt, same p, d, log2q, n_q,
  * boundary and centered, with the same errors) on a batch of pairs of
- * uneven lengths, in ONE persistent launch: every wave takes pairs from a
- * queue ordered longest first and multiplies each one alone.  n_q and the
+ * uneven lengths, in ONE persistent launch: the pairs, ordered longest
+ * first, are dealt to the waves in a fixed snake order and every wave
+ * multiplies each of its pairs alone.  n_q and the
  * block steps are chosen for the batch's longest chunk-pair sum.
  *   descs  host array of count descriptors; every byte of a, b in [0, p);
  *          la, lb >= 0 (FQT_ERR_INVALID_ARG if negative), at most
  *          1024 (d+1) each (FQT_ERR_UNSUPPORTED beyond); c must not overlap
  *          its own a or b (FQT_ERR_INVALID_ARG).
- * The first call with a given descriptor list builds a plan (queue order,
+ * The first call with a given descriptor list builds a plan (pair order,
  * device descriptors) and captures the launch in a hipGraph; later calls
- * with the same list replay it, on whatever stream s is given.  Replays of
- * one plan must not overlap on two streams (they share the plan's queue
- * counter). */
+ * with the same list replay it, on whatever stream s is given. */
 fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
                                     uint32_t boundary, uint32_t centered, int64_t count,
                                     const fqt_poly_desc* descs, fqt_stream_t s);
@@ -313,10 +312,9 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
  * (code under stream capture, serving loops, harnesses that forbid
  * hipMalloc): the same arguments, checks, errors and output bytes, but no
  * plan and no graph; it calls no hipMalloc, hipFree or other allocating
- * routine.  Each call copies the descriptors, in queue order, into a static
- * device array of this library (about 640 KiB, one per GPU, held until the
- * process ends) on stream s, clears the queue counters there with a kernel
- * and launches the batch.  At most 16384 pairs with output per call
+ * routine.  Each call copies the descriptors, in schedule order, into a
+ * static device array of this library (640 KiB, one per GPU, held until the
+ * process ends) on stream s and launches the batch on them.  At most 16384 pairs with output per call
  * (FQT_ERR_UNSUPPORTED beyond).  Every call on one GPU uses that GPU's one
  * array: calls that overlap in time on one GPU (two streams, two threads)
  * race and may write wrong bytes; calls ordered on one stream do not. */

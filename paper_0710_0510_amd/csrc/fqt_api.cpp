@@ -1144,12 +1144,10 @@ struct PolyPlan {
       if (graph) hipGraphDestroy(graph);
       hipFree(d_descs);
       hipFree(d_order);
-      hipFree(d_counter);
     });
   }
   PolyDesc* d_descs = nullptr;
   int32_t* d_order = nullptr;
-  uint32_t* d_counter = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = -1;
@@ -1189,6 +1187,7 @@ fqt_status fqt_polymul_dfqt(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
   g.count = count;
   g.len = (int32_t)len;
   g.nch = (int32_t)nch;
+  g.cap = (int32_t)nch;
   g.nq = (uint32_t)ch.nq;
   g.lg2q = ch.bq;
   g.pp = dfqt_params(p, centered, ch);
@@ -1204,12 +1203,13 @@ namespace {
 // and the resolved d-FQT parameters; *live counts the pairs with output.
 fqt_status poly_batch_check(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
                                    uint32_t boundary, uint32_t centered, int64_t count,
-                                   const fqt_poly_desc* descs, DfqtChoice* ch, int64_t* live) {
+                                   const fqt_poly_desc* descs, DfqtChoice* ch, int64_t* live,
+                                   int32_t* cap) {
   if (count < 0 || (count && !descs)) return fail(FQT_ERR_INVALID_ARG, "bad descriptor array");
   if (count > INT32_MAX) return fail(FQT_ERR_UNSUPPORTED, "more than 2^31 - 1 pairs");
   if (d > 7) return fail(FQT_ERR_UNSUPPORTED, "d = %u above 7 (chunks of at most 8 coefficients)", d);
   const int64_t ke = d + 1;
-  int64_t nprod = 1;
+  int64_t nprod = 1, chmax = 1;
   *live = 0;
   for (int64_t i = 0; i < count; ++i) {
     const fqt_poly_desc& e = descs[i];
@@ -1228,12 +1228,14 @@ fqt_status poly_batch_check(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q
     if (overlap(e.c, nc, e.a, (size_t)e.la) || overlap(e.c, nc, e.b, (size_t)e.lb))
       return fail(FQT_ERR_INVALID_ARG, "descriptor %lld: output overlaps an input", (long long)i);
     nprod = std::max(nprod, std::min(nca, ncb));
+    chmax = std::max(chmax, std::max(nca, ncb));
   }
+  *cap = (int32_t)chmax;
   return resolve_dfqt(p, d, log2q, n_q, boundary, centered, nprod, ch);
 }
 
 // Pairs with output, longest first (a pair costs about nca ncb chunk products).
-std::vector<int32_t> poly_queue_order(int64_t count, const fqt_poly_desc* descs,
+std::vector<int32_t> poly_order(int64_t count, const fqt_poly_desc* descs,
                                              int64_t ke) {
   std::vector<int32_t> order;
   for (int64_t i = 0; i < count; ++i)
@@ -1246,12 +1248,14 @@ std::vector<int32_t> poly_queue_order(int64_t count, const fqt_poly_desc* descs,
   return order;
 }
 
-// Four waves per workgroup, each with 16 KiB of LDS per operand: two
-// workgroups per CU; never more waves than pairs.
-fqt_status poly_grid(int dev, int64_t live, int* grid) {
+// Four waves per workgroup, each with LDS for cap chunks per operand: as
+// many workgroups as fit on every CU at once, never more waves than pairs.
+fqt_status poly_grid(int dev, int64_t live, const DfqtChoice& ch, uint32_t centered, int32_t cap,
+                     int* grid) {
   int cus = 0;
   FQT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  *grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * 2, (live + 3) / 4));
+  const int per_cu = dfqt_batched_occupancy((int)ch.ke, ch.mode, centered != 0, cap);
+  *grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, (live + 3) / 4));
   return ok();
 }
 
@@ -1264,7 +1268,9 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
                                     const fqt_poly_desc* descs, fqt_stream_t s) {
   DfqtChoice ch;
   int64_t live = 0;
-  fqt_status st = poly_batch_check(p, d, log2q, n_q, boundary, centered, count, descs, &ch, &live);
+  int32_t cap = 1;
+  fqt_status st = poly_batch_check(p, d, log2q, n_q, boundary, centered, count, descs, &ch, &live,
+                                   &cap);
   if (st) return st;
   if (live == 0) return ok();  // nothing to write: an empty product has no coefficient
   const int64_t ke = d + 1;
@@ -1277,28 +1283,25 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
   std::lock_guard<std::mutex> lk(g_poly_mu);
   PolyPlan* plan = g_poly_plans.find(key);
   if (!plan) {
-    const std::vector<int32_t> order = poly_queue_order(count, descs, ke);
+    const std::vector<int32_t> order = poly_order(count, descs, ke);
     auto pl = std::make_unique<PolyPlan>();
     pl->device = dev;
     pl->live = (int32_t)order.size();
     FQT_HIP(hipMalloc(&pl->d_descs, sizeof(PolyDesc) * count));
     FQT_HIP(hipMalloc(&pl->d_order, sizeof(int32_t) * std::max<size_t>(order.size(), 1)));
-    FQT_HIP(hipMalloc(&pl->d_counter, 2 * sizeof(uint32_t)));
     static_assert(sizeof(PolyDesc) == sizeof(fqt_poly_desc), "descriptor layouts agree");
     FQT_HIP(hipMemcpy(pl->d_descs, descs, sizeof(PolyDesc) * count, hipMemcpyHostToDevice));
     if (!order.empty())
       FQT_HIP(hipMemcpy(pl->d_order, order.data(), sizeof(int32_t) * order.size(),
                         hipMemcpyHostToDevice));
-    FQT_HIP(hipMemset(pl->d_counter, 0, 2 * sizeof(uint32_t)));
     int grid = 1;
-    st = poly_grid(dev, pl->live, &grid);
+    st = poly_grid(dev, pl->live, ch, centered, cap, &grid);
     if (st) return st;
     DfqtBatchArgs g{};
+    g.cap = cap;
     g.descs = pl->d_descs;
     g.order = pl->d_order;
     g.count = pl->live;
-    g.total_waves = (uint32_t)grid * 4u;
-    g.counter = pl->d_counter;
     g.nq = (uint32_t)ch.nq;
     g.lg2q = ch.bq;
     g.pp = dfqt_params(p, centered, ch);
@@ -1330,7 +1333,9 @@ fqt_status fqt_polymul_dfqt_batched_noalloc(uint32_t p, uint32_t d, uint32_t log
                                             fqt_stream_t s) {
   DfqtChoice ch;
   int64_t live = 0;
-  fqt_status st = poly_batch_check(p, d, log2q, n_q, boundary, centered, count, descs, &ch, &live);
+  int32_t cap = 1;
+  fqt_status st = poly_batch_check(p, d, log2q, n_q, boundary, centered, count, descs, &ch, &live,
+                                   &cap);
   if (st) return st;
   if (live > (int64_t)kDfqtNoAllocMaxPairs)
     return fail(FQT_ERR_UNSUPPORTED, "%lld pairs with output: the allocation-free batch takes "
@@ -1338,23 +1343,23 @@ fqt_status fqt_polymul_dfqt_batched_noalloc(uint32_t p, uint32_t d, uint32_t log
   if (live == 0) return ok();
   int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
-  // the descriptors in queue order, staged in a per-thread host array that
+  // the descriptors in schedule order, staged in a per-thread host array that
   // keeps its capacity across calls
-  thread_local std::vector<PolyDesc> queued;
-  const std::vector<int32_t> order = poly_queue_order(count, descs, (int64_t)d + 1);
-  queued.resize(order.size());
+  thread_local std::vector<PolyDesc> ordered;
+  const std::vector<int32_t> order = poly_order(count, descs, (int64_t)d + 1);
+  ordered.resize(order.size());
   for (size_t i = 0; i < order.size(); ++i)
-    std::memcpy(&queued[i], &descs[order[i]], sizeof(PolyDesc));
+    std::memcpy(&ordered[i], &descs[order[i]], sizeof(PolyDesc));
   int grid = 1;
-  st = poly_grid(dev, live, &grid);
+  st = poly_grid(dev, live, ch, centered, cap, &grid);
   if (st) return st;
   DfqtBatchArgs g{};
+  g.cap = cap;
   g.count = (int32_t)live;
-  g.total_waves = (uint32_t)grid * 4u;
   g.nq = (uint32_t)ch.nq;
   g.lg2q = ch.bq;
   g.pp = dfqt_params(p, centered, ch);
-  FQT_HIP(launch_dfqt_batched_noalloc((int)ch.ke, ch.mode, g, queued.data(), grid,
+  FQT_HIP(launch_dfqt_batched_noalloc((int)ch.ke, ch.mode, g, ordered.data(), grid,
                                       (hipStream_t)s));
   return ok();
 }

@@ -60,6 +60,7 @@ struct DfqtArgs {
   int32_t len, nch;      // coefficients, chunks per operand
   uint32_t nq, lg2q;     // products per block; q = 2^lg2q
   PackedParams pp;       // fa, qmod and fold_blocks are used
+  int32_t cap;           // LDS chunks per operand and wave (>= nch): sizes the launch's LDS
 };
 
 // One pair of an uneven polynomial batch: c (la + lb - 1 coefficients) =
@@ -71,17 +72,16 @@ struct PolyDesc {
   uint8_t* c;
 };
 
-// d-FQT over an uneven batch: pairs taken from one queue in the order
-// order[0 .. count) (longest first), counter[0] the queue, counter[1] the
-// waves done (both zero before a launch; the last wave leaves them zero).
+// d-FQT over an uneven batch: the pairs in the order order[0 .. count)
+// (longest first; null: descs is already in that order), dealt to the
+// waves of the grid in a fixed snake order.
 struct DfqtBatchArgs {
   const PolyDesc* descs;
   const int32_t* order;
   int32_t count;
-  uint32_t total_waves;
-  uint32_t* counter;
   uint32_t nq, lg2q;  // products per block; q = 2^lg2q
   PackedParams pp;    // fa, qmod, fold_blocks, centring as DfqtArgs
+  int32_t cap;        // LDS chunks per operand and wave (>= every nca, ncb)
 };
 
 // Classical product with delayed reduction (eq. (3)), the comparator.
@@ -303,20 +303,19 @@ hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s);
 hipError_t launch_polymul_delayed(const DelayedArgs& g, hipStream_t s);
 hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int grid,
                                hipStream_t s);
+// Workgroups of the batched d-FQT kernel that fit on one CU with LDS for
+// `cap` chunks per operand and wave.
+int dfqt_batched_occupancy(int ke, int mode, bool centered, int32_t cap);
 constexpr int kDfqtMaxChunks = 1024;  // chunks of one operand (in LDS)
 
-// The d-FQT batch variant that allocates nothing keeps its queue counters and
-// descriptors in one static device array of this many bytes per GPU: the
-// counters in the first 256 bytes, then at most kDfqtNoAllocMaxPairs
-// descriptors.
+// The d-FQT batch variant that allocates nothing keeps its descriptors in
+// one static device array of this many bytes per GPU: at most
+// kDfqtNoAllocMaxPairs descriptors.
 constexpr size_t kDfqtNoAllocMaxPairs = 16384;
-constexpr size_t kDfqtNoAllocDescOffset = 256;
-constexpr size_t kDfqtNoAllocScratch =
-    kDfqtNoAllocDescOffset + kDfqtNoAllocMaxPairs * sizeof(PolyDesc);
-// Copies `host_descs` (g.count descriptors, already in queue order) into the
-// current GPU's scratch array on stream s, clears the queue counters there
-// with a kernel and launches the batch on them; g.descs, g.order and
-// g.counter are ignored.
+constexpr size_t kDfqtNoAllocScratch = kDfqtNoAllocMaxPairs * sizeof(PolyDesc);
+// Copies `host_descs` (g.count descriptors, already in schedule order) into
+// the current GPU's scratch array on stream s and launches the batch on
+// them; g.descs and g.order are ignored.
 hipError_t launch_dfqt_batched_noalloc(int ke, int mode, DfqtBatchArgs g,
                                        const PolyDesc* host_descs, int grid, hipStream_t s);
 constexpr int kDelayedMaxLen = 8192;  // coefficients of one operand (in LDS)

@@ -13,7 +13,8 @@
 // overlap in d digits, which are added mod p.
 //
 // One wave per product, four per workgroup.  The packed chunks of both
-// operands sit in LDS.  Lane l accumulates S_t for the four consecutive
+// operands sit in LDS, sized at launch for the longest operand, so short
+// operands leave room for more workgroups per CU.  Lane l accumulates S_t for the four consecutive
 // t = t0 + 4l .. t0 + 4l + 3 over a chunk index i that runs in step across
 // the wave (so P_i is one broadcast read), keeping Q_{t-i} .. Q_{t+3-i} as a
 // sliding window (one more read per i); out-of-range chunks read as zero,
@@ -23,7 +24,7 @@
 // from t-1: the same lane for r > 0, the previous lane (a shuffle) for r = 0,
 // lane 63 of the previous pass for the first lane.
 // Pairs of uneven lengths (la, lb) run the same convolution over nca and
-// ncb chunks, every wave taking pairs from one queue (dfqt_batched_kernel).
+// ncb chunks, every wave taking its share of the pairs (dfqt_batched_kernel).
 
 #include "fqt_packed.h"
 
@@ -166,12 +167,12 @@ __device__ __forceinline__ void dfqt_convolve(const double* __restrict__ P, int 
 // One wave per product, four per workgroup, every pair of len coefficients.
 template <int KE, int MODE, bool CEN>
 __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
-  __shared__ double sh[4][2][kDfqtMaxChunks];
+  extern __shared__ double dsh[];  // 4 waves x (P, Q) x cap chunks
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t prod = (int64_t)blockIdx.x * 4 + w;
   const bool live = prod < g.count;  // idle waves still reach every barrier
-  double* P = sh[w][0];
-  double* Q = sh[w][1];
+  double* P = dsh + (size_t)w * 2 * g.cap;
+  double* Q = P + g.cap;
   const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
   const int len = g.len, nch = g.nch;
   const uint8_t* pa = g.a + (live ? prod : 0) * len;
@@ -186,44 +187,50 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
   dfqt_convolve<KE, MODE, CEN>(P, nch, Q, nch, 2 * len - 1, pc, g.nq, b, g.pp, lane);
 }
 
-// Uneven batch: every wave takes products from one queue (the host orders
-// them longest first) and computes each one alone in its own LDS region:
-// pack both operands, a wave-wide fence, the convolution.  The last wave out
-// resets the queue for the next launch.
+// Uneven batch: the host orders the pairs longest first and wave w of W
+// takes, in round r, pair r W + w (r even) or r W + W - 1 - w (r odd), so
+// the cost is spread evenly without a shared queue (one atomic counter
+// hammered by every wave of 8 XCDs costs more than short pairs do).  Each
+// pair is computed alone in the wave's LDS region: pack both operands, a
+// wave-wide fence, the convolution; the next pair's descriptor is read
+// while the current one runs.
 template <int KE, int MODE, bool CEN>
 __global__ __launch_bounds__(256) void dfqt_batched_kernel(DfqtBatchArgs g) {
-  __shared__ double sh[4][2][kDfqtMaxChunks];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double* P = sh[w][0];
-  double* Q = sh[w][1];
+  extern __shared__ double dsh[];  // 4 waves x (P, Q) x cap chunks
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int W = (int)gridDim.x * 4;
+  double* P = dsh + (size_t)(w & 3) * 2 * g.cap;
+  double* Q = P + g.cap;
   const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
-  for (;;) {
-    int32_t it = 0;
-    if (lane == 0) it = (int32_t)atomicAdd(&g.counter[0], 1u);
-    it = __builtin_amdgcn_readfirstlane(it);
-    if (it >= g.count) break;
-    const PolyDesc d = g.descs[g.order ? g.order[it] : it];
+  auto pick = [&](int r) -> int64_t {
+    const int64_t it = (int64_t)r * W + ((r & 1) ? W - 1 - w : w);
+    return it < g.count ? it : -1;
+  };
+  int64_t it = pick(0);
+  PolyDesc d{};
+  if (it >= 0) d = g.descs[g.order ? g.order[it] : it];
+  for (int r = 0; it >= 0; ++r) {
+    const int64_t nx = pick(r + 1);
+    PolyDesc dn{};
+    if (nx >= 0) dn = g.descs[g.order ? g.order[nx] : nx];
     const int la = __builtin_amdgcn_readfirstlane((int)d.la);
     const int lb = __builtin_amdgcn_readfirstlane((int)d.lb);
-    if (la == 0 || lb == 0) continue;  // empty product: no output
-    const int nca = (la + KE - 1) / KE, ncb = (lb + KE - 1) / KE;
-    // the previous product's reads of P and Q are done before they are rewritten
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    dfqt_pack<KE, CEN>(d.a, la, nca, b, g.pp, P, lane);
-    dfqt_pack<KE, CEN>(d.b, lb, ncb, b, g.pp, Q, lane);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    dfqt_convolve<KE, MODE, CEN>(P, nca, Q, ncb, la + lb - 1, d.c, g.nq, b, g.pp, lane);
-  }
-  if (lane == 0) {
-    __threadfence();
-    if (atomicAdd(&g.counter[1], 1u) == g.total_waves - 1) {
-      atomicExch(&g.counter[0], 0u);
-      atomicExch(&g.counter[1], 0u);
+    if (la > 0 && lb > 0) {
+      const int nca = (la + KE - 1) / KE, ncb = (lb + KE - 1) / KE;
+      // the previous pair's reads of P and Q are done before they are rewritten
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      dfqt_pack<KE, CEN>(d.a, la, nca, b, g.pp, P, lane);
+      dfqt_pack<KE, CEN>(d.b, lb, ncb, b, g.pp, Q, lane);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      dfqt_convolve<KE, MODE, CEN>(P, nca, Q, ncb, la + lb - 1, d.c, g.nq, b, g.pp, lane);
     }
+    it = nx;
+    d = dn;
   }
 }
 
@@ -281,15 +288,20 @@ __global__ __launch_bounds__(256) void polymul_delayed_kernel(DelayedArgs g) {
   }
 }
 
+// LDS of one workgroup: four waves, two operands of cap chunks each
+static size_t dfqt_lds_bytes(int32_t cap) { return (size_t)4 * 2 * (size_t)cap * sizeof(double); }
+
 template <int KE, bool CEN>
 static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
+  if (g.cap < g.nch || g.cap > kDfqtMaxChunks) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((g.count + 3) / 4));
+  const size_t lds = dfqt_lds_bytes(g.cap);
   switch (mode) {
-    case 0: hipLaunchKernelGGL((dfqt_kernel<KE, 0, CEN>), grid, dim3(256), 0, s, g); break;
-    case 1: hipLaunchKernelGGL((dfqt_kernel<KE, 1, CEN>), grid, dim3(256), 0, s, g); break;
+    case 0: hipLaunchKernelGGL((dfqt_kernel<KE, 0, CEN>), grid, dim3(256), lds, s, g); break;
+    case 1: hipLaunchKernelGGL((dfqt_kernel<KE, 1, CEN>), grid, dim3(256), lds, s, g); break;
     case 2:
       if constexpr (digit_sums_fit<KE>()) {
-        hipLaunchKernelGGL((dfqt_kernel<KE, 2, CEN>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((dfqt_kernel<KE, 2, CEN>), grid, dim3(256), lds, s, g);
         break;
       } else {
         return hipErrorInvalidValue;
@@ -306,12 +318,14 @@ static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
 
 template <int KE, bool CEN>
 static hipError_t dfqt_bk(int mode, const DfqtBatchArgs& g, int grid, hipStream_t s) {
+  if (g.cap < 1 || g.cap > kDfqtMaxChunks) return hipErrorInvalidValue;
+  const size_t lds = dfqt_lds_bytes(g.cap);
   switch (mode) {
-    case 0: hipLaunchKernelGGL((dfqt_batched_kernel<KE, 0, CEN>), grid, dim3(256), 0, s, g); break;
-    case 1: hipLaunchKernelGGL((dfqt_batched_kernel<KE, 1, CEN>), grid, dim3(256), 0, s, g); break;
+    case 0: hipLaunchKernelGGL((dfqt_batched_kernel<KE, 0, CEN>), grid, dim3(256), lds, s, g); break;
+    case 1: hipLaunchKernelGGL((dfqt_batched_kernel<KE, 1, CEN>), grid, dim3(256), lds, s, g); break;
     case 2:
       if constexpr (digit_sums_fit<KE>()) {
-        hipLaunchKernelGGL((dfqt_batched_kernel<KE, 2, CEN>), grid, dim3(256), 0, s, g);
+        hipLaunchKernelGGL((dfqt_batched_kernel<KE, 2, CEN>), grid, dim3(256), lds, s, g);
         break;
       } else {
         return hipErrorInvalidValue;
@@ -342,6 +356,47 @@ hipError_t launch_dfqt(int ke, int mode, const DfqtArgs& g, hipStream_t s) {
   }
 }
 
+template <int KE, int MODE, bool CEN>
+static int dfqt_occ(int32_t cap) {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &blocks, (const void*)dfqt_batched_kernel<KE, MODE, CEN>, 256,
+          dfqt_lds_bytes(cap)) != hipSuccess)
+    blocks = 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+template <int KE, bool CEN>
+static int dfqt_occ(int mode, int32_t cap) {
+  switch (mode) {
+    case 0: return dfqt_occ<KE, 0, CEN>(cap);
+    case 1: return dfqt_occ<KE, 1, CEN>(cap);
+    case 2:
+      if constexpr (digit_sums_fit<KE>()) return dfqt_occ<KE, 2, CEN>(cap);
+      return 1;
+    default: return 1;
+  }
+}
+
+template <int KE>
+static int dfqt_occ(int mode, bool centered, int32_t cap) {
+  return centered ? dfqt_occ<KE, true>(mode, cap) : dfqt_occ<KE, false>(mode, cap);
+}
+
+int dfqt_batched_occupancy(int ke, int mode, bool centered, int32_t cap) {
+  switch (ke) {
+    case 1: return dfqt_occ<1>(mode, centered, cap);
+    case 2: return dfqt_occ<2>(mode, centered, cap);
+    case 3: return dfqt_occ<3>(mode, centered, cap);
+    case 4: return dfqt_occ<4>(mode, centered, cap);
+    case 5: return dfqt_occ<5>(mode, centered, cap);
+    case 6: return dfqt_occ<6>(mode, centered, cap);
+    case 7: return dfqt_occ<7>(mode, centered, cap);
+    case 8: return dfqt_occ<8>(mode, centered, cap);
+    default: return 1;
+  }
+}
+
 hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int grid,
                                hipStream_t s) {
   switch (ke) {
@@ -358,14 +413,9 @@ hipError_t launch_dfqt_batched(int ke, int mode, const DfqtBatchArgs& g, int gri
 }
 
 // ---- the batch without allocation ---------------------------------------------
-// One scratch array per GPU (zero at load, kept until the process ends): the
-// two queue counters, then the descriptors in queue order.  Calls that
-// overlap on one GPU share it and race.
+// One scratch array per GPU (kept until the process ends): the descriptors
+// in schedule order.  Calls that overlap on one GPU share it and race.
 static __device__ __align__(256) uint8_t scratch[kDfqtNoAllocScratch];
-
-__global__ void dfqt_clear_queue(uint32_t* counter) {
-  if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
-}
 
 // The device address of the current GPU's copy of `scratch`, looked up once
 // per device with that device current (the array's name in host code is a
@@ -394,18 +444,13 @@ hipError_t launch_dfqt_batched_noalloc(int ke, int mode, DfqtBatchArgs g,
   uint8_t* base = nullptr;
   hipError_t e = noalloc_scratch(&base);
   if (e != hipSuccess) return e;
-  uint32_t* counter = reinterpret_cast<uint32_t*>(base);
-  PolyDesc* descs = reinterpret_cast<PolyDesc*>(base + kDfqtNoAllocDescOffset);
+  PolyDesc* descs = reinterpret_cast<PolyDesc*>(base);
   if (g.count == 0) return hipSuccess;
   e = hipMemcpyAsync(descs, host_descs, sizeof(PolyDesc) * (size_t)g.count,
                      hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(dfqt_clear_queue, dim3(1), dim3(64), 0, s, counter);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
   g.descs = descs;
-  g.order = nullptr;  // the descriptors are in queue order
-  g.counter = counter;
+  g.order = nullptr;  // the descriptors are in schedule order
   return launch_dfqt_batched(ke, mode, g, grid, s);
 }
 

@@ -4,7 +4,7 @@ Bit-exact.
 
 Two calls in a row on the same static per-GPU scratch array, the first at
 the largest batch it takes (16384 pairs), the second smaller: the second must
-not see the first's descriptors or queue state.  Then the refusal beyond the
+not see the first's descriptors.  Then the refusal beyond the
 maximum, before any device work.
 """
 import sys
@@ -49,7 +49,7 @@ def batch(p, lens, seed):
 @pytest.mark.parametrize("p,d,centered", [(3, 4, 0), (3, 4, 1), (7, 1, 0), (2, 5, 0)])
 def test_noalloc_matches_planned_batch_two_calls(p, d, centered):
     big = W.poly_uneven_lengths(21 + p + d, 16384, 1, 1024)
-    big[5] = (0, 9)  # an empty pair: no output, and not queued
+    big[5] = (0, 9)  # an empty pair: no output, and not scheduled
     small = W.poly_uneven_lengths(22 + p + d, 700, 1, 300)
     for name, lens in (("first, 16384 pairs", big), ("second, 700 pairs", small)):
         note(f"noalloc p={p} d={d} centered={centered} {name}")
