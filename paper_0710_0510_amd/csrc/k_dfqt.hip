@@ -33,36 +33,51 @@
 
 namespace fqt {
 
-// DQT of the chunks of one operand of len coefficients into X[0 .. nch):
-// sum_j c_j 2^(b j) < 2^52, exact in binary64; centred chunks take c - p for
-// c > (p-1)/2 (a signed sum, as exact).  The lanes of one wave split the
-// chunks.
+// DQT of one chunk from its coefficient bytes (those at or past len read as
+// zero): sum_j c_j 2^(b j) < 2^52, exact in binary64; centred chunks take
+// c - p for c > (p-1)/2 (a signed sum, as exact).
+template <int KE, bool CEN>
+__device__ __forceinline__ double dfqt_chunk(const uint32_t (&c)[KE], int first, int len,
+                                             uint32_t b, int32_t p, int32_t h) {
+  // sums of (possibly negative) c_j 2^(b j) in two's complement mod 2^64;
+  // the true value is below 2^52 in magnitude
+  uint64_t v = 0;
+#pragma unroll
+  for (int j = 0; j < KE; ++j) {
+    int32_t cx = first + j < len ? (int32_t)c[j] : 0;
+    if constexpr (CEN) cx -= cx > h ? p : 0;
+    v += (uint64_t)(int64_t)cx << (b * j);
+  }
+  return (double)(int64_t)v;
+}
+
+// DQT of the chunks of one operand of len coefficients into X[0 .. nch).  The
+// lanes of one wave split the chunks, two per lane and step; every byte is
+// read at an index clamped into the operand, so the loads carry no branch
+// and all of a step's loads are in flight together.
 template <int KE, bool CEN>
 __device__ __forceinline__ void dfqt_pack(const uint8_t* __restrict__ x, int len, int nch,
                                           uint32_t b, const PackedParams& pp,
                                           double* __restrict__ X, int lane) {
   const int32_t p = (int32_t)pp.fa.p, h = (p - 1) / 2;
-  for (int i = lane; i < nch; i += 64) {
-    // sums of (possibly negative) c_j 2^(b j) in two's complement mod 2^64;
-    // the true value is below 2^52 in magnitude
-    uint64_t v = 0;
+  for (int i = lane; i < nch; i += 128) {
+    const int i2 = i + 64;
+    uint32_t c0[KE], c1[KE];
 #pragma unroll
     for (int j = 0; j < KE; ++j) {
-      const int idx = i * KE + j;
-      if (idx < len) {
-        int32_t cx = x[idx];
-        if constexpr (CEN) cx -= cx > h ? p : 0;
-        v += (uint64_t)(int64_t)cx << (b * j);
-      }
+      c0[j] = x[min(i * KE + j, len - 1)];
+      c1[j] = x[min(i2 * KE + j, len - 1)];
     }
-    X[i] = (double)(int64_t)v;
+    X[i] = dfqt_chunk<KE, CEN>(c0, i * KE, len, b, p, h);
+    if (i2 < nch) X[i2] = dfqt_chunk<KE, CEN>(c1, i2 * KE, len, b, p, h);
   }
 }
 
 // The product of one pair by one wave from its packed chunks P (nca) and Q
 // (ncb) in LDS: S_t = sum_i P_i Q_{t-i} for t = 0 .. nca + ncb - 2, blocks of
 // nq products, digits mod p, overlap-add into the nc = la + lb - 1 output
-// coefficients.
+// coefficients.  Q[-1] and Q[ncb] hold zero: a window read clamps its index
+// into [-1, ncb] instead of branching.
 template <int KE, int MODE, bool CEN>
 __device__ __forceinline__ void dfqt_convolve(const double* __restrict__ P, int nca,
                                               const double* __restrict__ Q, int ncb, int nc,
@@ -87,16 +102,15 @@ __device__ __forceinline__ void dfqt_convolve(const double* __restrict__ P, int 
       for (int r = 0; r < 4; ++r) st[r].clear();
     }
     const int ilo = max(0, t0 - (ncb - 1)), ihi = min(nca - 1, t0 + 255);
+    auto qat = [&](int j) { return Q[min(max(j, -1), ncb)]; };
     double qw[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int j = tb + r - ilo;
-      qw[r] = (j >= 0 && j < ncb) ? Q[j] : 0.0;
-    }
+    for (int r = 0; r < 4; ++r) qw[r] = qat(tb + r - ilo);
     uint32_t cnt = 0, nbound = 0, nblk = 1;  // blocks of this pass (the centred shift counts them)
     uint32_t nadd = 0;                       // blocks in the lane state since its last fold
-    for (int i = ilo; i <= ihi; ++i) {
-      const double pi = P[i];
+    // one chunk index i: P_i times the window, the block step when a block
+    // is full, the window slid one chunk down Q (qn = Q_{t-i-1})
+    auto step = [&](double pi, double qn) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[r] = __builtin_fma(pi, qw[r], acc[r]);
       if constexpr (MULTI) {
@@ -117,13 +131,23 @@ __device__ __forceinline__ void dfqt_convolve(const double* __restrict__ P, int 
           }
         }
       }
-      // slide the window one chunk down Q
       qw[3] = qw[2];
       qw[2] = qw[1];
       qw[1] = qw[0];
+      qw[0] = qn;
+    };
+    // four chunk indices per round, their P and Q reads issued together
+    int i = ilo;
+    for (; i + 3 <= ihi; i += 4) {
+      const double p0 = P[i], p1 = P[i + 1], p2 = P[i + 2], p3 = P[i + 3];
       const int j = tb - i - 1;
-      qw[0] = (j >= 0 && j < ncb) ? Q[j] : 0.0;
+      const double n0 = qat(j), n1 = qat(j - 1), n2 = qat(j - 2), n3 = qat(j - 3);
+      step(p0, n0);
+      step(p1, n1);
+      step(p2, n2);
+      step(p3, n3);
     }
+    for (; i <= ihi; ++i) step(P[i], qat(tb - i - 1));
 
     // Thm. 2's residues u_i, then Alg. 2's second part (the Q_d correction of
     // Section 5.1): digit i mod p is (u_i - q u_{i+1}) mod p, the top one u_2d
@@ -167,12 +191,12 @@ __device__ __forceinline__ void dfqt_convolve(const double* __restrict__ P, int 
 // One wave per product, four per workgroup, every pair of len coefficients.
 template <int KE, int MODE, bool CEN>
 __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
-  extern __shared__ double dsh[];  // 4 waves x (P, Q) x cap chunks
+  extern __shared__ double dsh[];  // 4 waves x (P, zero, Q, zero): 2 cap + 2 chunks
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t prod = (int64_t)blockIdx.x * 4 + w;
   const bool live = prod < g.count;  // idle waves still reach every barrier
-  double* P = dsh + (size_t)w * 2 * g.cap;
-  double* Q = P + g.cap;
+  double* P = dsh + (size_t)w * (2 * g.cap + 2);
+  double* Q = P + g.cap + 1;
   const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
   const int len = g.len, nch = g.nch;
   const uint8_t* pa = g.a + (live ? prod : 0) * len;
@@ -181,6 +205,7 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
   if (live) {
     dfqt_pack<KE, CEN>(pa, len, nch, b, g.pp, P, lane);
     dfqt_pack<KE, CEN>(pb, len, nch, b, g.pp, Q, lane);
+    if (lane == 0) Q[-1] = Q[nch] = 0.0;
   }
   __syncthreads();
   if (!live) return;  // no barrier below
@@ -196,12 +221,12 @@ __global__ __launch_bounds__(256) void dfqt_kernel(DfqtArgs g) {
 // while the current one runs.
 template <int KE, int MODE, bool CEN>
 __global__ __launch_bounds__(256) void dfqt_batched_kernel(DfqtBatchArgs g) {
-  extern __shared__ double dsh[];  // 4 waves x (P, Q) x cap chunks
+  extern __shared__ double dsh[];  // 4 waves x (P, zero, Q, zero): 2 cap + 2 chunks
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   const int W = (int)gridDim.x * 4;
-  double* P = dsh + (size_t)(w & 3) * 2 * g.cap;
-  double* Q = P + g.cap;
+  double* P = dsh + (size_t)(w & 3) * (2 * g.cap + 2);
+  double* Q = P + g.cap + 1;
   const uint32_t b = MODE ? multi_block_b<KE>() : g.lg2q;
   auto pick = [&](int r) -> int64_t {
     const int64_t it = (int64_t)r * W + ((r & 1) ? W - 1 - w : w);
@@ -224,6 +249,7 @@ __global__ __launch_bounds__(256) void dfqt_batched_kernel(DfqtBatchArgs g) {
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       dfqt_pack<KE, CEN>(d.a, la, nca, b, g.pp, P, lane);
       dfqt_pack<KE, CEN>(d.b, lb, ncb, b, g.pp, Q, lane);
+      if (lane == 0) Q[-1] = Q[ncb] = 0.0;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -288,8 +314,11 @@ __global__ __launch_bounds__(256) void polymul_delayed_kernel(DelayedArgs g) {
   }
 }
 
-// LDS of one workgroup: four waves, two operands of cap chunks each
-static size_t dfqt_lds_bytes(int32_t cap) { return (size_t)4 * 2 * (size_t)cap * sizeof(double); }
+// LDS of one workgroup: four waves, two operands of cap chunks each and the
+// two zero chunks around the second
+static size_t dfqt_lds_bytes(int32_t cap) {
+  return (size_t)4 * (2 * (size_t)cap + 2) * sizeof(double);
+}
 
 template <int KE, bool CEN>
 static hipError_t dfqt_k(int mode, const DfqtArgs& g, hipStream_t s) {
