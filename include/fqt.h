@@ -134,10 +134,16 @@ typedef struct {
                       products (the largest multiple of 4 up to n_q and
                       16), q = 2^7 (log2q 0 or 7), digit-sum block steps
                       (boundary 0 or 2), centred packing for p = 3, 5, 7;
-                      other settings, operands not 4-byte aligned, or an
+                      other settings, A, B or C not 4-byte aligned, an
                       operand extent ((rows - 1) ld + cols) k of 2^30 bytes
-                      or more give FQT_ERR_UNSUPPORTED.  A single product
-                      runs as a batch of one.
+                      or more, or (M + 32) ldc k of 2^30 bytes or more give
+                      FQT_ERR_UNSUPPORTED.  A single product runs as a batch
+                      of one.
+                      INT8 path, id 11 (k = 4 only): one workgroup per strip
+                      of 16 output elements sweeping all rows, B' of each
+                      K-tile built once in LDS; A and B 4-byte aligned,
+                      operand extents and 256 rows of A or B below 2^30
+                      bytes, else FQT_ERR_UNSUPPORTED.
                       INT8 path: ids 1..3 and 7..10 expand B into B' (k x k
                       multiplication matrices) in a device workspace, then
                       run the INT8 GEMM (C' tiles 64 x 64, 128 x 128,

@@ -1958,11 +1958,13 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
     const uint64_t lim = 1ull << 30;  // buffer offsets stay below 2^31 with a far offset
     const uint64_t ea = e.M && e.K ? ((uint64_t)(e.M - 1) * e.lda + e.K) * k : 0;
     const uint64_t eb = e.K && e.N ? ((uint64_t)(e.K - 1) * e.ldb + e.N) * k : 0;
-    if (ea >= lim || eb >= lim)
+    // C: rows up to 31 past M are addressed (and their stores dropped)
+    const uint64_t ec = ((uint64_t)e.M + 32) * (uint64_t)e.ldc * k;
+    if (ea >= lim || eb >= lim || ec >= lim)
       return fail(FQT_ERR_UNSUPPORTED, "tile %d addresses operands below 2^30 bytes only "
                   "(descriptor %lld)", kWaveTile, (long long)d);
-    if ((((uintptr_t)e.A) | ((uintptr_t)e.B)) & 3)
-      return fail(FQT_ERR_UNSUPPORTED, "tile %d reads operands as words: A and B must be "
+    if ((((uintptr_t)e.A) | ((uintptr_t)e.B) | ((uintptr_t)e.C)) & 3)
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d moves elements as words: A, B and C must be "
                   "4-byte aligned (descriptor %lld)", kWaveTile, (long long)d);
   }
   DevTables dt;

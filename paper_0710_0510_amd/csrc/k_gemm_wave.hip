@@ -291,19 +291,29 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
           else kE += (uint64_t)cc << (7 * d);
         }
       }
+      // C through a buffer resource bounded by its last element: rows at or
+      // past M lie past the bound, and columns at or past N take an offset
+      // past it, so every store is issued and none needs a branch
       const int64_t m0 = (int64_t)ctm * 32, n0 = (int64_t)ctn * 32;
+      const uint32_t extC = (uint32_t)(((cg.M - 1) * cg.ldc + cg.N) * KE);
+      const auto rsc =
+          __builtin_amdgcn_make_buffer_rsrc(cg.C, (short)0, (int)extC, kBufferWord3);
+      const int32_t rstep = (int32_t)(4 * cg.ldc * KE);  // four rows
+      int32_t cbase[TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int64_t col = n0 + 2 * c + j;
+        cbase[j] = col < cg.N ? (int32_t)(((m0 + grp) * cg.ldc + col) * KE) : kFarOffset;
+      }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t row = m0 + 16 * i + grp + 4 * v;
+        for (int v = 0; v < 4; ++v)
 #pragma unroll
           for (int j = 0; j < TN; ++j) {
             const uint32_t e = digit_sums_elem(st[i][j][v], kE, kO, pp, Ls, Hs);
-            const int64_t col = n0 + 2 * c + j;
-            if (row < cg.M && col < cg.N) store_elem<KE>(cg.C + (row * cg.ldc + col) * KE, e);
+            __builtin_amdgcn_raw_buffer_store_b32(e, rsc, cbase[j] + (4 * i + v) * rstep, 0, 0);
           }
-        }
       clear_state();
       nblk = nadd = nbound = 0;
       cblk = 0;

@@ -483,3 +483,17 @@ def test_dfqt_batched_noalloc_validation_errors():
     assert status(3, 4, many) == "FQT_ERR_UNSUPPORTED"
     assert "16384" in fqt.last_error()
     assert status(3, 4, [(0, 5, 0, 0, 0)]) == "FQT_OK"
+
+
+def test_wave_tile_refuses_unaligned_c_and_far_c_rows():
+    # tile 15 stores elements as words through a buffer bounded by C: C must
+    # be 4-byte aligned and (M + 32) ldc k below 2^30 bytes
+    f = fqt.Field(3, 4, (2, 0, 0, 2))
+    opts = {"tile": 15}
+    assert _gemm_status(f, "packed", 8, 8, 8, 8, 8, 8, C=BOGUS + (1 << 31) + 1,
+                        opts=opts) == "FQT_ERR_UNSUPPORTED"
+    assert "aligned" in fqt.last_error()
+    big = 1 << 23                                  # (8 + 32) * 2^23 * 4 >= 2^30
+    assert _gemm_status(f, "packed", 8, 8, 8, 8, 8, big, C=BOGUS + (1 << 33),
+                        opts=opts) == "FQT_ERR_UNSUPPORTED"
+    assert "2^30" in fqt.last_error()
