@@ -456,7 +456,8 @@ def bench_batched(w, args, torch, fqt, gf):
         # INT8 coefficient-wise path, autotuned, byte-identical to the packed output
         dI = torch.zeros_like(dC)
         dI_descs = descs_for(dI)
-        iopts = fqt.autotune(f, dI_descs, only="int8")[1]
+        iopts = (json.loads(args.int8_opts) if args.int8_opts
+                 else fqt.autotune(f, dI_descs, only="int8")[1])
         tuned["int8"] = iopts
         fqt.gemm_batched(f, dI_descs, path="int8", opts=iopts)
         torch.cuda.synchronize()
@@ -815,6 +816,8 @@ def main():
                          "int8, plain)")
     ap.add_argument("--opts", default=None,
                     help="batched: JSON options of the packed path instead of autotuning")
+    ap.add_argument("--int8-opts", default=None,
+                    help="batched: JSON options of the INT8 path instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for HBM counter scaling)")
