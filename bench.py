@@ -502,7 +502,8 @@ def bench_batched(w, args, torch, fqt, gf):
         "config": {"workload": w.name, "field": f"GF({w.p}^{w.k})", "P": poly_str(w.P_low),
                    "count": len(As), "MNK_range": [w.lo, w.hi], "sum_MNK": work, "seed": w.seed,
                    "path": "packed (persistent, hipGraph replay)", "q_max": q, "n_q_max": nqmax,
-                   "tile": args.tile or "autotuned", "tuned": tuned},
+                   "tile": args.tile or ("given" if args.opts else "autotuned"),
+                   "tuned": tuned},
         "roofline": rl,
         "paths": paths,
         "parity": {"sampled_entries_vs_oracle": int(len(picks) * 4), "sampled_mismatches": bad,
