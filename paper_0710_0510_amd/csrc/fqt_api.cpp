@@ -160,8 +160,7 @@ struct BatchPlan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int device = -1;
-  int32_t* d_wbeg = nullptr;  // tile kWaveTile: first item of every run of every wave
-  WaveItem* d_witems = nullptr;  // tile kWaveTile: the tile records
+  int32_t* d_wbeg = nullptr;  // tile kWaveTile: first item of every wave
   // INT8 plans only
   I8Batch* d_i8 = nullptr;
   ExpandItem* d_exp = nullptr;
@@ -187,7 +186,6 @@ BatchPlan::~BatchPlan() {
     hipFree(d_items);
     hipFree(d_counter);
     hipFree(d_wbeg);
-    hipFree(d_witems);
     hipFree(d_i8);
     hipFree(d_exp);
   });
@@ -2042,26 +2040,13 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
           }
       }
     }
-    // the record of tile (a, b) of product i: operands moved to the tile
-    auto record = [&](const TileItem& t) {
-      const fqt_gemm_desc& d = descs[t.gemm];
-      const int64_t m0 = (int64_t)t.tm * 32, n0 = (int64_t)t.tn * 32;
-      WaveItem r{};
-      r.a = d.A + m0 * d.lda * k;
-      r.b = d.B + n0 * k;
-      r.c = d.C + (m0 * d.ldc + n0) * k;
-      r.ext_a = d.K ? (uint32_t)(((d.M - 1 - m0) * d.lda + d.K) * k) : 0u;
-      r.ext_b = d.K ? (uint32_t)(((d.K - 1) * d.ldb + d.N - n0) * k) : 0u;
-      r.ext_c = (uint32_t)(((d.M - 1 - m0) * d.ldc + d.N - n0) * k);
-      r.lda = (int32_t)(d.lda * k);
-      r.ldb = (int32_t)(d.ldb * k);
-      r.ldc = (int32_t)(d.ldc * k);
-      r.K = (int32_t)d.K;
-      r.nrem = (int32_t)(d.N - n0);
-      return r;
-    };
+    std::vector<GemmArgs> args(count);
+    for (int64_t i = 0; i < count; ++i) {
+      const fqt_gemm_desc& d = descs[i];
+      args[i] = GemmArgs{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
+    }
     // every wave's items in four runs by quarter class, each run in dealing order
-    std::vector<WaveItem> items;
+    std::vector<TileItem> items;
     std::vector<int32_t> wbeg(4 * (size_t)nwaves + 1);
     for (int w = 0; w < nwaves; ++w) {
       std::stable_sort(wl[w].begin(), wl[w].end(),
@@ -2069,7 +2054,7 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
       size_t at = 0;
       for (int cls = 0; cls < 4; ++cls) {
         wbeg[4 * (size_t)w + cls] = (int32_t)items.size();
-        while (at < wl[w].size() && wl[w][at].pad == cls) items.push_back(record(wl[w][at++]));
+        while (at < wl[w].size() && wl[w][at].pad == cls) items.push_back(wl[w][at++]);
       }
     }
     wbeg[4 * (size_t)nwaves] = (int32_t)items.size();
@@ -2077,10 +2062,12 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
     pl->n_items = (int32_t)items.size();
     pl->device = dev;
     pl->grid = grid;
-    FQT_HIP(hipMalloc(&pl->d_witems, sizeof(WaveItem) * std::max<size_t>(items.size(), 1)));
+    FQT_HIP(hipMalloc(&pl->d_descs, sizeof(GemmArgs) * std::max<int64_t>(count, 1)));
+    FQT_HIP(hipMalloc(&pl->d_items, sizeof(TileItem) * std::max<size_t>(items.size(), 1)));
     FQT_HIP(hipMalloc(&pl->d_wbeg, sizeof(int32_t) * wbeg.size()));
+    FQT_HIP(hipMemcpy(pl->d_descs, args.data(), sizeof(GemmArgs) * count, hipMemcpyHostToDevice));
     if (!items.empty())
-      FQT_HIP(hipMemcpy(pl->d_witems, items.data(), sizeof(WaveItem) * items.size(),
+      FQT_HIP(hipMemcpy(pl->d_items, items.data(), sizeof(TileItem) * items.size(),
                         hipMemcpyHostToDevice));
     FQT_HIP(hipMemcpy(pl->d_wbeg, wbeg.data(), sizeof(int32_t) * wbeg.size(),
                       hipMemcpyHostToDevice));
@@ -2125,7 +2112,7 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
     FQT_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     if (pl->n_items > 0)
-      le = launch_gemm_wave_batched(nqg, pl->d_witems, pl->d_wbeg, pl->grid, pp,
+      le = launch_gemm_wave_batched(nqg, pl->d_descs, pl->d_items, pl->d_wbeg, pl->grid, pp,
                                     cs);
     hipGraph_t graph = nullptr;
     hipError_t ce = hipStreamEndCapture(cs, &graph);

@@ -138,22 +138,6 @@ struct TileItem {
   int32_t pad;     // wave tile: its class of valid 16 x 16 quarters (0 = all four)
 };
 
-// One 32 x 32 output tile of the wave-persistent packed tile, with all its
-// wave needs in one 64-byte record (one scalar load): operand pointers moved
-// to the tile's first row of A, first column of B and first element of C,
-// the bytes from there to each operand's last byte, strides in bytes.
-struct WaveItem {
-  const uint8_t* a;
-  const uint8_t* b;
-  uint8_t* c;
-  uint32_t ext_a, ext_b, ext_c;  // 0 for A and B when K = 0
-  int32_t lda, ldb, ldc;         // bytes per row
-  int32_t K;
-  int32_t nrem;                  // N - n0: the tile's columns at or past it are not stored
-  int32_t pad[2];
-};
-static_assert(sizeof(WaveItem) == 64, "one 64-byte record per tile");
-
 // Tile configurations of the packed path, ids 1..kPackedTiles.
 // LDS-staged kernels (k_gemm_f64.hip), WG of 256 threads = 2x2 waves:
 // X(id, TM, TN, BK): wave tile 16TM x 16TN, workgroup tile 32TM x 32TN,
@@ -255,8 +239,9 @@ hipError_t launch_mat_addsub(int k, uint32_t p, const uint8_t* X, int64_t ldx, c
 // Wave-persistent batched kernel (tile kWaveTile, k = 4, q = 2^7): blocks of
 // 4 nqg products (nqg 1..4), items = 32 x 32 wave tiles; wave w of the grid
 // (workgroup w / 4) computes items[wave_begin[w] .. wave_begin[w + 1]).
-hipError_t launch_gemm_wave_batched(int nqg, const WaveItem* items, const int32_t* wave_begin,
-                                    int grid, const PackedParams& pp, hipStream_t s);
+hipError_t launch_gemm_wave_batched(int nqg, const GemmArgs* descs, const TileItem* items,
+                                    const int32_t* wave_begin, int grid, const PackedParams& pp,
+                                    hipStream_t s);
 int wave_batched_occupancy(int nqg, uint32_t tbl_log2);
 constexpr int kWaveMaxNqg = 4;
 

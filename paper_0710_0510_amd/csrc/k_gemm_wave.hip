@@ -113,26 +113,29 @@ struct WCtx {
 };
 
 template <int NQG>
-__device__ __forceinline__ void make_ctx(const WaveItem& g, WCtx<NQG>& x) {
+__device__ __forceinline__ void make_ctx(const GemmArgs& g, int tm, int tn, WCtx<NQG>& x) {
   constexpr int KE = kWaveKE, KB = 4 * NQG;
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, grp = lane >> 4;
-  x.rsa = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.a), (short)0, (int)g.ext_a,
+  const int64_t m0 = (int64_t)tm * 32, n0 = (int64_t)tn * 32;
+  // operand bounds: the last byte of A (M x K of lda) and of B (K x N of ldb)
+  const uint32_t extA = g.K ? (uint32_t)(((g.M - 1) * g.lda + g.K) * KE) : 0u;
+  const uint32_t extB = g.K ? (uint32_t)(((g.K - 1) * g.ldb + g.N) * KE) : 0u;
+  x.rsa = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.A), (short)0, (int)extA,
                                             kBufferWord3);
-  x.rsb = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.b), (short)0, (int)g.ext_b,
+  x.rsb = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t*>(g.B), (short)0, (int)extB,
                                             kBufferWord3);
   auto clamp_off = [](int64_t off) { return (int32_t)(off < kFarOffset ? off : kFarOffset); };
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-    x.voa[i] = clamp_off((int64_t)(16 * i + c) * g.lda + NQG * grp * KE);
+  for (int i = 0; i < 2; ++i) x.voa[i] = clamp_off(((m0 + 16 * i + c) * g.lda + NQG * grp) * KE);
 #pragma unroll
   for (int gk = 0; gk < NQG; ++gk)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
-      x.vob[gk][j] = clamp_off((int64_t)(NQG * grp + gk) * g.ldb + (16 * j + c) * KE);
+      x.vob[gk][j] = clamp_off(((int64_t)(NQG * grp + gk) * g.ldb + n0 + 16 * j + c) * KE);
   x.K = g.K;
   x.nb = g.K > 0 ? (g.K + KB - 1) / KB : 1;
-  x.bstep = (int64_t)KB * g.ldb;
+  x.bstep = (int64_t)KB * g.ldb * KE;
 }
 
 // Block s of an item into a stage: A segments of the TMV row halves, and B
@@ -196,7 +199,8 @@ __device__ __forceinline__ void block_mfma(const double (&av)[TMV][NQG],
 // item boundaries, so the next item's first blocks arrive while the current
 // item's epilogue runs.
 template <int NQG, int TMV, int TNV>
-__device__ __forceinline__ void wave_items(const WaveItem* __restrict__ items, int32_t beg,
+__device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
+                                           const TileItem* __restrict__ items, int32_t beg,
                                            int32_t end, const PackedParams& pp,
                                            const uint32_t* __restrict__ Ls,
                                            const uint32_t* __restrict__ Hs) {
@@ -206,24 +210,33 @@ __device__ __forceinline__ void wave_items(const WaveItem* __restrict__ items, i
   const int lane = threadIdx.x & 63;
   const int c = lane & 15, grp = lane >> 4;
 
-  // item records are read with uniform indices (scalar loads); the load
-  // cursor holds the record of its next item, read one item ahead
-  auto record = [&](int32_t it) { return items[__builtin_amdgcn_readfirstlane(it)]; };
+  auto item_args = [&](int32_t it, GemmArgs& g, int& tm, int& tn) {
+    const TileItem ti = items[it];
+    g = descs[__builtin_amdgcn_readfirstlane(ti.gemm)];
+    tm = __builtin_amdgcn_readfirstlane(ti.tm);
+    tn = __builtin_amdgcn_readfirstlane(ti.tn);
+  };
 
   // load cursor: item lit, its next block lblk
   int32_t lit = beg;
   int64_t lblk = 0;
   WCtx<NQG> lc;
-  make_ctx<NQG>(record(lit), lc);
-  WaveItem lnext = record(lit + 1 < end ? lit + 1 : lit);
+  {
+    GemmArgs g;
+    int tm, tn;
+    item_args(lit, g, tm, tn);
+    make_ctx<NQG>(g, tm, tn, lc);
+  }
   auto load_next = [&](St& x) {
     if (lit < end) {
       load_block<NQG, TMV, TNV>(lc, lblk, x);
       if (++lblk == lc.nb) {
         lblk = 0;
         if (++lit < end) {
-          make_ctx<NQG>(lnext, lc);
-          lnext = record(lit + 1 < end ? lit + 1 : lit);
+          GemmArgs g;
+          int tm, tn;
+          item_args(lit, g, tm, tn);
+          make_ctx<NQG>(g, tm, tn, lc);
         }
       }
     }
@@ -254,10 +267,12 @@ __device__ __forceinline__ void wave_items(const WaveItem* __restrict__ items, i
   clear_state();
   uint32_t nblk = 0, nadd = 0, nbound = 0;
 
-  // compute cursor: item cit (record cg), block cblk of cnb
+  // compute cursor: item cit (arguments cg, ctm, ctn), block cblk of cnb
   int32_t cit = beg;
   int64_t cblk = 0;
-  WaveItem cg = record(cit);
+  GemmArgs cg;
+  int ctm, ctn;
+  item_args(cit, cg, ctm, ctn);
   int64_t cnb = cg.K > 0 ? (cg.K + 4 * NQG - 1) / (4 * NQG) : 1;
 
   St stg[2];
@@ -304,14 +319,16 @@ __device__ __forceinline__ void wave_items(const WaveItem* __restrict__ items, i
       // C through a buffer resource bounded by its last element: rows at or
       // past M lie past the bound, and columns at or past N take an offset
       // past it, so every store is issued and none needs a branch
+      const int64_t m0 = (int64_t)ctm * 32, n0 = (int64_t)ctn * 32;
+      const uint32_t extC = (uint32_t)(((cg.M - 1) * cg.ldc + cg.N) * KE);
       const auto rsc =
-          __builtin_amdgcn_make_buffer_rsrc(cg.c, (short)0, (int)cg.ext_c, kBufferWord3);
-      const int32_t rstep = 4 * cg.ldc;  // four rows
+          __builtin_amdgcn_make_buffer_rsrc(cg.C, (short)0, (int)extC, kBufferWord3);
+      const int32_t rstep = (int32_t)(4 * cg.ldc * KE);  // four rows
       int32_t cbase[TNV];
 #pragma unroll
       for (int j = 0; j < TNV; ++j) {
-        const int col = 16 * j + c;
-        cbase[j] = col < cg.nrem ? grp * cg.ldc + col * KE : kFarOffset;
+        const int64_t col = n0 + 16 * j + c;
+        cbase[j] = col < cg.N ? (int32_t)(((m0 + grp) * cg.ldc + col) * KE) : kFarOffset;
       }
 #pragma unroll
       for (int i = 0; i < TMV; ++i)
@@ -328,7 +345,7 @@ __device__ __forceinline__ void wave_items(const WaveItem* __restrict__ items, i
       if (++cit >= end) {
         done = true;
       } else {
-        cg = record(cit);
+        item_args(cit, cg, ctm, ctn);
         cnb = cg.K > 0 ? (cg.K + 4 * NQG - 1) / (4 * NQG) : 1;
       }
     }
@@ -341,7 +358,8 @@ __device__ __forceinline__ void wave_items(const WaveItem* __restrict__ items, i
 // larger stages without spilling.
 template <int NQG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQG == 4 ? 2 : 3))) void gemm_wave_batched_kernel(
-    const WaveItem* __restrict__ items, const int32_t* __restrict__ wave_begin, PackedParams pp) {
+    const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items,
+    const int32_t* __restrict__ wave_begin, PackedParams pp) {
   extern __shared__ uint32_t tabs[];
   uint32_t* Ls = tabs;
   uint32_t* Hs = tabs + (1 << pp.tbl_log2);
@@ -350,17 +368,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQG == 4 ? 
   const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   const int32_t* wb = wave_begin + 4 * w;
   const int32_t b0 = wb[0], b1 = wb[1], b2 = wb[2], b3 = wb[3], b4 = wb[4];
-  if (b0 < b1) wave_items<NQG, 2, 2>(items, b0, b1, pp, Ls, Hs);
-  if (b1 < b2) wave_items<NQG, 2, 1>(items, b1, b2, pp, Ls, Hs);
-  if (b2 < b3) wave_items<NQG, 1, 2>(items, b2, b3, pp, Ls, Hs);
-  if (b3 < b4) wave_items<NQG, 1, 1>(items, b3, b4, pp, Ls, Hs);
+  if (b0 < b1) wave_items<NQG, 2, 2>(descs, items, b0, b1, pp, Ls, Hs);
+  if (b1 < b2) wave_items<NQG, 2, 1>(descs, items, b1, b2, pp, Ls, Hs);
+  if (b2 < b3) wave_items<NQG, 1, 2>(descs, items, b2, b3, pp, Ls, Hs);
+  if (b3 < b4) wave_items<NQG, 1, 1>(descs, items, b3, b4, pp, Ls, Hs);
 }
 
 template <int NQG>
-hipError_t launch_wave(const WaveItem* items, const int32_t* wave_begin, int grid,
-                       const PackedParams& pp, hipStream_t s) {
+hipError_t launch_wave(const GemmArgs* descs, const TileItem* items, const int32_t* wave_begin,
+                       int grid, const PackedParams& pp, hipStream_t s) {
   const size_t dyn = 2u * (1u << pp.tbl_log2) * sizeof(uint32_t);
-  hipLaunchKernelGGL(gemm_wave_batched_kernel<NQG>, dim3(grid), dim3(256), dyn, s, items,
+  hipLaunchKernelGGL(gemm_wave_batched_kernel<NQG>, dim3(grid), dim3(256), dyn, s, descs, items,
                      wave_begin, pp);
   return hipGetLastError();
 }
@@ -377,13 +395,14 @@ int occupancy_wave(uint32_t tbl_log2) {
 
 }  // namespace
 
-hipError_t launch_gemm_wave_batched(int nqg, const WaveItem* items, const int32_t* wave_begin,
-                                    int grid, const PackedParams& pp, hipStream_t s) {
+hipError_t launch_gemm_wave_batched(int nqg, const GemmArgs* descs, const TileItem* items,
+                                    const int32_t* wave_begin, int grid, const PackedParams& pp,
+                                    hipStream_t s) {
   switch (nqg) {
-    case 1: return launch_wave<1>(items, wave_begin, grid, pp, s);
-    case 2: return launch_wave<2>(items, wave_begin, grid, pp, s);
-    case 3: return launch_wave<3>(items, wave_begin, grid, pp, s);
-    case 4: return launch_wave<4>(items, wave_begin, grid, pp, s);
+    case 1: return launch_wave<1>(descs, items, wave_begin, grid, pp, s);
+    case 2: return launch_wave<2>(descs, items, wave_begin, grid, pp, s);
+    case 3: return launch_wave<3>(descs, items, wave_begin, grid, pp, s);
+    case 4: return launch_wave<4>(descs, items, wave_begin, grid, pp, s);
     default: return hipErrorInvalidValue;
   }
 }
