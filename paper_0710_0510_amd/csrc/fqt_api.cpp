@@ -1985,26 +1985,14 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
     int grid = prop.multiProcessorCount * wave_batched_occupancy(nqg, f->tbl_log2);
     grid = std::max(8, grid / 8 * 8);  // whole rounds over the 8 XCDs
     const int nwaves = grid * 4;
-    // valid 16-row and 16-column halves of tile (a, b) of product i
-    auto halves = [&](int64_t i, int a, int b, int* hm, int* hn) {
-      *hm = descs[i].M > (int64_t)a * 32 + 16 ? 2 : 1;
-      *hn = descs[i].N > (int64_t)b * 32 + 16 ? 2 : 1;
-    };
-    // cost of a tile in quarter-blocks: its K-blocks plus about one block's
-    // worth of epilogue, times its valid quarters
-    auto tile_cost = [&](int64_t i, int a, int b) {
-      int hm, hn;
-      halves(i, a, b, &hm, &hn);
-      return ((descs[i].K + kb - 1) / kb + 1) * hm * hn;
-    };
+    // cost of a 32 x 32 tile: its K-blocks plus about one block's worth of epilogue
+    auto tile_cost = [&](int64_t i) { return (descs[i].K + kb - 1) / kb + 1; };
     // products to XCDs: longest processing time first onto the lightest
     std::vector<int64_t> order(count);
     for (int64_t i = 0; i < count; ++i) order[i] = i;
-    std::vector<int64_t> pcost(count, 0);
-    for (int64_t i = 0; i < count; ++i)
-      for (int a = 0; a < (int)((descs[i].M + 31) / 32); ++a)
-        for (int b = 0; b < (int)((descs[i].N + 31) / 32); ++b) pcost[i] += tile_cost(i, a, b);
-    auto prod_cost = [&](int64_t i) { return pcost[i]; };
+    auto prod_cost = [&](int64_t i) {
+      return ((descs[i].M + 31) / 32) * ((descs[i].N + 31) / 32) * tile_cost(i);
+    };
     std::stable_sort(order.begin(), order.end(),
                      [&](int64_t a, int64_t b) { return prod_cost(a) > prod_cost(b); });
     std::vector<std::vector<int64_t>> xcd(8);
@@ -2032,11 +2020,8 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
           for (int b = 0; b < (int)((d.N + 31) / 32); ++b) {
             Slot sl = heap.top();
             heap.pop();
-            int hm, hn;
-            halves(i, a, b, &hm, &hn);
-            const int cls = 2 * (2 - hm) + (2 - hn);  // 0: 2 x 2 .. 3: 1 x 1 quarters
-            wl[sl.second].push_back(TileItem{(int32_t)i, a, b, cls});
-            heap.push({sl.first + tile_cost(i, a, b), sl.second});
+            wl[sl.second].push_back(TileItem{(int32_t)i, a, b, 0});
+            heap.push({sl.first + tile_cost(i), sl.second});
           }
       }
     }
@@ -2045,19 +2030,13 @@ static fqt_status batched_wave(fqt_field f, const PackedChoice& pc, int64_t coun
       const fqt_gemm_desc& d = descs[i];
       args[i] = GemmArgs{d.A, d.B, d.C, d.M, d.N, d.K, d.lda, d.ldb, d.ldc};
     }
-    // every wave's items in four runs by quarter class, each run in dealing order
     std::vector<TileItem> items;
-    std::vector<int32_t> wbeg(4 * (size_t)nwaves + 1);
+    std::vector<int32_t> wbeg(nwaves + 1);
     for (int w = 0; w < nwaves; ++w) {
-      std::stable_sort(wl[w].begin(), wl[w].end(),
-                       [](const TileItem& x, const TileItem& y) { return x.pad < y.pad; });
-      size_t at = 0;
-      for (int cls = 0; cls < 4; ++cls) {
-        wbeg[4 * (size_t)w + cls] = (int32_t)items.size();
-        while (at < wl[w].size() && wl[w][at].pad == cls) items.push_back(wl[w][at++]);
-      }
+      wbeg[w] = (int32_t)items.size();
+      items.insert(items.end(), wl[w].begin(), wl[w].end());
     }
-    wbeg[4 * (size_t)nwaves] = (int32_t)items.size();
+    wbeg[nwaves] = (int32_t)items.size();
     auto pl = std::make_unique<BatchPlan>();
     pl->n_items = (int32_t)items.size();
     pl->device = dev;

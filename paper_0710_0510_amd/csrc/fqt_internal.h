@@ -135,7 +135,7 @@ struct ExpandItem {
 struct TileItem {
   int32_t gemm;    // index into the descriptor array
   int32_t tm, tn;  // tile coordinates
-  int32_t pad;     // wave tile: its class of valid 16 x 16 quarters (0 = all four)
+  int32_t pad;
 };
 
 // Tile configurations of the packed path, ids 1..kPackedTiles.

@@ -17,10 +17,6 @@
 //    and columns of B at or past N only feed outputs that are never
 //    stored; k at or past K inside the last block must be zero on one side,
 //    so those B rows take an offset past the bound.
-//  * A tile is four 16 x 16 quarters (rows m0 + 16 i + .., columns
-//    n0 + 16 j + ..).  The host sorts every wave's items into runs of tiles
-//    with 2 x 2, 2 x 1, 1 x 2 and 1 x 1 valid quarters, one code path each,
-//    so quarters wholly past M or N cost nothing.
 // On gfx950 every VALU instruction takes issue cycles from the SIMD that
 // runs the FP64 MFMAs (measured: about 4 cycles per instruction beside 64
 // per v_mfma_f64_16x16x4f64, with one or two waves per SIMD), so the kernel
@@ -55,7 +51,7 @@ constexpr int32_t kFarOffset = 1 << 30;  // past every operand bound (extents < 
 template <int NQG>
 struct WStage {
   uint32_t a[2][NQG];  // A rows m0 + 16 i + c, k = 4 NQG s + NQG g .. + NQG - 1
-  uint32_t b[NQG][2];  // B rows 4 NQG s + NQG g + gk, columns n0 + 16 j + c
+  uint32_t b[NQG][2];  // B rows 4 NQG s + NQG g + gk, columns n0 + 2c, n0 + 2c + 1
 };
 
 // mu = x mod p for x < 2^24 (p >= 2): floor(x/p) from one high multiply,
@@ -106,7 +102,7 @@ __device__ __forceinline__ uint32_t digit_sums_elem(const BlockLanes<kWaveKE, 2>
 template <int NQG>
 struct WCtx {
   __amdgpu_buffer_rsrc_t rsa, rsb;
-  int32_t voa[2], vob[NQG][2];
+  int32_t voa[2], vob[NQG];
   int64_t nb;     // K-blocks, at least 1 (K = 0: one block of zeros)
   int64_t K;
   int64_t bstep;  // bytes of B per block of K
@@ -130,18 +126,15 @@ __device__ __forceinline__ void make_ctx(const GemmArgs& g, int tm, int tn, WCtx
   for (int i = 0; i < 2; ++i) x.voa[i] = clamp_off(((m0 + 16 * i + c) * g.lda + NQG * grp) * KE);
 #pragma unroll
   for (int gk = 0; gk < NQG; ++gk)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-      x.vob[gk][j] = clamp_off(((int64_t)(NQG * grp + gk) * g.ldb + n0 + 16 * j + c) * KE);
+    x.vob[gk] = clamp_off(((int64_t)(NQG * grp + gk) * g.ldb + n0 + 2 * c) * KE);
   x.K = g.K;
   x.nb = g.K > 0 ? (g.K + KB - 1) / KB : 1;
   x.bstep = (int64_t)KB * g.ldb * KE;
 }
 
-// Block s of an item into a stage: A segments of the TMV row halves, and B
-// words of the TNV column halves, rows with k at or past K read as zero (the
-// same loads for every block, no branch).
-template <int NQG, int TMV, int TNV>
+// Block s of an item into a stage: A segments, and B rows with k at or past
+// K read as zero (the same loads for every block, no branch).
+template <int NQG>
 __device__ __forceinline__ void load_block(const WCtx<NQG>& x, int64_t s, WStage<NQG>& st) {
   constexpr int KE = kWaveKE, KB = 4 * NQG;
   const int grp = (threadIdx.x & 63) >> 4;
@@ -150,61 +143,22 @@ __device__ __forceinline__ void load_block(const WCtx<NQG>& x, int64_t s, WStage
   int32_t krem = (int32_t)x.K - (int32_t)s * KB;
   krem = krem < KB ? krem : KB;
 #pragma unroll
-  for (int i = 0; i < TMV; ++i) buf_load<NQG>(x.rsa, x.voa[i], sa, st.a[i]);
+  for (int i = 0; i < 2; ++i) buf_load<NQG>(x.rsa, x.voa[i], sa, st.a[i]);
 #pragma unroll
-  for (int gk = 0; gk < NQG; ++gk) {
-    const bool live = NQG * grp + gk < krem;
-#pragma unroll
-    for (int j = 0; j < TNV; ++j) {
-      uint32_t wd[1];
-      buf_load<1>(x.rsb, live ? x.vob[gk][j] : kFarOffset, sb, wd);
-      st.b[gk][j] = wd[0];
-    }
-  }
+  for (int gk = 0; gk < NQG; ++gk)
+    buf_load<2>(x.rsb, NQG * grp + gk < krem ? x.vob[gk] : kFarOffset, sb, st.b[gk]);
 }
 
-// The MFMAs and the block step of one K-block on the TMV x TNV quarters.
-template <int NQG, int TMV, int TNV>
-__device__ __forceinline__ void block_mfma(const double (&av)[TMV][NQG],
-                                           const double (&bv)[NQG][TNV], const v4d& bias,
-                                           BlockLanes<kWaveKE, 2> (&st)[TMV][TNV][4],
-                                           const FieldArgs& fa) {
-  v4d acc[TMV][TNV];
-  // a block starts from the bias, passed as the first MFMA's addend
-#pragma unroll
-  for (int i = 0; i < TMV; ++i)
-#pragma unroll
-    for (int j = 0; j < TNV; ++j)
-      acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][0], bv[0][j], bias, 0, 0, 0);
-#pragma unroll
-  for (int gk = 1; gk < NQG; ++gk)
-#pragma unroll
-    for (int i = 0; i < TMV; ++i)
-#pragma unroll
-      for (int j = 0; j < TNV; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][gk], bv[gk][j], acc[i][j], 0, 0, 0);
-  // block step: the block's digits into the digit sums
-#pragma unroll
-  for (int i = 0; i < TMV; ++i)
-#pragma unroll
-    for (int j = 0; j < TNV; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) st[i][j][v].add(acc[i][j][v], fa);
-}
-
-// A run of one wave's items whose tiles all have TMV valid 16-row halves and
-// TNV valid 16-column halves (the host sorts every wave's items into such
-// runs): quarters wholly past M or N get no load, DQT, MFMA, block step or
-// epilogue.  The operand loads run two K-blocks ahead of the MFMAs across
-// item boundaries, so the next item's first blocks arrive while the current
-// item's epilogue runs.
-template <int NQG, int TMV, int TNV>
+// One wave's list of items, in order.  The operand loads run two K-blocks
+// ahead of the MFMAs across item boundaries, so the next item's first blocks
+// arrive while the current item's epilogue runs.
+template <int NQG>
 __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
                                            const TileItem* __restrict__ items, int32_t beg,
                                            int32_t end, const PackedParams& pp,
                                            const uint32_t* __restrict__ Ls,
                                            const uint32_t* __restrict__ Hs) {
-  constexpr int KE = kWaveKE;
+  constexpr int KE = kWaveKE, TM = 2, TN = 2;
   static_assert(multi_block_b<KE>() == 7, "q = 2^7 for k = 4");
   using St = WStage<NQG>;
   const int lane = threadIdx.x & 63;
@@ -229,7 +183,7 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
   }
   auto load_next = [&](St& x) {
     if (lit < end) {
-      load_block<NQG, TMV, TNV>(lc, lblk, x);
+      load_block<NQG>(lc, lblk, x);
       if (++lblk == lc.nb) {
         lblk = 0;
         if (++lit < end) {
@@ -242,25 +196,25 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
     }
   };
 
-  auto convert = [&](const St& x, double (&av)[TMV][NQG], double (&bv)[NQG][TNV]) {
+  auto convert = [&](const St& x, double (&av)[TM][NQG], double (&bv)[NQG][TN]) {
 #pragma unroll
-    for (int i = 0; i < TMV; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int e = 0; e < NQG; ++e) av[i][e] = wave_dqt(x.a[i][e], pp);
 #pragma unroll
     for (int gk = 0; gk < NQG; ++gk)
 #pragma unroll
-      for (int j = 0; j < TNV; ++j) bv[gk][j] = wave_dqt(x.b[gk][j], pp);
+      for (int j = 0; j < TN; ++j) bv[gk][j] = wave_dqt(x.b[gk][j], pp);
   };
 
   const double bz = pp.centered ? pp.cbias : kTwo52;
   const v4d bias = {bz, bz, bz, bz};
-  BlockLanes<KE, 2> st[TMV][TNV][4];
+  BlockLanes<KE, 2> st[TM][TN][4];
   auto clear_state = [&]() {
 #pragma unroll
-    for (int i = 0; i < TMV; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TNV; ++j)
+      for (int j = 0; j < TN; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) st[i][j][v].clear();
   };
@@ -283,10 +237,31 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       if (done) break;
-      double av[TMV][NQG], bv[NQG][TNV];
+      double av[TM][NQG], bv[NQG][TN];
       convert(stg[u], av, bv);
       load_next(stg[u]);
-      block_mfma<NQG, TMV, TNV>(av, bv, bias, st, pp.fa);
+      v4d acc[TM][TN];
+      // a block starts from the bias, passed as the first MFMA's addend
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][0], bv[0][j], bias, 0, 0, 0);
+#pragma unroll
+      for (int gk = 1; gk < NQG; ++gk)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            acc[i][j] =
+                __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][gk], bv[gk][j], acc[i][j], 0, 0, 0);
+      // block step: the block's digits into the digit sums
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) st[i][j][v].add(acc[i][j][v], pp.fa);
       ++nblk;
       ++nadd;
       if (++cblk < cnb) {
@@ -294,9 +269,9 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
         if (pp.fold_blocks && ++nbound == pp.fold_blocks) {
           nbound = 0;
 #pragma unroll
-          for (int i = 0; i < TMV; ++i)
+          for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TNV; ++j)
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
               for (int v = 0; v < 4; ++v) st[i][j][v].fold(pp.fa, nadd);
           nadd = 0;
@@ -324,18 +299,18 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
       const auto rsc =
           __builtin_amdgcn_make_buffer_rsrc(cg.C, (short)0, (int)extC, kBufferWord3);
       const int32_t rstep = (int32_t)(4 * cg.ldc * KE);  // four rows
-      int32_t cbase[TNV];
+      int32_t cbase[TN];
 #pragma unroll
-      for (int j = 0; j < TNV; ++j) {
-        const int64_t col = n0 + 16 * j + c;
+      for (int j = 0; j < TN; ++j) {
+        const int64_t col = n0 + 2 * c + j;
         cbase[j] = col < cg.N ? (int32_t)(((m0 + grp) * cg.ldc + col) * KE) : kFarOffset;
       }
 #pragma unroll
-      for (int i = 0; i < TMV; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-          for (int j = 0; j < TNV; ++j) {
+          for (int j = 0; j < TN; ++j) {
             const uint32_t e = digit_sums_elem(st[i][j][v], kE, kO, pp, Ls, Hs);
             __builtin_amdgcn_raw_buffer_store_b32(e, rsc, cbase[j] + (4 * i + v) * rstep, 0, 0);
           }
@@ -352,8 +327,7 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
   }
 }
 
-// Items of wave w: four runs, items[wave_begin[4w] .. wave_begin[4w + 4]),
-// of tiles with 2 x 2, 2 x 1, 1 x 2 and 1 x 1 valid 16 x 16 quarters.
+// Items of wave w: items[wave_begin[w] .. wave_begin[w + 1]), in order.
 // Three waves per SIMD; with NQG = 4 (p = 2) two, whose registers hold the
 // larger stages without spilling.
 template <int NQG>
@@ -366,12 +340,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQG == 4 ? 
   load_tables(pp, Ls, Hs);
   __syncthreads();
   const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
-  const int32_t* wb = wave_begin + 4 * w;
-  const int32_t b0 = wb[0], b1 = wb[1], b2 = wb[2], b3 = wb[3], b4 = wb[4];
-  if (b0 < b1) wave_items<NQG, 2, 2>(descs, items, b0, b1, pp, Ls, Hs);
-  if (b1 < b2) wave_items<NQG, 2, 1>(descs, items, b1, b2, pp, Ls, Hs);
-  if (b2 < b3) wave_items<NQG, 1, 2>(descs, items, b2, b3, pp, Ls, Hs);
-  if (b3 < b4) wave_items<NQG, 1, 1>(descs, items, b3, b4, pp, Ls, Hs);
+  const int32_t beg = wave_begin[w], end = wave_begin[w + 1];
+  if (beg < end) wave_items<NQG>(descs, items, beg, end, pp, Ls, Hs);
 }
 
 template <int NQG>
