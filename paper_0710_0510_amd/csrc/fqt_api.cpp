@@ -1266,6 +1266,22 @@ extern "C" {
 fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint32_t n_q,
                                     uint32_t boundary, uint32_t centered, int64_t count,
                                     const fqt_poly_desc* descs, fqt_stream_t s) {
+  if (count < 0 || (count && !descs)) return fail(FQT_ERR_INVALID_ARG, "bad descriptor array");
+  // plan key: the descriptors and the call's own arguments, which decide
+  // every check and every resolved parameter, and the device.  A list seen
+  // before replays its plan without walking the descriptors again.
+  int dev = -1;
+  const bool have_dev = count > 0 && hipGetDevice(&dev) == hipSuccess;
+  const uint32_t tag[8] = {p, d, log2q, n_q, boundary, centered, (uint32_t)dev, 0u};
+  const fqt_detail::PlanKey key{descs, sizeof(fqt_poly_desc) * (size_t)count,
+                                fqt_detail::key_tail(tag)};
+  if (have_dev) {
+    std::lock_guard<std::mutex> lk(g_poly_mu);
+    if (PolyPlan* plan = g_poly_plans.find(key)) {
+      if (plan->live > 0) FQT_HIP(hipGraphLaunch(plan->exec, (hipStream_t)s));
+      return ok();
+    }
+  }
   DfqtChoice ch;
   int64_t live = 0;
   int32_t cap = 1;
@@ -1274,12 +1290,7 @@ fqt_status fqt_polymul_dfqt_batched(uint32_t p, uint32_t d, uint32_t log2q, uint
   if (st) return st;
   if (live == 0) return ok();  // nothing to write: an empty product has no coefficient
   const int64_t ke = d + 1;
-  int dev = 0;
   FQT_HIP(hipGetDevice(&dev));
-  // plan key: descriptors, resolved parameters, p, centring, device
-  const uint32_t tag[8] = {p, ch.ke, ch.bq, (uint32_t)ch.nq, (uint32_t)ch.mode, ch.fold,
-                           centered, (uint32_t)dev};
-  const fqt_detail::PlanKey key{descs, sizeof(fqt_poly_desc) * count, fqt_detail::key_tail(tag)};
   std::lock_guard<std::mutex> lk(g_poly_mu);
   PolyPlan* plan = g_poly_plans.find(key);
   if (!plan) {
