@@ -46,11 +46,17 @@ MEASURED_TRAFFIC = {
         "bytes": 184_764_621,  # FETCH 49257.1 KiB x 2.000 + WRITE 81920 KiB x 1.000
         "source": "profiles/polymul_gf5_k3_2-24.md"},
     ("dfqt-gf3-n500-d4", "dfqt", 4, 1): {
-        "bytes": 34_088_960,  # FETCH 8581.0 KiB x 2.000 + WRITE 16128 KiB x 1.000
+        "bytes": 34_188_339,  # FETCH 8629.5 KiB x 2.000 + WRITE 16128 KiB x 1.000
         "source": "profiles/dfqt_gf3_n500_d4.md"},
     ("dfqt-gf3-n500-d4", "dfqt", 4, 0): {
-        "bytes": 34_073_600,  # FETCH 8573.5 KiB x 2.000 + WRITE 16128 KiB x 1.000
+        "bytes": 34_159_616,  # FETCH 8615.5 KiB x 2.000 + WRITE 16128 KiB x 1.000
         "source": "profiles/dfqt_gf3_n500_d4.md"},
+    ("batched-gf3^4-4096", "packed", 15): {
+        "bytes": 1_247_242_854,  # FETCH 451374.2 KiB x 2.000 + WRITE 315262.2 KiB x 1.000
+        "source": "profiles/batched_gf3-4_4096.md"},
+    ("batched-gf3^4-4096", "int8", 11): {
+        "bytes": 964_707_389,  # FETCH 306283.2 KiB x 2.000 + WRITE 329530.7 KiB x 1.000
+        "source": "profiles/batched_gf3-4_4096.md"},
 }
 
 
@@ -216,7 +222,9 @@ def roofline_for(path, k, work, ms, tile=0):
         ach = ops / (ms * 1e-3)
         return {"bound": "mfma", "achieved": ach / 1e12, "peak": PEAK_INT8 / 1e12,
                 "unit": "TOP/s", "frac": ach / PEAK_INT8, "traffic": None,
-                "kernel": ("gemm_i8f_kernel (B' built in LDS)" if tile >= 4 else
+                "kernel": ("gemm_i8cs_batched_kernel, tile 11 (strips of 16 outputs over all "
+                           "rows, B' of each K-tile built once in LDS)" if tile == 11 else
+                           "gemm_i8f_kernel (B' built in LDS)" if tile >= 4 else
                            "gemm_i8_kernel (+ expand_b_kernel in the step)"),
                 "algorithmic": "2 k^2 int8 ops per field mul-add"}
     if path == "plain":
@@ -470,6 +478,10 @@ def bench_batched(w, args, torch, fqt, gf):
                          "tile": int(iopts.get("tile", 0)),
                          "roofline_frac": roofline_for("int8", k, work, i8_ms,
                                                        int(iopts.get("tile", 0)))["frac"]}
+        tr8 = MEASURED_TRAFFIC.get((w.name, "int8", int(iopts.get("tile", 0))))
+        if tr8:
+            paths["int8"]["traffic"] = tr8["bytes"]
+            paths["int8"]["traffic_source"] = tr8["source"]
         identical.append("int8")
     if "plain" in args.paths and not args.no_plain:
         # the plain comparator: one launch per product, as the metric asks
