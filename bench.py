@@ -744,19 +744,19 @@ def bench_dfqt_batched(w, args, torch, fqt, gf):
                      args.steps, args.warmup, torch)
     dms = time_steps(lambda: fqt.polymul_delayed(w.p, Ad, Bd, out=ref), args.steps, args.warmup,
                      torch)
+    # the autotuner's choice, timed as it was chosen (its block-boundary mode too)
     main_key = (tuned["d"], tuned["centered"])
-    if main_key not in variants:  # the autotuner's d is outside the timed set
-        fn = lambda: fqt.polymul_dfqt_batched(w.p, main_key[0], descs, centered=main_key[1])
-        c.fill_(0xEE)
-        fn()
-        torch.cuda.synchronize()
-        if not torch.equal(c, ref_flat):
-            raise SystemExit(f"parity failure: batched d-FQT {main_key} differs")
-        ms = time_steps(fn, args.steps, args.warmup, torch)
-        variants[main_key] = {"value": work / (ms * 1e-3), "ms_per_step": ms,
-                              "fp64_tflops": 2.0 * chunk_products(main_key[0]) / (ms * 1e-3)
-                              / 1e12, "centered": main_key[1]}
-    main_v = variants[main_key]
+    fn = lambda: fqt.polymul_dfqt_batched(w.p, main_key[0], descs, centered=main_key[1],
+                                          boundary=tuned["boundary"])
+    c.fill_(0xEE)
+    fn()
+    torch.cuda.synchronize()
+    if not torch.equal(c, ref_flat):
+        raise SystemExit(f"parity failure: batched d-FQT {tuned} differs")
+    ms = time_steps(fn, args.steps, args.warmup, torch)
+    main_v = {"value": work / (ms * 1e-3), "ms_per_step": ms,
+              "fp64_tflops": 2.0 * chunk_products(main_key[0]) / (ms * 1e-3) / 1e12,
+              "centered": main_key[1]}
     out = {
         "metric": METRIC, "value": main_v["value"], "unit": "GF(p) mul-adds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_v["ms_per_step"],
@@ -764,7 +764,7 @@ def bench_dfqt_batched(w, args, torch, fqt, gf):
         "data": "synthetic",
         "config": {"workload": w.name, "p": w.p, "count": w.count, "lengths": f"{w.lo}..{w.hi}",
                    "seed": w.seed, "d": main_key[0], "centered": main_key[1],
-                   "autotuned": True},
+                   "boundary": tuned["boundary"], "autotuned": True},
         "products_per_s": w.count / (main_v["ms_per_step"] * 1e-3),
         "roofline": {"bound": "alu", "achieved": main_v["fp64_tflops"], "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": main_v["fp64_tflops"] * 1e12 / PEAK_FP64,

@@ -329,14 +329,16 @@ fqt_status fqt_polymul_dfqt_batched_noalloc(uint32_t p, uint32_t d, uint32_t log
                                             int64_t count, const fqt_poly_desc* descs,
                                             fqt_stream_t s);
 
-/* Time the d-FQT of an uneven batch for every chunk length d + 1 = 1..8 and,
- * for odd p, both chunk representations (default q and n_q); every
- * candidate's output must be byte-identical to the first admissible one's
- * (else FQT_ERR_DEVICE).  Writes the fastest (d, centered).  cache_path
- * (NULL: none) is a JSON-lines file read first and appended to. */
+/* Time the d-FQT of an uneven batch for every chunk length d + 1 = 1..8,
+ * for odd p both chunk representations, and both block-boundary modes
+ * (digit sums where q <= 2^12, REDQ residues); q and n_q are the largest
+ * eq. (2) admits for each.  Every candidate's output must be byte-identical
+ * to the first admissible one's (else FQT_ERR_DEVICE).  Writes the fastest
+ * (d, centered, boundary), each pointer may be NULL.  cache_path (NULL:
+ * none) is a JSON-lines file read first and appended to. */
 fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* descs,
                                 const char* cache_path, uint32_t* d, uint32_t* centered,
-                                fqt_stream_t s);
+                                uint32_t* boundary, fqt_stream_t s);
 
 /* The comparator of Section 6: the classical product with delayed reduction
  * (eq. (3)): every coefficient accumulated in 32-bit integers and reduced

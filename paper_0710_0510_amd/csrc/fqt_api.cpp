@@ -2865,7 +2865,8 @@ fqt_status fqt_autotune(fqt_field f, fqt_path only, int64_t count, const fqt_gem
 // only if every output byte equals the first admissible candidate's.
 fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* descs,
                                 const char* cache_path, uint32_t* best_d,
-                                uint32_t* best_centered, fqt_stream_t s) {
+                                uint32_t* best_centered, uint32_t* best_boundary,
+                                fqt_stream_t s) {
   if (count < 1 || !descs) return fail(FQT_ERR_INVALID_ARG, "empty batch");
   int64_t lmax = 0, total = 0;
   for (int64_t i = 0; i < count; ++i) {
@@ -2883,22 +2884,25 @@ fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* 
     if (FILE* fp = std::fopen(cache_path, "r")) {
       char line[256];
       bool found = false;
-      unsigned d = 0, cen = 0;
+      unsigned d = 0, cen = 0, bnd = 0;
       while (std::fgets(line, sizeof line, fp)) {
         char k[96];
-        unsigned dd = 0, cc = 0;
-        if (std::sscanf(line, "{\"key\": \"%95[^\"]\", \"d\": %u, \"centered\": %u", k, &dd,
-                        &cc) == 3 &&
+        unsigned dd = 0, cc = 0, bb = 0;
+        if (std::sscanf(line,
+                        "{\"key\": \"%95[^\"]\", \"d\": %u, \"centered\": %u, \"boundary\": %u",
+                        k, &dd, &cc, &bb) == 4 &&
             std::strcmp(k, keybuf) == 0) {
           d = dd;
           cen = cc;
-          found = true;
+          bnd = bb;
+          found = true;  // the last matching line wins
         }
       }
       std::fclose(fp);
       if (found) {
         if (best_d) *best_d = d;
         if (best_centered) *best_centered = cen;
+        if (best_boundary) *best_boundary = bnd;
         return ok();
       }
     }
@@ -2941,11 +2945,17 @@ fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* 
   FQT_HIP(hipEventCreate(&e1));
   bool have_ref = false;
   double best_ms = 1e30;
-  uint32_t bd = 0, bc = 0;
+  uint32_t bd = 0, bc = 0, bb = 0;
   fqt_status status = FQT_OK;
+  // chunk length d + 1, centring, and the block-boundary mode (2: digit sums,
+  // for q <= 2^12; 1: REDQ residues); q and n_q are then the largest eq. (2)
+  // admits, which is never slower (fewer block steps)
   for (uint32_t cen = 0; cen <= (p % 2 ? 1u : 0u) && status == FQT_OK; ++cen)
-    for (uint32_t d = 0; d <= 7 && status == FQT_OK; ++d) {
-      auto run = [&]() { return fqt_polymul_dfqt_batched(p, d, 0, 0, 0, cen, count, descs, s); };
+    for (uint32_t d = 0; d <= 7 && status == FQT_OK; ++d)
+    for (uint32_t bnd = 2; bnd >= 1 && status == FQT_OK; --bnd) {
+      auto run = [&]() {
+        return fqt_polymul_dfqt_batched(p, d, 0, 0, bnd, cen, count, descs, s);
+      };
       status = run();  // builds the plan and its graph
       if (status == FQT_ERR_UNSUPPORTED || status == FQT_ERR_BOUNDS) {
         status = FQT_OK;
@@ -2955,8 +2965,8 @@ fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* 
       status = snap(have_ref ? cur : ref);
       if (status) break;
       if (have_ref && std::memcmp(cur.p, ref.p, (size_t)total) != 0) {
-        status = fail(FQT_ERR_DEVICE, "polynomial autotune candidate d = %u, centered = %u is not "
-                      "byte-identical to the first", d, cen);
+        status = fail(FQT_ERR_DEVICE, "polynomial autotune candidate d = %u, centered = %u, "
+                      "boundary = %u is not byte-identical to the first", d, cen, bnd);
         break;
       }
       have_ref = true;
@@ -2971,6 +2981,7 @@ fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* 
         best_ms = ms / reps;
         bd = d;
         bc = cen;
+        bb = bnd;
       }
     }
   hipEventDestroy(e0);
@@ -2979,12 +2990,15 @@ fqt_status fqt_autotune_polymul(uint32_t p, int64_t count, const fqt_poly_desc* 
   if (!have_ref) return fail(FQT_ERR_UNSUPPORTED, "every candidate was refused for this batch");
   if (cache_path)
     if (FILE* fp = std::fopen(cache_path, "a")) {
-      std::fprintf(fp, "{\"key\": \"%s\", \"d\": %u, \"centered\": %u, \"ms\": %.6f}\n", keybuf,
-                   bd, bc, best_ms);
+      std::fprintf(fp,
+                   "{\"key\": \"%s\", \"d\": %u, \"centered\": %u, \"boundary\": %u, "
+                   "\"ms\": %.6f}\n",
+                   keybuf, bd, bc, bb, best_ms);
       std::fclose(fp);
     }
   if (best_d) *best_d = bd;
   if (best_centered) *best_centered = bc;
+  if (best_boundary) *best_boundary = bb;
   return ok();
 }
 

@@ -94,7 +94,7 @@ def lib() -> ctypes.CDLL:
                                                      c_i64, ctypes.POINTER(PolyDesc), vp]),
         "fqt_autotune_polymul": (c_int, [c_u32, c_i64, ctypes.POINTER(PolyDesc),
                                          ctypes.c_char_p, ctypes.POINTER(c_u32),
-                                         ctypes.POINTER(c_u32), vp]),
+                                         ctypes.POINTER(c_u32), ctypes.POINTER(c_u32), vp]),
         "fqt_gemm_gfpk": (c_int, [vp, c_int, c_i64, c_i64, c_i64, vp, c_i64, vp, c_i64, vp,
                                   c_i64, vp]),
         "fqt_gemm_gfpk_ex": (c_int, [vp, c_int, ctypes.POINTER(GemmOpts), c_i64, c_i64, c_i64,
@@ -316,12 +316,13 @@ def polymul_dfqt_batched_noalloc(p: int, d: int, descs, log2q: int = 0, n_q: int
 
 
 def autotune_polymul(p: int, descs, cache_path: Optional[str] = None, stream=None):
-    """The fastest (d, centered) for an uneven batch; returns a dict."""
-    d, cen = ctypes.c_uint32(0), ctypes.c_uint32(0)
+    """The fastest (d, centered, boundary) for an uneven batch; returns a dict."""
+    d, cen, bnd = ctypes.c_uint32(0), ctypes.c_uint32(0), ctypes.c_uint32(0)
     _check(lib().fqt_autotune_polymul(p, len(descs), descs,
                                       cache_path.encode() if cache_path else None,
-                                      ctypes.byref(d), ctypes.byref(cen), _stream(stream)))
-    return {"d": d.value, "centered": cen.value}
+                                      ctypes.byref(d), ctypes.byref(cen), ctypes.byref(bnd),
+                                      _stream(stream)))
+    return {"d": d.value, "centered": cen.value, "boundary": bnd.value}
 
 
 def polymul_delayed(p: int, a, b, out=None, stream=None):

@@ -207,9 +207,10 @@ def test_dfqt_batched_autotune():
     bt = Batch(3, uneven_lengths(9, 400), seed=9)
     note("dfqt batched autotune")
     best = fqt.autotune_polymul(3, bt.descs)
-    assert 0 <= best["d"] <= 7 and best["centered"] in (0, 1)
+    assert 0 <= best["d"] <= 7 and best["centered"] in (0, 1) and best["boundary"] in (1, 2)
     bt.clear()
-    fqt.polymul_dfqt_batched(3, best["d"], bt.descs, centered=best["centered"])
+    fqt.polymul_dfqt_batched(3, best["d"], bt.descs, centered=best["centered"],
+                             boundary=best["boundary"])
     bt.check(best)
 
 
