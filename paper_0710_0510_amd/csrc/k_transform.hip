@@ -10,7 +10,9 @@
 //   * Alg. 1 for a batch of independent polynomial products: pack, one FP64
 //     product, REDQ + Q_d.
 // These kernels are bound by HBM bandwidth; every workgroup stages its input
-// and output bytes through LDS so that global accesses are whole dwords.
+// and output bytes through LDS so that global accesses are whole dwords,
+// except Alg. 1 with all intermediates below 2^32, whose threads take four
+// pairs each straight from whole words of aligned buffers.
 
 #include "fqt_internal.h"
 
@@ -148,6 +150,7 @@ struct RedqArgs {
   double inv_p;
   uint32_t p, b, pow2, c;  // c = (-q) mod p
   uint32_t mod_magic;
+  uint32_t pm24;  // 2^24 - p: x - p y modulo 2^24 as x + pm24 y
 };
 
 // Residues u_0..u_{nd-1} of Alg. 2 for r < 2^53 (binary64 input, WIDE = 0)
@@ -228,6 +231,7 @@ static RedqArgs make_redq(uint64_t q, int pow2, uint32_t b, const FieldArgs& fa)
   ra.pow2 = (uint32_t)pow2;
   ra.c = (uint32_t)((fa.p - (q % fa.p)) % fa.p);
   ra.mod_magic = fa.mod_magic;
+  ra.pm24 = (1u << 24) - fa.p;
   return ra;
 }
 
@@ -293,11 +297,109 @@ __global__ __launch_bounds__(kTB) void polymul_k_kernel(const uint8_t* __restric
   stage_out16(c, sc, base * ND, (size_t)kPM * ND, n * ND);
 }
 
+// Alg. 1 when every intermediate fits in 32 bits (q = 2^b, (2K-1) b <= 32,
+// so r < q^(2K-1) <= 2^32), with 4-byte aligned operands and output.  No
+// LDS: thread t multiplies the four pairs 4t .. 4t+3, whose operand bytes
+// are K whole words of each input and whose digits are 2K-1 whole words of
+// the output, so a wave reads and writes contiguous runs.  The product is
+// the FP64 one of Alg. 1; rop = floor(r/p) comes from a binary64 estimate
+// and one correction, the u_i of Thm. 2 from 32-bit shifts.  The last
+// thread of a batch that is not a multiple of four goes byte by byte.
+template <int K>
+__global__ __launch_bounds__(kTB) void polymul_w32_kernel(const uint8_t* __restrict__ a,
+                                                          const uint8_t* __restrict__ bb,
+                                                          size_t n, RedqArgs ra,
+                                                          uint8_t* __restrict__ c) {
+  constexpr int ND = 2 * K - 1;
+  const size_t t = (size_t)blockIdx.x * kTB + threadIdx.x;
+  const size_t i0 = 4 * t;  // first pair of this thread
+  if (i0 >= n) return;
+  const int np = n - i0 < 4 ? (int)(n - i0) : 4;
+  uint32_t wa[K], wb[K];
+  if (np == 4) {
+    const uint32_t* sa = reinterpret_cast<const uint32_t*>(a + i0 * K);
+    const uint32_t* sb = reinterpret_cast<const uint32_t*>(bb + i0 * K);
+#pragma unroll
+    for (int w = 0; w < K; ++w) {
+      wa[w] = sa[w];
+      wb[w] = sb[w];
+    }
+  } else {
+#pragma unroll
+    for (int w = 0; w < K; ++w) wa[w] = wb[w] = 0;
+    for (int j = 0; j < np * K; ++j) {
+      wa[j >> 2] |= (uint32_t)a[i0 * K + j] << (8 * (j & 3));
+      wb[j >> 2] |= (uint32_t)bb[i0 * K + j] << (8 * (j & 3));
+    }
+  }
+  const uint32_t p = ra.p, b = ra.b;
+  uint32_t o[ND];
+#pragma unroll
+  for (int w = 0; w < ND; ++w) o[w] = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // DQT of both operands (Alg. 1 step 1)
+    uint32_t va = 0, vb = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int pos = e * K + j;
+      va |= ((wa[pos >> 2] >> (8 * (pos & 3))) & 0xffu) << (b * j);
+      vb |= ((wb[pos >> 2] >> (8 * (pos & 3))) & 0xffu) << (b * j);
+    }
+    // step 2: the exact FP64 product, below 2^32
+    const uint32_t r = (uint32_t)((double)va * (double)vb);
+    // Alg. 2: rop = floor(r / p), then u_i = floor(r/q^i) - p floor(rop/q^i).
+    // Every such difference is small (the remainder in [-p, 2p), each u_i
+    // and each reduction mod p in [0, p)), so it is taken modulo 2^24 with
+    // one 24-bit multiply-add by pm = 2^24 - p.
+    const uint32_t pm = ra.pm24;
+    uint32_t rop = (uint32_t)((double)r * ra.inv_p);
+    const int32_t rem = __builtin_amdgcn_sbfe((int32_t)(r + __umul24(rop, pm)), 0, 24);
+    rop = rem < 0 ? rop - 1 : (rem >= (int32_t)p ? rop + 1 : rop);
+    uint32_t u[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) u[i] = ((r >> (b * i)) + __umul24(rop >> (b * i), pm)) & 0xffffffu;
+    // Q_d: mu_i = u_i + c u_{i+1} mod p, the top digit as it is
+#pragma unroll
+    for (int d = 0; d < ND; ++d) {
+      uint32_t mu = u[d];
+      if (d < ND - 1) {
+        const uint32_t x = u[d] + __umul24(ra.c, u[d + 1]);
+        mu = (x + __umul24(__umulhi(x, ra.mod_magic), pm)) & 0xffffffu;
+      }
+      const int pos = e * ND + d;
+      o[pos >> 2] |= mu << (8 * (pos & 3));
+    }
+  }
+  if (np == 4) {
+    uint32_t* dst = reinterpret_cast<uint32_t*>(c + i0 * ND);
+#pragma unroll
+    for (int w = 0; w < ND; ++w) dst[w] = o[w];
+  } else {
+    for (int j = 0; j < np * ND; ++j) c[i0 * ND + j] = (uint8_t)(o[j >> 2] >> (8 * (j & 3)));
+  }
+}
+
 hipError_t launch_polymul(int k, uint64_t q, int pow2, uint32_t b, const FieldArgs& fa,
                           const uint8_t* a, const uint8_t* bb, size_t n, uint8_t* c,
                           hipStream_t s) {
   if (n == 0) return hipSuccess;
   const RedqArgs ra = make_redq(q, pow2, b, fa);
+  const bool words = ((((uintptr_t)a) | ((uintptr_t)bb) | ((uintptr_t)c)) & 3) == 0;
+  // k <= 5 always: eq. (2) needs q > k, so b >= 3 once k >= 4, and 11 b > 32
+  if (pow2 && (uint32_t)(2 * k - 1) * b <= 32 && words && k <= 5) {
+    const size_t gw = ((n + 3) / 4 + kTB - 1) / kTB;
+    switch (k) {
+#define FQT_PW_CASE(K)                                                                    \
+  case K:                                                                                 \
+    hipLaunchKernelGGL(polymul_w32_kernel<K>, dim3((unsigned)gw), dim3(kTB), 0, s, a, bb, n, \
+                       ra, c);                                                            \
+    return hipGetLastError();
+      FQT_PW_CASE(1) FQT_PW_CASE(2) FQT_PW_CASE(3) FQT_PW_CASE(4) FQT_PW_CASE(5)
+#undef FQT_PW_CASE
+      default: break;
+    }
+  }
   const size_t gk = (n + kPM - 1) / kPM;
   switch (k) {
 #define FQT_PM_CASE(K)                                                                   \

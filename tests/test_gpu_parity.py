@@ -95,8 +95,33 @@ def test_polymul_params(p, k, q, n):
     assert np.array_equal(out, gf.polymul_batch(a, b, p))
 
 
+@pytest.mark.parametrize("p,k,q,n", [(5, 3, 64, 1), (5, 3, 64, 2), (5, 3, 64, 3), (5, 3, 64, 4),
+                                     (5, 3, 64, 1029), (5, 3, 64, 4 * 256 * 3 + 2),
+                                     (2, 5, 8, 3001), (3, 3, 16, 1002), (5, 2, 64, 777),
+                                     (13, 2, 512, 3), (127, 1, 2 ** 14, 4099), (2, 1, 2, 5),
+                                     (2, 4, 8, 2048), (7, 2, 2 ** 10, 4097), (3, 2, 2 ** 8, 999),
+                                     (3, 1, 2 ** 32, 10)])
+def test_polymul_32bit_words(p, k, q, n):
+    # q = 2^b with (2k - 1) b <= 32 and word-aligned buffers: every pair's
+    # product and digits stay below 2^32 (four pairs per thread, the last
+    # thread of a ragged batch byte by byte); all-maximal rows put the
+    # largest r of the batch through the floor division by p
+    b = q.bit_length() - 1
+    assert q == 1 << b and (2 * k - 1) * b <= 32 and gf.eq2_holds(p, k, q, 1)
+    note(f"polymul 32-bit words p={p} k={k} q={q} n={n}")
+    rng = np.random.default_rng(p * 31 + k * 7 + n)
+    a = rng.integers(0, p, size=(n, k), dtype=np.uint8)
+    b_ = rng.integers(0, p, size=(n, k), dtype=np.uint8)
+    a[-1] = p - 1
+    b_[-1] = p - 1
+    a[0] = p - 1
+    b_[0] = p - 1
+    out = host(fqt.polymul_batch(p, k, q, dev(a), dev(b_)))
+    assert np.array_equal(out, gf.polymul_batch(a, b_, p))
+
+
 @pytest.mark.parametrize("p,k,q,n", [(3, 3, 256, 2049), (3, 4, 64, 1024), (2, 8, 9, 1025),
-                                     (5, 1, 2 ** 20, 5000)])
+                                     (5, 1, 2 ** 20, 5000), (2, 4, 8, 1031), (5, 3, 64, 1030)])
 def test_polymul_unaligned_views(p, k, q, n):
     # operands and output start one row into their buffers (k and 2k - 1
     # bytes: not 16-byte aligned), and the batch ends inside a workgroup
