@@ -46,6 +46,9 @@ MEASURED_TRAFFIC = {
     ("polymul-gf5-k3-2^24", "polymul", "polymul_w32_kernel"): {
         "bytes": 184_602_803,  # FETCH 49178.1 KiB x 2.000 + WRITE 81920.0 KiB x 1.000
         "source": "profiles/polymul_gf5_k3_2-24.md"},
+    ("transforms-gf5^3-2^24", "unpack_poly", "unpack_w_kernel<5, 5, false>"): {
+        "bytes": 218_159_124,  # FETCH 65562.99 KiB x 2.000 + WRITE 81920.04 KiB x 1.000
+        "source": "profiles/transforms_gf5-3_2-24.md"},
     ("dfqt-gf3-n500-d4", "dfqt", 4, 1): {
         "bytes": 34_188_339,  # FETCH 8629.5 KiB x 2.000 + WRITE 16128 KiB x 1.000
         "source": "profiles/dfqt_gf3_n500_d4.md"},
@@ -545,21 +548,12 @@ def bench_polymul(w, args, torch, fqt, gf):
     # Cache behind L2, so replaying one set would time cache hits: the timed
     # steps cycle through enough sets (copies of the same inputs) that the
     # cache cannot hold them; the one-set time is reported beside it.
-    nsets = args.rotate or max(2, -(-4 * INFINITY_CACHE_BYTES // nbytes))
-    sets = [(a, b, c)] + [(a.clone(), b.clone(), torch.empty_like(c)) for _ in range(nsets - 1)]
-    turn = [0]
-
-    def step():
-        x, y, z = sets[turn[0]]
-        turn[0] = (turn[0] + 1) % nsets
-        fqt.polymul_batch(w.p, w.k, w.q, x, y, out=z)
-
-    for _ in range(nsets):  # every set's output written before the timed steps
-        step()
-    size_counts(step, args, torch)
-    ms = time_steps(step, args.steps, args.warmup, torch)
-    ms_one_set = time_steps(lambda: fqt.polymul_batch(w.p, w.k, w.q, a, b, out=c), args.steps,
-                            args.warmup, torch)
+    sets = rotating_sets(
+        lambda i: (a, b, c) if i == 0 else (a.clone(), b.clone(), torch.empty_like(c)), nbytes,
+        args)
+    nsets = len(sets)
+    ms, ms_one_set = time_rotating(
+        lambda x, y, z: fqt.polymul_batch(w.p, w.k, w.q, x, y, out=z), sets, args, torch)
     torch.cuda.synchronize()
     for x, y, z in sets[1:]:
         if not torch.equal(z, c):
@@ -602,6 +596,108 @@ def bench_polymul(w, args, torch, fqt, gf):
         "one_set_ms_per_step": ms_one_set,
         "parity": {"full_output_vs_oracle": True},
         **cpu,
+    }
+
+
+def rotating_sets(make, nbytes, args):
+    """Buffer sets for a streaming leg: enough copies that the timed steps
+    cycle through more than four times the Infinity Cache (one step's
+    buffers would otherwise be served partly from that cache)."""
+    nsets = args.rotate or max(2, -(-4 * INFINITY_CACHE_BYTES // nbytes))
+    return [make(i) for i in range(nsets)]
+
+
+def time_rotating(call, sets, args, torch):
+    """ms per step over the buffer sets in turn, and over the first set alone."""
+    turn = [0]
+
+    def step():
+        call(*sets[turn[0]])
+        turn[0] = (turn[0] + 1) % len(sets)
+
+    for _ in range(len(sets)):  # every set's output written before the timed steps
+        step()
+    size_counts(step, args, torch)
+    ms = time_steps(step, args.steps, args.warmup, torch)
+    ms_one = time_steps(lambda: call(*sets[0]), args.steps, args.warmup, torch)
+    return ms, ms_one
+
+
+def bench_transforms(w, args, torch, fqt, gf):
+    """The boundary's standalone transforms on n elements: REDQ unpack of
+    binary64 values with 2k-1 base-q digits to polynomial digits (Alg. 2 and
+    the Q_d correction; `value`), the same values to field elements (L + H,
+    Thm. 3), and the DQT pack of coefficient bytes (eq. (1)).  Bytes per
+    element: 8 in + 2k-1 out, 8 in + k out, k in + 8 out."""
+    from paper_0710_0510_amd import workloads as W
+    c_h, r_h = W.transform_inputs(w)
+    f = fqt.Field(w.p, w.k, w.P_low)
+    nd = 2 * w.k - 1
+    c, r = torch.from_numpy(c_h).cuda(), torch.from_numpy(r_h).cuda()
+    poly = fqt.unpack_redq(f, w.q, r, nd, fqt.UNPACK_POLY)
+    field = fqt.unpack_redq(f, w.q, r, nd, fqt.UNPACK_FIELD)
+    packed = fqt.pack(f, w.q, c)
+    torch.cuda.synchronize()
+    # parity on a sample of every leg against the oracle's definitions
+    rng = np.random.default_rng(99)
+    idx = rng.integers(0, w.n, size=max(64, 16 * args.samples))
+    idx[:2] = [0, w.n - 1]
+    poly_h, field_h, packed_h = poly.cpu().numpy(), field.cpu().numpy(), packed.cpu().numpy()
+    bad = 0
+    for i in idx.tolist():
+        dg = gf.dqt_inverse(int(r_h[i]), w.q, nd, w.p)
+        bad += poly_h[i].tolist() != dg
+        bad += field_h[i].tolist() != gf.poly_rem(dg, w.P_low, w.p)
+        bad += float(packed_h[i]) != float(gf.dqt(c_h[i].tolist(), w.q))
+    if bad:
+        raise SystemExit(f"parity failure: {bad} sampled transform outputs differ from the oracle")
+    b_q = w.q.bit_length() - 1
+    pow2 = w.q == 1 << b_q
+    legs = {
+        "unpack_poly": (8 + nd, r, poly,
+                        lambda x, y: fqt.unpack_redq(f, w.q, x, nd, fqt.UNPACK_POLY, out=y),
+                        f"unpack_w_kernel<{nd}, {nd}, false>" if pow2 else "unpack_kernel<false>"),
+        "unpack_field": (8 + w.k, r, field,
+                         lambda x, y: fqt.unpack_redq(f, w.q, x, nd, fqt.UNPACK_FIELD, out=y),
+                         f"unpack_w_kernel<{nd}, {w.k}, true>" if pow2 else "unpack_kernel<false>"),
+        "pack": (w.k + 8, c, packed, lambda x, y: fqt.pack(f, w.q, x, out=y),
+                 f"pack_w_kernel<{w.k}>" if pow2 else "pack_kernel"),
+    }
+    res = {}
+    for name, (eb, x0, y0, call, kern) in legs.items():
+        sets = rotating_sets(lambda i: (x0, y0) if i == 0 else (x0.clone(), torch.empty_like(y0)),
+                             w.n * eb, args)
+        ms, ms_one = time_rotating(call, sets, args, torch)
+        torch.cuda.synchronize()
+        for x, y in sets[1:]:
+            if not torch.equal(y, y0):
+                raise SystemExit(f"parity failure: {name} output differs between buffer sets")
+        gbps = w.n * eb / (ms * 1e-3) / 1e9
+        res[name] = {"ms_per_step": ms, "values_per_s": w.n / (ms * 1e-3), "GBps": gbps,
+                     "roofline_frac": gbps * 1e9 / PEAK_HBM, "bytes_per_value": eb,
+                     "buffer_sets": len(sets), "one_set_ms_per_step": ms_one, "kernel": kern}
+        del sets
+    main_r = res.pop("unpack_poly")
+    ms = main_r["ms_per_step"]
+    ach = w.n * (8 + nd) / (ms * 1e-3)
+    kern = main_r["kernel"]
+    return {
+        "metric": "REDQ unpack values/s (boundary transform, binary64 in, 2k-1 digits out)",
+        "value": w.n / (ms * 1e-3), "unit": "values/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name, "p": w.p, "k": w.k, "q": w.q, "n": w.n, "seed": w.seed,
+                   "ndigits": nd},
+        "roofline": {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                     "frac": ach / PEAK_HBM,
+                     "traffic": (MEASURED_TRAFFIC.get((w.name, "unpack_poly", kern)) or {}).get(
+                         "bytes"),
+                     "kernel": kern,
+                     "algorithmic": f"8 B in + {nd} B out per value"},
+        "buffer_sets": main_r["buffer_sets"],
+        "one_set_ms_per_step": main_r["one_set_ms_per_step"],
+        "paths": res,
+        "parity": {"sampled_values_vs_oracle": int(len(idx)), "legs": 3},
     }
 
 
@@ -861,7 +957,7 @@ def main():
                     help="batched: JSON options of the INT8 path instead of autotuning")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--rotate", type=int, default=0, metavar="SETS",
-                    help="polymul workloads: buffer sets cycled by the timed steps "
+                    help="streaming workloads (polymul, transforms): buffer sets cycled by the timed steps "
                          "(0: enough to exceed 4x the Infinity Cache)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for HBM counter scaling)")
@@ -897,6 +993,8 @@ def main():
         out = bench_dfqt_batched(w, args, torch, fqt, gf)
     elif w.kind == "batched":
         out = bench_batched(w, args, torch, fqt, gf)
+    elif w.kind == "transforms":
+        out = bench_transforms(w, args, torch, fqt, gf)
     else:
         out = bench_polymul(w, args, torch, fqt, gf)
     print(json.dumps(out), flush=True)

@@ -9,10 +9,11 @@
 //     H[u_{k-1}..u_{2k-2}] (Thm. 3) for field output.
 //   * Alg. 1 for a batch of independent polynomial products: pack, one FP64
 //     product, REDQ + Q_d.
-// These kernels are bound by HBM bandwidth; every workgroup stages its input
-// and output bytes through LDS so that global accesses are whole dwords,
-// except Alg. 1 with all intermediates below 2^32, whose threads take four
-// pairs each straight from whole words of aligned buffers.
+// These kernels are bound by HBM bandwidth.  With q = 2^b and word-aligned
+// buffers (pack, unpack; Alg. 1 also needs every intermediate below 2^32)
+// each thread takes four consecutive items straight from whole words;
+// otherwise every workgroup stages its input and output bytes through LDS so
+// that global accesses are whole dwords.
 
 #include "fqt_internal.h"
 
@@ -133,9 +134,64 @@ __global__ __launch_bounds__(kTB) void pack_kernel(const uint8_t* __restrict__ c
   if (i < n) out[i] = dqt_eval(buf + threadIdx.x * k, k, pow2, b, qd);
 }
 
+// DQT pack for q = 2^b from word-aligned coefficient bytes: thread t packs
+// elements 4t .. 4t+3 from K whole words and writes their four binary64
+// values, with no LDS.  Each value is sum_j c_j 2^(b j) built by exact FP64
+// multiply-adds (every partial sum is an integer below 2^53).
+template <int K>
+__global__ __launch_bounds__(kTB) void pack_w_kernel(const uint8_t* __restrict__ coeffs, size_t n,
+                                                     uint32_t b, double* __restrict__ out) {
+  const size_t t = (size_t)blockIdx.x * kTB + threadIdx.x;
+  const size_t i0 = 4 * t;
+  if (i0 >= n) return;
+  const int nv = n - i0 < 4 ? (int)(n - i0) : 4;
+  uint32_t w[K];
+  if (nv == 4) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(coeffs + i0 * K);
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = src[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) w[j] = 0;
+    for (int j = 0; j < nv * K; ++j) w[j >> 2] |= (uint32_t)coeffs[i0 * K + j] << (8 * (j & 3));
+  }
+  double qj[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) qj[j] = __builtin_ldexp(1.0, (int)(b * j));
+  double v[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double x = 0.0;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      const int pos = e * K + j;
+      x = __builtin_fma((double)((w[pos >> 2] >> (8 * (pos & 3))) & 0xffu), qj[j], x);
+    }
+    v[e] = x;
+  }
+  if (nv == 4) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[i0 + e] = v[e];
+  } else {
+    for (int e = 0; e < nv; ++e) out[i0 + e] = v[e];
+  }
+}
+
 hipError_t launch_pack(int k, uint64_t q, int pow2, uint32_t b, const uint8_t* coeffs, size_t n,
                        double* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  if (pow2 && ((uintptr_t)coeffs & 3) == 0 && ((uintptr_t)out & 7) == 0) {
+    const size_t gw = ((n + 3) / 4 + kTB - 1) / kTB;
+    switch (k) {
+#define FQT_PK_CASE(K)                                                                      \
+  case K:                                                                                   \
+    hipLaunchKernelGGL(pack_w_kernel<K>, dim3((unsigned)gw), dim3(kTB), 0, s, coeffs, n, b, out); \
+    return hipGetLastError();
+      FQT_PK_CASE(1) FQT_PK_CASE(2) FQT_PK_CASE(3) FQT_PK_CASE(4)  // fields have k <= 4
+#undef FQT_PK_CASE
+      default: break;
+    }
+  }
   const size_t grid = (n + kTB - 1) / kTB;
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)grid), dim3(kTB), 0, s, coeffs, n, k, pow2, b,
                      (double)q, out);
@@ -235,10 +291,132 @@ static RedqArgs make_redq(uint64_t q, int pow2, uint32_t b, const FieldArgs& fa)
   return ra;
 }
 
+// The integer value of a binary64 holding an integer below 2^53, as words.
+__device__ __forceinline__ uint64_t f64_to_u64(double v) {
+  const double hi = __builtin_trunc(v * 0x1p-32);
+  const uint32_t lo = (uint32_t)__builtin_fma(hi, -0x1p32, v);
+  return ((uint64_t)(uint32_t)hi << 32) | lo;
+}
+
+// REDQ unpack for q = 2^b and binary64 input, NR residues per value known at
+// compile time, word-aligned output.  Thread t unpacks values 4t .. 4t+3
+// (two 16-byte loads) and writes their 4 OB output bytes as OB whole words,
+// with no LDS.  rop = floor(r/p) from a binary64 estimate and one exact
+// correction (fma); u_i = floor(r/q^i) - p floor(rop/q^i) lies in [0, p), so
+// its low 24 bits, from the low words of the two shifted values and one
+// 24-bit multiply-add, are the residue itself.  POLY: Q_d correction, NR = OB
+// digits.  FIELD: L + H (Thm. 3) on NR = 2k-1 residues, OB = k bytes.
+template <int NR, int OB, bool FIELD>
+__global__ __launch_bounds__(kTB) void unpack_w_kernel(const double* __restrict__ in, size_t n,
+                                                       RedqArgs ra, FieldArgs fa,
+                                                       const uint32_t* __restrict__ L,
+                                                       const uint32_t* __restrict__ H,
+                                                       uint8_t* __restrict__ out) {
+  constexpr int K = (NR + 1) / 2;  // FIELD: the extension degree
+  const size_t t = (size_t)blockIdx.x * kTB + threadIdx.x;
+  const size_t i0 = 4 * t;
+  if (i0 >= n) return;
+  const int nv = n - i0 < 4 ? (int)(n - i0) : 4;
+  double v[4];
+  if (nv == 4) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = in[i0 + e];
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = e < nv ? in[i0 + e] : 0.0;
+  }
+  const uint32_t p = ra.p, b = ra.b, pm = ra.pm24;
+  const double pd = (double)p;
+  uint32_t o[OB];
+#pragma unroll
+  for (int w = 0; w < OB; ++w) o[w] = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    // Alg. 2's first step: rop = floor(r / p)
+    double td = __builtin_floor(v[e] * ra.inv_p);
+    const double rem = __builtin_fma(-pd, td, v[e]);  // exact: |rem| < 2p
+    td += rem < 0.0 ? -1.0 : (rem >= pd ? 1.0 : 0.0);
+    uint64_t x = f64_to_u64(v[e]), y = f64_to_u64(td);
+    uint32_t u[NR];
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      u[i] = ((uint32_t)x + __umul24((uint32_t)y, pm)) & 0xffffffu;
+      x >>= b;  // one digit at a time: b < 64, and digits past the value read 0
+      y >>= b;
+    }
+    if constexpr (!FIELD) {
+      // Q_d: mu_i = u_i + c u_{i+1} mod p, the top digit as it is
+#pragma unroll
+      for (int d = 0; d < NR; ++d) {
+        uint32_t mu = u[d];
+        if (d < NR - 1) {
+          const uint32_t x = u[d] + __umul24(ra.c, u[d + 1]);
+          mu = (x + __umul24(__umulhi(x, ra.mod_magic), pm)) & 0xffffffu;
+        }
+        const int pos = e * OB + d;
+        o[pos >> 2] |= mu << (8 * (pos & 3));
+      }
+    } else {
+      uint32_t il = 0, ih = 0;
+#pragma unroll
+      for (int d = 0; d < K; ++d) {
+        il |= u[d] << (fa.cb * d);
+        ih |= u[K - 1 + d] << (fa.cb * d);
+      }
+      const uint32_t tmask = (1u << (fa.cb * K)) - 1u;  // keeps lookups inside the tables
+      const uint32_t x = add_bytes_mod_p(L[il & tmask], H[ih & tmask], fa);
+#pragma unroll
+      for (int d = 0; d < OB; ++d) {
+        const int pos = e * OB + d;
+        o[pos >> 2] |= ((x >> (8 * d)) & 0xffu) << (8 * (pos & 3));
+      }
+    }
+  }
+  if (nv == 4) {
+    uint32_t* dst = reinterpret_cast<uint32_t*>(out + i0 * OB);
+#pragma unroll
+    for (int w = 0; w < OB; ++w) dst[w] = o[w];
+  } else {
+    for (int j = 0; j < nv * OB; ++j) out[i0 * OB + j] = (uint8_t)(o[j >> 2] >> (8 * (j & 3)));
+  }
+}
+
+template <int NR, int OB, bool FIELD>
+static hipError_t launch_unpack_w(const double* in, size_t n, const RedqArgs& ra,
+                                  const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
+                                  uint8_t* out, hipStream_t s) {
+  const size_t grid = ((n + 3) / 4 + kTB - 1) / kTB;
+  hipLaunchKernelGGL((unpack_w_kernel<NR, OB, FIELD>), dim3((unsigned)grid), dim3(kTB), 0, s, in,
+                     n, ra, fa, L, H, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_unpack_f64(int k, uint32_t nd, int mode, uint64_t q, int pow2, uint32_t b,
                              const FieldArgs& fa, const uint32_t* L, const uint32_t* H,
                              const double* in, size_t n, uint8_t* out, hipStream_t s) {
   if (n == 0) return hipSuccess;
+  if (pow2 && ((uintptr_t)out & 3) == 0 && ((uintptr_t)in & 7) == 0) {
+    const RedqArgs ra = make_redq(q, pow2, b, fa);
+    if (mode == 0) {
+      switch (nd) {
+#define FQT_UP_CASE(D) \
+  case D: return launch_unpack_w<D, D, false>(in, n, ra, fa, L, H, out, s);
+        FQT_UP_CASE(1) FQT_UP_CASE(2) FQT_UP_CASE(3) FQT_UP_CASE(4) FQT_UP_CASE(5)
+        FQT_UP_CASE(6) FQT_UP_CASE(7) FQT_UP_CASE(8) FQT_UP_CASE(9) FQT_UP_CASE(10)
+        FQT_UP_CASE(11) FQT_UP_CASE(12) FQT_UP_CASE(13) FQT_UP_CASE(14) FQT_UP_CASE(15)
+#undef FQT_UP_CASE
+        default: break;
+      }
+    } else {
+      switch (k) {
+#define FQT_UF_CASE(K) \
+  case K: return launch_unpack_w<2 * K - 1, K, true>(in, n, ra, fa, L, H, out, s);
+        FQT_UF_CASE(1) FQT_UF_CASE(2) FQT_UF_CASE(3) FQT_UF_CASE(4)  // fields have k <= 4
+#undef FQT_UF_CASE
+        default: break;
+      }
+    }
+  }
   const size_t grid = (n + 4 * kTB - 1) / (4 * kTB);
   hipLaunchKernelGGL(unpack_kernel<false>, dim3((unsigned)grid), dim3(kTB), 0, s,
                      (const void*)in, n, k, (int)nd, mode, make_redq(q, pow2, b, fa), fa, L, H,

@@ -37,7 +37,7 @@ GF3_2 = Field(3, 2, (1, 0))          # X^2 + 1
 @dataclass(frozen=True)
 class Workload:
     name: str
-    kind: str                 # "polymul" | "gemm" | "batched" | "dfqt" | "dfqt_batched"
+    kind: str                 # "polymul" | "gemm" | "batched" | "dfqt" | "dfqt_batched" | "transforms"
     p: int
     k: int
     P_low: Tuple[int, ...] = ()
@@ -76,6 +76,11 @@ WORKLOADS = {
     # uniform in 1..1024 coefficients, one persistent launch for the batch
     "dfqt-uneven-gf3-1024": Workload("dfqt-uneven-gf3-1024", "dfqt_batched", 3, 1, (), seed=8,
                                      count=16384, lo=1, hi=1024, d=4),
+    # the boundary's standalone transforms on 2^24 elements of GF(5^3) at
+    # q = 2^6: DQT pack of coefficient bytes, REDQ unpack of values with
+    # 2k - 1 = 5 base-q digits to polynomial digits and to field elements
+    "transforms-gf5^3-2^24": Workload("transforms-gf5^3-2^24", "transforms", 5, 3, GF5_3.P_low,
+                                      seed=9, n=1 << 24, q=64),
 }
 
 
@@ -89,6 +94,18 @@ def polymul_inputs(w: Workload):
     a = coeffs(rng, (w.n,), w.p, w.k)
     b = coeffs(rng, (w.n,), w.p, w.k)
     return a, b
+
+
+def transform_inputs(w: Workload):
+    """n elements' coefficient bytes (uniform in [0, p)) for the pack, and n
+    integers uniform in [0, q^(2k-1)) as binary64 (exact: q^(2k-1) <= 2^53)
+    for the unpack."""
+    rng = np.random.default_rng(w.seed)
+    c = coeffs(rng, (w.n,), w.p, w.k)
+    top = w.q ** (2 * w.k - 1)
+    assert top <= 1 << 53
+    r = rng.integers(0, top, size=w.n, dtype=np.int64).astype(np.float64)
+    return c, r
 
 
 def poly_long_inputs(w: Workload, count: int = 0):

@@ -159,6 +159,32 @@ def test_pack(p, k, P, qkind):
     assert np.array_equal(out, want)
 
 
+@pytest.mark.parametrize("p,k", [(2, 1), (127, 1), (7, 2), (5, 3), (3, 4), (13, 2)])
+def test_pack_word_kernel_largest_q(p, k):
+    # q = 2^b, the largest b the host admits (packed values exact in
+    # binary64, q^k at most 2^70); 1027 elements end inside a thread's group
+    # of four; then the same bytes one element into their buffer (not
+    # word-aligned unless k = 4) packed into an output view one value into
+    # its buffer
+    b = max(bb for bb in range(1, 64)
+            if (p - 1) * sum(2 ** (bb * j) for j in range(k)) <= 2 ** 53 and bb * k <= 70)
+    q = 1 << b
+    note(f"pack word kernel GF({p}^{k}) q=2^{b}")
+    f = fqt.Field(p, k, _first_irreducible(p, k))
+    rng = np.random.default_rng(p + k)
+    n = 1027
+    c = rng.integers(0, p, size=(n + 1, k), dtype=np.uint8)
+    c[1] = p - 1
+    c[-1] = p - 1
+    want = np.array([float(gf.dqt(row.tolist(), q)) for row in c])
+    out = host(fqt.pack(f, q, dev(c)))
+    assert np.array_equal(out, want)
+    big = torch.full((n + 1,), -1.0, dtype=torch.float64, device="cuda")
+    fqt.pack(f, q, dev(c)[1:], out=big[1:])
+    got = host(big)
+    assert np.array_equal(got[1:], want[1:]) and got[0] == -1.0
+
+
 def _random_packed(rng, n, nd, q):
     digits = rng.integers(0, q, size=(n, nd), dtype=np.int64)
     digits[0] = q - 1
@@ -192,6 +218,69 @@ def test_unpack_poly_and_field(p, k, P, qkind):
     packed64 = dev(np.array(vals, dtype=np.int64))
     assert np.array_equal(host(fqt.unpack_redq(f, q, packed64, nd, fqt.UNPACK_POLY)), want_poly)
     assert np.array_equal(host(fqt.unpack_redq(f, q, packed64, nd, fqt.UNPACK_FIELD)), want_field)
+
+
+def _first_irreducible(p, k):
+    for idx in range(p ** k):
+        P = [(idx // p ** j) % p for j in range(k)]
+        if P[0] != 0 and gf.is_irreducible(P, p):
+            return tuple(P)
+    raise AssertionError("no irreducible polynomial")
+
+
+def _edge_values(rng, n, top, p):
+    # uniform values below top, then the largest ones, zero and multiples of p
+    vals = [int(v) for v in rng.integers(0, top, size=n, dtype=np.int64)]
+    edges = [top - 1, top - 2, 0, 1, p, top - 1 - (top - 1) % p]
+    vals[:len(edges)] = edges
+    vals[-1] = top - 1
+    return vals
+
+
+@pytest.mark.parametrize("nd", list(range(1, 16)))
+def test_unpack_poly_word_kernel_every_ndigits(nd):
+    # q = 2^b with q^nd <= 2^53: the word-direct kernel (four values per
+    # thread, NR = nd digits fixed at compile time); 1001 values end inside
+    # a thread's group of four
+    p, k, P = 5, 3, (3, 3, 0)
+    b = min(53 // nd, 40)
+    q = 1 << b
+    note(f"unpack POLY word kernel nd={nd} q=2^{b}")
+    f = fqt.Field(p, k, P)
+    vals = _edge_values(np.random.default_rng(nd), 1001, q ** nd, p)
+    out = host(fqt.unpack_redq(f, q, dev(np.array(vals, dtype=np.float64)), nd, fqt.UNPACK_POLY))
+    want = np.array([gf.dqt_inverse(v, q, nd, p) for v in vals], dtype=np.uint8)
+    assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("p,k", [(2, 1), (127, 1), (3, 2), (7, 2), (13, 2), (2, 3), (5, 3),
+                                 (2, 4), (3, 4)])
+def test_unpack_field_word_kernel_every_k(p, k):
+    P = _first_irreducible(p, k)
+    nr = 2 * k - 1
+    b = 53 // nr
+    q = 1 << b
+    note(f"unpack FIELD word kernel GF({p}^{k}) q=2^{b}")
+    f = fqt.Field(p, k, P)
+    vals = _edge_values(np.random.default_rng(p * 10 + k), 1003, q ** nr, p)
+    out = host(fqt.unpack_redq(f, q, dev(np.array(vals, dtype=np.float64)), nr, fqt.UNPACK_FIELD))
+    want = np.array([gf.poly_rem(gf.dqt_inverse(v, q, nr, p), P, p) for v in vals],
+                    dtype=np.uint8)
+    assert np.array_equal(out, want)
+
+
+def test_unpack_field_fewer_digits_than_residues():
+    # FIELD mode with ndigits < 2k - 1 at a q whose (2k-1)-th power is far
+    # above 2^64: the residues past the value are zero
+    p, k, P = 5, 3, (3, 3, 0)
+    q, nd = 2 ** 17, 3
+    note("unpack FIELD ndigits 3 of 5 at q=2^17")
+    f = fqt.Field(p, k, P)
+    vals = _edge_values(np.random.default_rng(17), 999, q ** nd, p)
+    out = host(fqt.unpack_redq(f, q, dev(np.array(vals, dtype=np.float64)), nd, fqt.UNPACK_FIELD))
+    want = np.array([gf.poly_rem(gf.dqt_inverse(v, q, 2 * k - 1, p), P, p) for v in vals],
+                    dtype=np.uint8)
+    assert np.array_equal(out, want)
 
 
 def test_unpack_example2_uint64():
