@@ -59,7 +59,7 @@ MEASURED_TRAFFIC = {
         "bytes": 1_247_242_854,  # FETCH 451374.2 KiB x 2.000 + WRITE 315262.2 KiB x 1.000
         "source": "profiles/batched_gf3-4_4096.md"},
     ("batched-gf3^4-4096", "int8", 11): {
-        "bytes": 964_707_389,  # FETCH 306283.2 KiB x 2.000 + WRITE 329530.7 KiB x 1.000
+        "bytes": 1_028_396_073,  # FETCH 330734.4 KiB x 2.000 + WRITE 342824.3 KiB x 1.000
         "source": "profiles/batched_gf3-4_4096.md"},
 }
 

@@ -58,11 +58,13 @@ __device__ __forceinline__ uint32_t cs_mod_big(int32_t x, uint32_t p, double inv
 struct CsParams {
   uint32_t p, cb, tmask, magic;
   uint32_t red_tiles;  // K-tiles between reductions mod p (0: never)
-  uint32_t small;      // every accumulator stays below 2^25: the cheap reduction
   double inv_p;
 };
 
-// One strip: C[0 .. M)[n0 .. n0 + 16) of product g.
+// One strip: C[0 .. M)[n0 .. n0 + 16) of product g.  SMALL: every final
+// accumulator stays below 2^25, so the epilogue takes the cheap reduction
+// (a compile-time choice: a run-time one branches around every accumulator).
+template <bool SMALL>
 __device__ __forceinline__ void cs_strip(const GemmArgs& g, int64_t n0, const CsParams& cp,
                                          const uint8_t* __restrict__ mts,
                                          uint8_t (*Bs)[64 * kCsRow]) {
@@ -208,8 +210,8 @@ __device__ __forceinline__ void cs_strip(const GemmArgs& g, int64_t n0, const Cs
 #pragma unroll
           for (int j = 0; j < 4; ++j) {
             const int32_t x = acc[h][rb][j][v];
-            const uint32_t m = cp.small ? cs_mod_small(x, cp.magic, cp.p)
-                                        : cs_mod_big(x, cp.p, cp.inv_p);
+            const uint32_t m = SMALL ? cs_mod_small(x, cp.magic, cp.p)
+                                     : cs_mod_big(x, cp.p, cp.inv_p);
             e |= m << (8 * j);
           }
           if (row < g.M && col < g.N) store_elem<4>(g.C + (row * g.ldc + col) * 4, e);
@@ -219,6 +221,7 @@ __device__ __forceinline__ void cs_strip(const GemmArgs& g, int64_t n0, const Cs
 }
 
 // Strips of workgroup w: items[wg_begin[w] .. wg_begin[w + 1]), in order.
+template <bool SMALL>
 __global__ __launch_bounds__(256) void gemm_i8cs_batched_kernel(
     const GemmArgs* __restrict__ descs, const CsItem* __restrict__ items,
     const int32_t* __restrict__ wg_begin, const uint8_t* __restrict__ mt, uint32_t tbl_log2,
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(256) void gemm_i8cs_batched_kernel(
   for (int32_t it = beg; it < end; ++it) {
     const CsItem ci = items[it];
     const GemmArgs g = descs[__builtin_amdgcn_readfirstlane(ci.gemm)];
-    cs_strip(g, (int64_t)__builtin_amdgcn_readfirstlane(ci.nc) * kCsN, cp, mts, Bs);
+    cs_strip<SMALL>(g, (int64_t)__builtin_amdgcn_readfirstlane(ci.nc) * kCsN, cp, mts, Bs);
     __syncthreads();  // the next strip's first expansion reuses buffer 0
   }
 }
@@ -251,7 +254,7 @@ int i8cs_occupancy(uint32_t tbl_log2) {
   int blocks = 0;
   const size_t dyn = ((size_t)1 << tbl_log2) * 16;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &blocks, (const void*)gemm_i8cs_batched_kernel, 256, dyn) != hipSuccess)
+          &blocks, (const void*)gemm_i8cs_batched_kernel<true>, 256, dyn) != hipSuccess)
     blocks = 1;
   return blocks > 0 ? blocks : 1;
 }
@@ -266,11 +269,14 @@ hipError_t launch_gemm_i8cs_batched(const GemmArgs* descs, const int32_t* items_
   cp.tmask = (1u << tbl_log2) - 1u;
   cp.magic = (uint32_t)(((1ull << 32) + p - 1) / p);
   cp.red_tiles = red_tiles;
-  cp.small = small;
   cp.inv_p = 1.0 / (double)p;
   const size_t dyn = ((size_t)1 << tbl_log2) * 16;
-  hipLaunchKernelGGL(gemm_i8cs_batched_kernel, dim3(grid), dim3(256), dyn, s, descs,
-                     reinterpret_cast<const CsItem*>(items_raw), wg_begin, mt, tbl_log2, cp);
+  if (small)
+    hipLaunchKernelGGL(gemm_i8cs_batched_kernel<true>, dim3(grid), dim3(256), dyn, s, descs,
+                       reinterpret_cast<const CsItem*>(items_raw), wg_begin, mt, tbl_log2, cp);
+  else
+    hipLaunchKernelGGL(gemm_i8cs_batched_kernel<false>, dim3(grid), dim3(256), dyn, s, descs,
+                       reinterpret_cast<const CsItem*>(items_raw), wg_begin, mt, tbl_log2, cp);
   return hipGetLastError();
 }
 
