@@ -65,3 +65,40 @@ def test_roofline_names_the_kernel_of_the_tuned_tile():
     assert "gemm_i8f_kernel" in bench.roofline_for("int8", 2, 1e9, 1.0, 5)["kernel"]
     rl = bench.roofline_for("packed", 2, 1024 ** 3, 0.03876, 12)
     assert abs(rl["frac"] - 2 * 1024 ** 3 / 0.03876e-3 / 78.6e12) < 1e-12
+
+
+def test_streaming_legs_cycle_buffer_sets_past_the_cache(monkeypatch):
+    # enough sets that the timed steps touch over four times the 256 MiB
+    # Infinity Cache; --rotate overrides; every set is written once before
+    # the timed steps, which then take the sets in turn
+    args = types.SimpleNamespace(rotate=0, steps=5, warmup=2)
+    assert len(bench.rotating_sets(lambda i: i, 184_549_376, args)) == 6
+    assert len(bench.rotating_sets(lambda i: i, 2 << 30, args)) == 2  # at least two
+    args.rotate = 3
+    sets = bench.rotating_sets(lambda i: i, 184_549_376, args)
+    assert sets == [0, 1, 2]
+    seen = []
+
+    def fake_time_steps(fn, steps, warmup, torch):
+        for _ in range(warmup + steps):
+            fn()
+        return 1.0
+
+    monkeypatch.setattr(bench, "time_steps", fake_time_steps)
+    ms, one = bench.time_rotating(lambda x: seen.append(x), [(i,) for i in sets], args,
+                                  _fake_torch())
+    assert (ms, one) == (1.0, 1.0)
+    cycled = [0, 1, 2] + [i % 3 for i in range(7)]  # fill, then warmup + steps in turn
+    assert seen[:10] == cycled and seen[10:] == [0] * 7  # then the first set alone
+
+
+def test_transform_inputs_are_exact_and_in_range():
+    from paper_0710_0510_amd import workloads as W
+    w = W.Workload("t", "transforms", 5, 3, (3, 3, 0), seed=9, n=5000, q=64)
+    c, r = W.transform_inputs(w)
+    assert c.shape == (5000, 3) and c.dtype == np.uint8 and int(c.max()) < 5
+    assert r.dtype == np.float64 and (r == np.floor(r)).all()
+    assert float(r.min()) >= 0 and float(r.max()) < 64 ** 5
+    c2, r2 = W.transform_inputs(w)
+    assert np.array_equal(c, c2) and np.array_equal(r, r2)  # seeded
+    assert W.WORKLOADS["transforms-gf5^3-2^24"].q ** 5 <= 2 ** 53
