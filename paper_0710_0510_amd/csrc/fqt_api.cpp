@@ -688,6 +688,9 @@ fqt_status resolve_packed(const fqt_field_s* f, const fqt_gemm_opts* o, int64_t 
     if (nqg == 0)
       return fail(FQT_ERR_UNSUPPORTED, "tile %d needs blocks of at least 4 products (n_q = %"
                   PRIu64 ")", kWaveTile, nq);
+    if ((uint64_t)p * p * p * p > (uint64_t)kWaveDqtEntries)  // implied by n_q >= 4
+      return fail(FQT_ERR_UNSUPPORTED, "tile %d tabulates at most %d elements (p = %u)",
+                  kWaveTile, kWaveDqtEntries, p);
     // digit sums in fields of 2b bits: every absorbed block adds at most q - 1
     // to a field (its digits; centred: shifted digits), a fold leaves < p,
     // and the epilogue adds an offset below p (the centred shift's removal);

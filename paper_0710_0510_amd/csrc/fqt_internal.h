@@ -244,6 +244,9 @@ hipError_t launch_gemm_wave_batched(int nqg, const GemmArgs* descs, const TileIt
                                     hipStream_t s);
 int wave_batched_occupancy(int nqg, uint32_t tbl_log2);
 constexpr int kWaveMaxNqg = 4;
+// Its DQT reads the packed value of each element of GF(p^4) from a table of
+// p^4 entries in LDS: p = 2 or 3, the only p whose n_q at q = 2^7 reaches 4.
+constexpr int kWaveDqtEntries = 81;
 
 // d-split kernels (tile ids kFirstSplitTile..kLastSplitTile, k = 3 or 4).
 hipError_t launch_gemm_split(int k, int tile, const GemmArgs& g, const PackedParams& pp,

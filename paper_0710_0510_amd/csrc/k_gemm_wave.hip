@@ -20,11 +20,13 @@
 // On gfx950 every VALU instruction takes issue cycles from the SIMD that
 // runs the FP64 MFMAs (measured: about 4 cycles per instruction beside 64
 // per v_mfma_f64_16x16x4f64, with one or two waves per SIMD), so the kernel
-// counts instructions: the DQT is a byte permutation (centred
-// coefficients), two byte dot products, a shift-add and a conversion per
-// element (wave_dqt); a block step is two masks and two
-// 64-bit adds per accumulator (digit sums), and the next block starts by
-// passing the bias as the MFMA addend, so no accumulator is re-seeded.
+// counts instructions: the DQT is one byte dot product (the element's
+// index, as the byte offset of its entry), a clamp and an LDS read of the
+// packed value from a table of the p^4 <= 81 elements' values built at
+// launch by wave_dqt (a byte permutation for centring, two byte dot
+// products, a shift-add and a conversion); a block step is two masks and
+// two 64-bit adds per accumulator (digit sums), and the next block starts
+// by passing the bias as the MFMA addend, so no accumulator is re-seeded.
 //
 // Epilogue: the digit sums D_j of all blocks give mu_j = D_j mod p, the
 // coefficients of sum_l A_l B_l in GF(p)[X] (Alg. 2's mu, every block's
@@ -71,6 +73,21 @@ __device__ __forceinline__ double wave_dqt(uint32_t w, const PackedParams& pp) {
   const uint32_t hi = __builtin_amdgcn_udot4(x, 0x80010000u, 0u, false);
   return (double)(int32_t)(lo + (hi << 14));
 }
+
+// The DQT by table: the element's index sum_j c_j p^j selects its packed
+// value, built at launch from wave_dqt itself.  One byte dot product with
+// the weights 8, 8p, 8p^2, 8p^3 (bytes for p <= 3) gives the entry's byte
+// offset, clamped into the table.
+struct DqtTable {
+  const double* v;   // LDS, p^4 values
+  uint32_t weights;  // bytes 8, 8p, 8p^2, 8p^3
+  uint32_t last;     // byte offset of the last entry, 8 (p^4 - 1)
+  __device__ __forceinline__ double operator()(uint32_t w) const {
+    const uint32_t o = __builtin_amdgcn_udot4(w, weights, 0u, false);
+    return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(v) +
+                                            (o < last ? o : last));
+  }
+};
 
 // Field element of the digit sums held in (E, T), q = 2^7, tables for
 // q = 0 mod p.  kE and kO are the tile's constants for the even and the odd
@@ -157,7 +174,7 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
                                            const TileItem* __restrict__ items, int32_t beg,
                                            int32_t end, const PackedParams& pp,
                                            const uint32_t* __restrict__ Ls,
-                                           const uint32_t* __restrict__ Hs) {
+                                           const uint32_t* __restrict__ Hs, const DqtTable dq) {
   constexpr int KE = kWaveKE, TM = 2, TN = 2;
   static_assert(multi_block_b<KE>() == 7, "q = 2^7 for k = 4");
   using St = WStage<NQG>;
@@ -200,11 +217,11 @@ __device__ __forceinline__ void wave_items(const GemmArgs* __restrict__ descs,
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int e = 0; e < NQG; ++e) av[i][e] = wave_dqt(x.a[i][e], pp);
+      for (int e = 0; e < NQG; ++e) av[i][e] = dq(x.a[i][e]);
 #pragma unroll
     for (int gk = 0; gk < NQG; ++gk)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) bv[gk][j] = wave_dqt(x.b[gk][j], pp);
+      for (int j = 0; j < TN; ++j) bv[gk][j] = dq(x.b[gk][j]);
   };
 
   const double bz = pp.centered ? pp.cbias : kTwo52;
@@ -335,13 +352,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQG == 4 ? 
     const GemmArgs* __restrict__ descs, const TileItem* __restrict__ items,
     const int32_t* __restrict__ wave_begin, PackedParams pp) {
   extern __shared__ uint32_t tabs[];
+  __shared__ double dqt_tab[kWaveDqtEntries];
   uint32_t* Ls = tabs;
   uint32_t* Hs = tabs + (1 << pp.tbl_log2);
   load_tables(pp, Ls, Hs);
+  const uint32_t p = pp.fa.p;
+  const uint32_t ne = p * p * p * p;  // at most kWaveDqtEntries (checked on the host)
+  for (uint32_t t = threadIdx.x; t < ne && t < (uint32_t)kWaveDqtEntries; t += blockDim.x) {
+    uint32_t x = t, wd = 0;
+#pragma unroll
+    for (int j = 0; j < kWaveKE; ++j) {
+      wd |= (x % p) << (8 * j);
+      x /= p;
+    }
+    dqt_tab[t] = wave_dqt(wd, pp);
+  }
   __syncthreads();
+  DqtTable dq;
+  dq.v = dqt_tab;
+  dq.weights = 8u * (1u | (p << 8) | (p * p << 16) | (p * p * p << 24));  // 8 p^3 <= 216
+  dq.last = 8u * ((ne < (uint32_t)kWaveDqtEntries ? ne : (uint32_t)kWaveDqtEntries) - 1u);
   const int w = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
   const int32_t beg = wave_begin[w], end = wave_begin[w + 1];
-  if (beg < end) wave_items<NQG>(descs, items, beg, end, pp, Ls, Hs);
+  if (beg < end) wave_items<NQG>(descs, items, beg, end, pp, Ls, Hs, dq);
 }
 
 template <int NQG>
