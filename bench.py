@@ -56,7 +56,7 @@ MEASURED_TRAFFIC = {
         "bytes": 34_159_616,  # FETCH 8615.5 KiB x 2.000 + WRITE 16128 KiB x 1.000
         "source": "profiles/dfqt_gf3_n500_d4.md"},
     ("batched-gf3^4-4096", "packed", 15): {
-        "bytes": 1_247_242_854,  # FETCH 451374.2 KiB x 2.000 + WRITE 315262.2 KiB x 1.000
+        "bytes": 1_256_045_087,  # FETCH 454595.3 KiB x 2.000 + WRITE 317415.9 KiB x 1.000
         "source": "profiles/batched_gf3-4_4096.md"},
     ("batched-gf3^4-4096", "int8", 11): {
         "bytes": 1_028_396_073,  # FETCH 330734.4 KiB x 2.000 + WRITE 342824.3 KiB x 1.000
