@@ -602,8 +602,9 @@ def bench_polymul(w, args, torch, fqt, gf):
 def rotating_sets(make, nbytes, args):
     """Buffer sets for a streaming leg: enough copies that the timed steps
     cycle through more than four times the Infinity Cache (one step's
-    buffers would otherwise be served partly from that cache)."""
-    nsets = args.rotate or max(2, -(-4 * INFINITY_CACHE_BYTES // nbytes))
+    buffers would otherwise be served partly from that cache), at most 64:
+    a step small enough to need more is bound by its launch, not by HBM."""
+    nsets = args.rotate or min(64, max(2, -(-4 * INFINITY_CACHE_BYTES // nbytes)))
     return [make(i) for i in range(nsets)]
 
 

@@ -74,6 +74,7 @@ def test_streaming_legs_cycle_buffer_sets_past_the_cache(monkeypatch):
     args = types.SimpleNamespace(rotate=0, steps=5, warmup=2)
     assert len(bench.rotating_sets(lambda i: i, 184_549_376, args)) == 6
     assert len(bench.rotating_sets(lambda i: i, 2 << 30, args)) == 2  # at least two
+    assert len(bench.rotating_sets(lambda i: i, 65536 * 11, args)) == 64  # at most 64
     args.rotate = 3
     sets = bench.rotating_sets(lambda i: i, 184_549_376, args)
     assert sets == [0, 1, 2]
