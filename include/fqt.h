@@ -214,8 +214,12 @@ fqt_status fqt_params(uint32_t p, uint32_t k, uint64_t n_q, int pow2_q,
 
 /* packed[i] = sum_j coeffs[i*k + j] * q^j as an exact binary64.
  *   coeffs  device, n*k bytes;  packed  device, n doubles.
- *   q       2 <= q, p*q^(k-1) <= 2^53 (FQT_ERR_BOUNDS otherwise).  Powers of
- *           two use shifts; other q use an exact FP64 Horner evaluation. */
+ *   q       2 <= q; the largest packed value (p-1) sum_{j<k} q^j at most
+ *           2^53 and q^k at most 2^70 (FQT_ERR_BOUNDS otherwise).  Powers of
+ *           two use shifts; other q use an exact FP64 Horner evaluation.
+ *   With q a power of two, coeffs 4-byte and packed 8-byte aligned, each
+ *   thread packs four elements from whole words (the faster kernel); other
+ *   calls stage bytes through LDS.  Results are the same either way. */
 fqt_status fqt_pack(fqt_field f, uint64_t q, const uint8_t* coeffs, size_t n,
                     double* packed, fqt_stream_t s);
 
@@ -228,7 +232,11 @@ fqt_status fqt_pack(fqt_field f, uint64_t q, const uint8_t* coeffs, size_t n,
  *   FIELD: ndigits <= 2k-1; out holds n*k bytes, the element
  *          sum_j (d_j mod p) X^j reduced modulo P (REDQ residues, then the
  *          L and H tables of Thm. 3 and one addition in the field).
- *   q      2 <= q, q^ndigits <= 2^53 (FQT_ERR_BOUNDS), ndigits in [1, 16]. */
+ *   q      2 <= q, q^ndigits <= 2^53 (FQT_ERR_BOUNDS), ndigits in [1, 15]
+ *          (FQT_ERR_UNSUPPORTED otherwise).
+ *   With q a power of two and out 4-byte aligned, each thread unpacks four
+ *   values and writes whole words, with the digit count fixed at compile
+ *   time (the faster kernel); other calls stage bytes through LDS. */
 fqt_status fqt_unpack_redq(fqt_field f, uint64_t q, const double* packed,
                            size_t n, uint32_t ndigits, fqt_unpack_mode mode,
                            uint8_t* out, fqt_stream_t s);
@@ -248,7 +256,10 @@ fqt_status fqt_unpack_redq_u64(fqt_field f, uint64_t q, const uint64_t* packed,
  * REDQ and the Q_d correction.
  *   a, b  device, n*k bytes;  c  device, n*(2k-1) bytes.
  *   q     must satisfy eq. (2) with n_q = 1 (FQT_ERR_BOUNDS), any q >= 2;
- *         powers of two use the shift path.  1 <= k <= 8. */
+ *         powers of two use the shift path.  1 <= k <= 8.
+ *   With q = 2^b, (2k-1) b <= 32 and a, b, c 4-byte aligned, every
+ *   intermediate fits 32 bits and each thread multiplies four pairs from
+ *   whole words (the faster kernel); other calls stage bytes through LDS. */
 fqt_status fqt_polymul_batch(uint32_t p, uint32_t k, uint64_t q,
                              const uint8_t* a, const uint8_t* b, size_t n,
                              uint8_t* c, fqt_stream_t s);

@@ -232,7 +232,12 @@ def test_unpack_pack_validation_errors():
     assert name(L.fqt_unpack_redq_u64(f.handle, 10 ** 4, v, 4, 7, 0, o, None)) == "FQT_ERR_BOUNDS"
     assert name(L.fqt_unpack_redq(f.handle, 64, v, 4, 6, 1, o, None)) == "FQT_ERR_INVALID_ARG"
     assert name(L.fqt_unpack_redq(f.handle, 64, v, 4, 0, 0, o, None)) == "FQT_ERR_UNSUPPORTED"
+    # ndigits in [1, 15]: 16 digits of q = 2 fit 2^53 but are refused
+    assert name(L.fqt_unpack_redq(f.handle, 2, v, 4, 16, 0, o, None)) == "FQT_ERR_UNSUPPORTED"
     assert name(L.fqt_pack(f.handle, 2 ** 30, v, 4, o, None)) == "FQT_ERR_BOUNDS"
+    # GF(5^2) at q = 2^36: packed values stay below 2^53, but q^k = 2^72 is refused
+    f2 = fqt.Field(5, 2, (2, 0))
+    assert name(L.fqt_pack(f2.handle, 2 ** 36, v, 4, o, None)) == "FQT_ERR_BOUNDS"
     assert name(L.fqt_pack(f.handle, 1, v, 4, o, None)) == "FQT_ERR_INVALID_ARG"
 
 
